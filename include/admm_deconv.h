@@ -1,0 +1,176 @@
+/*
+ * admm_deconv.h — C ABI of the MI355X (gfx950) mask-decoupled ADMM deconvolution library.
+ *
+ * Problem (Almeida & Figueiredo, Sec. IV-A, eq. (34)): recover an H x W image x
+ * from y = M A x + n, where A is a periodic convolution with an odd k x k kernel
+ * on the unknown domain and M keeps the observed pixels (the valid region,
+ * optionally minus missing interior pixels). Solvers:
+ *
+ *   ADMM_REG_TV     TV-MD (Sec. IV-D): Alg. 3 with the data step of eq. (49),
+ *                   objective eq. (48).
+ *   ADMM_REG_FRAME  FA-MD (Sec. IV-C): Alg. 2 with H1 = A, H2 = P (undecimated
+ *                   Haar Parseval frame, J levels, 3J+1 bands), z-step
+ *                   eqs. (24)-(25), prox eqs. (40) and (16), objective eq. (44).
+ *
+ * Conventions shared by every entry point:
+ *  - Images are row-major float32 planes of H*W elements (pitch W).
+ *  - "DEVICE" pointers are HIP device allocations on the current device;
+ *    "HOST" pointers are ordinary host memory.
+ *  - Every call enqueues its GPU work on the plan's stream; the call returns
+ *    after that work is complete (the library synchronises the stream), so
+ *    outputs may be read immediately.
+ *  - Functions return an admm_status and never throw. On failure the
+ *    thread-local message from admm_last_error() says why. Not converging
+ *    within max_iters is NOT an error (info.converged = 0).
+ *  - A plan is not re-entrant: do not call it from two threads at once.
+ */
+#ifndef ADMM_DECONV_H
+#define ADMM_DECONV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ADMM_OK = 0,
+    ADMM_E_INVALID = 1,      /* null pointer, bad size/count, negative lambda ...      */
+    ADMM_E_UNSUPPORTED = 2,  /* even or too large kernel, side not 7-smooth or > 2048 */
+    ADMM_E_SINGULAR = 3,     /* TV with sum(kernel) == 0: the z-step matrix is singular */
+    ADMM_E_NOMEM = 4,        /* device allocation failed                                */
+    ADMM_E_DEVICE = 5,       /* HIP runtime error (no device, launch failure ...)       */
+    ADMM_E_DIVERGED = 6      /* non-finite iterate (info.diverged = 1)                  */
+} admm_status;
+
+typedef enum { ADMM_REG_TV = 0, ADMM_REG_FRAME = 1 } admm_reg;
+
+/* One problem of a plan. */
+typedef struct {
+    int32_t H, W;            /* unknown-domain size; each side 7-smooth, 8..2048       */
+    int32_t ksize;           /* odd kernel side k = 2l+1, 1 <= k <= min(H, W)          */
+    const float* kernel;     /* HOST, k*k row-major, tap (l, l) is the centre; copied  */
+    const uint8_t* mask;     /* HOST, H*W, 1 = observed (row of M), 0 = unobserved;
+                                copied at plan time                                    */
+    int32_t reg;             /* admm_reg                                               */
+    int32_t levels;          /* frame levels J (1..4) for ADMM_REG_FRAME, else ignored */
+    double lambda;           /* regularisation weight, >= 0                            */
+    double mu1, mu2;         /* ADMM penalties; a value <= 0 selects the rule of Sec. V:
+                                mu2 = 10 lambda, mu1 = min(1, 5000 mu2)                */
+} admm_problem;
+
+/* Solve options. */
+typedef struct {
+    int32_t max_iters;       /* iterations to run at most (>= 1)                        */
+    double tol;              /* stop when r_pri <= tol and r_dual <= tol; <= 0: run
+                                exactly max_iters                                      */
+    int32_t check_every;     /* residual check period c (>= 1); the last iteration is
+                                always checked so info is filled                       */
+    uint32_t flags;          /* ADMM_FLAG_* below                                      */
+} admm_opts;
+
+/* ADMM_FLAG_GRAPH: runs of iterations that need no host decision are replayed
+ * from hipGraphs captured once per plan (captured on an internal stream,
+ * launched on the plan's stream); results are identical to eager launches.
+ * ADMM_FLAG_PROFILE: time every kernel launch with HIP events (eager launches
+ * only; read the totals with admm_plan_kernel_times).                        */
+#define ADMM_FLAG_GRAPH 1u
+#define ADMM_FLAG_PROFILE 2u
+
+/* Result of one problem. Residuals (the paper stops on the objective instead):
+ *   r_pri  = ||G z - u|| / max(||G z||, ||u||)
+ *   r_dual = ||Ups (u_k - u_{k-1})|| / max(||Ups d_k||, 1e-30)
+ * with G the stacked operator of eq. (3) and Ups = diag(mu1, mu2) of eq. (5);
+ * objective = F(z) of eq. (48) or (44) at the last checked iterate.              */
+typedef struct {
+    int32_t iters;           /* iterations performed                                    */
+    int32_t converged;       /* 1 if both residuals reached tol                         */
+    int32_t diverged;        /* 1 if a non-finite value appeared                        */
+    int32_t reserved;
+    double r_pri, r_dual, objective;
+} admm_info;
+
+/* ADMM splitting state (u, d) of Alg. 2, DEVICE planes owned by the caller.
+ * TV:    u1, d1: H*W;  ureg, dreg: 2*H*W as [horizontal plane, vertical plane].
+ * FRAME: u1, d1: H*W;  ureg, dreg: (3J+1)*H*W, band order: for j = 1..J the
+ *        detail bands (low-vert/high-horiz, high-vert/low-horiz, high/high) of
+ *        level j (dilation 2^(j-1)), then the level-J low-low band.
+ * Passed to solve/batch it is the initial state (Theorem 1: any u0, d0
+ * converge) and receives the final state, so a solve can be resumed exactly.  */
+typedef struct {
+    float* u1;
+    float* d1;
+    float* ureg;
+    float* dreg;
+} admm_state;
+
+typedef struct admm_plan admm_plan;
+
+/* Validate `count` problems, allocate their device workspaces (spectra, duals,
+ * tables) and precompute each kernel's spectrum Lambda (eq. (19)).
+ * hip_stream: a hipStream_t (NULL = the null stream). *out receives the plan.
+ * Errors: ADMM_E_INVALID, ADMM_E_UNSUPPORTED, ADMM_E_SINGULAR, ADMM_E_NOMEM,
+ * ADMM_E_DEVICE; on error *out is set to NULL and nothing is leaked.          */
+admm_status admm_deconv_plan(const admm_problem* probs, int32_t count, void* hip_stream,
+                             admm_plan** out);
+
+/* Solve the single problem of a plan with count == 1.
+ * y:    DEVICE H*W observation; entries where mask == 0 are ignored.
+ * x:    DEVICE H*W output, the last iterate z_k.
+ * st:   NULL for a cold start (u0 = d0 = 0), else initial state in / final out.
+ * info: HOST, receives the result.                                            */
+admm_status admm_deconv_solve(admm_plan* plan, const float* y, float* x, admm_state* st,
+                              const admm_opts* opts, admm_info* info);
+
+/* Solve all problems of a plan together (ragged sizes allowed).
+ * y, x: HOST arrays of `count` DEVICE pointers; st: NULL or HOST array of
+ * `count` states; infos: HOST array of `count` results.                       */
+admm_status admm_deconv_batch(admm_plan* plan, const float* const* y, float* const* x,
+                              admm_state* st, const admm_opts* opts, admm_info* infos);
+
+/* Apply the forward blur of problem `index` through its spectral path:
+ * Ax = A x (eq. (19)), both DEVICE H*W planes.                                */
+admm_status admm_deconv_blur(admm_plan* plan, int32_t index, const float* x, float* Ax);
+
+/* Warm-start state from an initial guess (not in the paper; see Theorem 1):
+ * u1 = A x0, d1 = M^T (y - M A x0) / mu1, u_TV = D x0,
+ * d_TV = -(lambda / mu2) p0 / max(1, |p0|) per pixel.
+ * x0: DEVICE H*W; p0: DEVICE 2*H*W [horizontal, vertical]; y: DEVICE H*W;
+ * st: state to fill (TV problems only).                                       */
+admm_status admm_warmstart_map(admm_plan* plan, int32_t index, const float* x0,
+                               const float* p0, const float* y, admm_state* st);
+
+/* Per-kernel GPU time of the most recent solve/batch run with ADMM_FLAG_PROFILE.
+ * Kernel classes: "col" (column DFT + circulant solve), "row_tv" (fused TV row
+ * pass), "row_inv" (FA inverse rows + data step), "frame" (FA frame step),
+ * "row_fwd" (forward rows), "reduce" (residual reduction).                    */
+typedef struct {
+    char name[16];
+    int32_t launches;
+    int32_t reserved;
+    double total_ms;
+} admm_kernel_time;
+
+/* Copies up to `cap` entries to out (HOST) and returns how many classes exist. */
+int32_t admm_plan_kernel_times(const admm_plan* plan, admm_kernel_time* out, int32_t cap);
+
+/* Release every resource of a plan (NULL is ignored).                         */
+void admm_plan_destroy(admm_plan* plan);
+
+/* Human-readable message for the last error of the calling thread.            */
+const char* admm_last_error(void);
+
+/* Host-only helpers (no device work; usable without a GPU).
+ * admm_fft_radices: radix schedule the library uses for a length-n transform;
+ * writes up to `cap` radices to out and returns their count, or -1 if n is not
+ * a supported 7-smooth length.                                                 */
+int32_t admm_fft_radices(int32_t n, int32_t* out, int32_t cap);
+
+/* admm_validate_problem: the plan-time checks for one problem, no allocation. */
+admm_status admm_validate_problem(const admm_problem* prob);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADMM_DECONV_H */

@@ -1,0 +1,286 @@
+"""Thin ctypes binding of ``libadmmdeconv.so`` (declared in include/admm_deconv.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device arrays are torch tensors on the current HIP device (float32,
+contiguous); the binding passes their data pointers and the current torch
+stream. There is no CPU fallback: if the library is not built, loading it
+raises.
+"""
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int32, c_uint8, c_uint32, c_void_p, c_char_p
+
+import numpy as np
+
+__all__ = [
+    "ADMM_OK", "ADMM_E_INVALID", "ADMM_E_UNSUPPORTED", "ADMM_E_SINGULAR", "ADMM_E_NOMEM",
+    "ADMM_E_DEVICE", "ADMM_E_DIVERGED", "ADMM_REG_TV", "ADMM_REG_FRAME", "ADMM_FLAG_GRAPH",
+    "ADMM_FLAG_PROFILE", "admm_plan_kernel_times",
+    "AdmmError", "lib", "lib_path", "exported_symbols",
+    "admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
+    "admm_warmstart_map", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
+    "admm_validate_problem", "Plan", "make_problem", "alloc_state",
+]
+
+ADMM_OK, ADMM_E_INVALID, ADMM_E_UNSUPPORTED, ADMM_E_SINGULAR, ADMM_E_NOMEM, ADMM_E_DEVICE, ADMM_E_DIVERGED = range(7)
+ADMM_REG_TV, ADMM_REG_FRAME = 0, 1
+ADMM_FLAG_GRAPH = 1
+ADMM_FLAG_PROFILE = 2
+
+_STATUS = {0: "OK", 1: "INVALID", 2: "UNSUPPORTED", 3: "SINGULAR", 4: "NOMEM", 5: "DEVICE", 6: "DIVERGED"}
+
+
+class AdmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class admm_problem(ctypes.Structure):
+    _fields_ = [("H", c_int32), ("W", c_int32), ("ksize", c_int32),
+                ("kernel", POINTER(c_float)), ("mask", POINTER(c_uint8)),
+                ("reg", c_int32), ("levels", c_int32),
+                ("lam", c_double), ("mu1", c_double), ("mu2", c_double)]
+
+
+class admm_opts(ctypes.Structure):
+    _fields_ = [("max_iters", c_int32), ("tol", c_double), ("check_every", c_int32), ("flags", c_uint32)]
+
+
+class admm_info(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("converged", c_int32), ("diverged", c_int32), ("reserved", c_int32),
+                ("r_pri", c_double), ("r_dual", c_double), ("objective", c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k in ("iters", "converged", "diverged", "r_pri", "r_dual", "objective")}
+
+
+class admm_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 16), ("launches", c_int32), ("reserved", c_int32), ("total_ms", c_double)]
+
+
+class admm_state(ctypes.Structure):
+    _fields_ = [("u1", c_void_p), ("d1", c_void_p), ("ureg", c_void_p), ("dreg", c_void_p)]
+
+
+_LIB = None
+
+
+def lib_path():
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "libadmmdeconv.so")
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        path = lib_path()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with `python -m paper_1210_2687_amd.build`")
+        L = ctypes.CDLL(path)
+        L.admm_deconv_plan.argtypes = [POINTER(admm_problem), c_int32, c_void_p, POINTER(c_void_p)]
+        L.admm_deconv_solve.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(admm_state), POINTER(admm_opts),
+                                        POINTER(admm_info)]
+        L.admm_deconv_batch.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(admm_state),
+                                        POINTER(admm_opts), POINTER(admm_info)]
+        L.admm_deconv_blur.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
+        L.admm_warmstart_map.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, POINTER(admm_state)]
+        L.admm_plan_destroy.argtypes = [c_void_p]
+        L.admm_plan_destroy.restype = None
+        L.admm_last_error.restype = c_char_p
+        L.admm_fft_radices.argtypes = [c_int32, POINTER(c_int32), c_int32]
+        L.admm_validate_problem.argtypes = [POINTER(admm_problem)]
+        L.admm_plan_kernel_times.argtypes = [c_void_p, POINTER(admm_kernel_time), c_int32]
+        L.admm_plan_kernel_times.restype = c_int32
+        for f in ("admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
+                  "admm_warmstart_map", "admm_fft_radices", "admm_validate_problem"):
+            getattr(L, f).restype = c_int32
+        _LIB = L
+    return _LIB
+
+
+def exported_symbols():
+    """Names of the C entry points declared in include/admm_deconv.h."""
+    return ["admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
+            "admm_warmstart_map", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
+            "admm_validate_problem", "admm_plan_kernel_times"]
+
+
+def admm_last_error():
+    return lib().admm_last_error().decode()
+
+
+def _check(status):
+    if status != ADMM_OK:
+        raise AdmmError(status, admm_last_error())
+
+
+def admm_fft_radices(n):
+    buf = (c_int32 * 16)()
+    k = lib().admm_fft_radices(n, buf, 16)
+    return None if k < 0 else list(buf[:k])
+
+
+def make_problem(kernel, mask, lam, mu1=-1.0, mu2=-1.0, reg=ADMM_REG_TV, levels=0):
+    """Host-side problem description; keeps the host arrays alive with it."""
+    kernel = np.ascontiguousarray(kernel, dtype=np.float32)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    p = admm_problem()
+    p.H, p.W = mask.shape
+    p.ksize = kernel.shape[0]
+    p.kernel = kernel.ctypes.data_as(POINTER(c_float))
+    p.mask = mask.ctypes.data_as(POINTER(c_uint8))
+    p.reg = reg
+    p.levels = levels
+    p.lam, p.mu1, p.mu2 = float(lam), float(mu1), float(mu2)
+    p._keep = (kernel, mask)
+    return p
+
+
+def admm_validate_problem(prob):
+    return lib().admm_validate_problem(ctypes.byref(prob))
+
+
+def _stream_ptr(stream):
+    if stream is not None:
+        return c_void_p(stream)
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def admm_deconv_plan(problems, stream=None):
+    """Plan a list of problems (see ``make_problem``); returns an opaque handle."""
+    arr = (admm_problem * len(problems))(*problems)
+    out = c_void_p()
+    _check(lib().admm_deconv_plan(arr, len(problems), _stream_ptr(stream), ctypes.byref(out)))
+    return out
+
+
+def admm_plan_destroy(plan):
+    lib().admm_plan_destroy(plan)
+
+
+def _dev(t, n=None):
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float32 tensor on the GPU")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return c_void_p(t.data_ptr())
+
+
+def _state(st, n, R):
+    if st is None:
+        return None
+    s = admm_state()
+    s.u1, s.d1 = _dev(st["u1"], n), _dev(st["d1"], n)
+    s.ureg, s.dreg = _dev(st["ureg"], R * n), _dev(st["dreg"], R * n)
+    return s
+
+
+def _opts(max_iters, tol, check_every, graph, profile=False):
+    o = admm_opts()
+    o.max_iters, o.tol, o.check_every = int(max_iters), float(tol), int(check_every)
+    o.flags = (ADMM_FLAG_GRAPH if graph else 0) | (ADMM_FLAG_PROFILE if profile else 0)
+    return o
+
+
+def admm_deconv_solve(plan, y, x, state=None, max_iters=100, tol=0.0, check_every=10, graph=False,
+                      profile=False, nreg=2):
+    n = y.numel()
+    info = admm_info()
+    st = _state(state, n, nreg)
+    _check(lib().admm_deconv_solve(plan, _dev(y), _dev(x, n), ctypes.byref(st) if st else None,
+                                   ctypes.byref(_opts(max_iters, tol, check_every, graph, profile)),
+                                   ctypes.byref(info)))
+    return info.as_dict()
+
+
+def admm_deconv_batch(plan, ys, xs, states=None, max_iters=100, tol=0.0, check_every=10, graph=False,
+                      profile=False, nregs=None, raise_on_diverged=True):
+    cnt = len(ys)
+    yp = (c_void_p * cnt)(*[_dev(t) for t in ys])
+    xp = (c_void_p * cnt)(*[_dev(t, ys[i].numel()) for i, t in enumerate(xs)])
+    sts = None
+    if states is not None:
+        nregs = nregs or [2] * cnt
+        sts = (admm_state * cnt)(*[_state(s, ys[i].numel(), nregs[i]) for i, s in enumerate(states)])
+    infos = (admm_info * cnt)()
+    status = lib().admm_deconv_batch(plan, yp, xp, sts,
+                                     ctypes.byref(_opts(max_iters, tol, check_every, graph, profile)), infos)
+    if status != ADMM_OK and not (status == ADMM_E_DIVERGED and not raise_on_diverged):
+        _check(status)
+    return [i.as_dict() for i in infos]
+
+
+def admm_plan_kernel_times(plan):
+    """{class: (launches, total_ms)} of the last run made with profile=True."""
+    buf = (admm_kernel_time * 8)()
+    k = lib().admm_plan_kernel_times(plan, buf, 8)
+    return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(min(k, 8))}
+
+
+def admm_deconv_blur(plan, index, x, Ax):
+    _check(lib().admm_deconv_blur(plan, int(index), _dev(x), _dev(Ax, x.numel())))
+
+
+def admm_warmstart_map(plan, index, x0, p0, y, state):
+    n = x0.numel()
+    st = _state(state, n, 2)
+    _check(lib().admm_warmstart_map(plan, int(index), _dev(x0, n), _dev(p0, 2 * n), _dev(y, n),
+                                    ctypes.byref(st)))
+
+
+def alloc_state(H, W, nreg=2, device="cuda"):
+    """Zero ADMM state planes (u1, d1: H x W; ureg, dreg: nreg x H x W)."""
+    import torch
+    z = lambda *s: torch.zeros(*s, dtype=torch.float32, device=device)
+    return {"u1": z(H, W), "d1": z(H, W), "ureg": z(nreg, H, W), "dreg": z(nreg, H, W)}
+
+
+class Plan:
+    """Convenience owner of a plan handle built from ``workloads.Problem``-like objects."""
+
+    def __init__(self, problems, stream=None):
+        self.problems = list(problems)
+        self._cprobs = []
+        for p in self.problems:
+            reg = ADMM_REG_FRAME if getattr(p, "reg", "tv") == "frame" else ADMM_REG_TV
+            self._cprobs.append(make_problem(p.kernel, p.mask, p.lam, p.mu1, p.mu2, reg, getattr(p, "levels", 0)))
+        self.nregs = [3 * p.levels + 1 if getattr(p, "reg", "tv") == "frame" else 2 for p in self.problems]
+        self.handle = admm_deconv_plan(self._cprobs, stream)
+
+    def solve(self, y, x, state=None, **kw):
+        return admm_deconv_solve(self.handle, y, x, state, nreg=self.nregs[0], **kw)
+
+    def batch(self, ys, xs, states=None, **kw):
+        return admm_deconv_batch(self.handle, ys, xs, states, nregs=self.nregs, **kw)
+
+    def blur(self, index, x, Ax):
+        admm_deconv_blur(self.handle, index, x, Ax)
+
+    def kernel_times(self):
+        return admm_plan_kernel_times(self.handle)
+
+    def warmstart_map(self, index, x0, p0, y, state):
+        admm_warmstart_map(self.handle, index, x0, p0, y, state)
+
+    def close(self):
+        if self.handle:
+            admm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,771 @@
+// admm_api.hip — host implementation of the C ABI declared in include/admm_deconv.h.
+//
+// A plan owns one device arena per batch holding, for every problem, the
+// transposed half-spectrum ping-pong buffers, the kernel spectrum Lambda,
+// the working duals, the mask and scratch planes (layout in admm_internal.h),
+// plus shared twiddle tables, problem descriptors and work-item lists.
+// solve/batch drive the iteration on the plan's stream: per iteration one
+// column launch and the row launches of each regulariser family; every
+// check_every iterations a reduction launch fills the per-problem residuals
+// and the host reads the active flags to stop early.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/admm_deconv.h"
+#include "admm_internal.h"
+#include "admm_launch.h"
+
+using namespace admm;
+
+namespace {
+
+thread_local std::string g_err;
+
+admm_status fail(admm_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) {                                                                     \
+            return fail(e_ == hipErrorOutOfMemory ? ADMM_E_NOMEM : ADMM_E_DEVICE, "%s failed: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                          \
+        }                                                                                           \
+    } while (0)
+
+bool smooth7(int n) {
+    if (n < 1) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// Radix schedule: powers of two as radix 8 with a tail of 4 or 2, then 7, 5, 3.
+int radices(int n, int* out, int cap) {
+    if (!smooth7(n)) return -1;
+    std::vector<int> r;
+    int a = 0;
+    while (n % 2 == 0) {
+        n /= 2;
+        ++a;
+    }
+    int n8 = a / 3, rem = a % 3;
+    if (rem == 1 && n8 > 0) {
+        --n8;
+        r.insert(r.end(), n8, 8);
+        r.push_back(4);
+        r.push_back(4);
+    } else {
+        r.insert(r.end(), n8, 8);
+        if (rem == 1) r.push_back(2);
+        if (rem == 2) r.push_back(4);
+    }
+    for (int p : {7, 5, 3})
+        while (n % p == 0) {
+            n /= p;
+            r.push_back(p);
+        }
+    if ((int)r.size() > cap) return -1;
+    for (size_t i = 0; i < r.size(); ++i) out[i] = r[i];
+    return (int)r.size();
+}
+
+// Does a block of NT threads with MAXE registers per thread fit `ntrans`
+// length-N transforms for every radix of the schedule?
+bool fits(int ntrans, const FftPlanDev& f, int maxe) {
+    const int nt = block_threads();
+    for (int s = 0; s < f.nst; ++s) {
+        const int R = f.rad[s];
+        const long long bf = (long long)ntrans * (f.N / R);
+        if ((bf + nt - 1) / nt > maxe / R) return false;
+    }
+    return true;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct admm_plan {
+    hipStream_t stream = nullptr;
+    int count = 0;
+    std::vector<admm_problem> probs;      // copies (host pointers cleared)
+    std::vector<ProbDesc> hd;             // host copy of the descriptors
+    std::vector<int> col_beg, col_end, row_beg, row_end, frm_beg, frm_end;   // item ranges per problem
+    int ncol = 0, nrowtv = 0, nrowfa = 0, nfrm = 0;
+    int ntv = 0, nfa = 0;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    ProbDesc* d_desc = nullptr;
+    WorkItem* d_items = nullptr;
+    InfoDev* d_info = nullptr;
+    InfoDev* h_info = nullptr;            // pinned
+    double* d_partials = nullptr;
+    float2* d_tw = nullptr;
+    float* d_s2 = nullptr;
+    LaunchCtx all, tv, fa;
+    size_t lds_col = 0, lds_rowtv = 0, lds_row = 0, lds_frm = 0;
+    // graph replay of plain iterations: executable per chunk length (even)
+    hipStream_t cap_stream = nullptr;
+    std::map<int, hipGraphExec_t> graphs;
+    // profiling: per-class totals of the last profiled run
+    double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+    int prof_n[6] = {0, 0, 0, 0, 0, 0};
+};
+
+static const char* const kProfNames[6] = {"col", "row_tv", "row_inv", "frame", "row_fwd", "reduce"};
+
+namespace {
+
+admm_status validate(const admm_problem& p) {
+    if (p.H < 8 || p.W < 8 || p.H > ADMM_MAX_SIDE || p.W > ADMM_MAX_SIDE)
+        return fail(ADMM_E_UNSUPPORTED, "sides %dx%d outside 8..%d", p.H, p.W, ADMM_MAX_SIDE);
+    if (!smooth7(p.H) || !smooth7(p.W))
+        return fail(ADMM_E_UNSUPPORTED, "sides %dx%d must be 7-smooth (2^a 3^b 5^c 7^d)", p.H, p.W);
+    if (!p.kernel || !p.mask) return fail(ADMM_E_INVALID, "null kernel or mask pointer");
+    if (p.ksize < 1 || p.ksize % 2 == 0 || p.ksize > std::min(p.H, p.W))
+        return fail(ADMM_E_UNSUPPORTED, "kernel side %d must be odd and <= min(H, W)", p.ksize);
+    if (p.reg != ADMM_REG_TV && p.reg != ADMM_REG_FRAME) return fail(ADMM_E_INVALID, "unknown regulariser %d", p.reg);
+    if (p.reg == ADMM_REG_FRAME && (p.levels < 1 || p.levels > 4))
+        return fail(ADMM_E_UNSUPPORTED, "frame levels %d outside 1..4", p.levels);
+    if (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)) return fail(ADMM_E_INVALID, "lambda must be finite and >= 0");
+    if (!std::isfinite(p.mu1) || !std::isfinite(p.mu2)) return fail(ADMM_E_INVALID, "mu must be finite");
+    double sum = 0.0, asum = 0.0;
+    for (int i = 0; i < p.ksize * p.ksize; ++i) {
+        if (!std::isfinite(p.kernel[i])) return fail(ADMM_E_INVALID, "non-finite kernel tap %d", i);
+        sum += p.kernel[i];
+        asum += std::fabs(p.kernel[i]);
+    }
+    if (asum == 0.0) return fail(ADMM_E_SINGULAR, "kernel is identically zero");
+    if (p.reg == ADMM_REG_TV && std::fabs(sum) <= 1e-12 * asum)
+        return fail(ADMM_E_SINGULAR, "TV needs a kernel with nonzero sum (DC gain), got %g", sum);
+    return ADMM_OK;
+}
+
+void penalties(const admm_problem& p, double* mu1, double* mu2) {
+    double m2 = p.mu2 > 0 ? p.mu2 : 10.0 * p.lambda;
+    double m1 = p.mu1 > 0 ? p.mu1 : std::min(1.0, 5000.0 * (p.mu2 > 0 ? p.mu2 : 10.0 * p.lambda));
+    if (m2 <= 0) m2 = 1e-3;   // lambda == 0 with the heuristic: any positive penalty converges
+    if (m1 <= 0) m1 = 1e-3;
+    *mu1 = m1;
+    *mu2 = m2;
+}
+
+}  // namespace
+
+extern "C" const char* admm_last_error(void) { return g_err.c_str(); }
+
+extern "C" int32_t admm_fft_radices(int32_t n, int32_t* out, int32_t cap) {
+    if (!out || cap <= 0) return -1;
+    return radices(n, out, cap);
+}
+
+extern "C" admm_status admm_validate_problem(const admm_problem* prob) {
+    if (!prob) return fail(ADMM_E_INVALID, "null problem");
+    return validate(*prob);
+}
+
+extern "C" void admm_plan_destroy(admm_plan* P) {
+    if (!P) return;
+    for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    if (P->arena) (void)hipFree(P->arena);
+    if (P->h_info) (void)hipHostFree(P->h_info);
+    delete P;
+}
+
+static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t count, void* hip_stream);
+
+extern "C" admm_status admm_deconv_plan(const admm_problem* probs, int32_t count, void* hip_stream, admm_plan** out) {
+    if (!out) return fail(ADMM_E_INVALID, "null output pointer");
+    *out = nullptr;
+    if (!probs || count < 1) return fail(ADMM_E_INVALID, "need at least one problem");
+    for (int i = 0; i < count; ++i) {
+        admm_status s = validate(probs[i]);
+        if (s != ADMM_OK) {
+            g_err = "problem " + std::to_string(i) + ": " + g_err;
+            return s;
+        }
+    }
+    admm_plan* P = new admm_plan();
+    admm_status s = build_plan(P, probs, count, hip_stream);
+    if (s != ADMM_OK) {
+        admm_plan_destroy(P);
+        return s;
+    }
+    *out = P;
+    return ADMM_OK;
+}
+
+static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t count, void* hip_stream) {
+    auto bail = [](admm_status s) { return s; };
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int lds_cap = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t cap = std::min<size_t>((size_t)lds_cap, 65536);
+    P->stream = (hipStream_t)hip_stream;
+    P->count = count;
+    P->probs.assign(probs, probs + count);
+    P->hd.resize(count);
+
+    // distinct transform lengths -> table offsets
+    std::map<int, int> tab_off;
+    int tab_len = 0;
+    for (int i = 0; i < count; ++i)
+        for (int N : {probs[i].H, probs[i].W})
+            if (!tab_off.count(N)) {
+                tab_off[N] = tab_len;
+                tab_len += N;
+            }
+
+    const int target_blocks = 1024;
+    for (int i = 0; i < count; ++i) {
+        const admm_problem& q = probs[i];
+        ProbDesc& d = P->hd[i];
+        std::memset(&d, 0, sizeof d);
+        d.H = q.H;
+        d.W = q.W;
+        d.P = q.W / 2 + 1;
+        d.reg = q.reg;
+        d.J = q.reg == ADMM_REG_FRAME ? q.levels : 0;
+        d.nb = q.reg == ADMM_REG_FRAME ? 3 * q.levels + 1 : 2;
+        double mu1, mu2;
+        penalties(q, &mu1, &mu2);
+        d.mu1 = (float)mu1;
+        d.mu2 = (float)mu2;
+        d.lam = (float)q.lambda;
+        d.tau = (float)(q.lambda / mu2);
+        d.inv_hw = (float)(1.0 / ((double)q.H * q.W));
+        d.inv1pmu1 = (float)(1.0 / (1.0 + mu1));
+        d.fr.N = q.W;
+        d.fr.nst = radices(q.W, d.fr.rad, ADMM_MAX_STAGES);
+        d.fr.tw_off = tab_off[q.W];
+        d.fc.N = q.H;
+        d.fc.nst = radices(q.H, d.fc.rad, ADMM_MAX_STAGES);
+        d.fc.tw_off = tab_off[q.H];
+        const int per = std::max(1, (target_blocks + count - 1) / count);
+        // column tile width
+        int tcmax = 1;
+        while (tcmax + 1 <= d.P && fits(tcmax + 1, d.fc, col_maxe()) && lds_col_bytes(q.H, tcmax + 1) <= cap) ++tcmax;
+        if (!fits(1, d.fc, col_maxe()) || lds_col_bytes(q.H, 1) > cap)
+            return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: column length %d does not fit a block", i, q.H));
+        d.TC = std::max(1, std::min(tcmax, (d.P + per - 1) / per));
+        // rows per block
+        int bmax = 0;
+        if (q.reg == ADMM_REG_TV) {
+            while (bmax + 1 <= q.H && fits(bmax + 3, d.fr, row_maxe()) && lds_rowtv_bytes(q.W, bmax + 1) <= cap) ++bmax;
+        } else {
+            while (bmax + 1 <= q.H && fits(bmax + 1, d.fr, row_maxe()) && lds_row_bytes(q.W, bmax + 1) <= cap) ++bmax;
+        }
+        if (bmax < 1) return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: row length %d does not fit a block", i, q.W));
+        const int bmin = q.reg == ADMM_REG_TV ? std::min(bmax, 4) : 1;
+        d.B = std::max(bmin, std::min(bmax, (q.H + per - 1) / per));
+        d.nrowblk = (q.H + d.B - 1) / d.B;
+        d.ncolblk = (d.P + d.TC - 1) / d.TC;
+        if (q.reg == ADMM_REG_FRAME) {
+            d.frm_tile = q.levels >= 4 ? 16 : 32;
+            d.nfrmblk = ((q.H + d.frm_tile - 1) / d.frm_tile) * ((q.W + d.frm_tile - 1) / d.frm_tile);
+        }
+    }
+
+    // work items: problems in order of decreasing size (largest first), each problem's items contiguous
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (long long)P->hd[a].H * P->hd[a].W > (long long)P->hd[b].H * P->hd[b].W;
+    });
+    std::vector<WorkItem> col, rowtv, rowfa, frm;
+    P->col_beg.assign(count, 0);
+    P->col_end.assign(count, 0);
+    P->row_beg.assign(count, 0);
+    P->row_end.assign(count, 0);
+    P->frm_beg.assign(count, 0);
+    P->frm_end.assign(count, 0);
+    int part = 0;
+    for (int i : order) {
+        ProbDesc& d = P->hd[i];
+        P->col_beg[i] = (int)col.size();
+        for (int b = 0; b < d.ncolblk; ++b) col.push_back({i, b * d.TC, b, 0});
+        P->col_end[i] = (int)col.size();
+        auto& rows = d.reg == REG_TV ? rowtv : rowfa;
+        P->row_beg[i] = (int)rows.size();
+        for (int b = 0; b < d.nrowblk; ++b) rows.push_back({i, b * d.B, b, 0});
+        P->row_end[i] = (int)rows.size();
+        P->frm_beg[i] = (int)frm.size();
+        for (int b = 0; b < d.nfrmblk; ++b) frm.push_back({i, b, b, 0});
+        P->frm_end[i] = (int)frm.size();
+        d.part_base = part;
+        part += d.nrowblk + d.nfrmblk;
+        if (d.reg == REG_TV) {
+            ++P->ntv;
+            P->lds_rowtv = std::max(P->lds_rowtv, lds_rowtv_bytes(d.W, d.B));
+        } else {
+            ++P->nfa;
+            P->lds_frm = std::max(P->lds_frm, lds_frame_bytes(d.frm_tile, d.J));
+        }
+        P->lds_row = std::max(P->lds_row, lds_row_bytes(d.W, d.B));
+        P->lds_col = std::max(P->lds_col, lds_col_bytes(d.H, d.TC));
+    }
+    P->ncol = (int)col.size();
+    P->nrowtv = (int)rowtv.size();
+    P->nrowfa = (int)rowfa.size();
+    P->nfrm = (int)frm.size();
+
+    // arena layout
+    std::vector<size_t> base(count);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off += align256(b);
+        return o;
+    };
+    const size_t o_desc = take(sizeof(ProbDesc) * count);
+    const size_t nitems = col.size() + rowtv.size() + rowfa.size() + frm.size();
+    const size_t o_items = take(sizeof(WorkItem) * nitems);
+    const size_t o_info = take(sizeof(InfoDev) * count);
+    const size_t o_part = take(sizeof(double) * ADMM_NSUM * std::max(part, 1));
+    const size_t o_tw = take(sizeof(float2) * tab_len);
+    const size_t o_s2 = take(sizeof(float) * tab_len);
+    struct Offs {
+        size_t spec0, spec1, lam, d1, dreg0, dreg1, u1p, uregp, tmpA, tmpB, zpl, mask;
+    };
+    std::vector<Offs> po(count);
+    for (int i = 0; i < count; ++i) {
+        const ProbDesc& d = P->hd[i];
+        const size_t n = (size_t)d.H * d.W, hp = (size_t)d.H * d.P;
+        Offs& o = po[i];
+        o.spec0 = take(hp * sizeof(float4));
+        o.spec1 = d.reg == REG_TV ? take(hp * sizeof(float4)) : o.spec0;
+        o.lam = take(hp * sizeof(float2));
+        o.d1 = take(n * sizeof(float));
+        o.dreg0 = take(n * d.nb * sizeof(float));
+        o.dreg1 = take(n * d.nb * sizeof(float));
+        o.u1p = take(n * sizeof(float));
+        o.uregp = take(n * d.nb * sizeof(float));
+        o.tmpA = take(n * sizeof(float));
+        o.tmpB = take(n * sizeof(float));
+        o.zpl = d.reg == REG_FRAME ? take(n * sizeof(float)) : o.tmpA;
+        o.mask = take(n);
+    }
+    P->arena_bytes = off;
+    {
+        hipError_t e = hipMalloc((void**)&P->arena, off);
+        if (e != hipSuccess) {
+            P->arena = nullptr;
+            (void)hipGetLastError();
+            return bail(fail(e == hipErrorOutOfMemory ? ADMM_E_NOMEM : ADMM_E_DEVICE,
+                             "device allocation of %zu bytes failed: %s", off, hipGetErrorString(e)));
+        }
+    }
+    {
+        hipError_t e = hipHostMalloc((void**)&P->h_info, sizeof(InfoDev) * count, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            P->h_info = nullptr;
+            return bail(fail(ADMM_E_NOMEM, "pinned host allocation failed: %s", hipGetErrorString(e)));
+        }
+    }
+    char* A = P->arena;
+    P->d_desc = (ProbDesc*)(A + o_desc);
+    P->d_items = (WorkItem*)(A + o_items);
+    P->d_info = (InfoDev*)(A + o_info);
+    P->d_partials = (double*)(A + o_part);
+    P->d_tw = (float2*)(A + o_tw);
+    P->d_s2 = (float*)(A + o_s2);
+    for (int i = 0; i < count; ++i) {
+        ProbDesc& d = P->hd[i];
+        const Offs& o = po[i];
+        d.spec0 = (float4*)(A + o.spec0);
+        d.spec1 = (float4*)(A + o.spec1);
+        d.lamhat = (float2*)(A + o.lam);
+        d.d1 = (float*)(A + o.d1);
+        d.dreg0 = (float*)(A + o.dreg0);
+        d.dreg1 = (float*)(A + o.dreg1);
+        d.u1p = (float*)(A + o.u1p);
+        d.uregp = (float*)(A + o.uregp);
+        d.tmpA = (float*)(A + o.tmpA);
+        d.tmpB = (float*)(A + o.tmpB);
+        d.zpl = (float*)(A + o.zpl);
+        d.mask = (const uint8_t*)(A + o.mask);
+    }
+
+    // twiddle and |Delta|^2 tables, in double then rounded once
+    {
+        std::vector<float2> tw(tab_len);
+        std::vector<float> s2(tab_len);
+        for (auto& kv : tab_off) {
+            const int N = kv.first, b = kv.second;
+            for (int k = 0; k < N; ++k) {
+                const double ang = 2.0 * M_PI * (double)k / (double)N;
+                tw[b + k] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+                const double sn = std::sin(M_PI * (double)k / (double)N);
+                s2[b + k] = (float)(4.0 * sn * sn);
+            }
+        }
+        HIP_TRY(hipMemcpy(P->d_tw, tw.data(), sizeof(float2) * tab_len, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(P->d_s2, s2.data(), sizeof(float) * tab_len, hipMemcpyHostToDevice));
+    }
+    // items and descriptors
+    std::vector<WorkItem> all;
+    all.insert(all.end(), col.begin(), col.end());
+    all.insert(all.end(), rowtv.begin(), rowtv.end());
+    all.insert(all.end(), rowfa.begin(), rowfa.end());
+    all.insert(all.end(), frm.begin(), frm.end());
+    if (!all.empty()) HIP_TRY(hipMemcpy(P->d_items, all.data(), sizeof(WorkItem) * all.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(P->d_desc, P->hd.data(), sizeof(ProbDesc) * count, hipMemcpyHostToDevice));
+    for (int i = 0; i < count; ++i) {
+        const size_t n = (size_t)P->hd[i].H * P->hd[i].W;
+        HIP_TRY(hipMemcpy((void*)P->hd[i].mask, probs[i].mask, n, hipMemcpyHostToDevice));
+    }
+
+    // launch contexts
+    LaunchCtx base_ctx;
+    base_ctx.stream = P->stream;
+    base_ctx.desc = P->d_desc;
+    base_ctx.info = P->d_info;
+    base_ctx.partials = P->d_partials;
+    base_ctx.tw = P->d_tw;
+    base_ctx.s2 = P->d_s2;
+    base_ctx.lds_col = P->lds_col;
+    base_ctx.lds_rowtv = P->lds_rowtv;
+    base_ctx.lds_row = P->lds_row;
+    base_ctx.lds_frm = P->lds_frm;
+    base_ctx.col_items = P->d_items;
+    base_ctx.ncol = P->ncol;
+    P->all = base_ctx;
+    P->tv = base_ctx;
+    P->tv.row_items = P->d_items + col.size();
+    P->tv.nrow = P->nrowtv;
+    P->fa = base_ctx;
+    P->fa.row_items = P->d_items + col.size() + rowtv.size();
+    P->fa.nrow = P->nrowfa;
+    P->fa.frm_items = P->d_items + col.size() + rowtv.size() + rowfa.size();
+    P->fa.nfrm = P->nfrm;
+
+    // kernel spectra Lambda (eq. (19)): host computes the row sums T[a][k2] in double
+    for (int i = 0; i < count; ++i) {
+        const ProbDesc& d = P->hd[i];
+        const int ks = probs[i].ksize, l = ks / 2;
+        std::vector<float2> T((size_t)ks * d.P);
+        for (int a = -l; a <= l; ++a)
+            for (int k2 = 0; k2 < d.P; ++k2) {
+                double re = 0, im = 0;
+                for (int b = -l; b <= l; ++b) {
+                    const double w = probs[i].kernel[(a + l) * ks + (b + l)];
+                    const long long e = ((long long)k2 * (b < 0 ? b + d.W : b)) % d.W;
+                    const double ang = -2.0 * M_PI * (double)e / (double)d.W;
+                    re += w * std::cos(ang);
+                    im += w * std::sin(ang);
+                }
+                T[(size_t)(a + l) * d.P + k2] = make_float2((float)re, (float)im);
+            }
+        float2* dT = nullptr;
+        HIP_TRY(hipMalloc((void**)&dT, sizeof(float2) * T.size()));
+        hipError_t e1 = hipMemcpy(dT, T.data(), sizeof(float2) * T.size(), hipMemcpyHostToDevice);
+        hipError_t e2 = e1 == hipSuccess ? launch_lambda(P->all, i, (size_t)d.H * d.P, dT, ks) : e1;
+        hipError_t e3 = e2 == hipSuccess ? hipStreamSynchronize(P->stream) : e2;
+        (void)hipFree(dT);
+        if (e3 != hipSuccess) return bail(fail(ADMM_E_DEVICE, "kernel spectrum: %s", hipGetErrorString(e3)));
+    }
+    return ADMM_OK;
+}
+
+namespace {
+
+admm_status upload_desc(admm_plan* P) {
+    HIP_TRY(hipMemcpyAsync(P->d_desc, P->hd.data(), sizeof(ProbDesc) * P->count, hipMemcpyHostToDevice, P->stream));
+    return ADMM_OK;
+}
+
+admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state* st, const admm_opts* o,
+                admm_info* infos) {
+    if (!o || !infos || !y || !x) return fail(ADMM_E_INVALID, "null argument");
+    if (o->max_iters < 1 || o->check_every < 1) return fail(ADMM_E_INVALID, "max_iters and check_every must be >= 1");
+    const int count = P->count;
+    for (int i = 0; i < count; ++i) {
+        if (!y[i] || !x[i]) return fail(ADMM_E_INVALID, "null y/x for problem %d", i);
+        if (st && (!st[i].u1 || !st[i].d1 || !st[i].ureg || !st[i].dreg))
+            return fail(ADMM_E_INVALID, "null state buffer for problem %d", i);
+        ProbDesc& d = P->hd[i];
+        d.y = y[i];
+        d.x = x[i];
+        d.st_u1 = st ? st[i].u1 : nullptr;
+        d.st_d1 = st ? st[i].d1 : nullptr;
+        d.st_ureg = st ? st[i].ureg : nullptr;
+        d.st_dreg = st ? st[i].dreg : nullptr;
+    }
+    admm_status s = upload_desc(P);
+    if (s != ADMM_OK) return s;
+    hipStream_t sm = P->stream;
+    // initial state
+    for (int i = 0; i < count; ++i) {
+        const ProbDesc& d = P->hd[i];
+        const size_t n = (size_t)d.H * d.W, hp = (size_t)d.H * d.P;
+        if (!st) {
+            HIP_TRY(hipMemsetAsync(d.spec0, 0, hp * sizeof(float4), sm));
+            HIP_TRY(hipMemsetAsync(d.d1, 0, n * sizeof(float), sm));
+            HIP_TRY(hipMemsetAsync(d.dreg0, 0, n * d.nb * sizeof(float), sm));
+            HIP_TRY(hipMemsetAsync(d.u1p, 0, n * sizeof(float), sm));
+            HIP_TRY(hipMemsetAsync(d.uregp, 0, n * d.nb * sizeof(float), sm));
+        } else {
+            HIP_TRY(hipMemcpyAsync(d.u1p, st[i].u1, n * sizeof(float), hipMemcpyDeviceToDevice, sm));
+            HIP_TRY(hipMemcpyAsync(d.uregp, st[i].ureg, n * d.nb * sizeof(float), hipMemcpyDeviceToDevice, sm));
+            if (d.reg == REG_TV) {
+                HIP_TRY(launch_import_tv(P->all, i, n));
+            } else {
+                HIP_TRY(launch_import_fa(P->all, i, n));
+            }
+        }
+    }
+    if (st) {
+        if (P->nfa) HIP_TRY(launch_frame(P->fa, 1, 0, 1, false));     // q, working d2 <- state
+        if (P->nrowtv) {
+            LaunchCtx c = P->tv;
+            HIP_TRY(launch_row_fwd(c, 0, 0, false));
+        }
+        if (P->nrowfa) HIP_TRY(launch_row_fwd(P->fa, 0, 0, false));
+    }
+    {
+        std::vector<InfoDev> h(count);
+        for (auto& f : h) {
+            std::memset(&f, 0, sizeof f);
+            f.active = 1;
+        }
+        std::memcpy(P->h_info, h.data(), sizeof(InfoDev) * count);
+        HIP_TRY(hipMemcpyAsync(P->d_info, P->h_info, sizeof(InfoDev) * count, hipMemcpyHostToDevice, sm));
+    }
+    const int K = o->max_iters, c = o->check_every;
+    const double tol = o->tol;
+    const bool profile = (o->flags & ADMM_FLAG_PROFILE) != 0;
+    const bool use_graph = (o->flags & ADMM_FLAG_GRAPH) && !profile;
+    auto is_check = [&](int k) { return k == K || (tol > 0 && k % c == 0); };
+    auto is_plain = [&](int k) { return k < K && !is_check(k) && !is_check(k + 1); };
+
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+    auto timed = [&](int cls, auto&& fn) -> hipError_t {
+        if (!profile) return fn();
+        hipEvent_t a = nullptr, b = nullptr;
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e == hipSuccess) e = hipEventRecord(a, sm);
+        if (e == hipSuccess) e = fn();
+        if (e == hipSuccess) e = hipEventRecord(b, sm);
+        ev.push_back({cls, {a, b}});
+        return e;
+    };
+    auto release_events = [&]() {
+        for (auto& x : ev) {
+            if (x.second.first) (void)hipEventDestroy(x.second.first);
+            if (x.second.second) (void)hipEventDestroy(x.second.second);
+        }
+        ev.clear();
+    };
+    // one iteration on contexts cA (all), cT (TV rows), cF (FA rows/frame)
+    auto iteration = [&](const LaunchCtx& cA, const LaunchCtx& cT, const LaunchCtx& cF, int par, int flags,
+                         bool last) -> hipError_t {
+        hipError_t e = timed(0, [&] { return launch_col(cA, par, COL_SOLVE); });
+        if (e == hipSuccess && P->nrowtv) e = timed(1, [&] { return launch_row_tv(cT, par, flags); });
+        if (e == hipSuccess && P->nrowfa) {
+            e = timed(2, [&] { return launch_row_inv(cF, 0, 1, flags, true); });
+            if (e == hipSuccess) e = timed(3, [&] { return launch_frame(cF, par, flags, 0, true); });
+            if (e == hipSuccess && !last) e = timed(4, [&] { return launch_row_fwd(cF, 0, 0, true); });
+        }
+        return e;
+    };
+    auto get_graph = [&](int G, hipGraphExec_t* exec) -> admm_status {
+        auto it = P->graphs.find(G);
+        if (it != P->graphs.end()) {
+            *exec = it->second;
+            return ADMM_OK;
+        }
+        if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+        LaunchCtx cA = P->all, cT = P->tv, cF = P->fa;
+        cA.stream = cT.stream = cF.stream = P->cap_stream;
+        HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < G && e == hipSuccess; ++i) e = iteration(cA, cT, cF, i & 1, F_FORWARD, false);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(P->cap_stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(ADMM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        hipGraphExec_t x = nullptr;
+        hipError_t e3 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return fail(ADMM_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e3));
+        P->graphs[G] = x;
+        *exec = x;
+        return ADMM_OK;
+    };
+
+    int par = 0;
+    int k = 1;
+    while (k <= K) {
+        if (use_graph && par == 0 && is_plain(k)) {
+            int run = 0;
+            while (k + run <= K && is_plain(k + run)) ++run;
+            int G = 64;
+            while (G > run) G >>= 1;
+            if (G >= 2) {
+                hipGraphExec_t exec = nullptr;
+                admm_status gs = get_graph(G, &exec);
+                if (gs != ADMM_OK) return gs;
+                HIP_TRY(hipGraphLaunch(exec, sm));
+                k += G;
+                continue;
+            }
+        }
+        const bool last = k == K, check = is_check(k), next_check = !last && is_check(k + 1);
+        int flags = (last ? 0 : F_FORWARD) | (next_check ? F_WRITE_UPREV : 0);
+        if (check) flags |= F_CHECK | F_WRITE_X | (st ? F_EXPORT : 0);
+        {
+            hipError_t e = iteration(P->all, P->tv, P->fa, par, flags, last);
+            if (e != hipSuccess) {
+                release_events();
+                return fail(ADMM_E_DEVICE, "iteration %d launch failed: %s", k, hipGetErrorString(e));
+            }
+        }
+        if (check) {
+            hipError_t e = timed(5, [&] { return launch_reduce(P->all, count, tol, k, last ? 1 : 0); });
+            if (e != hipSuccess) {
+                release_events();
+                return fail(ADMM_E_DEVICE, "reduction launch failed: %s", hipGetErrorString(e));
+            }
+            if (!last && tol > 0) {
+                HIP_TRY(hipMemcpyAsync(P->h_info, P->d_info, sizeof(InfoDev) * count, hipMemcpyDeviceToHost, sm));
+                HIP_TRY(hipStreamSynchronize(sm));
+                bool any = false;
+                for (int i = 0; i < count; ++i) any = any || P->h_info[i].active;
+                if (!any) break;
+            }
+        }
+        par ^= 1;
+        ++k;
+    }
+    if (profile) {
+        HIP_TRY(hipStreamSynchronize(sm));
+        for (int i = 0; i < 6; ++i) {
+            P->prof_ms[i] = 0;
+            P->prof_n[i] = 0;
+        }
+        for (auto& x : ev) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, x.second.first, x.second.second) == hipSuccess) {
+                P->prof_ms[x.first] += ms;
+                P->prof_n[x.first] += 1;
+            }
+        }
+        release_events();
+    }
+    HIP_TRY(hipMemcpyAsync(P->h_info, P->d_info, sizeof(InfoDev) * count, hipMemcpyDeviceToHost, sm));
+    HIP_TRY(hipStreamSynchronize(sm));
+    bool diverged = false;
+    for (int i = 0; i < count; ++i) {
+        const InfoDev& f = P->h_info[i];
+        infos[i].iters = f.iters;
+        infos[i].converged = f.converged;
+        infos[i].diverged = f.diverged;
+        infos[i].reserved = 0;
+        infos[i].r_pri = f.r_pri;
+        infos[i].r_dual = f.r_dual;
+        infos[i].objective = f.objective;
+        diverged = diverged || f.diverged;
+    }
+    if (diverged) return fail(ADMM_E_DIVERGED, "non-finite iterate");
+    return ADMM_OK;
+}
+
+}  // namespace
+
+extern "C" admm_status admm_deconv_solve(admm_plan* P, const float* y, float* x, admm_state* st, const admm_opts* o,
+                                         admm_info* info) {
+    if (!P) return fail(ADMM_E_INVALID, "null plan");
+    if (P->count != 1) return fail(ADMM_E_INVALID, "solve needs a plan with one problem (has %d); use batch", P->count);
+    return run(P, &y, &x, st, o, info);
+}
+
+extern "C" admm_status admm_deconv_batch(admm_plan* P, const float* const* y, float* const* x, admm_state* st,
+                                         const admm_opts* o, admm_info* infos) {
+    if (!P) return fail(ADMM_E_INVALID, "null plan");
+    return run(P, y, x, st, o, infos);
+}
+
+namespace {
+
+// Context restricted to the items of one problem.
+LaunchCtx single(const admm_plan* P, int i) {
+    const ProbDesc& d = P->hd[i];
+    LaunchCtx c = d.reg == REG_TV ? P->tv : P->fa;
+    c.col_items = P->all.col_items + P->col_beg[i];
+    c.ncol = P->col_end[i] - P->col_beg[i];
+    c.row_items += P->row_beg[i];
+    c.nrow = P->row_end[i] - P->row_beg[i];
+    c.frm_items = nullptr;
+    c.nfrm = 0;
+    return c;
+}
+
+admm_status blur_into_tmpB(admm_plan* P, int i, const float* x) {
+    const ProbDesc& d = P->hd[i];
+    const size_t n = (size_t)d.H * d.W;
+    LaunchCtx c = single(P, i);
+    HIP_TRY(hipMemcpyAsync(d.tmpA, x, n * sizeof(float), hipMemcpyDeviceToDevice, P->stream));
+    HIP_TRY(launch_row_fwd(c, 0, 1, false));
+    HIP_TRY(launch_col(c, 0, COL_BLUR));
+    HIP_TRY(launch_row_inv(c, 0, 0, 0, false));
+    return ADMM_OK;
+}
+
+}  // namespace
+
+extern "C" admm_status admm_deconv_blur(admm_plan* P, int32_t index, const float* x, float* Ax) {
+    if (!P || !x || !Ax) return fail(ADMM_E_INVALID, "null argument");
+    if (index < 0 || index >= P->count) return fail(ADMM_E_INVALID, "index %d out of range", index);
+    admm_status s = blur_into_tmpB(P, index, x);
+    if (s != ADMM_OK) return s;
+    const ProbDesc& d = P->hd[index];
+    HIP_TRY(hipMemcpyAsync(Ax, d.tmpB, (size_t)d.H * d.W * sizeof(float), hipMemcpyDeviceToDevice, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    return ADMM_OK;
+}
+
+extern "C" admm_status admm_warmstart_map(admm_plan* P, int32_t index, const float* x0, const float* p0, const float* y,
+                                          admm_state* st) {
+    if (!P || !x0 || !p0 || !y || !st || !st->u1 || !st->d1 || !st->ureg || !st->dreg)
+        return fail(ADMM_E_INVALID, "null argument");
+    if (index < 0 || index >= P->count) return fail(ADMM_E_INVALID, "index %d out of range", index);
+    const ProbDesc& d = P->hd[index];
+    if (d.reg != REG_TV) return fail(ADMM_E_INVALID, "warm-start mapping is defined for TV problems");
+    admm_status s = blur_into_tmpB(P, index, x0);
+    if (s != ADMM_OK) return s;
+    HIP_TRY(launch_warmstart(P->all, index, (size_t)d.H * d.W, x0, p0, y, st->u1, st->d1, st->ureg, st->dreg));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    return ADMM_OK;
+}
+
+extern "C" int32_t admm_plan_kernel_times(const admm_plan* P, admm_kernel_time* out, int32_t cap) {
+    if (!P) return 0;
+    for (int i = 0; i < 6 && out && i < cap; ++i) {
+        std::memset(&out[i], 0, sizeof out[i]);
+        std::snprintf(out[i].name, sizeof out[i].name, "%s", kProfNames[i]);
+        out[i].launches = P->prof_n[i];
+        out[i].total_ms = P->prof_ms[i];
+    }
+    return 6;
+}

@@ -1,0 +1,97 @@
+// admm_internal.h — descriptors shared by the host library and the gfx950 kernels.
+//
+// Data layout in HBM, per problem (H x W unknown domain, P = W/2 + 1):
+//   planes      row-major H x W float32 (pitch W): duals d1, d^h, d^v (TV) or
+//               d1 and 3J+1 frame bands (FA), the observation y and mask m;
+//   spectra     two ping-pong buffers of P x H float4, stored TRANSPOSED
+//               ([k2][k1], k1 fastest) so the column pass reads contiguous
+//               columns; each float4 holds two complex values: after the row
+//               pass the row-DFT half spectra of (zeta1, s); after the column
+//               pass the row-DFT half spectra of (z, A z);
+//   lamhat      P x H float2 ([k2][k1]): the kernel spectrum Lambda of eq. (19).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define ADMM_MAX_STAGES 12
+#define ADMM_NSUM 12
+#define ADMM_MAX_SIDE 2048
+#define ADMM_MAX_BANDS 16
+
+namespace admm {
+
+enum { REG_TV = 0, REG_FRAME = 1 };
+
+// Row-kernel flags (per launch).
+enum {
+    F_WRITE_X = 1,      // write z into the output image
+    F_WRITE_UPREV = 2,  // keep u_k for the next iteration's dual residual
+    F_CHECK = 4,        // accumulate the residual / objective sums
+    F_EXPORT = 8,       // write (u, d) to the caller's state buffers
+    F_FORWARD = 16,     // finish with the next iteration's forward row DFT
+};
+
+// Column-kernel modes.
+enum { COL_SOLVE = 0, COL_BLUR = 1 };
+
+struct FftPlanDev {
+    int N;
+    int nst;
+    int tw_off;                 // offset of this length's tables in the shared table arrays
+    int rad[ADMM_MAX_STAGES];
+};
+
+// Residual sums (index into the per-block partial vector):
+//  0 |A z - u1|^2   1 |G_reg z - u_reg|^2   2 |A z|^2   3 |G_reg z|^2
+//  4 |u1|^2         5 |u_reg|^2             6 |u1 - u1_prev|^2
+//  7 |u_reg - u_reg_prev|^2   8 |d1|^2      9 |d_reg|^2
+// 10 sum m (y - A z)^2       11 regulariser value (TV sum of |D_i z|, or |P z|_1)
+struct ProbDesc {
+    int H, W, P, reg, J, nb;
+    int B, TC;                  // rows per row block, columns per column tile
+    int nrowblk, ncolblk, nfrmblk, frm_tile;
+    int part_base;              // first partial-vector slot of this problem
+    float mu1, mu2, tau, lam, inv_hw, inv1pmu1;
+    FftPlanDev fr, fc;          // row (length W) and column (length H) transforms
+    float4* spec0;
+    float4* spec1;
+    float2* lamhat;
+    float* d1;
+    float* dreg0;               // regulariser duals, ping: TV [d^h, d^v]; FA 3J+1 bands
+    float* dreg1;               // pong (neighbouring blocks read halos of the old values)
+    float* u1p;                 // u1 of the previous iteration (dual residual)
+    float* uregp;               // u_reg of the previous iteration (2 or nb planes)
+    float* tmpA;                // zeta1 plane (FA per iteration; TV at initialisation)
+    float* tmpB;                // s / q plane
+    float* zpl;                 // z plane (FA)
+    const float* y;             // caller's observation (read where mask == 1)
+    const uint8_t* mask;
+    float* x;                   // caller's output
+    float* st_u1;               // caller's state buffers (export / import), may be null
+    float* st_d1;
+    float* st_ureg;
+    float* st_dreg;
+};
+
+struct WorkItem {
+    int prob;
+    int start;                  // first row (row pass), first column (column pass) or tile index
+    int blk;                    // block index within the problem (partial-sum slot)
+    int pad;
+};
+
+struct InfoDev {
+    int iters, converged, diverged, active;
+    double r_pri, r_dual, objective;
+};
+
+// Map a linear block id so that consecutive work items land on the same XCD
+// (workgroups are dispatched round-robin over the 8 XCDs of an MI355X, each
+// with its own L2; neighbouring items share halo rows and cache lines).
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+    const int xcd = bid & 7, slot = bid >> 3;
+    const int per = nblk >> 3, rem = nblk & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + slot;
+}
+
+}  // namespace admm

@@ -1,0 +1,550 @@
+// admm_kernels.hip — gfx950 kernels of the mask-decoupled ADMM iteration.
+//
+// One TV-MD iteration (Alg. 3 with the data step of eq. (49)) is two launches:
+//
+//   k_col     column pass, one work item = TC columns of the transposed half
+//             spectrum: forward column DFT of (zeta1^, s^), the circulant solve
+//             z^ = K (mu1 conj(Lambda) zeta1^ + s^) with
+//             K = 1 / (mu1 |Lambda|^2 + mu2 (|Delta^h|^2 + |Delta^v|^2))   (eq. (33)),
+//             A z^ = Lambda z^, inverse column DFT; in place.
+//   k_row_tv  row pass, one work item = B rows plus a one-row halo on each side:
+//             inverse row DFT of (z^ + i A z^) -> z, A z; mask prox and data
+//             dual (eq. (49)); vector soft threshold and TV duals (Sec. III-C);
+//             zeta1 = u1 + d1 and s = mu2 D^T (u_TV + d_TV) for the next
+//             iteration; forward row DFT of (zeta1 + i s) -> next half spectra.
+//             Residual partial sums on check iterations.
+//
+// FA-MD (Sec. IV-C) uses k_col with K = 1 / (mu1 |Lambda|^2 + mu2) (eq. (25)),
+// then k_row_inv (inverse rows + data step), k_frame (frame analysis, soft
+// threshold, frame duals and synthesis q = mu2 P^T (u2 + d2)) and k_row_fwd.
+#include "admm_internal.h"
+#include "fft_lds.h"
+#include "admm_launch.h"
+
+namespace admm {
+
+constexpr int NT = 256;            // threads per block of the FFT passes
+constexpr int MAXE_COL = 16;       // float4 elements per thread in the column pass
+constexpr int MAXE_ROW = 32;       // float2 elements per thread in the row passes
+constexpr int MAXC = ADMM_MAX_SIDE / NT;   // columns per thread in the epilogue
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// ------------------------------------------------------------ block reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sum ADMM_NSUM per-thread values over the block and write them to out[0..NSUM).
+// scratch: >= (NT/64) * ADMM_NSUM doubles of LDS.
+__device__ void block_sums_write(const double* v, double* scratch, double* out) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ADMM_NSUM; ++i) {
+        double s = wave_sum(v[i]);
+        if (lane == 0) scratch[wave * ADMM_NSUM + i] = s;
+    }
+    __syncthreads();
+    if (tid < ADMM_NSUM) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += scratch[w * ADMM_NSUM + tid];
+        out[tid] = s;
+    }
+}
+
+// ------------------------------------------------------------ column pass
+template <int MAXE>
+__global__ __launch_bounds__(NT) void k_col(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                            int nitems, int par, int mode, const InfoDev* __restrict__ info,
+                                            const float2* __restrict__ tw, const float* __restrict__ s2tab) {
+    extern __shared__ float4 cl[];
+    const int wi = xcd_remap(blockIdx.x, gridDim.x);
+    const WorkItem it = items[wi];
+    if (info && !info[it.prob].active) return;
+    const ProbDesc& p = pd[it.prob];
+    const int H = p.H, P = p.P, c0 = it.start;
+    const int nc = min(p.TC, P - c0);
+    const int tid = threadIdx.x;
+    float4* S = ((p.reg == REG_TV && par) ? p.spec1 : p.spec0) + (size_t)c0 * H;
+    const int tot = nc * H;
+    for (int i = tid; i < tot; i += NT) cl[i] = S[i];
+    __syncthreads();
+    fft_lds<MAXE, false>(cl, H, nc, H, p.fc.rad, p.fc.nst, tw + p.fc.tw_off, tid, NT);
+
+    const float2* L = p.lamhat + (size_t)c0 * H;
+    const float* s2H = s2tab + p.fc.tw_off;
+    const float* s2W = s2tab + p.fr.tw_off;
+    const float mu1 = p.mu1, mu2 = p.mu2, ihw = p.inv_hw;
+    const bool tv = p.reg == REG_TV;
+    for (int i = tid; i < tot; i += NT) {
+        const int col = i / H;
+        const int k1 = i - col * H;
+        const float2 lam = L[i];
+        const float4 f = cl[i];
+        float4 o;
+        if (mode == COL_SOLVE) {
+            const float w = tv ? (s2H[k1] + s2W[c0 + col]) : 1.0f;
+            const float l2 = fmaf(lam.x, lam.x, lam.y * lam.y);
+            const float K = ihw / fmaf(mu1, l2, mu2 * w);
+            // r = mu1 conj(Lambda) zeta1^ + s^
+            const float rx = fmaf(mu1, fmaf(lam.x, f.x, lam.y * f.y), f.z);
+            const float ry = fmaf(mu1, fmaf(lam.x, f.y, -(lam.y * f.x)), f.w);
+            const float zx = K * rx, zy = K * ry;
+            o = make_float4(zx, zy, fmaf(lam.x, zx, -(lam.y * zy)), fmaf(lam.x, zy, lam.y * zx));
+        } else {  // COL_BLUR: (x^, 0) -> (Lambda x^ / (H W), 0)
+            const float ax = fmaf(lam.x, f.x, -(lam.y * f.y)), ay = fmaf(lam.x, f.y, lam.y * f.x);
+            o = make_float4(ax * ihw, ay * ihw, 0.f, 0.f);
+        }
+        cl[i] = o;
+    }
+    __syncthreads();
+    fft_lds<MAXE, true>(cl, H, nc, H, p.fc.rad, p.fc.nst, tw + p.fc.tw_off, tid, NT);
+    for (int i = tid; i < tot; i += NT) S[i] = cl[i];
+}
+
+// ------------------------------------------------------------ row helpers
+// Load transposed half-spectrum rows [rbeg, rbeg + nrows) (wrapping mod H) as
+// full complex rows Y = z^ + i A z^ (Hermitian completion of both halves).
+__device__ __forceinline__ void load_rows_hermitian(float2* X, const float4* __restrict__ S, int H, int W, int P,
+                                                    int rbeg, int nrows, int tid) {
+    const int tot = P * nrows;
+    for (int i = tid; i < tot; i += NT) {
+        const int k2 = i / nrows;
+        const int rr = i - k2 * nrows;
+        const int r = wrapi(rbeg + rr, H);
+        const float4 f = S[(size_t)k2 * H + r];
+        float2* row = X + rr * W;
+        if (k2 == 0 || 2 * k2 == W) {
+            row[k2] = make_float2(f.x, f.z);  // real parts only at DC / Nyquist
+        } else {
+            row[k2] = make_float2(f.x - f.w, f.y + f.z);
+            if (k2 <= W - P) row[W - k2] = make_float2(f.x + f.w, f.z - f.y);
+        }
+    }
+}
+
+// Split the row DFTs C of (a + i b) in X rows [0, nrows) into the half spectra of
+// a and b and store them transposed at rows [r0, r0 + nrows).
+__device__ __forceinline__ void store_rows_split(const float2* X, float4* __restrict__ S, int H, int W, int P,
+                                                 int r0, int nrows, int tid) {
+    const int tot = P * nrows;
+    for (int i = tid; i < tot; i += NT) {
+        const int k2 = i / nrows;
+        const int rr = i - k2 * nrows;
+        const float2 c = X[rr * W + k2];
+        const float2 m = X[rr * W + (k2 == 0 ? 0 : W - k2)];
+        // A^ = (C + conj(Cm)) / 2 ; B^ = (C - conj(Cm)) / (2 i)
+        S[(size_t)k2 * H + r0 + rr] =
+            make_float4(0.5f * (c.x + m.x), 0.5f * (c.y - m.y), 0.5f * (c.y + m.y), 0.5f * (m.x - c.x));
+    }
+}
+
+// ------------------------------------------------------------ fused TV row pass
+template <int MAXE>
+__global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                               int nitems, int par, int flags, const InfoDev* __restrict__ info,
+                                               const float2* __restrict__ tw, double* __restrict__ partials) {
+    extern __shared__ float2 X[];
+    const int wi = xcd_remap(blockIdx.x, gridDim.x);
+    const WorkItem it = items[wi];
+    if (!info[it.prob].active) return;
+    const ProbDesc& p = pd[it.prob];
+    const int H = p.H, W = p.W, P = p.P, r0 = it.start;
+    const int nr = min(p.B, H - r0);
+    const int nrh = nr + 2;
+    const int tid = threadIdx.x;
+    const size_t n = (size_t)H * W;
+    float* dl = reinterpret_cast<float*>(X + nrh * W);   // 2 x W: delta^h of the current row (ping-pong)
+
+    const float4* Sin = par ? p.spec1 : p.spec0;
+    float4* Sout = par ? p.spec0 : p.spec1;
+    const float* dh_in = par ? p.dreg1 : p.dreg0;
+    const float* dv_in = dh_in + n;
+    float* dh_out = par ? p.dreg0 : p.dreg1;
+    float* dv_out = dh_out + n;
+
+    load_rows_hermitian(X, Sin, H, W, P, r0 - 1, nrh, tid);
+    __syncthreads();
+    fft_lds<MAXE, true>(X, W, nrh, W, p.fr.rad, p.fr.nst, tw + p.fr.tw_off, tid, NT);
+    // X[rr][c] = z + i A z for row r0 - 1 + rr
+
+    const float tau = p.tau, mu2 = p.mu2, c1 = p.inv1pmu1;
+    const bool chk = flags & F_CHECK;
+    double acc[ADMM_NSUM];
+#pragma unroll
+    for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
+    float dvp[MAXC], zet[MAXC], dvc[MAXC];
+
+    for (int rr = 0; rr <= nr; ++rr) {
+        const int r = wrapi(r0 - 1 + rr, H);
+        const float2* Xr = X + rr * W;
+        const float2* Xn = X + (rr + 1) * W;
+        float* dlr = dl + (rr & 1) * W;
+#pragma unroll
+        for (int j = 0; j < MAXC; ++j) {
+            const int c = tid + j * NT;
+            if (c < W) {
+                const float zc = Xr[c].x;
+                const float zh = Xr[c + 1 == W ? 0 : c + 1].x - zc;
+                const float zv = Xn[c].x - zc;
+                const size_t g = (size_t)r * W + c;
+                const float dh = dh_in[g], dv = dv_in[g];
+                const float vh = zh - dh, vv = zv - dv;
+                const float rho = sqrtf(fmaf(vh, vh, vv * vv));
+                const float sc = rho > tau ? (rho - tau) / rho : 0.0f;
+                const float uh = vh * sc, uv = vv * sc;
+                const float dhn = uh - vh, dvn = uv - vv;      // d - (D z - u)
+                dlr[c] = uh + dhn;
+                dvc[j] = uv + dvn;
+                if (rr > 0) {
+                    const float Az = Xr[c].y;
+                    const float d1o = p.d1[g];
+                    const bool obs = p.mask[g] != 0;
+                    const float yv = obs ? p.y[g] : 0.0f;
+                    const float v1 = Az - d1o;
+                    const float u1 = obs ? fmaf(yv - v1, c1, v1) : v1;   // (y + mu1 v)/(1 + mu1) or v
+                    const float d1n = u1 - v1;                           // d1 - (A z - u1)
+                    p.d1[g] = d1n;
+                    dh_out[g] = dhn;
+                    dv_out[g] = dvn;
+                    zet[j] = u1 + d1n;
+                    if (flags & F_WRITE_X) p.x[g] = zc;
+                    if (chk) {
+                        const float u1q = p.u1p[g], uhq = p.uregp[g], uvq = p.uregp[n + g];
+                        const float e0 = Az - u1, e1h = zh - uh, e1v = zv - uv;
+                        const float f6 = u1 - u1q, f7h = uh - uhq, f7v = uv - uvq;
+                        const float ry = yv - Az;
+                        acc[0] += (double)(e0 * e0);
+                        acc[1] += (double)fmaf(e1h, e1h, e1v * e1v);
+                        acc[2] += (double)(Az * Az);
+                        acc[3] += (double)fmaf(zh, zh, zv * zv);
+                        acc[4] += (double)(u1 * u1);
+                        acc[5] += (double)fmaf(uh, uh, uv * uv);
+                        acc[6] += (double)(f6 * f6);
+                        acc[7] += (double)fmaf(f7h, f7h, f7v * f7v);
+                        acc[8] += (double)(d1n * d1n);
+                        acc[9] += (double)fmaf(dhn, dhn, dvn * dvn);
+                        acc[10] += obs ? (double)(ry * ry) : 0.0;
+                        acc[11] += (double)sqrtf(fmaf(zh, zh, zv * zv));
+                    }
+                    if (flags & F_WRITE_UPREV) {
+                        p.u1p[g] = u1;
+                        p.uregp[g] = uh;
+                        p.uregp[n + g] = uv;
+                    }
+                    if (flags & F_EXPORT) {
+                        p.st_u1[g] = u1;
+                        p.st_d1[g] = d1n;
+                        p.st_ureg[g] = uh;
+                        p.st_ureg[n + g] = uv;
+                        p.st_dreg[g] = dhn;
+                        p.st_dreg[n + g] = dvn;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (rr > 0) {
+            float2* Xw = X + rr * W;
+#pragma unroll
+            for (int j = 0; j < MAXC; ++j) {
+                const int c = tid + j * NT;
+                if (c < W) {
+                    const float s = mu2 * ((dlr[c == 0 ? W - 1 : c - 1] - dlr[c]) + (dvp[j] - dvc[j]));
+                    Xw[c] = make_float2(zet[j], s);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < MAXC; ++j) dvp[j] = dvc[j];
+    }
+    __syncthreads();
+    if (flags & F_FORWARD) {
+        fft_lds<MAXE, false>(X + W, W, nr, W, p.fr.rad, p.fr.nst, tw + p.fr.tw_off, tid, NT);
+        store_rows_split(X + W, Sout, H, W, P, r0, nr, tid);
+    }
+    if (chk) block_sums_write(acc, reinterpret_cast<double*>(X), partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM);
+}
+
+// ------------------------------------------------------------ plane -> spectrum rows
+// Forward row DFT of (a + i b) for rows [r0, r0 + nr) of two planes.
+template <int MAXE>
+__global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                                int nitems, int par, int src, const InfoDev* __restrict__ info,
+                                                const float2* __restrict__ tw) {
+    extern __shared__ float2 X[];
+    const int wi = xcd_remap(blockIdx.x, gridDim.x);
+    const WorkItem it = items[wi];
+    if (info && !info[it.prob].active) return;
+    const ProbDesc& p = pd[it.prob];
+    const int H = p.H, W = p.W, P = p.P, r0 = it.start;
+    const int nr = min(p.B, H - r0);
+    const int tid = threadIdx.x;
+    // src 0: (tmpA, tmpB); src 1: (x, 0) read from tmpA only
+    const float* a = p.tmpA + (size_t)r0 * W;
+    const float* b = p.tmpB + (size_t)r0 * W;
+    const int tot = nr * W;
+    for (int i = tid; i < tot; i += NT) X[i] = make_float2(a[i], src == 0 ? b[i] : 0.0f);
+    __syncthreads();
+    fft_lds<MAXE, false>(X, W, nr, W, p.fr.rad, p.fr.nst, tw + p.fr.tw_off, tid, NT);
+    store_rows_split(X, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
+}
+
+// ------------------------------------------------------------ spectrum rows -> planes
+// Inverse row DFT of (z^ + i A z^) for rows [r0, r0 + nr).
+//   mode 0 (blur): write z (the real part) to tmpB.
+//   mode 1 (FA data step): z -> zpl, mask prox and data dual (eq. (40)), zeta1 -> tmpA.
+template <int MAXE>
+__global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                                int nitems, int par, int mode, int flags,
+                                                const InfoDev* __restrict__ info, const float2* __restrict__ tw,
+                                                double* __restrict__ partials) {
+    extern __shared__ float2 X[];
+    const int wi = xcd_remap(blockIdx.x, gridDim.x);
+    const WorkItem it = items[wi];
+    if (info && !info[it.prob].active) return;
+    const ProbDesc& p = pd[it.prob];
+    const int H = p.H, W = p.W, P = p.P, r0 = it.start;
+    const int nr = min(p.B, H - r0);
+    const int tid = threadIdx.x;
+    load_rows_hermitian(X, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
+    __syncthreads();
+    fft_lds<MAXE, true>(X, W, nr, W, p.fr.rad, p.fr.nst, tw + p.fr.tw_off, tid, NT);
+    const int tot = nr * W;
+    const size_t off = (size_t)r0 * W;
+    if (mode == 0) {
+        for (int i = tid; i < tot; i += NT) p.tmpB[off + i] = X[i].x;
+        return;
+    }
+    const float c1 = p.inv1pmu1;
+    const bool chk = flags & F_CHECK;
+    double acc[ADMM_NSUM];
+#pragma unroll
+    for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
+    for (int i = tid; i < tot; i += NT) {
+        const size_t g = off + i;
+        const float z = X[i].x, Az = X[i].y;
+        const float d1o = p.d1[g];
+        const bool obs = p.mask[g] != 0;
+        const float yv = obs ? p.y[g] : 0.0f;
+        const float v1 = Az - d1o;
+        const float u1 = obs ? fmaf(yv - v1, c1, v1) : v1;
+        const float d1n = u1 - v1;
+        p.d1[g] = d1n;
+        p.tmpA[g] = u1 + d1n;
+        p.zpl[g] = z;
+        if (flags & F_WRITE_X) p.x[g] = z;
+        if (chk) {
+            const float e0 = Az - u1, f6 = u1 - p.u1p[g], ry = yv - Az;
+            acc[0] += (double)(e0 * e0);
+            acc[2] += (double)(Az * Az);
+            acc[4] += (double)(u1 * u1);
+            acc[6] += (double)(f6 * f6);
+            acc[8] += (double)(d1n * d1n);
+            acc[10] += obs ? (double)(ry * ry) : 0.0;
+        }
+        if (flags & F_WRITE_UPREV) p.u1p[g] = u1;
+        if (flags & F_EXPORT) {
+            p.st_u1[g] = u1;
+            p.st_d1[g] = d1n;
+        }
+    }
+    if (chk) block_sums_write(acc, reinterpret_cast<double*>(X), partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM);
+}
+
+// ------------------------------------------------------------ TV state import
+// From a caller state (u, d): working duals, zeta1 = u1 + d1 -> tmpA and
+// s = mu2 D^T (u_TV + d_TV) -> tmpB, with the same expressions (and rounding)
+// as the fused row pass so that a resumed solve continues bit for bit.
+__global__ void k_import_tv(const ProbDesc* __restrict__ pd, int prob) {
+    const ProbDesc& p = pd[prob];
+    const int H = p.H, W = p.W;
+    const size_t n = (size_t)H * W;
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int r = (int)(g / W), c = (int)(g - (size_t)r * W);
+    const float* uh = p.st_ureg;
+    const float* uv = p.st_ureg + n;
+    const float* dh = p.st_dreg;
+    const float* dv = p.st_dreg + n;
+    const size_t gl = (size_t)r * W + (c == 0 ? W - 1 : c - 1);
+    const size_t gu = (size_t)(r == 0 ? H - 1 : r - 1) * W + c;
+    const float dlc = uh[g] + dh[g], dll = uh[gl] + dh[gl];
+    const float dvc = uv[g] + dv[g], dvu = uv[gu] + dv[gu];
+    p.tmpB[g] = p.mu2 * ((dll - dlc) + (dvu - dvc));
+    p.tmpA[g] = p.st_u1[g] + p.st_d1[g];
+    p.d1[g] = p.st_d1[g];
+    p.dreg0[g] = dh[g];
+    p.dreg0[n + g] = dv[g];
+}
+
+// ------------------------------------------------------------ second-stage reduction
+// One block per problem: sum the block partials in a fixed order (deterministic),
+// form the residuals and objective, update the problem's info and active flag.
+__global__ __launch_bounds__(NT) void k_reduce(const ProbDesc* __restrict__ pd, const double* __restrict__ partials,
+                                               InfoDev* __restrict__ info, double tol, int iter, int final_iter) {
+    __shared__ double sm[NT / 64][ADMM_NSUM];
+    const int prob = blockIdx.x;
+    if (!info[prob].active) return;
+    const ProbDesc& p = pd[prob];
+    const int nblk = p.nrowblk + p.nfrmblk;
+    const int tid = threadIdx.x;
+    double v[ADMM_NSUM];
+#pragma unroll
+    for (int i = 0; i < ADMM_NSUM; ++i) v[i] = 0.0;
+    for (int b = tid; b < nblk; b += NT) {
+        const double* q = partials + (size_t)(p.part_base + b) * ADMM_NSUM;
+#pragma unroll
+        for (int i = 0; i < ADMM_NSUM; ++i) v[i] += q[i];
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int i = 0; i < ADMM_NSUM; ++i) {
+        double s = wave_sum(v[i]);
+        if (lane == 0) sm[wave][i] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double s[ADMM_NSUM];
+        for (int i = 0; i < ADMM_NSUM; ++i) {
+            s[i] = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s[i] += sm[w][i];
+        }
+        const double mu1 = p.mu1, mu2 = p.mu2;
+        const double pri = sqrt(s[0] + s[1]);
+        const double den = fmax(fmax(sqrt(s[2] + s[3]), sqrt(s[4] + s[5])), 1e-30);
+        const double dual = sqrt(mu1 * mu1 * s[6] + mu2 * mu2 * s[7]);
+        const double dden = fmax(sqrt(mu1 * mu1 * s[8] + mu2 * mu2 * s[9]), 1e-30);
+        InfoDev f = info[prob];
+        f.iters = iter;
+        f.r_pri = pri / den;
+        f.r_dual = dual / dden;
+        f.objective = 0.5 * s[10] + (double)p.lam * s[11];
+        bool finite = true;
+        for (int i = 0; i < ADMM_NSUM; ++i) finite = finite && isfinite(s[i]);
+        if (!finite) {
+            f.diverged = 1;
+            f.active = 0;
+        } else if (tol > 0.0 && f.r_pri <= tol && f.r_dual <= tol) {
+            f.converged = 1;
+            f.active = 0;
+        }
+        if (final_iter) f.active = 0;
+        info[prob] = f;
+    }
+}
+
+// ------------------------------------------------------------ kernel spectrum
+// Lambda[k2][k1] = sum_a exp(-2 pi i k1 a / H) T[a][k2], T[a][k2] = sum_b h[a, b]
+// exp(-2 pi i k2 b / W) (eq. (19) for the centred kernel), T precomputed on the host.
+__global__ void k_lambda(const ProbDesc* __restrict__ pd, int prob, const float2* __restrict__ T, int ks,
+                         const float2* __restrict__ tw) {
+    const ProbDesc& p = pd[prob];
+    const int H = p.H, P = p.P;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)H * P) return;
+    const int k2 = (int)(i / H), k1 = (int)(i - (size_t)k2 * H);
+    const float2* twH = tw + p.fc.tw_off;
+    const int l = ks / 2;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int a = -l; a <= l; ++a) {
+        int e = (int)(((long long)k1 * (a < 0 ? a + H : a)) % H);
+        const float2 w = twH[e];
+        const float2 t = T[(size_t)(a + l) * P + k2];
+        acc.x = fmaf(w.x, t.x, fmaf(-w.y, t.y, acc.x));
+        acc.y = fmaf(w.x, t.y, fmaf(w.y, t.x, acc.y));
+    }
+    p.lamhat[i] = acc;
+}
+
+// ------------------------------------------------------------ warm-start mapping
+// u1 = A x0 (already in tmpB), d1 = m (y - A x0) / mu1, u_TV = D x0,
+// d_TV = -(lambda / mu2) p0 / max(1, |p0|).
+__global__ void k_warmstart(const ProbDesc* __restrict__ pd, int prob, const float* __restrict__ x0,
+                            const float* __restrict__ p0, const float* __restrict__ y, float* u1, float* d1,
+                            float* ureg, float* dreg) {
+    const ProbDesc& p = pd[prob];
+    const int H = p.H, W = p.W;
+    const size_t n = (size_t)H * W;
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int r = (int)(g / W), c = (int)(g - (size_t)r * W);
+    const float Ax = p.tmpB[g];
+    const float xc = x0[g];
+    u1[g] = Ax;
+    d1[g] = p.mask[g] ? (y[g] - Ax) / p.mu1 : 0.0f;
+    ureg[g] = x0[(size_t)r * W + (c + 1 == W ? 0 : c + 1)] - xc;
+    ureg[n + g] = x0[(size_t)(r + 1 == H ? 0 : r + 1) * W + c] - xc;
+    const float ph = p0[g], pv = p0[n + g];
+    const float nrm = fmaxf(1.0f, sqrtf(fmaf(ph, ph, pv * pv)));
+    const float sc = -(p.lam / p.mu2) / nrm;
+    dreg[g] = sc * ph;
+    dreg[n + g] = sc * pv;
+}
+
+// ------------------------------------------------------------ host launchers
+static size_t col_lds(int H, int TC) { return (size_t)H * TC * sizeof(float4); }
+static size_t rowtv_lds(int W, int B) { return (size_t)(B + 2) * W * sizeof(float2) + 2 * (size_t)W * sizeof(float); }
+static size_t row_lds(int W, int B) { return (size_t)B * W * sizeof(float2) + NT / 64 * ADMM_NSUM * sizeof(double); }
+
+hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
+    hipLaunchKernelGGL(k_col<MAXE_COL>, dim3(L.ncol), dim3(NT), L.lds_col, L.stream, L.desc, L.col_items, L.ncol,
+                       par, mode, mode == COL_SOLVE ? L.info : nullptr, L.tw, L.s2);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags) {
+    hipLaunchKernelGGL(k_row_tv<MAXE_ROW>, dim3(L.nrow), dim3(NT), L.lds_rowtv, L.stream, L.desc, L.row_items,
+                       L.nrow, par, flags, L.info, L.tw, L.partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
+    hipLaunchKernelGGL(k_row_fwd<MAXE_ROW>, dim3(L.nrow), dim3(NT), L.lds_row, L.stream, L.desc, L.row_items,
+                       L.nrow, par, src, gated ? L.info : nullptr, L.tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool gated) {
+    hipLaunchKernelGGL(k_row_inv<MAXE_ROW>, dim3(L.nrow), dim3(NT), L.lds_row, L.stream, L.desc, L.row_items,
+                       L.nrow, par, mode, flags, gated ? L.info : nullptr, L.tw, L.partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const LaunchCtx& L, int count, double tol, int iter, int final_iter) {
+    hipLaunchKernelGGL(k_reduce, dim3(count), dim3(NT), 0, L.stream, L.desc, L.partials, L.info, tol, iter,
+                       final_iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_import_tv(const LaunchCtx& L, int prob, size_t n) {
+    hipLaunchKernelGGL(k_import_tv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.stream, L.desc, prob);
+    return hipGetLastError();
+}
+
+hipError_t launch_lambda(const LaunchCtx& L, int prob, size_t HP, const float2* T, int ks) {
+    hipLaunchKernelGGL(k_lambda, dim3((unsigned)((HP + 255) / 256)), dim3(256), 0, L.stream, L.desc, prob, T, ks,
+                       L.tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_warmstart(const LaunchCtx& L, int prob, size_t n, const float* x0, const float* p0,
+                            const float* y, float* u1, float* d1, float* ureg, float* dreg) {
+    hipLaunchKernelGGL(k_warmstart, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.stream, L.desc, prob, x0, p0,
+                       y, u1, d1, ureg, dreg);
+    return hipGetLastError();
+}
+
+size_t lds_col_bytes(int H, int TC) { return col_lds(H, TC); }
+size_t lds_rowtv_bytes(int W, int B) { return rowtv_lds(W, B); }
+size_t lds_row_bytes(int W, int B) { return row_lds(W, B); }
+int col_max_elems() { return MAXE_COL * NT; }
+int row_max_elems() { return MAXE_ROW * NT; }
+int col_maxe() { return MAXE_COL; }
+int row_maxe() { return MAXE_ROW; }
+int block_threads() { return NT; }
+
+}  // namespace admm

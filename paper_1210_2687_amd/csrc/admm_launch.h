@@ -1,0 +1,45 @@
+// admm_launch.h — host-side launchers of the gfx950 kernels (internal interface).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "admm_internal.h"
+
+namespace admm {
+
+// Everything a launch needs; item lists are device arrays, counts are the grid sizes.
+struct LaunchCtx {
+    hipStream_t stream = nullptr;
+    const ProbDesc* desc = nullptr;
+    const WorkItem* col_items = nullptr;
+    int ncol = 0;
+    const WorkItem* row_items = nullptr;   // rows of TV problems (fused pass) or of FA problems
+    int nrow = 0;
+    const WorkItem* frm_items = nullptr;
+    int nfrm = 0;
+    InfoDev* info = nullptr;
+    double* partials = nullptr;
+    const float2* tw = nullptr;
+    const float* s2 = nullptr;
+    size_t lds_col = 0, lds_rowtv = 0, lds_row = 0, lds_frm = 0;
+};
+
+hipError_t launch_col(const LaunchCtx& L, int par, int mode);
+hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags);
+hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated);
+hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool gated);
+hipError_t launch_frame(const LaunchCtx& L, int par, int flags, int import_mode, bool gated);
+hipError_t launch_reduce(const LaunchCtx& L, int count, double tol, int iter, int final_iter);
+hipError_t launch_import_tv(const LaunchCtx& L, int prob, size_t n);
+hipError_t launch_import_fa(const LaunchCtx& L, int prob, size_t n);
+hipError_t launch_lambda(const LaunchCtx& L, int prob, size_t HP, const float2* T, int ks);
+hipError_t launch_warmstart(const LaunchCtx& L, int prob, size_t n, const float* x0, const float* p0,
+                            const float* y, float* u1, float* d1, float* ureg, float* dreg);
+
+size_t lds_col_bytes(int H, int TC);
+size_t lds_rowtv_bytes(int W, int B);
+size_t lds_row_bytes(int W, int B);
+size_t lds_frame_bytes(int FT, int J);
+int col_maxe();
+int row_maxe();
+int block_threads();
+
+}  // namespace admm

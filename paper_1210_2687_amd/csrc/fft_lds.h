@@ -1,0 +1,229 @@
+// fft_lds.h — radix-staged in-LDS FFT for gfx950 (device code only).
+//
+// The z-step of the splitting is a circulant solve diagonalised by the 2-D DFT
+// (eqs. (19), (25), (33)); this header provides the 1-D transforms from which
+// the row and column passes are built.
+//
+// Algorithm: Stockham auto-sort, mixed radix {2,3,4,5,7,8}. At a stage of
+// radix R with Ns = product of the radices already applied, butterfly j of a
+// length-N transform reads x[j + r N/R] (r < R), multiplies input r by the
+// twiddle w_N^{r (j mod Ns) N/(Ns R)}, takes an R-point DFT and writes output r
+// to position (j / Ns) Ns R + (j mod Ns) + r Ns. After the last stage the data
+// is in natural order. Several transforms of one block share the stages; all
+// live in one LDS buffer and each thread holds its butterflies' operands in
+// registers between the two barriers of a stage, so the transform is in place.
+//
+// Twiddles come from a per-length table tw[k] = exp(-2 pi i k / N) computed in
+// double precision on the host and rounded once; the inverse uses conj(tw).
+// Arithmetic uses explicit fmaf where a fused multiply-add is wanted and the
+// library is compiled with -ffp-contract=off, so every instantiation rounds
+// identically (a requirement for bit-exact checkpoint/resume).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace admm {
+
+// ----------------------------------------------------------- complex helpers
+// float2 = one complex value; float4 = a pair of complex values (x,y) and (z,w)
+// that are transformed together with the same twiddles.
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float4 cadd(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+__device__ __forceinline__ float4 csub(float4 a, float4 b) { return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
+    return make_float2(fmaf(a.x, w.x, -(a.y * w.y)), fmaf(a.x, w.y, a.y * w.x));
+}
+__device__ __forceinline__ float4 cmul(float4 a, float2 w) {
+    return make_float4(fmaf(a.x, w.x, -(a.y * w.y)), fmaf(a.x, w.y, a.y * w.x),
+                       fmaf(a.z, w.x, -(a.w * w.y)), fmaf(a.z, w.y, a.w * w.x));
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float4 cscale(float4 a, float s) { return make_float4(a.x * s, a.y * s, a.z * s, a.w * s); }
+
+// multiply by -i (forward direction) or +i (inverse direction)
+template <bool INV> __device__ __forceinline__ float2 cmuli(float2 a) {
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+template <bool INV> __device__ __forceinline__ float4 cmuli(float4 a) {
+    return INV ? make_float4(-a.y, a.x, -a.w, a.z) : make_float4(a.y, -a.x, a.w, -a.z);
+}
+
+// a + s * b for a real scalar s (fused)
+__device__ __forceinline__ float2 caxpy(float s, float2 b, float2 a) { return make_float2(fmaf(s, b.x, a.x), fmaf(s, b.y, a.y)); }
+__device__ __forceinline__ float4 caxpy(float s, float4 b, float4 a) {
+    return make_float4(fmaf(s, b.x, a.x), fmaf(s, b.y, a.y), fmaf(s, b.z, a.z), fmaf(s, b.w, a.w));
+}
+
+// ----------------------------------------------------------- small DFTs
+// X_k = sum_m v_m exp(s 2 pi i k m / R), s = -1 forward, +1 inverse.
+
+template <bool INV, typename E> __device__ __forceinline__ void dft2(E* v) {
+    E a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <bool INV, typename E> __device__ __forceinline__ void dft4(E* v) {
+    E t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    E t2 = cadd(v[1], v[3]), t3 = cmuli<INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+}
+
+template <bool INV, typename E> __device__ __forceinline__ void dft8(E* v) {
+    constexpr float H = 0.70710678118654752f;   // sqrt(1/2)
+    E e[4] = {v[0], v[2], v[4], v[6]};
+    E o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<INV>(e);
+    dft4<INV>(o);
+    // o_k *= w8^k, w8 = exp(s 2 pi i / 8)
+    o[1] = cmul(o[1], make_float2(H, INV ? H : -H));
+    o[2] = cmuli<INV>(o[2]);
+    o[3] = cmul(o[3], make_float2(-H, INV ? H : -H));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        E a = e[k], b = o[k];
+        v[k] = cadd(a, b);
+        v[k + 4] = csub(a, b);
+    }
+}
+
+// Odd radix R = 2h+1: X_k = v0 + sum_m (v_m + v_{R-m}) cos(2 pi k m / R)
+//                         + s i sum_m (v_m - v_{R-m}) sin(2 pi k m / R),
+// and X_{R-k} is the same with the sine part negated.
+template <int R> struct OddTab;
+template <> struct OddTab<3> {
+    static __device__ __forceinline__ float c(int j) { return -0.5f; }
+    static __device__ __forceinline__ float s(int j) { return 0.86602540378443865f; }
+};
+template <> struct OddTab<5> {
+    static __device__ __forceinline__ float c(int j) { return j == 1 ? 0.30901699437494742f : -0.80901699437494742f; }
+    static __device__ __forceinline__ float s(int j) { return j == 1 ? 0.95105651629515357f : 0.58778525229247313f; }
+};
+template <> struct OddTab<7> {
+    static __device__ __forceinline__ float c(int j) {
+        return j == 1 ? 0.62348980185873353f : (j == 2 ? -0.22252093395631440f : -0.90096886790241913f);
+    }
+    static __device__ __forceinline__ float s(int j) {
+        return j == 1 ? 0.78183148246802981f : (j == 2 ? 0.97492791218182361f : 0.43388373911755812f);
+    }
+};
+
+// cos / sin of 2 pi j / R for any integer j (reduced with the symmetries)
+template <int R> __device__ __forceinline__ float oddcos(int j) {
+    j %= R;
+    if (j > R / 2) j = R - j;
+    return OddTab<R>::c(j);
+}
+template <int R> __device__ __forceinline__ float oddsin(int j) {
+    j %= R;
+    return j > R / 2 ? -OddTab<R>::s(R - j) : OddTab<R>::s(j);
+}
+
+template <int R, bool INV, typename E> __device__ __forceinline__ void dft_odd(E* v) {
+    constexpr int h = R / 2;
+    E A[h], B[h];
+#pragma unroll
+    for (int m = 1; m <= h; ++m) {
+        A[m - 1] = cadd(v[m], v[R - m]);
+        B[m - 1] = csub(v[m], v[R - m]);
+    }
+    E x0 = v[0];
+    E sum = v[0];
+#pragma unroll
+    for (int m = 0; m < h; ++m) sum = cadd(sum, A[m]);
+#pragma unroll
+    for (int k = 1; k <= h; ++k) {
+        E P = x0, Q;
+#pragma unroll
+        for (int m = 1; m <= h; ++m) P = caxpy(oddcos<R>(k * m), A[m - 1], P);
+        Q = cscale(B[0], oddsin<R>(k));
+#pragma unroll
+        for (int m = 2; m <= h; ++m) Q = caxpy(oddsin<R>(k * m), B[m - 1], Q);
+        // s i Q with s = -1 (forward) -> -i Q ; s = +1 (inverse) -> +i Q
+        E iQ = cmuli<INV>(Q);
+        v[k] = cadd(P, iQ);
+        v[R - k] = csub(P, iQ);
+    }
+    v[0] = sum;
+}
+
+template <int R, bool INV, typename E> __device__ __forceinline__ void dft(E* v) {
+    if constexpr (R == 2) dft2<INV>(v);
+    else if constexpr (R == 4) dft4<INV>(v);
+    else if constexpr (R == 8) dft8<INV>(v);
+    else dft_odd<R, INV>(v);
+}
+
+// ----------------------------------------------------------- Stockham stage
+// buf holds `ntrans` transforms of length N at stride `tstride` (elements).
+// Requirement (checked on the host): ntrans * N / R <= (MAXE / R) * nthr.
+template <int R, int MAXE, bool INV, typename E>
+__device__ __forceinline__ void stockham_stage(E* buf, int N, int ntrans, int tstride, int Ns,
+                                               const float2* __restrict__ tw, int tid, int nthr) {
+    constexpr int NB = MAXE / R;
+    const int nbf = N / R;
+    const int total = ntrans * nbf;
+    const int twmul = N / (Ns * R);
+    E v[NB][R];
+    int dst[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int q = tid + i * nthr;
+        dst[i] = -1;
+        if (q < total) {
+            const int t = q / nbf;
+            const int j = q - t * nbf;
+            const int jq = j / Ns;
+            const int k = j - jq * Ns;
+            const E* b = buf + t * tstride;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = b[j + r * nbf];
+            const int tws = twmul * k;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[tws * r];
+                if (INV) w.y = -w.y;
+                v[i][r] = cmul(v[i][r], w);
+            }
+            dft<R, INV>(v[i]);
+            dst[i] = t * tstride + jq * Ns * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        if (dst[i] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[dst[i] + r * Ns] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full transform of `ntrans` length-N sequences in LDS (natural order in and out).
+// rad[0..nst) is the radix schedule (product N). Unnormalised in both directions.
+template <int MAXE, bool INV, typename E>
+__device__ __forceinline__ void fft_lds(E* buf, int N, int ntrans, int tstride, const int* rad, int nst,
+                                        const float2* __restrict__ tw, int tid, int nthr) {
+    int Ns = 1;
+    for (int s = 0; s < nst; ++s) {
+        const int R = rad[s];
+        switch (R) {
+            case 8: stockham_stage<8, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
+            case 4: stockham_stage<4, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
+            case 2: stockham_stage<2, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
+            case 3: stockham_stage<3, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
+            case 5: stockham_stage<5, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
+            case 7: stockham_stage<7, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
+            default: break;
+        }
+        Ns *= R;
+    }
+}
+
+}  // namespace admm

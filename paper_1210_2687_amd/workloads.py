@@ -16,7 +16,8 @@ Recipe (all draws from ``numpy.random.Generator(PCG64(seed))``):
   axis-aligned rectangle (sides U[0.05,0.4] min(H,W)) or a rotated ellipse
   (semi-axes U[0.03,0.25] min(H,W)), intensity U[0,1], painted in order;
   optional Gaussian random field (white noise smoothed by a Gaussian of std
-  ``grf_scale`` px, periodic, unit std, times 0.2) added, then clipped to [0,1];
+  ``grf_scale`` px, periodic, zero mean, unit std, times 0.2) added, then
+  clipped to [0,1];
 * kernels: uniform 1/k^2; Gaussian exp(-(a^2+b^2)/(2 s^2)); linear motion (a
   centred segment of length L at angle theta, 64 samples splatted bilinearly);
   disk (pixel coverage of a radius-r disk by 16x16 supersampling); all
@@ -88,7 +89,7 @@ def synth_image(g, H, W, grf_scale=None):
         x[sel] = val
     if grf_scale:
         f = ndimage.gaussian_filter(g.standard_normal((H, W)), grf_scale, mode="wrap")
-        f /= max(f.std(), 1e-12)
+        f = (f - f.mean()) / max(f.std(), 1e-12)
         x = np.clip(x + 0.2 * f, 0.0, 1.0)
     return x
 

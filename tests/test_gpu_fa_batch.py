@@ -1,0 +1,135 @@
+"""GPU parity of FA-MD and of ragged batches against the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1210_2687_amd import admm as A
+from paper_1210_2687_amd import workloads as WL
+from gpu_util import dev, host, rel, gpu_solve, announce, fast_tv_problem
+
+pytestmark = pytest.mark.gpu
+
+ITER_TOL = 1e-4
+
+
+def _fa(p, K, ks=()):
+    return O.fa_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, p.levels, iters=K, record=ks)
+
+
+@pytest.mark.parametrize("size,levels", [(64, 3), (96, 2), (80, 4), (48, 1)])
+def test_fa_parity(size, levels):
+    announce(f"fa parity {size} J={levels}")
+    p = WL.config3(size=size, levels=levels)
+    ks = [1, 2, 10, 60]
+    ref = _fa(p, max(ks), ks)
+    with A.Plan([p]) as plan:
+        for k in ks:
+            z, info = gpu_solve(plan, p, k)
+            if k == 1:
+                assert np.all(z == 0.0)
+                continue
+            e = rel(z, ref["zs"][k])
+            announce(f"  k={k} rel err {e:.3e}")
+            assert e <= ITER_TOL, (k, e)
+    F = lambda x: O.fa_objective(x, p.y, p.mask, p.kernel, p.lam, p.levels)
+    assert abs(F(z) - F(ref["z"])) <= 1e-4 * F(ref["z"])        # not converged: diagnostic bar
+    assert abs(info["objective"] - F(z)) <= 1e-4 * F(z)
+
+
+def test_fa_non_square_and_state():
+    announce("fa non-square with state")
+    g = WL.rng(21)
+    H, W = 72, 120
+    x = WL.synth_image(g, H, W)
+    h = WL.kernel_disk(3.0)
+    m = WL.valid_mask(H, W, h.shape[0] // 2)
+    p = WL.Problem(y=WL.observe(g, x, h, m, 1e-3), mask=m, kernel=h, lam=5e-4, mu1=0.02, mu2=0.01,
+                   reg="frame", levels=3)
+    st = A.alloc_state(H, W, nreg=10)
+    with A.Plan([p]) as plan:
+        z, _ = gpu_solve(plan, p, 30, state=st)
+    ref = _fa(p, 30)
+    assert rel(z, ref["z"]) <= ITER_TOL
+    assert rel(host(st["u1"]), ref["state"].u1) <= ITER_TOL
+    assert rel(host(st["dreg"]), ref["state"].d2) <= 1e-3
+
+
+def test_fa_resume_is_bitwise():
+    import torch
+    announce("fa resume bitwise")
+    p = WL.config3(size=64)
+    with A.Plan([p]) as plan:
+        s1 = A.alloc_state(64, 64, nreg=10)
+        x40, _ = gpu_solve(plan, p, 40, state=s1)
+        s2 = A.alloc_state(64, 64, nreg=10)
+        gpu_solve(plan, p, 20, state=s2)
+        x20b, _ = gpu_solve(plan, p, 20, state=s2)
+    assert np.array_equal(x40, x20b)
+    for key in ("u1", "d1", "ureg", "dreg"):
+        assert torch.equal(s1[key], s2[key]), key
+
+
+def _ragged(n, lo=40, hi=140):
+    probs = [WL.config4(i, side_lo=lo, side_hi=hi) for i in range(n)]
+    return probs
+
+
+def test_ragged_batch_matches_oracle_per_problem():
+    import torch
+    announce("ragged batch")
+    probs = _ragged(5)
+    f = WL.config3(size=48, levels=2)
+    probs.append(f)
+    K = 40
+    with A.Plan(probs) as plan:
+        ys = [dev(p.y) for p in probs]
+        xs = [torch.zeros_like(y) for y in ys]
+        infos = plan.batch(ys, xs, max_iters=K)
+    for p, x, info in zip(probs, xs, infos):
+        assert info["iters"] == K
+        if p.reg == "frame":
+            ref = _fa(p, K)["z"]
+        else:
+            ref = O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=K)["z"]
+        e = rel(host(x), ref)
+        announce(f"  {p.shape} k={p.kernel.shape[0]} rel err {e:.3e}")
+        assert e <= ITER_TOL
+
+
+def test_batch_equals_individual_solves():
+    import torch
+    announce("batch vs single")
+    probs = _ragged(3)
+    K = 25
+    with A.Plan(probs) as plan:
+        ys = [dev(p.y) for p in probs]
+        xs = [torch.zeros_like(y) for y in ys]
+        plan.batch(ys, xs, max_iters=K)
+    for p, x in zip(probs, xs):
+        with A.Plan([p]) as single:
+            z, _ = gpu_solve(single, p, K)
+        # same kernels, same plan choices per problem size -> identical up to tiling choices
+        assert rel(host(x), z) <= 1e-5
+
+
+def test_tolerance_batch_stops_each_problem_independently():
+    import torch
+    announce("batch tolerance")
+    probs = [fast_tv_problem(s, H, W, k) for s, (H, W), k in
+             [(31, (64, 64), 7), (32, (72, 96), 9), (33, (48, 60), 5), (34, (80, 56), 7)]]
+    tol, c = 1e-4, 10
+    with A.Plan(probs) as plan:
+        ys = [dev(p.y) for p in probs]
+        xs = [torch.zeros_like(y) for y in ys]
+        infos = plan.batch(ys, xs, max_iters=4000, tol=tol, check_every=c)
+    iters = set()
+    for p, x, info in zip(probs, xs, infos):
+        ref = O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=4000, tol=tol, check_every=c)
+        announce(f"  {p.shape}: gpu {info['iters']} oracle {ref['iters']}")
+        assert info["converged"] == 1 and ref["converged"]
+        assert abs(info["iters"] - ref["iters"]) <= c
+        iters.add(info["iters"])
+        F = lambda z: O.tv_objective(z, p.y, p.mask, p.kernel, p.lam)
+        assert abs(F(host(x)) - F(ref["z"])) <= 2e-5 * F(ref["z"])
+    assert len(iters) > 1      # problems stopped at their own iterations
