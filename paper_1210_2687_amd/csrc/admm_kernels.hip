@@ -23,9 +23,9 @@
 
 namespace admm {
 
-constexpr int NT = 256;            // threads per block of the FFT passes
-constexpr int MAXE_COL = 16;       // float4 elements per thread in the column pass
-constexpr int MAXE_ROW = 32;       // float2 elements per thread in the row passes
+constexpr int NT = 512;            // threads per block of the FFT passes
+constexpr int MAXE_COL = 8;        // float4 elements per thread in the column pass
+constexpr int MAXE_ROW = 16;       // float2 elements per thread in the row passes
 constexpr int MAXC = ADMM_MAX_SIDE / NT;   // columns per thread in the epilogue
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -487,7 +487,11 @@ __global__ void k_warmstart(const ProbDesc* __restrict__ pd, int prob, const flo
 
 // ------------------------------------------------------------ host launchers
 static size_t col_lds(int H, int TC) { return (size_t)H * TC * sizeof(float4); }
-static size_t rowtv_lds(int W, int B) { return (size_t)(B + 2) * W * sizeof(float2) + 2 * (size_t)W * sizeof(float); }
+static size_t rowtv_lds(int W, int B) {
+    const size_t b = (size_t)(B + 2) * W * sizeof(float2) + 2 * (size_t)W * sizeof(float);
+    const size_t scratch = NT / 64 * ADMM_NSUM * sizeof(double);   // block partial sums reuse the buffer
+    return b > scratch ? b : scratch;
+}
 static size_t row_lds(int W, int B) { return (size_t)B * W * sizeof(float2) + NT / 64 * ADMM_NSUM * sizeof(double); }
 
 hipError_t launch_col(const LaunchCtx& L, int par, int mode) {

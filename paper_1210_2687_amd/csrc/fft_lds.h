@@ -23,6 +23,28 @@
 
 namespace admm {
 
+// Pointers into LDS (address space 3) and global memory (address space 1). The
+// radix stages are separate functions (keeping the register allocation of each
+// radix independent), so the LDS address space is spelled out to keep ds_*
+// instructions instead of flat ones.
+#define ADMM_LDS __attribute__((address_space(3)))
+#define ADMM_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ ADMM_GLOBAL T* gptr(T* p) { return (ADMM_GLOBAL T*)p; }
+template <typename T> __device__ __forceinline__ const ADMM_GLOBAL T* gptr(const T* p) { return (const ADMM_GLOBAL T*)p; }
+
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float2 lds_ld(const ADMM_LDS float2* p) {
+    const vf2 v = *(const ADMM_LDS vf2*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float4 lds_ld(const ADMM_LDS float4* p) {
+    const vf4 v = *(const ADMM_LDS vf4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void lds_st(ADMM_LDS float2* p, float2 a) { *(ADMM_LDS vf2*)p = vf2{a.x, a.y}; }
+__device__ __forceinline__ void lds_st(ADMM_LDS float4* p, float4 a) { *(ADMM_LDS vf4*)p = vf4{a.x, a.y, a.z, a.w}; }
+
 // ----------------------------------------------------------- complex helpers
 // float2 = one complex value; float4 = a pair of complex values (x,y) and (z,w)
 // that are transformed together with the same twiddles.
@@ -163,7 +185,7 @@ template <int R, bool INV, typename E> __device__ __forceinline__ void dft(E* v)
 // buf holds `ntrans` transforms of length N at stride `tstride` (elements).
 // Requirement (checked on the host): ntrans * N / R <= (MAXE / R) * nthr.
 template <int R, int MAXE, bool INV, typename E>
-__device__ __forceinline__ void stockham_stage(E* buf, int N, int ntrans, int tstride, int Ns,
+__device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, int N, int ntrans, int tstride, int Ns,
                                                const float2* __restrict__ tw, int tid, int nthr) {
     constexpr int NB = MAXE / R;
     const int nbf = N / R;
@@ -180,9 +202,9 @@ __device__ __forceinline__ void stockham_stage(E* buf, int N, int ntrans, int ts
             const int j = q - t * nbf;
             const int jq = j / Ns;
             const int k = j - jq * Ns;
-            const E* b = buf + t * tstride;
+            const ADMM_LDS E* b = buf + t * tstride;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = b[j + r * nbf];
+            for (int r = 0; r < R; ++r) v[i][r] = lds_ld(b + j + r * nbf);
             const int tws = twmul * k;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
@@ -199,7 +221,7 @@ __device__ __forceinline__ void stockham_stage(E* buf, int N, int ntrans, int ts
     for (int i = 0; i < NB; ++i) {
         if (dst[i] >= 0) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[dst[i] + r * Ns] = v[i][r];
+            for (int r = 0; r < R; ++r) lds_st(buf + dst[i] + r * Ns, v[i][r]);
         }
     }
     __syncthreads();
@@ -208,8 +230,9 @@ __device__ __forceinline__ void stockham_stage(E* buf, int N, int ntrans, int ts
 // Full transform of `ntrans` length-N sequences in LDS (natural order in and out).
 // rad[0..nst) is the radix schedule (product N). Unnormalised in both directions.
 template <int MAXE, bool INV, typename E>
-__device__ __forceinline__ void fft_lds(E* buf, int N, int ntrans, int tstride, const int* rad, int nst,
+__device__ __forceinline__ void fft_lds(E* gbuf, int N, int ntrans, int tstride, const int* rad, int nst,
                                         const float2* __restrict__ tw, int tid, int nthr) {
+    ADMM_LDS E* buf = (ADMM_LDS E*)gbuf;
     int Ns = 1;
     for (int s = 0; s < nst; ++s) {
         const int R = rad[s];
