@@ -93,8 +93,22 @@ def lib():
         L.admm_validate_problem.argtypes = [POINTER(admm_problem)]
         L.admm_plan_kernel_times.argtypes = [c_void_p, POINTER(admm_kernel_time), c_int32]
         L.admm_plan_kernel_times.restype = c_int32
+        vp = c_void_p
+        L.admm_conv3x3_pack_weights.argtypes = [vp, c_int32, c_int32, vp, vp, vp]
+        L.admm_conv3x3_bf16_fwd.argtypes = [vp, c_int32, c_int32, c_int32, c_int32, vp, vp, c_int32, c_int32,
+                                            vp, vp, vp]
+        L.admm_conv3x3_bf16_wgrad_workspace.argtypes = [c_int32] * 6
+        L.admm_conv3x3_bf16_wgrad_workspace.restype = ctypes.c_size_t
+        L.admm_conv3x3_bf16_wgrad.argtypes = [vp, vp, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, vp,
+                                              ctypes.c_size_t, vp, vp, vp]
+        L.admm_adam_step.argtypes = [vp, vp, vp, vp, c_int32, c_float, c_float, c_float, c_float, c_int32, vp]
+        L.admm_ws_input.argtypes = [vp, vp, vp, c_int32, c_int32, c_int32, vp, vp]
+        L.admm_ws_loss.argtypes = [vp, vp, vp, vp, vp, c_int32, c_int32, c_int32, c_float, vp, vp, vp]
+        L.admm_ws_output.argtypes = [vp, vp, vp, c_int32, c_int32, c_int32, vp, vp, vp]
         for f in ("admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
-                  "admm_warmstart_map", "admm_fft_radices", "admm_validate_problem"):
+                  "admm_warmstart_map", "admm_fft_radices", "admm_validate_problem",
+                  "admm_conv3x3_pack_weights", "admm_conv3x3_bf16_fwd", "admm_conv3x3_bf16_wgrad",
+                  "admm_adam_step", "admm_ws_input", "admm_ws_loss", "admm_ws_output"):
             getattr(L, f).restype = c_int32
         _LIB = L
     return _LIB
@@ -104,7 +118,9 @@ def exported_symbols():
     """Names of the C entry points declared in include/admm_deconv.h."""
     return ["admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
             "admm_warmstart_map", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
-            "admm_validate_problem", "admm_plan_kernel_times"]
+            "admm_validate_problem", "admm_plan_kernel_times",
+            "admm_conv3x3_pack_weights", "admm_conv3x3_bf16_fwd", "admm_conv3x3_bf16_wgrad_workspace",
+            "admm_conv3x3_bf16_wgrad", "admm_adam_step", "admm_ws_input", "admm_ws_loss", "admm_ws_output"]
 
 
 def admm_last_error():
@@ -221,6 +237,53 @@ def admm_plan_kernel_times(plan):
     buf = (admm_kernel_time * 8)()
     k = lib().admm_plan_kernel_times(plan, buf, 8)
     return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(min(k, 8))}
+
+
+# ---------------------------------------------------------------- learned warm start
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def admm_conv3x3_pack_weights(w, cin, cout, wfwd, wbwd=None):
+    _check(lib().admm_conv3x3_pack_weights(_ptr(w), cin, cout, _ptr(wfwd), _ptr(wbwd), _stream()))
+
+
+def admm_conv3x3_bf16_fwd(x, N, H, W, cin, wpacked, bias, cout, relu, gate, y):
+    _check(lib().admm_conv3x3_bf16_fwd(_ptr(x), N, H, W, cin, _ptr(wpacked), _ptr(bias), cout, int(relu),
+                                       _ptr(gate), _ptr(y), _stream()))
+
+
+def admm_conv3x3_bf16_wgrad_workspace(N, H, W, cin, cout, chunk):
+    return lib().admm_conv3x3_bf16_wgrad_workspace(N, H, W, cin, cout, chunk)
+
+
+def admm_conv3x3_bf16_wgrad(x, dy, N, H, W, cin, cout, chunk, workspace, dw, db):
+    _check(lib().admm_conv3x3_bf16_wgrad(_ptr(x), _ptr(dy), N, H, W, cin, cout, chunk, _ptr(workspace),
+                                         workspace.numel() * workspace.element_size(), _ptr(dw), _ptr(db),
+                                         _stream()))
+
+
+def admm_adam_step(p, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().admm_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), lr, beta1, beta2, eps, int(t),
+                                _stream()))
+
+
+def admm_ws_input(y, mask, emb, N, H, W, x0):
+    _check(lib().admm_ws_input(_ptr(y), _ptr(mask), _ptr(emb), N, H, W, _ptr(x0), _stream()))
+
+
+def admm_ws_loss(out, y, mask, xt, pt, N, H, W, alpha, dout, lpart):
+    _check(lib().admm_ws_loss(_ptr(out), _ptr(y), _ptr(mask), _ptr(xt), _ptr(pt), N, H, W, alpha, _ptr(dout),
+                              _ptr(lpart), _stream()))
+
+
+def admm_ws_output(out, y, mask, N, H, W, x0, p0):
+    _check(lib().admm_ws_output(_ptr(out), _ptr(y), _ptr(mask), N, H, W, _ptr(x0), _ptr(p0), _stream()))
 
 
 def admm_deconv_blur(plan, index, x, Ax):

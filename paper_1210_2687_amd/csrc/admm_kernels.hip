@@ -11,7 +11,7 @@
 //             inverse row DFT of (z^ + i A z^) -> z, A z; mask prox and data
 //             dual (eq. (49)); vector soft threshold and TV duals (Sec. III-C);
 //             zeta1 = u1 + d1 and s = mu2 D^T (u_TV + d_TV) for the next
-//             iteration; forward row DFT of (zeta1 + i s) -> next half spectra.
+//             iteration; forward row DFT of (mu1 zeta1 + i s) -> next half spectra.
 //             Residual partial sums on check iterations.
 //
 // FA-MD (Sec. IV-C) uses k_col with K = 1 / (mu1 |Lambda|^2 + mu2) (eq. (25)),
@@ -89,9 +89,12 @@ __global__ __launch_bounds__(NT) void k_col(const ProbDesc* __restrict__ pd, con
             const float w = tv ? (s2H[k1] + s2W[c0 + col]) : 1.0f;
             const float l2 = fmaf(lam.x, lam.x, lam.y * lam.y);
             const float K = ihw / fmaf(mu1, l2, mu2 * w);
-            // r = mu1 conj(Lambda) zeta1^ + s^
-            const float rx = fmaf(mu1, fmaf(lam.x, f.x, lam.y * f.y), f.z);
-            const float ry = fmaf(mu1, fmaf(lam.x, f.y, -(lam.y * f.x)), f.w);
+            // r = conj(Lambda) (mu1 zeta1)^ + s^ ; the row pass transforms mu1 zeta1
+            // (not zeta1) so that both halves of the packed complex transform have
+            // comparable magnitude: the rounding of the larger half leaks into the
+            // other one when they are separated, and s is O(mu) while zeta1 is O(1)
+            const float rx = fmaf(lam.x, f.x, lam.y * f.y) + f.z;
+            const float ry = fmaf(lam.x, f.y, -(lam.y * f.x)) + f.w;
             const float zx = K * rx, zy = K * ry;
             o = make_float4(zx, zy, fmaf(lam.x, zx, -(lam.y * zy)), fmaf(lam.x, zy, lam.y * zx));
         } else {  // COL_BLUR: (x^, 0) -> (Lambda x^ / (H W), 0)
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                 const int c = tid + j * NT;
                 if (c < W) {
                     const float s = mu2 * ((dlr[c == 0 ? W - 1 : c - 1] - dlr[c]) + (dvp[j] - dvc[j]));
-                    Xw[c] = make_float2(zet[j], s);
+                    Xw[c] = make_float2(p.mu1 * zet[j], s);
                 }
             }
         }
@@ -283,11 +286,16 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
     const int H = p.H, W = p.W, P = p.P, r0 = it.start;
     const int nr = min(p.B, H - r0);
     const int tid = threadIdx.x;
-    // src 0: (tmpA, tmpB); src 1: (x, 0) read from tmpA only
+    // src 0: (mu1 * zeta1, s) from (tmpA, tmpB); src 1: (x, 0) from tmpA (blur)
     const float* a = p.tmpA + (size_t)r0 * W;
     const float* b = p.tmpB + (size_t)r0 * W;
     const int tot = nr * W;
-    for (int i = tid; i < tot; i += NT) X[i] = make_float2(a[i], src == 0 ? b[i] : 0.0f);
+    const float mu1 = p.mu1;
+    if (src == 0) {
+        for (int i = tid; i < tot; i += NT) X[i] = make_float2(mu1 * a[i], b[i]);
+    } else {
+        for (int i = tid; i < tot; i += NT) X[i] = make_float2(a[i], 0.0f);
+    }
     __syncthreads();
     fft_lds<MAXE, false>(X, W, nr, W, p.fr.rad, p.fr.nst, tw + p.fr.tw_off, tid, NT);
     store_rows_split(X, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);

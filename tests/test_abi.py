@@ -22,8 +22,10 @@ def _declared(header):
 
 def test_library_exports_every_declared_symbol():
     L = A.lib()
-    names = _declared("admm_deconv.h")
-    assert len(names) >= 9
+    headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert headers == ["admm_deconv.h", "admm_warmstart.h"]
+    names = sorted(set(n for h in headers for n in _declared(h)))
+    assert len(names) >= 18
     for name in names:
         assert hasattr(L, name), name
     assert sorted(A.exported_symbols()) == names
