@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -98,6 +99,22 @@ bool fits(int ntrans, const FftPlanDev& f, int maxe) {
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+void fill_plan(FftPlanDev& f, int N, int tw_off) {
+    f.N = N;
+    f.tw_off = tw_off;
+    f.nst = radices(N, f.rad, ADMM_MAX_STAGES);
+    int Ns = 1;
+    for (int s = 0; s < f.nst; ++s) {
+        const int R = f.rad[s];
+        f.ns[s] = Ns;
+        f.nbf[s] = N / R;
+        f.twm[s] = N / (Ns * R);
+        f.mnbf[s] = div_magic((unsigned)f.nbf[s]);
+        f.mns[s] = div_magic((unsigned)Ns);
+        Ns *= R;
+    }
+}
 
 }  // namespace
 
@@ -235,6 +252,10 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
             }
 
     const int target_blocks = 1024;
+    int tv_maxw = 0;
+    for (int i = 0; i < count; ++i)
+        if (probs[i].reg == ADMM_REG_TV) tv_maxw = std::max(tv_maxw, (int)probs[i].W);
+    const int tv_rows_cap = row_tv_max_rows(tv_maxw);
     for (int i = 0; i < count; ++i) {
         const admm_problem& q = probs[i];
         ProbDesc& d = P->hd[i];
@@ -253,12 +274,8 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         d.tau = (float)(q.lambda / mu2);
         d.inv_hw = (float)(1.0 / ((double)q.H * q.W));
         d.inv1pmu1 = (float)(1.0 / (1.0 + mu1));
-        d.fr.N = q.W;
-        d.fr.nst = radices(q.W, d.fr.rad, ADMM_MAX_STAGES);
-        d.fr.tw_off = tab_off[q.W];
-        d.fc.N = q.H;
-        d.fc.nst = radices(q.H, d.fc.rad, ADMM_MAX_STAGES);
-        d.fc.tw_off = tab_off[q.H];
+        fill_plan(d.fr, q.W, tab_off[q.W]);
+        fill_plan(d.fc, q.H, tab_off[q.H]);
         const int per = std::max(1, (target_blocks + count - 1) / count);
         // column tile width
         int tcmax = 1;
@@ -266,16 +283,20 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         if (!fits(1, d.fc, col_maxe()) || lds_col_bytes(q.H, 1) > cap)
             return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: column length %d does not fit a block", i, q.H));
         d.TC = std::max(1, std::min(tcmax, (d.P + per - 1) / per));
+        if (const char* e = std::getenv("ADMM_TC")) d.TC = std::max(1, std::min(tcmax, std::atoi(e)));
         // rows per block
         int bmax = 0;
         if (q.reg == ADMM_REG_TV) {
-            while (bmax + 1 <= q.H && fits(bmax + 3, d.fr, row_maxe()) && lds_rowtv_bytes(q.W, bmax + 1) <= cap) ++bmax;
+            while (bmax + 1 <= std::min(q.H, tv_rows_cap) && fits(bmax + 3, d.fr, row_maxe()) &&
+                   lds_rowtv_bytes(q.W, bmax + 1) <= cap)
+                ++bmax;
         } else {
             while (bmax + 1 <= q.H && fits(bmax + 1, d.fr, row_maxe()) && lds_row_bytes(q.W, bmax + 1) <= cap) ++bmax;
         }
         if (bmax < 1) return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: row length %d does not fit a block", i, q.W));
         const int bmin = q.reg == ADMM_REG_TV ? std::min(bmax, 4) : 1;
         d.B = std::max(bmin, std::min(bmax, (q.H + per - 1) / per));
+        if (const char* e = std::getenv("ADMM_ROWS")) d.B = std::max(1, std::min(bmax, std::atoi(e)));
         d.nrowblk = (q.H + d.B - 1) / d.B;
         d.ncolblk = (d.P + d.TC - 1) / d.TC;
         if (q.reg == ADMM_REG_FRAME) {
@@ -445,6 +466,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     base_ctx.lds_rowtv = P->lds_rowtv;
     base_ctx.lds_row = P->lds_row;
     base_ctx.lds_frm = P->lds_frm;
+    base_ctx.tv_maxw = tv_maxw;
     base_ctx.col_items = P->d_items;
     base_ctx.ncol = P->ncol;
     P->all = base_ctx;

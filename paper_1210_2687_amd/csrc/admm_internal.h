@@ -34,12 +34,26 @@ enum {
 // Column-kernel modes.
 enum { COL_SOLVE = 0, COL_BLUR = 1 };
 
+// Radix schedule of one transform length with the per-stage constants the
+// Stockham stages need: for stage s of radix R after Ns = prod of earlier
+// radices, nbf = N / R butterflies per transform, twm = N / (Ns R) twiddle
+// stride, and exact reciprocal multipliers for dividing by nbf and Ns
+// (x / d == umulhi(x, ceil(2^32 / d)) for x, d < 2^16; d == 1 is handled apart).
 struct FftPlanDev {
     int N;
     int nst;
     int tw_off;                 // offset of this length's tables in the shared table arrays
     int rad[ADMM_MAX_STAGES];
+    int ns[ADMM_MAX_STAGES];
+    int nbf[ADMM_MAX_STAGES];
+    int twm[ADMM_MAX_STAGES];
+    unsigned mnbf[ADMM_MAX_STAGES];
+    unsigned mns[ADMM_MAX_STAGES];
 };
+
+// exact division for operands below 2^16 by a divisor with multiplier m = ceil(2^32 / d)
+__host__ __device__ inline unsigned div_magic(unsigned d) { return d <= 1 ? 0u : (unsigned)((0x100000000ull + d - 1) / d); }
+__device__ __forceinline__ unsigned udiv16(unsigned x, unsigned d, unsigned m) { return d == 1 ? x : __umulhi(x, m); }
 
 // Residual sums (index into the per-block partial vector):
 //  0 |A z - u1|^2   1 |G_reg z - u_reg|^2   2 |A z|^2   3 |G_reg z|^2

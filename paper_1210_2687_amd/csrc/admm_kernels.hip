@@ -26,7 +26,6 @@ namespace admm {
 constexpr int NT = 512;            // threads per block of the FFT passes
 constexpr int MAXE_COL = 8;        // float4 elements per thread in the column pass
 constexpr int MAXE_ROW = 16;       // float2 elements per thread in the row passes
-constexpr int MAXC = ADMM_MAX_SIDE / NT;   // columns per thread in the epilogue
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -70,19 +69,33 @@ __global__ __launch_bounds__(NT) void k_col(const ProbDesc* __restrict__ pd, con
     const int tid = threadIdx.x;
     float4* S = ((p.reg == REG_TV && par) ? p.spec1 : p.spec0) + (size_t)c0 * H;
     const int tot = nc * H;
+    // Lambda is loaded together with the spectrum so that its latency is not
+    // exposed after the forward transform (a block holds at most MAXE entries per thread)
+    const float2* L = p.lamhat + (size_t)c0 * H;
+    float2 lamr[MAXE];
+#pragma unroll
+    for (int k = 0; k < MAXE; ++k) {
+        const int i = tid + k * NT;
+        lamr[k] = i < tot ? L[i] : make_float2(0.f, 0.f);
+    }
+    float2* twl = reinterpret_cast<float2*>(cl + (size_t)p.TC * H);
+    load_twiddles(twl, tw + p.fc.tw_off, H, tid, NT);
     for (int i = tid; i < tot; i += NT) cl[i] = S[i];
     __syncthreads();
-    fft_lds<MAXE, false>(cl, H, nc, H, p.fc.rad, p.fc.nst, tw + p.fc.tw_off, tid, NT);
+    fft_lds<MAXE, false>(cl, p.fc, twl, nc, H, tid, NT);
+    const unsigned mH = div_magic((unsigned)H);
 
-    const float2* L = p.lamhat + (size_t)c0 * H;
     const float* s2H = s2tab + p.fc.tw_off;
     const float* s2W = s2tab + p.fr.tw_off;
     const float mu1 = p.mu1, mu2 = p.mu2, ihw = p.inv_hw;
     const bool tv = p.reg == REG_TV;
-    for (int i = tid; i < tot; i += NT) {
-        const int col = i / H;
+#pragma unroll
+    for (int k = 0; k < MAXE; ++k) {
+        const int i = tid + k * NT;
+        if (i >= tot) break;
+        const int col = (int)udiv16((unsigned)i, (unsigned)H, mH);
         const int k1 = i - col * H;
-        const float2 lam = L[i];
+        const float2 lam = lamr[k];
         const float4 f = cl[i];
         float4 o;
         if (mode == COL_SOLVE) {
@@ -104,7 +117,7 @@ __global__ __launch_bounds__(NT) void k_col(const ProbDesc* __restrict__ pd, con
         cl[i] = o;
     }
     __syncthreads();
-    fft_lds<MAXE, true>(cl, H, nc, H, p.fc.rad, p.fc.nst, tw + p.fc.tw_off, tid, NT);
+    fft_lds<MAXE, true>(cl, p.fc, twl, nc, H, tid, NT);
     for (int i = tid; i < tot; i += NT) S[i] = cl[i];
 }
 
@@ -114,8 +127,9 @@ __global__ __launch_bounds__(NT) void k_col(const ProbDesc* __restrict__ pd, con
 __device__ __forceinline__ void load_rows_hermitian(float2* X, const float4* __restrict__ S, int H, int W, int P,
                                                     int rbeg, int nrows, int tid) {
     const int tot = P * nrows;
+    const unsigned mr = div_magic((unsigned)nrows);
     for (int i = tid; i < tot; i += NT) {
-        const int k2 = i / nrows;
+        const int k2 = (int)udiv16((unsigned)i, (unsigned)nrows, mr);
         const int rr = i - k2 * nrows;
         const int r = wrapi(rbeg + rr, H);
         const float4 f = S[(size_t)k2 * H + r];
@@ -134,8 +148,9 @@ __device__ __forceinline__ void load_rows_hermitian(float2* X, const float4* __r
 __device__ __forceinline__ void store_rows_split(const float2* X, float4* __restrict__ S, int H, int W, int P,
                                                  int r0, int nrows, int tid) {
     const int tot = P * nrows;
+    const unsigned mr = div_magic((unsigned)nrows);
     for (int i = tid; i < tot; i += NT) {
-        const int k2 = i / nrows;
+        const int k2 = (int)udiv16((unsigned)i, (unsigned)nrows, mr);
         const int rr = i - k2 * nrows;
         const float2 c = X[rr * W + k2];
         const float2 m = X[rr * W + (k2 == 0 ? 0 : W - k2)];
@@ -146,7 +161,11 @@ __device__ __forceinline__ void store_rows_split(const float2* X, float4* __rest
 }
 
 // ------------------------------------------------------------ fused TV row pass
-template <int MAXE>
+// CPT: columns per thread (W <= CPT * NT); RB: most rows per block. All global
+// inputs of the epilogue are loaded in one burst after the inverse transform
+// (register arrays indexed by the unrolled row loop), so the row steps, which
+// exchange delta^h through LDS, wait on memory once rather than once per row.
+template <int MAXE, int CPT, int RB>
 __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                int nitems, int par, int flags, const InfoDev* __restrict__ info,
                                                const float2* __restrict__ tw, double* __restrict__ partials) {
@@ -160,7 +179,8 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     const int nrh = nr + 2;
     const int tid = threadIdx.x;
     const size_t n = (size_t)H * W;
-    float* dl = reinterpret_cast<float*>(X + nrh * W);   // 2 x W: delta^h of the current row (ping-pong)
+    float* dl = reinterpret_cast<float*>(X + (size_t)(p.B + 2) * W);   // 2 x W: delta^h of the row (ping-pong)
+    float2* twl = reinterpret_cast<float2*>(dl + 2 * W);                 // row twiddles
 
     const float4* Sin = par ? p.spec1 : p.spec0;
     float4* Sout = par ? p.spec0 : p.spec1;
@@ -169,9 +189,10 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     float* dh_out = par ? p.dreg0 : p.dreg1;
     float* dv_out = dh_out + n;
 
+    load_twiddles(twl, tw + p.fr.tw_off, W, tid, NT);
     load_rows_hermitian(X, Sin, H, W, P, r0 - 1, nrh, tid);
     __syncthreads();
-    fft_lds<MAXE, true>(X, W, nrh, W, p.fr.rad, p.fr.nst, tw + p.fr.tw_off, tid, NT);
+    fft_lds<MAXE, true>(X, p.fr, twl, nrh, W, tid, NT);
     // X[rr][c] = z + i A z for row r0 - 1 + rr
 
     const float tau = p.tau, mu2 = p.mu2, c1 = p.inv1pmu1;
@@ -179,22 +200,47 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     double acc[ADMM_NSUM];
 #pragma unroll
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
-    float dvp[MAXC], zet[MAXC], dvc[MAXC];
 
-    for (int rr = 0; rr <= nr; ++rr) {
+    // burst of epilogue loads: duals of rows r0-1 .. r0+nr-1, data of rows r0 .. r0+nr-1
+    float pdh[CPT][RB + 1], pdv[CPT][RB + 1], pd1[CPT][RB], py[CPT][RB];
+    bool pob[CPT][RB];
+#pragma unroll
+    for (int rr = 0; rr <= RB; ++rr) {
+        if (rr > nr) break;
+        const int r = wrapi(r0 - 1 + rr, H);
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int c = tid + j * NT;
+            if (c < W) {
+                const size_t g = (size_t)r * W + c;
+                pdh[j][rr] = dh_in[g];
+                pdv[j][rr] = dv_in[g];
+                if (rr > 0) {
+                    pd1[j][rr - 1] = p.d1[g];
+                    pob[j][rr - 1] = p.mask[g] != 0;
+                    py[j][rr - 1] = p.y[g];
+                }
+            }
+        }
+    }
+    float dvp[CPT], zet[CPT], dvc[CPT];
+
+#pragma unroll
+    for (int rr = 0; rr <= RB; ++rr) {
+        if (rr > nr) break;
         const int r = wrapi(r0 - 1 + rr, H);
         const float2* Xr = X + rr * W;
         const float2* Xn = X + (rr + 1) * W;
         float* dlr = dl + (rr & 1) * W;
 #pragma unroll
-        for (int j = 0; j < MAXC; ++j) {
+        for (int j = 0; j < CPT; ++j) {
             const int c = tid + j * NT;
             if (c < W) {
                 const float zc = Xr[c].x;
                 const float zh = Xr[c + 1 == W ? 0 : c + 1].x - zc;
                 const float zv = Xn[c].x - zc;
                 const size_t g = (size_t)r * W + c;
-                const float dh = dh_in[g], dv = dv_in[g];
+                const float dh = pdh[j][rr], dv = pdv[j][rr];
                 const float vh = zh - dh, vv = zv - dv;
                 const float rho = sqrtf(fmaf(vh, vh, vv * vv));
                 const float sc = rho > tau ? (rho - tau) / rho : 0.0f;
@@ -204,9 +250,9 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                 dvc[j] = uv + dvn;
                 if (rr > 0) {
                     const float Az = Xr[c].y;
-                    const float d1o = p.d1[g];
-                    const bool obs = p.mask[g] != 0;
-                    const float yv = obs ? p.y[g] : 0.0f;
+                    const float d1o = pd1[j][rr - 1];
+                    const bool obs = pob[j][rr - 1];
+                    const float yv = obs ? py[j][rr - 1] : 0.0f;
                     const float v1 = Az - d1o;
                     const float u1 = obs ? fmaf(yv - v1, c1, v1) : v1;   // (y + mu1 v)/(1 + mu1) or v
                     const float d1n = u1 - v1;                           // d1 - (A z - u1)
@@ -253,7 +299,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
         if (rr > 0) {
             float2* Xw = X + rr * W;
 #pragma unroll
-            for (int j = 0; j < MAXC; ++j) {
+            for (int j = 0; j < CPT; ++j) {
                 const int c = tid + j * NT;
                 if (c < W) {
                     const float s = mu2 * ((dlr[c == 0 ? W - 1 : c - 1] - dlr[c]) + (dvp[j] - dvc[j]));
@@ -262,11 +308,11 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
             }
         }
 #pragma unroll
-        for (int j = 0; j < MAXC; ++j) dvp[j] = dvc[j];
+        for (int j = 0; j < CPT; ++j) dvp[j] = dvc[j];
     }
     __syncthreads();
     if (flags & F_FORWARD) {
-        fft_lds<MAXE, false>(X + W, W, nr, W, p.fr.rad, p.fr.nst, tw + p.fr.tw_off, tid, NT);
+        fft_lds<MAXE, false>(X + W, p.fr, twl, nr, W, tid, NT);
         store_rows_split(X + W, Sout, H, W, P, r0, nr, tid);
     }
     if (chk) block_sums_write(acc, reinterpret_cast<double*>(X), partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM);
@@ -291,13 +337,15 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
     const float* b = p.tmpB + (size_t)r0 * W;
     const int tot = nr * W;
     const float mu1 = p.mu1;
+    float2* twl = X + (size_t)p.B * W;
+    load_twiddles(twl, tw + p.fr.tw_off, W, tid, NT);
     if (src == 0) {
         for (int i = tid; i < tot; i += NT) X[i] = make_float2(mu1 * a[i], b[i]);
     } else {
         for (int i = tid; i < tot; i += NT) X[i] = make_float2(a[i], 0.0f);
     }
     __syncthreads();
-    fft_lds<MAXE, false>(X, W, nr, W, p.fr.rad, p.fr.nst, tw + p.fr.tw_off, tid, NT);
+    fft_lds<MAXE, false>(X, p.fr, twl, nr, W, tid, NT);
     store_rows_split(X, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
 }
 
@@ -318,9 +366,11 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     const int H = p.H, W = p.W, P = p.P, r0 = it.start;
     const int nr = min(p.B, H - r0);
     const int tid = threadIdx.x;
+    float2* twl = X + (size_t)p.B * W;
+    load_twiddles(twl, tw + p.fr.tw_off, W, tid, NT);
     load_rows_hermitian(X, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
     __syncthreads();
-    fft_lds<MAXE, true>(X, W, nr, W, p.fr.rad, p.fr.nst, tw + p.fr.tw_off, tid, NT);
+    fft_lds<MAXE, true>(X, p.fr, twl, nr, W, tid, NT);
     const int tot = nr * W;
     const size_t off = (size_t)r0 * W;
     if (mode == 0) {
@@ -494,13 +544,17 @@ __global__ void k_warmstart(const ProbDesc* __restrict__ pd, int prob, const flo
 }
 
 // ------------------------------------------------------------ host launchers
-static size_t col_lds(int H, int TC) { return (size_t)H * TC * sizeof(float4); }
+static size_t col_lds(int H, int TC) { return (size_t)H * TC * sizeof(float4) + (size_t)H * sizeof(float2); }
 static size_t rowtv_lds(int W, int B) {
-    const size_t b = (size_t)(B + 2) * W * sizeof(float2) + 2 * (size_t)W * sizeof(float);
+    const size_t b = (size_t)(B + 2) * W * sizeof(float2) + 2 * (size_t)W * sizeof(float) + (size_t)W * sizeof(float2);
     const size_t scratch = NT / 64 * ADMM_NSUM * sizeof(double);   // block partial sums reuse the buffer
     return b > scratch ? b : scratch;
 }
-static size_t row_lds(int W, int B) { return (size_t)B * W * sizeof(float2) + NT / 64 * ADMM_NSUM * sizeof(double); }
+static size_t row_lds(int W, int B) {
+    const size_t b = (size_t)(B + 1) * W * sizeof(float2);            // rows + twiddles
+    const size_t scratch = NT / 64 * ADMM_NSUM * sizeof(double);    // block sums reuse the rows
+    return b > scratch ? b : scratch;
+}
 
 hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
     hipLaunchKernelGGL(k_col<MAXE_COL>, dim3(L.ncol), dim3(NT), L.lds_col, L.stream, L.desc, L.col_items, L.ncol,
@@ -509,10 +563,19 @@ hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
 }
 
 hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags) {
-    hipLaunchKernelGGL(k_row_tv<MAXE_ROW>, dim3(L.nrow), dim3(NT), L.lds_rowtv, L.stream, L.desc, L.row_items,
-                       L.nrow, par, flags, L.info, L.tw, L.partials);
+    if (L.tv_maxw <= NT)
+        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 1, 8>), dim3(L.nrow), dim3(NT), L.lds_rowtv, L.stream, L.desc,
+                           L.row_items, L.nrow, par, flags, L.info, L.tw, L.partials);
+    else if (L.tv_maxw <= 2 * NT)
+        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 2, 6>), dim3(L.nrow), dim3(NT), L.lds_rowtv, L.stream, L.desc,
+                           L.row_items, L.nrow, par, flags, L.info, L.tw, L.partials);
+    else
+        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 4, 2>), dim3(L.nrow), dim3(NT), L.lds_rowtv, L.stream, L.desc,
+                           L.row_items, L.nrow, par, flags, L.info, L.tw, L.partials);
     return hipGetLastError();
 }
+
+int row_tv_max_rows(int maxw) { return maxw <= NT ? 8 : (maxw <= 2 * NT ? 6 : 2); }
 
 hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
     hipLaunchKernelGGL(k_row_fwd<MAXE_ROW>, dim3(L.nrow), dim3(NT), L.lds_row, L.stream, L.desc, L.row_items,

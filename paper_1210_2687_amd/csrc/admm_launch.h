@@ -20,6 +20,7 @@ struct LaunchCtx {
     const float2* tw = nullptr;
     const float* s2 = nullptr;
     size_t lds_col = 0, lds_rowtv = 0, lds_row = 0, lds_frm = 0;
+    int tv_maxw = 0;                       // widest TV problem (selects the row-pass instantiation)
 };
 
 hipError_t launch_col(const LaunchCtx& L, int par, int mode);
@@ -39,6 +40,7 @@ size_t lds_rowtv_bytes(int W, int B);
 size_t lds_row_bytes(int W, int B);
 size_t lds_frame_bytes(int FT, int J);
 int col_maxe();
+int row_tv_max_rows(int maxw);
 int row_maxe();
 int block_threads();
 

@@ -14,12 +14,14 @@
 // registers between the two barriers of a stage, so the transform is in place.
 //
 // Twiddles come from a per-length table tw[k] = exp(-2 pi i k / N) computed in
-// double precision on the host and rounded once; the inverse uses conj(tw).
+// double precision on the host and rounded once, copied to LDS by each block;
+// the inverse uses conj(tw).
 // Arithmetic uses explicit fmaf where a fused multiply-add is wanted and the
 // library is compiled with -ffp-contract=off, so every instantiation rounds
 // identically (a requirement for bit-exact checkpoint/resume).
 #pragma once
 #include <hip/hip_runtime.h>
+#include "admm_internal.h"
 
 namespace admm {
 
@@ -182,15 +184,16 @@ template <int R, bool INV, typename E> __device__ __forceinline__ void dft(E* v)
 }
 
 // ----------------------------------------------------------- Stockham stage
-// buf holds `ntrans` transforms of length N at stride `tstride` (elements).
-// Requirement (checked on the host): ntrans * N / R <= (MAXE / R) * nthr.
+// buf holds `ntrans` transforms of length N at stride `tstride` (elements);
+// twl is the length-N twiddle table in LDS. Requirement (checked on the host):
+// ntrans * N / R <= (MAXE / R) * nthr. Index arithmetic is 32-bit with the
+// per-stage reciprocal multipliers of FftPlanDev (no runtime division).
 template <int R, int MAXE, bool INV, typename E>
-__device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, int N, int ntrans, int tstride, int Ns,
-                                               const float2* __restrict__ tw, int tid, int nthr) {
+__device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS float2* twl, int ntrans, int tstride,
+                                            int Ns, int nbf, int twm, unsigned mnbf, unsigned mns, int tid,
+                                            int nthr) {
     constexpr int NB = MAXE / R;
-    const int nbf = N / R;
     const int total = ntrans * nbf;
-    const int twmul = N / (Ns * R);
     E v[NB][R];
     int dst[NB];
 #pragma unroll
@@ -198,17 +201,17 @@ __device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, int N, int ntrans, 
         const int q = tid + i * nthr;
         dst[i] = -1;
         if (q < total) {
-            const int t = q / nbf;
+            const int t = (int)udiv16((unsigned)q, (unsigned)nbf, mnbf);
             const int j = q - t * nbf;
-            const int jq = j / Ns;
+            const int jq = (int)udiv16((unsigned)j, (unsigned)Ns, mns);
             const int k = j - jq * Ns;
-            const ADMM_LDS E* b = buf + t * tstride;
+            const ADMM_LDS E* b = buf + t * tstride + j;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = lds_ld(b + j + r * nbf);
-            const int tws = twmul * k;
+            for (int r = 0; r < R; ++r) v[i][r] = lds_ld(b + r * nbf);
+            const int tws = twm * k;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = tw[tws * r];
+                float2 w = lds_ld(twl + tws * r);
                 if (INV) w.y = -w.y;
                 v[i][r] = cmul(v[i][r], w);
             }
@@ -220,33 +223,40 @@ __device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, int N, int ntrans, 
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         if (dst[i] >= 0) {
+            ADMM_LDS E* o = buf + dst[i];
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds_st(buf + dst[i] + r * Ns, v[i][r]);
+            for (int r = 0; r < R; ++r) lds_st(o + r * Ns, v[i][r]);
         }
     }
     __syncthreads();
 }
 
 // Full transform of `ntrans` length-N sequences in LDS (natural order in and out).
-// rad[0..nst) is the radix schedule (product N). Unnormalised in both directions.
+// Unnormalised in both directions. twl: the plan's twiddle table copied to LDS.
 template <int MAXE, bool INV, typename E>
-__device__ __forceinline__ void fft_lds(E* gbuf, int N, int ntrans, int tstride, const int* rad, int nst,
-                                        const float2* __restrict__ tw, int tid, int nthr) {
+__device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const float2* gtwl, int ntrans, int tstride,
+                                        int tid, int nthr) {
     ADMM_LDS E* buf = (ADMM_LDS E*)gbuf;
-    int Ns = 1;
+    const ADMM_LDS float2* twl = (const ADMM_LDS float2*)gtwl;
+    const int nst = f.nst;
     for (int s = 0; s < nst; ++s) {
-        const int R = rad[s];
+        const int R = f.rad[s], Ns = f.ns[s], nbf = f.nbf[s], twm = f.twm[s];
+        const unsigned mnbf = f.mnbf[s], mns = f.mns[s];
         switch (R) {
-            case 8: stockham_stage<8, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
-            case 4: stockham_stage<4, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
-            case 2: stockham_stage<2, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
-            case 3: stockham_stage<3, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
-            case 5: stockham_stage<5, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
-            case 7: stockham_stage<7, MAXE, INV>(buf, N, ntrans, tstride, Ns, tw, tid, nthr); break;
+            case 8: stockham_stage<8, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
+            case 4: stockham_stage<4, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
+            case 2: stockham_stage<2, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
+            case 3: stockham_stage<3, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
+            case 5: stockham_stage<5, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
+            case 7: stockham_stage<7, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
             default: break;
         }
-        Ns *= R;
     }
+}
+
+// Copy the length-N twiddle table to LDS (before the first barrier of a kernel).
+__device__ __forceinline__ void load_twiddles(float2* twl, const float2* __restrict__ tw, int N, int tid, int nthr) {
+    for (int i = tid; i < N; i += nthr) twl[i] = tw[i];
 }
 
 }  // namespace admm
