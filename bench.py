@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--iters", type=int, default=500, help="ADMM iterations per step")
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--cpu-iters", type=int, default=8, help="oracle iterations per sampled image")
+    ap.add_argument("--cpu-iters", type=int, default=120, help="oracle iterations per sampled image")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event-timing pass")
@@ -171,7 +171,7 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                     "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": alg[dom],
-                    "kernel_ms": {k: round(v[1] / max(v[0], 1) * 1e3, 3) for k, v in kt.items() if v[0]}}
+                    "kernel_us": {k: round(v[1] / max(v[0], 1) * 1e3, 3) for k, v in kt.items() if v[0]}}
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_iters)
     out = {

@@ -251,7 +251,8 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
                 tab_len += N;
             }
 
-    const int target_blocks = 1024;
+    // about two blocks per compute unit per pass (measured best on 8 x 512^2: TC = 4, B = 8)
+    const int target_blocks = 512;
     int tv_maxw = 0;
     for (int i = 0; i < count; ++i)
         if (probs[i].reg == ADMM_REG_TV) tv_maxw = std::max(tv_maxw, (int)probs[i].W);
@@ -282,7 +283,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         while (tcmax + 1 <= d.P && fits(tcmax + 1, d.fc, col_maxe()) && lds_col_bytes(q.H, tcmax + 1) <= cap) ++tcmax;
         if (!fits(1, d.fc, col_maxe()) || lds_col_bytes(q.H, 1) > cap)
             return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: column length %d does not fit a block", i, q.H));
-        d.TC = std::max(1, std::min(tcmax, (d.P + per - 1) / per));
+        d.TC = std::max(1, std::min(tcmax, d.P / per));
         if (const char* e = std::getenv("ADMM_TC")) d.TC = std::max(1, std::min(tcmax, std::atoi(e)));
         // rows per block
         int bmax = 0;
