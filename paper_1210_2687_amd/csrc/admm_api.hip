@@ -65,22 +65,31 @@ int radices(int n, int* out, int cap) {
         n /= 2;
         ++a;
     }
+    // with at least two factors of 8 the schedule starts and ends with radix 8
+    // (the column pass then keeps the last forward and first inverse stage in
+    // registers); the other radices go in between
+    const bool ends = a >= 6;
+    if (ends) a -= 6;
+    std::vector<int> mid;
     int n8 = a / 3, rem = a % 3;
     if (rem == 1 && n8 > 0) {
         --n8;
-        r.insert(r.end(), n8, 8);
-        r.push_back(4);
-        r.push_back(4);
+        mid.insert(mid.end(), n8, 8);
+        mid.push_back(4);
+        mid.push_back(4);
     } else {
-        r.insert(r.end(), n8, 8);
-        if (rem == 1) r.push_back(2);
-        if (rem == 2) r.push_back(4);
+        mid.insert(mid.end(), n8, 8);
+        if (rem == 1) mid.push_back(2);
+        if (rem == 2) mid.push_back(4);
     }
     for (int p : {7, 5, 3})
         while (n % p == 0) {
             n /= p;
-            r.push_back(p);
+            mid.push_back(p);
         }
+    if (ends) r.push_back(8);
+    r.insert(r.end(), mid.begin(), mid.end());
+    if (ends) r.push_back(8);
     if ((int)r.size() > cap) return -1;
     for (size_t i = 0; i < r.size(); ++i) out[i] = r[i];
     return (int)r.size();
@@ -104,6 +113,7 @@ void fill_plan(FftPlanDev& f, int N, int tw_off) {
     f.N = N;
     f.tw_off = tw_off;
     f.nst = radices(N, f.rad, ADMM_MAX_STAGES);
+    f.ends8 = f.nst >= 1 && f.rad[0] == 8 && f.rad[f.nst - 1] == 8;
     int Ns = 1;
     for (int s = 0; s < f.nst; ++s) {
         const int R = f.rad[s];
@@ -278,13 +288,13 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         fill_plan(d.fr, q.W, tab_off[q.W]);
         fill_plan(d.fc, q.H, tab_off[q.H]);
         const int per = std::max(1, (target_blocks + count - 1) / count);
-        // column tile width
-        int tcmax = 1;
-        while (tcmax + 1 <= d.P && fits(tcmax + 1, d.fc, col_maxe()) && lds_col_bytes(q.H, tcmax + 1) <= cap) ++tcmax;
-        if (!fits(1, d.fc, col_maxe()) || lds_col_bytes(q.H, 1) > cap)
+        // column tile: one column per wave of the column-pass block, as many as LDS holds
+        int tcmax = 0;
+        while (tcmax + 1 <= col_max_tiles() && lds_col_bytes(q.H, tcmax + 1) <= cap) ++tcmax;
+        if (tcmax < 1)
             return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: column length %d does not fit a block", i, q.H));
-        d.TC = std::max(1, std::min(tcmax, d.P / per));
-        if (const char* e = std::getenv("ADMM_TC")) d.TC = std::max(1, std::min(tcmax, std::atoi(e)));
+        d.TC = std::min(tcmax, d.P);
+        if (const char* e = std::getenv("ADMM_TC")) d.TC = std::max(1, std::min(d.TC, std::atoi(e)));
         // rows per block
         int bmax = 0;
         if (q.reg == ADMM_REG_TV) {
@@ -468,6 +478,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     base_ctx.lds_row = P->lds_row;
     base_ctx.lds_frm = P->lds_frm;
     base_ctx.tv_maxw = tv_maxw;
+    for (int i = 0; i < count; ++i) base_ctx.col_maxh = std::max(base_ctx.col_maxh, (int)probs[i].H);
     base_ctx.col_items = P->d_items;
     base_ctx.ncol = P->ncol;
     P->all = base_ctx;

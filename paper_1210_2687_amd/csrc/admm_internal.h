@@ -42,6 +42,7 @@ enum { COL_SOLVE = 0, COL_BLUR = 1 };
 struct FftPlanDev {
     int N;
     int nst;
+    int ends8;                  // first and last stage are radix 8 (register-fused column pass)
     int tw_off;                 // offset of this length's tables in the shared table arrays
     int rad[ADMM_MAX_STAGES];
     int ns[ADMM_MAX_STAGES];

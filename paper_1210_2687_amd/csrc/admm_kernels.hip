@@ -24,7 +24,6 @@
 namespace admm {
 
 constexpr int NT = 512;            // threads per block of the FFT passes
-constexpr int MAXE_COL = 8;        // float4 elements per thread in the column pass
 constexpr int MAXE_ROW = 16;       // float2 elements per thread in the row passes
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -55,70 +54,173 @@ __device__ void block_sums_write(const double* v, double* scratch, double* out) 
 }
 
 // ------------------------------------------------------------ column pass
-template <int MAXE>
-__global__ __launch_bounds__(NT) void k_col(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
-                                            int nitems, int par, int mode, const InfoDev* __restrict__ info,
-                                            const float2* __restrict__ tw, const float* __restrict__ s2tab) {
+// Block of NTC threads = 4 waves; wave w owns column c0 + w of the work item
+// (TC <= 4 columns; with fewer columns the spare waves leave after the shared
+// twiddle table is loaded). The spectral solve of one entry:
+//   TV  z^ = K (conj(Lambda) (mu1 zeta1)^ + s^),
+//       K = 1 / (H W (mu1 |Lambda|^2 + mu2 (|Delta^h|^2 + |Delta^v|^2)))   (eq. (33))
+//   FA  the same with mu2 in place of mu2 (|Delta^h|^2 + |Delta^v|^2)      (eq. (25))
+// followed by A z^ = Lambda z^; the 1/(H W) of the inverse 2-D DFT is folded in.
+// The row pass transforms mu1 zeta1 (not zeta1) so that both halves of the
+// packed complex transform have comparable magnitude: the rounding of the
+// larger half leaks into the other one when they are separated, and s is
+// O(mu) while zeta1 is O(1).
+constexpr int NTC = 256;
+
+__device__ __forceinline__ float4 col_solve(float4 f, float2 lam, float w, float mu1, float mu2, float ihw, int mode) {
+    if (mode == COL_SOLVE) {
+        const float l2 = fmaf(lam.x, lam.x, lam.y * lam.y);
+        const float K = ihw / fmaf(mu1, l2, mu2 * w);
+        const float rx = fmaf(lam.x, f.x, lam.y * f.y) + f.z;
+        const float ry = fmaf(lam.x, f.y, -(lam.y * f.x)) + f.w;
+        const float zx = K * rx, zy = K * ry;
+        return make_float4(zx, zy, fmaf(lam.x, zx, -(lam.y * zy)), fmaf(lam.x, zy, lam.y * zx));
+    }
+    // COL_BLUR: (x^, 0) -> (Lambda x^ / (H W), 0)
+    const float ax = fmaf(lam.x, f.x, -(lam.y * f.y)), ay = fmaf(lam.x, f.y, lam.y * f.x);
+    return make_float4(ax * ihw, ay * ihw, 0.f, 0.f);
+}
+
+// EPL: most column entries per lane (H <= 64 EPL).
+template <int EPL>
+__global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                             int nitems, int par, int mode, const InfoDev* __restrict__ info,
+                                             const float2* __restrict__ tw, const float* __restrict__ s2tab) {
     extern __shared__ float4 cl[];
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
     const WorkItem it = items[wi];
     if (info && !info[it.prob].active) return;
     const ProbDesc& p = pd[it.prob];
-    const int H = p.H, P = p.P, c0 = it.start;
-    const int nc = min(p.TC, P - c0);
-    const int tid = threadIdx.x;
-    float4* S = ((p.reg == REG_TV && par) ? p.spec1 : p.spec0) + (size_t)c0 * H;
-    const int tot = nc * H;
-    // Lambda is loaded together with the spectrum so that its latency is not
-    // exposed after the forward transform (a block holds at most MAXE entries per thread)
-    const float2* L = p.lamhat + (size_t)c0 * H;
-    float2 lamr[MAXE];
-#pragma unroll
-    for (int k = 0; k < MAXE; ++k) {
-        const int i = tid + k * NT;
-        lamr[k] = i < tot ? L[i] : make_float2(0.f, 0.f);
-    }
-    float2* twl = reinterpret_cast<float2*>(cl + (size_t)p.TC * H);
-    load_twiddles(twl, tw + p.fc.tw_off, H, tid, NT);
-    for (int i = tid; i < tot; i += NT) cl[i] = S[i];
-    __syncthreads();
-    fft_lds<MAXE, false>(cl, p.fc, twl, nc, H, tid, NT);
-    const unsigned mH = div_magic((unsigned)H);
-
+    const int H = p.H, c0 = it.start;
+    const int nc = min(p.TC, p.P - c0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool fused = p.fc.ends8;
+    const int nbf = H >> 3;
+    const int col = c0 + wave;
+    const bool live = wave < nc;
+    float4* S = ((p.reg == REG_TV && par) ? p.spec1 : p.spec0) + (size_t)col * H;
+    const float2* L = p.lamhat + (size_t)col * H;
     const float* s2H = s2tab + p.fc.tw_off;
-    const float* s2W = s2tab + p.fr.tw_off;
     const float mu1 = p.mu1, mu2 = p.mu2, ihw = p.inv_hw;
-    const bool tv = p.reg == REG_TV;
+    const float w2 = (p.reg == REG_TV && live) ? s2tab[p.fr.tw_off + col] : 0.0f;
+
+    // first radix-8 stage operands, Lambda and |Delta^v|^2 of the entries this
+    // lane holds after the last forward stage (both sets are j + r H / 8)
+    constexpr int NB8 = (EPL + 7) / 8;
+    constexpr bool PF = EPL <= 16;
+    float4 v[NB8][8];
+    float2 lam[PF ? NB8 : 1][8];
+    float wv[PF ? NB8 : 1][8];
+    if (fused && live) {
 #pragma unroll
-    for (int k = 0; k < MAXE; ++k) {
-        const int i = tid + k * NT;
-        if (i >= tot) break;
-        const int col = (int)udiv16((unsigned)i, (unsigned)H, mH);
-        const int k1 = i - col * H;
-        const float2 lam = lamr[k];
-        const float4 f = cl[i];
-        float4 o;
-        if (mode == COL_SOLVE) {
-            const float w = tv ? (s2H[k1] + s2W[c0 + col]) : 1.0f;
-            const float l2 = fmaf(lam.x, lam.x, lam.y * lam.y);
-            const float K = ihw / fmaf(mu1, l2, mu2 * w);
-            // r = conj(Lambda) (mu1 zeta1)^ + s^ ; the row pass transforms mu1 zeta1
-            // (not zeta1) so that both halves of the packed complex transform have
-            // comparable magnitude: the rounding of the larger half leaks into the
-            // other one when they are separated, and s is O(mu) while zeta1 is O(1)
-            const float rx = fmaf(lam.x, f.x, lam.y * f.y) + f.z;
-            const float ry = fmaf(lam.x, f.y, -(lam.y * f.x)) + f.w;
-            const float zx = K * rx, zy = K * ry;
-            o = make_float4(zx, zy, fmaf(lam.x, zx, -(lam.y * zy)), fmaf(lam.x, zy, lam.y * zx));
-        } else {  // COL_BLUR: (x^, 0) -> (Lambda x^ / (H W), 0)
-            const float ax = fmaf(lam.x, f.x, -(lam.y * f.y)), ay = fmaf(lam.x, f.y, lam.y * f.x);
-            o = make_float4(ax * ihw, ay * ihw, 0.f, 0.f);
+        for (int i = 0; i < NB8; ++i) {
+            const int j = lane + 64 * i;
+            if (j < nbf) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) v[i][r] = S[j + r * nbf];
+                if (PF) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) {
+                        lam[PF ? i : 0][r] = L[j + r * nbf];
+                        wv[PF ? i : 0][r] = s2H[j + r * nbf];
+                    }
+                }
+            }
         }
-        cl[i] = o;
     }
+    float2* twg = reinterpret_cast<float2*>(cl);
+    load_twiddles(twg, tw + p.fc.tw_off, H, tid, NTC);
     __syncthreads();
-    fft_lds<MAXE, true>(cl, p.fc, twl, nc, H, tid, NT);
-    for (int i = tid; i < tot; i += NT) S[i] = cl[i];
+    if (!live) return;
+    const ADMM_LDS float2* twl = (const ADMM_LDS float2*)twg;
+    ADMM_LDS float4* buf = (ADMM_LDS float4*)(cl + (H + 1) / 2 + wave * pidx_len(H));
+    const int nst = p.fc.nst;
+
+    if (fused) {
+        // forward: stage 0 (radix 8, no twiddles) from registers
+#pragma unroll
+        for (int i = 0; i < NB8; ++i) {
+            const int j = lane + 64 * i;
+            if (j < nbf) {
+                dft<8, false>(v[i]);
+                if (nst > 1) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) lds_st(buf + pidx(8 * j + r), v[i][r]);
+                }
+            }
+        }
+        if (nst > 1) {
+            wave_stages<EPL, false>(buf, twl, p.fc, 1, nst - 1, lane);
+            // last stage (radix 8, Ns = H / 8): output r of butterfly j is entry j + r H / 8
+#pragma unroll
+            for (int i = 0; i < NB8; ++i) {
+                const int j = lane + 64 * i;
+                if (j < nbf) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) v[i][r] = lds_ld(buf + pidx(j + r * nbf));
+#pragma unroll
+                    for (int r = 1; r < 8; ++r) v[i][r] = cmul(v[i][r], lds_ld(twl + j * r));
+                    dft<8, false>(v[i]);
+                }
+            }
+        }
+        // solve, then the first inverse stage (radix 8, no twiddles) on the same entries
+#pragma unroll
+        for (int i = 0; i < NB8; ++i) {
+            const int j = lane + 64 * i;
+            if (j < nbf) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int k1 = j + r * nbf;
+                    const float2 lm = PF ? lam[PF ? i : 0][r] : L[k1];
+                    const float w = p.reg == REG_TV ? (PF ? wv[PF ? i : 0][r] : s2H[k1]) + w2 : 1.0f;
+                    v[i][r] = col_solve(v[i][r], lm, w, mu1, mu2, ihw, mode);
+                }
+                dft<8, true>(v[i]);
+                if (nst > 1) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) lds_st(buf + pidx(8 * j + r), v[i][r]);
+                }
+            }
+        }
+        if (nst > 1) {
+            wave_stages<EPL, true>(buf, twl, p.fc, 1, nst - 1, lane);
+#pragma unroll
+            for (int i = 0; i < NB8; ++i) {
+                const int j = lane + 64 * i;
+                if (j < nbf) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) v[i][r] = lds_ld(buf + pidx(j + r * nbf));
+#pragma unroll
+                    for (int r = 1; r < 8; ++r) {
+                        float2 w = lds_ld(twl + j * r);
+                        w.y = -w.y;
+                        v[i][r] = cmul(v[i][r], w);
+                    }
+                    dft<8, true>(v[i]);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NB8; ++i) {
+            const int j = lane + 64 * i;
+            if (j < nbf) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) S[j + r * nbf] = v[i][r];
+            }
+        }
+        return;
+    }
+
+    // general schedule: the whole column goes through LDS
+    for (int e = lane; e < H; e += 64) lds_st(buf + pidx(e), S[e]);
+    wave_stages<EPL, false>(buf, twl, p.fc, 0, nst, lane);
+    for (int e = lane; e < H; e += 64) {
+        const float w = p.reg == REG_TV ? s2H[e] + w2 : 1.0f;
+        lds_st(buf + pidx(e), col_solve(lds_ld(buf + pidx(e)), L[e], w, mu1, mu2, ihw, mode));
+    }
+    wave_stages<EPL, true>(buf, twl, p.fc, 0, nst, lane);
+    for (int e = lane; e < H; e += 64) S[e] = lds_ld(buf + pidx(e));
 }
 
 // ------------------------------------------------------------ row helpers
@@ -544,7 +646,9 @@ __global__ void k_warmstart(const ProbDesc* __restrict__ pd, int prob, const flo
 }
 
 // ------------------------------------------------------------ host launchers
-static size_t col_lds(int H, int TC) { return (size_t)H * TC * sizeof(float4) + (size_t)H * sizeof(float2); }
+static size_t col_lds(int H, int TC) {
+    return (size_t)((H + 1) / 2) * sizeof(float4) + (size_t)TC * pidx_len(H) * sizeof(float4);
+}
 static size_t rowtv_lds(int W, int B) {
     const size_t b = (size_t)(B + 2) * W * sizeof(float2) + 2 * (size_t)W * sizeof(float) + (size_t)W * sizeof(float2);
     const size_t scratch = NT / 64 * ADMM_NSUM * sizeof(double);   // block partial sums reuse the buffer
@@ -557,8 +661,16 @@ static size_t row_lds(int W, int B) {
 }
 
 hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
-    hipLaunchKernelGGL(k_col<MAXE_COL>, dim3(L.ncol), dim3(NT), L.lds_col, L.stream, L.desc, L.col_items, L.ncol,
-                       par, mode, mode == COL_SOLVE ? L.info : nullptr, L.tw, L.s2);
+    const InfoDev* info = mode == COL_SOLVE ? L.info : nullptr;
+    if (L.col_maxh <= 512)
+        hipLaunchKernelGGL(k_col<8>, dim3(L.ncol), dim3(NTC), L.lds_col, L.stream, L.desc, L.col_items, L.ncol, par,
+                           mode, info, L.tw, L.s2);
+    else if (L.col_maxh <= 1024)
+        hipLaunchKernelGGL(k_col<16>, dim3(L.ncol), dim3(NTC), L.lds_col, L.stream, L.desc, L.col_items, L.ncol, par,
+                           mode, info, L.tw, L.s2);
+    else
+        hipLaunchKernelGGL(k_col<32>, dim3(L.ncol), dim3(NTC), L.lds_col, L.stream, L.desc, L.col_items, L.ncol, par,
+                           mode, info, L.tw, L.s2);
     return hipGetLastError();
 }
 
@@ -616,9 +728,8 @@ hipError_t launch_warmstart(const LaunchCtx& L, int prob, size_t n, const float*
 size_t lds_col_bytes(int H, int TC) { return col_lds(H, TC); }
 size_t lds_rowtv_bytes(int W, int B) { return rowtv_lds(W, B); }
 size_t lds_row_bytes(int W, int B) { return row_lds(W, B); }
-int col_max_elems() { return MAXE_COL * NT; }
 int row_max_elems() { return MAXE_ROW * NT; }
-int col_maxe() { return MAXE_COL; }
+int col_max_tiles() { return NTC / 64; }
 int row_maxe() { return MAXE_ROW; }
 int block_threads() { return NT; }
 

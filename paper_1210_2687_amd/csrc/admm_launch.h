@@ -21,6 +21,7 @@ struct LaunchCtx {
     const float* s2 = nullptr;
     size_t lds_col = 0, lds_rowtv = 0, lds_row = 0, lds_frm = 0;
     int tv_maxw = 0;                       // widest TV problem (selects the row-pass instantiation)
+    int col_maxh = 0;                      // tallest problem (selects the column-pass instantiation)
 };
 
 hipError_t launch_col(const LaunchCtx& L, int par, int mode);
@@ -39,7 +40,7 @@ size_t lds_col_bytes(int H, int TC);
 size_t lds_rowtv_bytes(int W, int B);
 size_t lds_row_bytes(int W, int B);
 size_t lds_frame_bytes(int FT, int J);
-int col_maxe();
+int col_max_tiles();                       // columns per column-pass block (one per wave)
 int row_tv_max_rows(int maxw);
 int row_maxe();
 int block_threads();

@@ -254,6 +254,74 @@ __device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const floa
     }
 }
 
+// ----------------------------------------------------------- wave-level transforms
+// Used by the column pass: one 64-lane wave owns one length-N sequence in LDS
+// and transforms it alone (lane l takes butterflies j = l, l + 64, ... of every
+// stage). A wave's LDS instructions are executed in issue order, so a stage
+// needs no block barrier: all of a wave's loads of a stage are issued before
+// its stores, and the next stage's loads after those stores. Waves therefore
+// run their columns independently and overlap one another's memory phases.
+// The sequence is stored padded, element e at pidx(e) = e + e / 8, so that the
+// stride-8 element accesses of a first radix-8 stage fall in distinct banks.
+__host__ __device__ constexpr int pidx_len(int n) { return n + (n >> 3) + 1; }
+__device__ __forceinline__ int pidx(int e) { return e + (e >> 3); }
+
+// One radix-R stage of a wave-owned transform; NB bounds the butterflies per lane.
+template <int R, int NB, bool INV, typename E>
+__device__ __noinline__ void wave_stage(ADMM_LDS E* buf, const ADMM_LDS float2* twl, int Ns, int nbf, int twm,
+                                        unsigned mns, int lane) {
+    E v[NB][R];
+    int dst[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = lane + 64 * i;
+        dst[i] = -1;
+        if (j < nbf) {
+            const int jq = (int)udiv16((unsigned)j, (unsigned)Ns, mns);
+            const int k = j - jq * Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = lds_ld(buf + pidx(j + r * nbf));
+            if (Ns > 1) {
+                const int tws = twm * k;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    float2 w = lds_ld(twl + tws * r);
+                    if (INV) w.y = -w.y;
+                    v[i][r] = cmul(v[i][r], w);
+                }
+            }
+            dft<R, INV>(v[i]);
+            dst[i] = jq * Ns * R + k;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        if (dst[i] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds_st(buf + pidx(dst[i] + r * Ns), v[i][r]);
+        }
+    }
+}
+
+// Stages [s0, s1) of plan f on the wave-owned sequence buf; EPL bounds N / 64.
+template <int EPL, bool INV, typename E>
+__device__ __forceinline__ void wave_stages(ADMM_LDS E* buf, const ADMM_LDS float2* twl, const FftPlanDev& f, int s0,
+                                            int s1, int lane) {
+    for (int s = s0; s < s1; ++s) {
+        const int Ns = f.ns[s], nbf = f.nbf[s], twm = f.twm[s];
+        const unsigned mns = f.mns[s];
+        switch (f.rad[s]) {
+            case 8: wave_stage<8, (EPL + 7) / 8, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
+            case 4: wave_stage<4, (EPL + 3) / 4, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
+            case 2: wave_stage<2, (EPL + 1) / 2, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
+            case 3: wave_stage<3, (EPL + 2) / 3, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
+            case 5: wave_stage<5, (EPL + 4) / 5, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
+            case 7: wave_stage<7, (EPL + 6) / 7, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
+            default: break;
+        }
+    }
+}
+
 // Copy the length-N twiddle table to LDS (before the first barrier of a kernel).
 __device__ __forceinline__ void load_twiddles(float2* twl, const float2* __restrict__ tw, int N, int tid, int nthr) {
     for (int i = tid; i < N; i += nthr) twl[i] = tw[i];
