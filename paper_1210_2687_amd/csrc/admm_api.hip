@@ -59,40 +59,7 @@ bool smooth7(int n) {
 // Radix schedule: powers of two as radix 8 with a tail of 4 or 2, then 7, 5, 3.
 int radices(int n, int* out, int cap) {
     if (!smooth7(n)) return -1;
-    std::vector<int> r;
-    int a = 0;
-    while (n % 2 == 0) {
-        n /= 2;
-        ++a;
-    }
-    // with at least two factors of 8 the schedule starts and ends with radix 8
-    // (the column pass then keeps the last forward and first inverse stage in
-    // registers); the other radices go in between
-    const bool ends = a >= 6;
-    if (ends) a -= 6;
-    std::vector<int> mid;
-    int n8 = a / 3, rem = a % 3;
-    if (rem == 1 && n8 > 0) {
-        --n8;
-        mid.insert(mid.end(), n8, 8);
-        mid.push_back(4);
-        mid.push_back(4);
-    } else {
-        mid.insert(mid.end(), n8, 8);
-        if (rem == 1) mid.push_back(2);
-        if (rem == 2) mid.push_back(4);
-    }
-    for (int p : {7, 5, 3})
-        while (n % p == 0) {
-            n /= p;
-            mid.push_back(p);
-        }
-    if (ends) r.push_back(8);
-    r.insert(r.end(), mid.begin(), mid.end());
-    if (ends) r.push_back(8);
-    if ((int)r.size() > cap) return -1;
-    for (size_t i = 0; i < r.size(); ++i) out[i] = r[i];
-    return (int)r.size();
+    return fft_schedule(n, out, cap);
 }
 
 // Does a block of NT threads with MAXE registers per thread fit `ntrans`
@@ -109,19 +76,39 @@ bool fits(int ntrans, const FftPlanDev& f, int maxe) {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// tw_off: the length's slot in the table arrays (2 N entries: the natural
+// twiddles exp(-2 pi i k / N), then the stage table)
 void fill_plan(FftPlanDev& f, int N, int tw_off) {
     f.N = N;
     f.tw_off = tw_off;
     f.nst = radices(N, f.rad, ADMM_MAX_STAGES);
     f.ends8 = f.nst >= 1 && f.rad[0] == 8 && f.rad[f.nst - 1] == 8;
-    int Ns = 1;
+    int Ns = 1, off = 0;
     for (int s = 0; s < f.nst; ++s) {
         const int R = f.rad[s];
         f.ns[s] = Ns;
         f.nbf[s] = N / R;
-        f.twm[s] = N / (Ns * R);
+        f.tso[s] = off;
         f.mnbf[s] = div_magic((unsigned)f.nbf[s]);
         f.mns[s] = div_magic((unsigned)Ns);
+        off += Ns * (R - 1);
+        Ns *= R;
+    }
+}
+
+// The stage table of length N (N - 1 entries), in double then rounded once.
+void stage_twiddles(int N, float2* out) {
+    int rad[ADMM_MAX_STAGES] = {};
+    const int nst = radices(N, rad, ADMM_MAX_STAGES);
+    int Ns = 1, off = 0;
+    for (int s = 0; s < nst; ++s) {
+        const int R = rad[s];
+        for (int k = 0; k < Ns; ++k)
+            for (int r = 1; r < R; ++r) {
+                const double ang = 2.0 * M_PI * (double)k * r / ((double)Ns * R);
+                out[off + k * (R - 1) + r - 1] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+            }
+        off += Ns * (R - 1);
         Ns *= R;
     }
 }
@@ -245,7 +232,15 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     HIP_TRY(hipGetDevice(&dev));
     int lds_cap = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t cap = std::min<size_t>((size_t)lds_cap, 65536);
+    // the pass kernels may use the whole LDS of a compute unit; if the runtime
+    // refuses, plan within the 64 KiB every device allows
+    size_t cap = std::min<size_t>((size_t)lds_cap, 65536);
+    if (lds_cap > 65536) {
+        if (allow_dynamic_lds(lds_cap) == hipSuccess)
+            cap = (size_t)lds_cap;
+        else
+            (void)hipGetLastError();
+    }
     P->stream = (hipStream_t)hip_stream;
     P->count = count;
     P->probs.assign(probs, probs + count);
@@ -258,7 +253,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         for (int N : {probs[i].H, probs[i].W})
             if (!tab_off.count(N)) {
                 tab_off[N] = tab_len;
-                tab_len += N;
+                tab_len += 2 * N;
             }
 
     // about two blocks per compute unit per pass (measured best on 8 x 512^2: TC = 4, B = 8)
@@ -295,7 +290,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
             return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: column length %d does not fit a block", i, q.H));
         d.TC = std::min(tcmax, d.P);
         if (const char* e = std::getenv("ADMM_TC")) d.TC = std::max(1, std::min(d.TC, std::atoi(e)));
-        // rows per block
+        // rows per row-pass block
         int bmax = 0;
         if (q.reg == ADMM_REG_TV) {
             while (bmax + 1 <= std::min(q.H, tv_rows_cap) && fits(bmax + 3, d.fr, row_maxe()) &&
@@ -448,6 +443,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
                 const double sn = std::sin(M_PI * (double)k / (double)N);
                 s2[b + k] = (float)(4.0 * sn * sn);
             }
+            stage_twiddles(N, tw.data() + b + N);
         }
         HIP_TRY(hipMemcpy(P->d_tw, tw.data(), sizeof(float2) * tab_len, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(P->d_s2, s2.data(), sizeof(float) * tab_len, hipMemcpyHostToDevice));
@@ -478,7 +474,9 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     base_ctx.lds_row = P->lds_row;
     base_ctx.lds_frm = P->lds_frm;
     base_ctx.tv_maxw = tv_maxw;
-    for (int i = 0; i < count; ++i) base_ctx.col_maxh = std::max(base_ctx.col_maxh, (int)probs[i].H);
+    for (int i = 0; i < count; ++i) {
+        base_ctx.col_maxh = std::max(base_ctx.col_maxh, (int)probs[i].H);
+    }
     base_ctx.col_items = P->d_items;
     base_ctx.ncol = P->ncol;
     P->all = base_ctx;

@@ -34,11 +34,59 @@ enum {
 // Column-kernel modes.
 enum { COL_SOLVE = 0, COL_BLUR = 1 };
 
-// Radix schedule of one transform length with the per-stage constants the
-// Stockham stages need: for stage s of radix R after Ns = prod of earlier
-// radices, nbf = N / R butterflies per transform, twm = N / (Ns R) twiddle
-// stride, and exact reciprocal multipliers for dividing by nbf and Ns
-// (x / d == umulhi(x, ceil(2^32 / d)) for x, d < 2^16; d == 1 is handled apart).
+// Radix schedule of a 7-smooth length n >= 2, written to out[0..nst) (returns
+// nst, or -1 if n is not 7-smooth or needs more than cap stages). Radix 8 as
+// far as the power of two allows (a leftover 2^4 as 4 x 4 rather than 8 x 2),
+// then 7, 5, 3. With at least two factors of 8 the schedule starts and ends
+// with radix 8 and the other radices go in between: the column pass then keeps
+// the last forward and the first inverse stage in registers. The host plans
+// and the compile-time transforms of the kernels share this one definition.
+__host__ __device__ constexpr int fft_schedule(int n, int* out, int cap) {
+    if (n < 2) return -1;
+    int a = 0;
+    while (n % 2 == 0) {
+        n /= 2;
+        ++a;
+    }
+    int r[40] = {};
+    int m = 0;
+    const bool ends = a >= 6;
+    if (ends) a -= 6;
+    int n8 = a / 3;
+    const int rem = a % 3;
+    const bool split = rem == 1 && n8 > 0;
+    if (split) --n8;
+    for (int i = 0; i < n8; ++i) r[m++] = 8;
+    if (split) {
+        r[m++] = 4;
+        r[m++] = 4;
+    } else if (rem == 1) {
+        r[m++] = 2;
+    } else if (rem == 2) {
+        r[m++] = 4;
+    }
+    for (int p = 7; p >= 3; p -= 2)
+        while (n % p == 0) {
+            n /= p;
+            r[m++] = p;
+        }
+    if (n != 1) return -1;
+    const int nst = m + (ends ? 2 : 0);
+    if (nst > cap) return -1;
+    int o = 0;
+    if (ends) out[o++] = 8;
+    for (int i = 0; i < m; ++i) out[o++] = r[i];
+    if (ends) out[o++] = 8;
+    return nst;
+}
+
+// Per-stage constants of one transform length: for stage s of radix R after
+// Ns = product of the earlier radices, nbf = N / R butterflies, the exact
+// reciprocal multipliers of nbf and Ns (x / d == umulhi(x, ceil(2^32 / d)) for x, d <
+// 2^16; d == 1 is handled apart) and tso, the offset of the stage's twiddles
+// in the length's stage table. The stage table holds, for each stage, entries
+// [k][r - 1] = exp(-2 pi i k r / (Ns R)) for k < Ns, 1 <= r < R (N - 1
+// entries over all stages), so that a butterfly's R - 1 twiddles are adjacent.
 struct FftPlanDev {
     int N;
     int nst;
@@ -47,7 +95,7 @@ struct FftPlanDev {
     int rad[ADMM_MAX_STAGES];
     int ns[ADMM_MAX_STAGES];
     int nbf[ADMM_MAX_STAGES];
-    int twm[ADMM_MAX_STAGES];
+    int tso[ADMM_MAX_STAGES];
     unsigned mnbf[ADMM_MAX_STAGES];
     unsigned mns[ADMM_MAX_STAGES];
 };

@@ -35,6 +35,16 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Sum ADMM_NSUM per-thread values over each wave into wsum[wave][0..NSUM) (LDS).
+__device__ __forceinline__ void wave_sums_to_lds(const double* v, double* wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < ADMM_NSUM; ++i) {
+        const double s = wave_sum(v[i]);
+        if (lane == 0) wsum[wave * ADMM_NSUM + i] = s;
+    }
+}
+
 // Sum ADMM_NSUM per-thread values over the block and write them to out[0..NSUM).
 // scratch: >= (NT/64) * ADMM_NSUM doubles of LDS.
 __device__ void block_sums_write(const double* v, double* scratch, double* out) {
@@ -117,11 +127,11 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
             const int j = lane + 64 * i;
             if (j < nbf) {
 #pragma unroll
-                for (int r = 0; r < 8; ++r) v[i][r] = S[j + r * nbf];
+                for (int r = 0; r < 8; ++r) v[i][r] = gld(S, j + r * nbf);
                 if (PF) {
 #pragma unroll
                     for (int r = 0; r < 8; ++r) {
-                        lam[PF ? i : 0][r] = L[j + r * nbf];
+                        lam[PF ? i : 0][r] = gld(L, j + r * nbf);
                         wv[PF ? i : 0][r] = s2H[j + r * nbf];
                     }
                 }
@@ -129,12 +139,18 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
         }
     }
     float2* twg = reinterpret_cast<float2*>(cl);
-    load_twiddles(twg, tw + p.fc.tw_off, H, tid, NTC);
+    load_twiddles(twg, tw + p.fc.tw_off + H, H, tid, NTC);   // the stage table
     __syncthreads();
     if (!live) return;
-    const ADMM_LDS float2* twl = (const ADMM_LDS float2*)twg;
+    const ADMM_LDS float2* stw = (const ADMM_LDS float2*)twg;
     ADMM_LDS float4* buf = (ADMM_LDS float4*)(cl + (H + 1) / 2 + wave * pidx_len(H));
     const int nst = p.fc.nst;
+    // the fixed-length transform when the column length is the instantiation's maximum
+    constexpr int NF = 64 * EPL;
+    constexpr int NST = CSched<NF>::nst();
+    static_assert(CSched<NF>::rad(0) == 8 && CSched<NF>::rad(NST - 1) == 8 && CSt<NF, 0>::NB == NB8,
+                  "fixed column length must start and end with radix 8");
+    const bool fixed = H == NF;
 
     if (fused) {
         // forward: stage 0 (radix 8, no twiddles) from registers
@@ -145,24 +161,33 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
                 dft<8, false>(v[i]);
                 if (nst > 1) {
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) lds_st(buf + pidx(8 * j + r), v[i][r]);
+                    for (int r = 0; r < 8; ++r) lds_st(buf + 9 * j + r, v[i][r]);   // pidx(8 j + r)
                 }
             }
         }
         if (nst > 1) {
-            wave_stages<EPL, false>(buf, twl, p.fc, 1, nst - 1, lane);
-            // last stage (radix 8, Ns = H / 8): output r of butterfly j is entry j + r H / 8
+            lane_exchange_fence();
+            if (fixed) {
+                c_stages<NF, 1, NST - 1, false>(buf, stw, lane);
+                c_load<NF, NST - 1>(buf, v, lane);
+                c_bfly<NF, NST - 1, false>(stw, v, lane);
+            } else {
+                wave_stages<EPL, false>(buf, stw, p.fc, 1, nst - 1, lane);
+                // last stage (radix 8, Ns = H / 8): output r of butterfly j is entry j + r H / 8
+                const ADMM_LDS float2* tl = stw + p.fc.tso[nst - 1];
 #pragma unroll
-            for (int i = 0; i < NB8; ++i) {
-                const int j = lane + 64 * i;
-                if (j < nbf) {
+                for (int i = 0; i < NB8; ++i) {
+                    const int j = lane + 64 * i;
+                    if (j < nbf) {
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) v[i][r] = lds_ld(buf + pidx(j + r * nbf));
+                        for (int r = 0; r < 8; ++r) v[i][r] = lds_ld(buf + pidx(j + r * nbf));
 #pragma unroll
-                    for (int r = 1; r < 8; ++r) v[i][r] = cmul(v[i][r], lds_ld(twl + j * r));
-                    dft<8, false>(v[i]);
+                        for (int r = 1; r < 8; ++r) v[i][r] = cmul(v[i][r], lds_ld(tl + 7 * j + r - 1));
+                        dft<8, false>(v[i]);
+                    }
                 }
             }
+            lane_exchange_fence();
         }
         // solve, then the first inverse stage (radix 8, no twiddles) on the same entries
 #pragma unroll
@@ -172,32 +197,40 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const int k1 = j + r * nbf;
-                    const float2 lm = PF ? lam[PF ? i : 0][r] : L[k1];
+                    const float2 lm = PF ? lam[PF ? i : 0][r] : gld(L, k1);
                     const float w = p.reg == REG_TV ? (PF ? wv[PF ? i : 0][r] : s2H[k1]) + w2 : 1.0f;
                     v[i][r] = col_solve(v[i][r], lm, w, mu1, mu2, ihw, mode);
                 }
                 dft<8, true>(v[i]);
                 if (nst > 1) {
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) lds_st(buf + pidx(8 * j + r), v[i][r]);
+                    for (int r = 0; r < 8; ++r) lds_st(buf + 9 * j + r, v[i][r]);
                 }
             }
         }
         if (nst > 1) {
-            wave_stages<EPL, true>(buf, twl, p.fc, 1, nst - 1, lane);
+            lane_exchange_fence();
+            if (fixed) {
+                c_stages<NF, 1, NST - 1, true>(buf, stw, lane);
+                c_load<NF, NST - 1>(buf, v, lane);
+                c_bfly<NF, NST - 1, true>(stw, v, lane);
+            } else {
+                wave_stages<EPL, true>(buf, stw, p.fc, 1, nst - 1, lane);
+                const ADMM_LDS float2* tl = stw + p.fc.tso[nst - 1];
 #pragma unroll
-            for (int i = 0; i < NB8; ++i) {
-                const int j = lane + 64 * i;
-                if (j < nbf) {
+                for (int i = 0; i < NB8; ++i) {
+                    const int j = lane + 64 * i;
+                    if (j < nbf) {
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) v[i][r] = lds_ld(buf + pidx(j + r * nbf));
+                        for (int r = 0; r < 8; ++r) v[i][r] = lds_ld(buf + pidx(j + r * nbf));
 #pragma unroll
-                    for (int r = 1; r < 8; ++r) {
-                        float2 w = lds_ld(twl + j * r);
-                        w.y = -w.y;
-                        v[i][r] = cmul(v[i][r], w);
+                        for (int r = 1; r < 8; ++r) {
+                            float2 w = lds_ld(tl + 7 * j + r - 1);
+                            w.y = -w.y;
+                            v[i][r] = cmul(v[i][r], w);
+                        }
+                        dft<8, true>(v[i]);
                     }
-                    dft<8, true>(v[i]);
                 }
             }
         }
@@ -206,21 +239,25 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
             const int j = lane + 64 * i;
             if (j < nbf) {
 #pragma unroll
-                for (int r = 0; r < 8; ++r) S[j + r * nbf] = v[i][r];
+                for (int r = 0; r < 8; ++r) gst(S, j + r * nbf, v[i][r]);
             }
         }
         return;
     }
 
     // general schedule: the whole column goes through LDS
-    for (int e = lane; e < H; e += 64) lds_st(buf + pidx(e), S[e]);
-    wave_stages<EPL, false>(buf, twl, p.fc, 0, nst, lane);
+    for (int e = lane; e < H; e += 64) lds_st(buf + pidx(e), gld(S, e));
+    lane_exchange_fence();
+    wave_stages<EPL, false>(buf, stw, p.fc, 0, nst, lane);
+    lane_exchange_fence();
     for (int e = lane; e < H; e += 64) {
         const float w = p.reg == REG_TV ? s2H[e] + w2 : 1.0f;
-        lds_st(buf + pidx(e), col_solve(lds_ld(buf + pidx(e)), L[e], w, mu1, mu2, ihw, mode));
+        lds_st(buf + pidx(e), col_solve(lds_ld(buf + pidx(e)), gld(L, e), w, mu1, mu2, ihw, mode));
     }
-    wave_stages<EPL, true>(buf, twl, p.fc, 0, nst, lane);
-    for (int e = lane; e < H; e += 64) S[e] = lds_ld(buf + pidx(e));
+    lane_exchange_fence();
+    wave_stages<EPL, true>(buf, stw, p.fc, 0, nst, lane);
+    lane_exchange_fence();
+    for (int e = lane; e < H; e += 64) gst(S, e, lds_ld(buf + pidx(e)));
 }
 
 // ------------------------------------------------------------ row helpers
@@ -234,7 +271,7 @@ __device__ __forceinline__ void load_rows_hermitian(float2* X, const float4* __r
         const int k2 = (int)udiv16((unsigned)i, (unsigned)nrows, mr);
         const int rr = i - k2 * nrows;
         const int r = wrapi(rbeg + rr, H);
-        const float4 f = S[(size_t)k2 * H + r];
+        const float4 f = gld(S, (unsigned)(k2 * H + r));
         float2* row = X + rr * W;
         if (k2 == 0 || 2 * k2 == W) {
             row[k2] = make_float2(f.x, f.z);  // real parts only at DC / Nyquist
@@ -257,8 +294,8 @@ __device__ __forceinline__ void store_rows_split(const float2* X, float4* __rest
         const float2 c = X[rr * W + k2];
         const float2 m = X[rr * W + (k2 == 0 ? 0 : W - k2)];
         // A^ = (C + conj(Cm)) / 2 ; B^ = (C - conj(Cm)) / (2 i)
-        S[(size_t)k2 * H + r0 + rr] =
-            make_float4(0.5f * (c.x + m.x), 0.5f * (c.y - m.y), 0.5f * (c.y + m.y), 0.5f * (m.x - c.x));
+        gst(S, (unsigned)(k2 * H + r0 + rr),
+            make_float4(0.5f * (c.x + m.x), 0.5f * (c.y - m.y), 0.5f * (c.y + m.y), 0.5f * (m.x - c.x)));
     }
 }
 
@@ -280,7 +317,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     const int nr = min(p.B, H - r0);
     const int nrh = nr + 2;
     const int tid = threadIdx.x;
-    const size_t n = (size_t)H * W;
+    const unsigned n = (unsigned)(H * W);   // planes hold at most 2048^2 values: 32-bit offsets
     float* dl = reinterpret_cast<float*>(X + (size_t)(p.B + 2) * W);   // 2 x W: delta^h of the row (ping-pong)
     float2* twl = reinterpret_cast<float2*>(dl + 2 * W);                 // row twiddles
 
@@ -291,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     float* dh_out = par ? p.dreg0 : p.dreg1;
     float* dv_out = dh_out + n;
 
-    load_twiddles(twl, tw + p.fr.tw_off, W, tid, NT);
+    load_twiddles(twl, tw + p.fr.tw_off + W, W, tid, NT);   // the stage table
     load_rows_hermitian(X, Sin, H, W, P, r0 - 1, nrh, tid);
     __syncthreads();
     fft_lds<MAXE, true>(X, p.fr, twl, nrh, W, tid, NT);
@@ -314,13 +351,13 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
         for (int j = 0; j < CPT; ++j) {
             const int c = tid + j * NT;
             if (c < W) {
-                const size_t g = (size_t)r * W + c;
-                pdh[j][rr] = dh_in[g];
-                pdv[j][rr] = dv_in[g];
+                const unsigned g = (unsigned)(r * W + c);
+                pdh[j][rr] = gld(dh_in, g);
+                pdv[j][rr] = gld(dv_in, g);
                 if (rr > 0) {
-                    pd1[j][rr - 1] = p.d1[g];
-                    pob[j][rr - 1] = p.mask[g] != 0;
-                    py[j][rr - 1] = p.y[g];
+                    pd1[j][rr - 1] = gld(p.d1, g);
+                    pob[j][rr - 1] = gld(p.mask, g) != 0;
+                    py[j][rr - 1] = gld(p.y, g);
                 }
             }
         }
@@ -341,11 +378,13 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                 const float zc = Xr[c].x;
                 const float zh = Xr[c + 1 == W ? 0 : c + 1].x - zc;
                 const float zv = Xn[c].x - zc;
-                const size_t g = (size_t)r * W + c;
+                const unsigned g = (unsigned)(r * W + c);
                 const float dh = pdh[j][rr], dv = pdv[j][rr];
                 const float vh = zh - dh, vv = zv - dv;
-                const float rho = sqrtf(fmaf(vh, vh, vv * vv));
-                const float sc = rho > tau ? (rho - tau) / rho : 0.0f;
+                // hardware square root and reciprocal (about 1 ulp): the prox only
+                // needs them when rho > tau > 0
+                const float rho = __builtin_amdgcn_sqrtf(fmaf(vh, vh, vv * vv));
+                const float sc = rho > tau ? (rho - tau) * __builtin_amdgcn_rcpf(rho) : 0.0f;
                 const float uh = vh * sc, uv = vv * sc;
                 const float dhn = uh - vh, dvn = uv - vv;      // d - (D z - u)
                 dlr[c] = uh + dhn;
@@ -358,13 +397,13 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                     const float v1 = Az - d1o;
                     const float u1 = obs ? fmaf(yv - v1, c1, v1) : v1;   // (y + mu1 v)/(1 + mu1) or v
                     const float d1n = u1 - v1;                           // d1 - (A z - u1)
-                    p.d1[g] = d1n;
-                    dh_out[g] = dhn;
-                    dv_out[g] = dvn;
+                    gst(p.d1, g, d1n);
+                    gst(dh_out, g, dhn);
+                    gst(dv_out, g, dvn);
                     zet[j] = u1 + d1n;
-                    if (flags & F_WRITE_X) p.x[g] = zc;
+                    if (flags & F_WRITE_X) gst(p.x, g, zc);
                     if (chk) {
-                        const float u1q = p.u1p[g], uhq = p.uregp[g], uvq = p.uregp[n + g];
+                        const float u1q = gld(p.u1p, g), uhq = gld(p.uregp, g), uvq = gld(p.uregp, n + g);
                         const float e0 = Az - u1, e1h = zh - uh, e1v = zv - uv;
                         const float f6 = u1 - u1q, f7h = uh - uhq, f7v = uv - uvq;
                         const float ry = yv - Az;
@@ -382,17 +421,17 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                         acc[11] += (double)sqrtf(fmaf(zh, zh, zv * zv));
                     }
                     if (flags & F_WRITE_UPREV) {
-                        p.u1p[g] = u1;
-                        p.uregp[g] = uh;
-                        p.uregp[n + g] = uv;
+                        gst(p.u1p, g, u1);
+                        gst(p.uregp, g, uh);
+                        gst(p.uregp, n + g, uv);
                     }
                     if (flags & F_EXPORT) {
-                        p.st_u1[g] = u1;
-                        p.st_d1[g] = d1n;
-                        p.st_ureg[g] = uh;
-                        p.st_ureg[n + g] = uv;
-                        p.st_dreg[g] = dhn;
-                        p.st_dreg[n + g] = dvn;
+                        gst(p.st_u1, g, u1);
+                        gst(p.st_d1, g, d1n);
+                        gst(p.st_ureg, g, uh);
+                        gst(p.st_ureg, n + g, uv);
+                        gst(p.st_dreg, g, dhn);
+                        gst(p.st_dreg, n + g, dvn);
                     }
                 }
             }
@@ -440,11 +479,11 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
     const int tot = nr * W;
     const float mu1 = p.mu1;
     float2* twl = X + (size_t)p.B * W;
-    load_twiddles(twl, tw + p.fr.tw_off, W, tid, NT);
+    load_twiddles(twl, tw + p.fr.tw_off + W, W, tid, NT);   // the stage table
     if (src == 0) {
-        for (int i = tid; i < tot; i += NT) X[i] = make_float2(mu1 * a[i], b[i]);
+        for (int i = tid; i < tot; i += NT) X[i] = make_float2(mu1 * gld(a, i), gld(b, i));
     } else {
-        for (int i = tid; i < tot; i += NT) X[i] = make_float2(a[i], 0.0f);
+        for (int i = tid; i < tot; i += NT) X[i] = make_float2(gld(a, i), 0.0f);
     }
     __syncthreads();
     fft_lds<MAXE, false>(X, p.fr, twl, nr, W, tid, NT);
@@ -469,14 +508,14 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     const int nr = min(p.B, H - r0);
     const int tid = threadIdx.x;
     float2* twl = X + (size_t)p.B * W;
-    load_twiddles(twl, tw + p.fr.tw_off, W, tid, NT);
+    load_twiddles(twl, tw + p.fr.tw_off + W, W, tid, NT);   // the stage table
     load_rows_hermitian(X, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
     __syncthreads();
     fft_lds<MAXE, true>(X, p.fr, twl, nr, W, tid, NT);
     const int tot = nr * W;
-    const size_t off = (size_t)r0 * W;
+    const unsigned off = (unsigned)(r0 * W);
     if (mode == 0) {
-        for (int i = tid; i < tot; i += NT) p.tmpB[off + i] = X[i].x;
+        for (int i = tid; i < tot; i += NT) gst(p.tmpB, off + i, X[i].x);
         return;
     }
     const float c1 = p.inv1pmu1;
@@ -485,20 +524,20 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
 #pragma unroll
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
     for (int i = tid; i < tot; i += NT) {
-        const size_t g = off + i;
+        const unsigned g = off + i;
         const float z = X[i].x, Az = X[i].y;
-        const float d1o = p.d1[g];
-        const bool obs = p.mask[g] != 0;
-        const float yv = obs ? p.y[g] : 0.0f;
+        const float d1o = gld(p.d1, g);
+        const bool obs = gld(p.mask, g) != 0;
+        const float yv = obs ? gld(p.y, g) : 0.0f;
         const float v1 = Az - d1o;
         const float u1 = obs ? fmaf(yv - v1, c1, v1) : v1;
         const float d1n = u1 - v1;
-        p.d1[g] = d1n;
-        p.tmpA[g] = u1 + d1n;
-        p.zpl[g] = z;
-        if (flags & F_WRITE_X) p.x[g] = z;
+        gst(p.d1, g, d1n);
+        gst(p.tmpA, g, u1 + d1n);
+        gst(p.zpl, g, z);
+        if (flags & F_WRITE_X) gst(p.x, g, z);
         if (chk) {
-            const float e0 = Az - u1, f6 = u1 - p.u1p[g], ry = yv - Az;
+            const float e0 = Az - u1, f6 = u1 - gld(p.u1p, g), ry = yv - Az;
             acc[0] += (double)(e0 * e0);
             acc[2] += (double)(Az * Az);
             acc[4] += (double)(u1 * u1);
@@ -506,10 +545,10 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
             acc[8] += (double)(d1n * d1n);
             acc[10] += obs ? (double)(ry * ry) : 0.0;
         }
-        if (flags & F_WRITE_UPREV) p.u1p[g] = u1;
+        if (flags & F_WRITE_UPREV) gst(p.u1p, g, u1);
         if (flags & F_EXPORT) {
-            p.st_u1[g] = u1;
-            p.st_d1[g] = d1n;
+            gst(p.st_u1, g, u1);
+            gst(p.st_d1, g, d1n);
         }
     }
     if (chk) block_sums_write(acc, reinterpret_cast<double*>(X), partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM);
@@ -725,10 +764,27 @@ hipError_t launch_warmstart(const LaunchCtx& L, int prob, size_t n, const float*
     return hipGetLastError();
 }
 
+// Allow dynamic LDS beyond the 64 KiB default on every pass kernel (gfx950 has
+// 160 KiB per compute unit). Returns the first error, if any.
+hipError_t allow_dynamic_lds(int bytes) {
+    const void* fns[] = {
+        reinterpret_cast<const void*>(&k_col<8>),     reinterpret_cast<const void*>(&k_col<16>),
+        reinterpret_cast<const void*>(&k_col<32>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 4, 2>),
+        reinterpret_cast<const void*>(&k_row_fwd<MAXE_ROW>),
+        reinterpret_cast<const void*>(&k_row_inv<MAXE_ROW>)};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 size_t lds_col_bytes(int H, int TC) { return col_lds(H, TC); }
 size_t lds_rowtv_bytes(int W, int B) { return rowtv_lds(W, B); }
 size_t lds_row_bytes(int W, int B) { return row_lds(W, B); }
-int row_max_elems() { return MAXE_ROW * NT; }
 int col_max_tiles() { return NTC / 64; }
 int row_maxe() { return MAXE_ROW; }
 int block_threads() { return NT; }

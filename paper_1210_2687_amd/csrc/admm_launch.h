@@ -36,6 +36,7 @@ hipError_t launch_lambda(const LaunchCtx& L, int prob, size_t HP, const float2* 
 hipError_t launch_warmstart(const LaunchCtx& L, int prob, size_t n, const float* x0, const float* p0,
                             const float* y, float* u1, float* d1, float* ureg, float* dreg);
 
+hipError_t allow_dynamic_lds(int bytes);
 size_t lds_col_bytes(int H, int TC);
 size_t lds_rowtv_bytes(int W, int B);
 size_t lds_row_bytes(int W, int B);

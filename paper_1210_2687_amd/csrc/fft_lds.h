@@ -9,9 +9,8 @@
 // length-N transform reads x[j + r N/R] (r < R), multiplies input r by the
 // twiddle w_N^{r (j mod Ns) N/(Ns R)}, takes an R-point DFT and writes output r
 // to position (j / Ns) Ns R + (j mod Ns) + r Ns. After the last stage the data
-// is in natural order. Several transforms of one block share the stages; all
-// live in one LDS buffer and each thread holds its butterflies' operands in
-// registers between the two barriers of a stage, so the transform is in place.
+// is in natural order. Each lane holds its butterflies' operands in registers
+// between the loads and the stores of a stage, so the transform is in place.
 //
 // Twiddles come from a per-length table tw[k] = exp(-2 pi i k / N) computed in
 // double precision on the host and rounded once, copied to LDS by each block;
@@ -45,6 +44,48 @@ __device__ __forceinline__ float4 lds_ld(const ADMM_LDS float4* p) {
     return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ void lds_st(ADMM_LDS float2* p, float2 a) { *(ADMM_LDS vf2*)p = vf2{a.x, a.y}; }
+
+// Global-memory accesses through pointers held in the problem descriptors: the
+// compiler cannot tell where a pointer loaded from memory points, so without
+// the address space it emits flat instructions, which also count against the
+// LDS wait counter and so stall the LDS traffic of the same wave.
+__device__ __forceinline__ float4 gld(const float4* p) {
+    const vf4 v = *(const ADMM_GLOBAL vf4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 gld(const float2* p) {
+    const vf2 v = *(const ADMM_GLOBAL vf2*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float gld(const float* p) { return *(const ADMM_GLOBAL float*)p; }
+__device__ __forceinline__ uint8_t gld(const uint8_t* p) { return *(const ADMM_GLOBAL uint8_t*)p; }
+__device__ __forceinline__ void gst(float4* p, float4 a) { *(ADMM_GLOBAL vf4*)p = vf4{a.x, a.y, a.z, a.w}; }
+__device__ __forceinline__ void gst(float2* p, float2 a) { *(ADMM_GLOBAL vf2*)p = vf2{a.x, a.y}; }
+__device__ __forceinline__ void gst(float* p, float a) { *(ADMM_GLOBAL float*)p = a; }
+// base[i] with a 32-bit byte offset (every plane and spectrum is far below
+// 4 GiB), so the access takes a scalar base plus one 32-bit vector offset
+// instead of a 64-bit vector address per element
+template <typename T> __device__ __forceinline__ ADMM_GLOBAL T* gat(T* base, unsigned i) {
+    return (ADMM_GLOBAL T*)((ADMM_GLOBAL char*)base + i * (unsigned)sizeof(T));
+}
+template <typename T> __device__ __forceinline__ const ADMM_GLOBAL T* gat(const T* base, unsigned i) {
+    return (const ADMM_GLOBAL T*)((const ADMM_GLOBAL char*)base + i * (unsigned)sizeof(T));
+}
+__device__ __forceinline__ float4 gld(const float4* base, unsigned i) {
+    const vf4 v = *(const ADMM_GLOBAL vf4*)gat(base, i);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 gld(const float2* base, unsigned i) {
+    const vf2 v = *(const ADMM_GLOBAL vf2*)gat(base, i);
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float gld(const float* base, unsigned i) { return *gat(base, i); }
+__device__ __forceinline__ uint8_t gld(const uint8_t* base, unsigned i) { return *gat(base, i); }
+__device__ __forceinline__ void gst(float4* base, unsigned i, float4 a) {
+    *(ADMM_GLOBAL vf4*)gat(base, i) = vf4{a.x, a.y, a.z, a.w};
+}
+__device__ __forceinline__ void gst(float2* base, unsigned i, float2 a) { *(ADMM_GLOBAL vf2*)gat(base, i) = vf2{a.x, a.y}; }
+__device__ __forceinline__ void gst(float* base, unsigned i, float a) { *gat(base, i) = a; }
 __device__ __forceinline__ void lds_st(ADMM_LDS float4* p, float4 a) { *(ADMM_LDS vf4*)p = vf4{a.x, a.y, a.z, a.w}; }
 
 // ----------------------------------------------------------- complex helpers
@@ -183,15 +224,16 @@ template <int R, bool INV, typename E> __device__ __forceinline__ void dft(E* v)
     else dft_odd<R, INV>(v);
 }
 
-// ----------------------------------------------------------- Stockham stage
-// buf holds `ntrans` transforms of length N at stride `tstride` (elements);
-// twl is the length-N twiddle table in LDS. Requirement (checked on the host):
-// ntrans * N / R <= (MAXE / R) * nthr. Index arithmetic is 32-bit with the
-// per-stage reciprocal multipliers of FftPlanDev (no runtime division).
+// ----------------------------------------------------------- block-level transforms
+// Used by the row passes: the `ntrans` transforms of length N of one block, at
+// stride `tstride` (elements) in LDS, share the stages; every thread takes
+// butterflies q = tid, tid + nthr, ... over all transforms, and the block
+// synchronises between the loads and the stores of a stage. Requirement
+// (checked on the host): ntrans * N / R <= (MAXE / R) * nthr. stw: the stage's
+// twiddle block (entries [k][r - 1]).
 template <int R, int MAXE, bool INV, typename E>
-__device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS float2* twl, int ntrans, int tstride,
-                                            int Ns, int nbf, int twm, unsigned mnbf, unsigned mns, int tid,
-                                            int nthr) {
+__device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS float2* stw, int ntrans, int tstride,
+                                            int Ns, int nbf, unsigned mnbf, unsigned mns, int tid, int nthr) {
     constexpr int NB = MAXE / R;
     const int total = ntrans * nbf;
     E v[NB][R];
@@ -208,12 +250,14 @@ __device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS floa
             const ADMM_LDS E* b = buf + t * tstride + j;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = lds_ld(b + r * nbf);
-            const int tws = twm * k;
+            if (Ns > 1) {
+                const ADMM_LDS float2* tk = stw + k * (R - 1);
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                float2 w = lds_ld(twl + tws * r);
-                if (INV) w.y = -w.y;
-                v[i][r] = cmul(v[i][r], w);
+                for (int r = 1; r < R; ++r) {
+                    float2 w = lds_ld(tk + r - 1);
+                    if (INV) w.y = -w.y;
+                    v[i][r] = cmul(v[i][r], w);
+                }
             }
             dft<R, INV>(v[i]);
             dst[i] = t * tstride + jq * Ns * R + k;
@@ -231,31 +275,32 @@ __device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS floa
     __syncthreads();
 }
 
-// Full transform of `ntrans` length-N sequences in LDS (natural order in and out).
-// Unnormalised in both directions. twl: the plan's twiddle table copied to LDS.
+// Full transform of `ntrans` length-N sequences in LDS (natural order in and
+// out, unnormalised); stw: the length's stage table in LDS.
 template <int MAXE, bool INV, typename E>
-__device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const float2* gtwl, int ntrans, int tstride,
+__device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const float2* gstw, int ntrans, int tstride,
                                         int tid, int nthr) {
     ADMM_LDS E* buf = (ADMM_LDS E*)gbuf;
-    const ADMM_LDS float2* twl = (const ADMM_LDS float2*)gtwl;
+    const ADMM_LDS float2* stw = (const ADMM_LDS float2*)gstw;
     const int nst = f.nst;
     for (int s = 0; s < nst; ++s) {
-        const int R = f.rad[s], Ns = f.ns[s], nbf = f.nbf[s], twm = f.twm[s];
+        const int R = f.rad[s], Ns = f.ns[s], nbf = f.nbf[s];
         const unsigned mnbf = f.mnbf[s], mns = f.mns[s];
+        const ADMM_LDS float2* t = stw + f.tso[s];
         switch (R) {
-            case 8: stockham_stage<8, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
-            case 4: stockham_stage<4, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
-            case 2: stockham_stage<2, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
-            case 3: stockham_stage<3, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
-            case 5: stockham_stage<5, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
-            case 7: stockham_stage<7, MAXE, INV>(buf, twl, ntrans, tstride, Ns, nbf, twm, mnbf, mns, tid, nthr); break;
+            case 8: stockham_stage<8, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 4: stockham_stage<4, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 2: stockham_stage<2, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 3: stockham_stage<3, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 5: stockham_stage<5, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 7: stockham_stage<7, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
             default: break;
         }
     }
 }
 
 // ----------------------------------------------------------- wave-level transforms
-// Used by the column pass: one 64-lane wave owns one length-N sequence in LDS
+// One 64-lane wave owns one length-N sequence in LDS
 // and transforms it alone (lane l takes butterflies j = l, l + 64, ... of every
 // stage). A wave's LDS instructions are executed in issue order, so a stage
 // needs no block barrier: all of a wave's loads of a stage are issued before
@@ -266,10 +311,17 @@ __device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const floa
 __host__ __device__ constexpr int pidx_len(int n) { return n + (n >> 3) + 1; }
 __device__ __forceinline__ int pidx(int e) { return e + (e >> 3); }
 
-// One radix-R stage of a wave-owned transform; NB bounds the butterflies per lane.
+// Keeps the compiler from moving LDS accesses across a stage boundary: the
+// stages of a wave-owned transform exchange data between lanes, which the
+// per-lane alias analysis cannot see.
+__device__ __forceinline__ void lane_exchange_fence() { asm volatile("" ::: "memory"); }
+
+// ---- general lengths: schedule read from the plan at run time
+// One radix-R stage; NB bounds the butterflies per lane. stw: the stage's
+// twiddle block (entries [k][r - 1]).
 template <int R, int NB, bool INV, typename E>
-__device__ __noinline__ void wave_stage(ADMM_LDS E* buf, const ADMM_LDS float2* twl, int Ns, int nbf, int twm,
-                                        unsigned mns, int lane) {
+__device__ __noinline__ void wave_stage(ADMM_LDS E* buf, const ADMM_LDS float2* stw, int Ns, int nbf, unsigned mns,
+                                        int lane) {
     E v[NB][R];
     int dst[NB];
 #pragma unroll
@@ -282,10 +334,10 @@ __device__ __noinline__ void wave_stage(ADMM_LDS E* buf, const ADMM_LDS float2* 
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = lds_ld(buf + pidx(j + r * nbf));
             if (Ns > 1) {
-                const int tws = twm * k;
+                const ADMM_LDS float2* tk = stw + k * (R - 1);
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    float2 w = lds_ld(twl + tws * r);
+                    float2 w = lds_ld(tk + r - 1);
                     if (INV) w.y = -w.y;
                     v[i][r] = cmul(v[i][r], w);
                 }
@@ -303,23 +355,154 @@ __device__ __noinline__ void wave_stage(ADMM_LDS E* buf, const ADMM_LDS float2* 
     }
 }
 
-// Stages [s0, s1) of plan f on the wave-owned sequence buf; EPL bounds N / 64.
+// Stages [s0, s1) of plan f on the wave-owned sequence buf; EPL bounds N / 64;
+// stw: the length's stage table.
 template <int EPL, bool INV, typename E>
-__device__ __forceinline__ void wave_stages(ADMM_LDS E* buf, const ADMM_LDS float2* twl, const FftPlanDev& f, int s0,
+__device__ __forceinline__ void wave_stages(ADMM_LDS E* buf, const ADMM_LDS float2* stw, const FftPlanDev& f, int s0,
                                             int s1, int lane) {
     for (int s = s0; s < s1; ++s) {
-        const int Ns = f.ns[s], nbf = f.nbf[s], twm = f.twm[s];
+        const int Ns = f.ns[s], nbf = f.nbf[s];
         const unsigned mns = f.mns[s];
+        const ADMM_LDS float2* t = stw + f.tso[s];
         switch (f.rad[s]) {
-            case 8: wave_stage<8, (EPL + 7) / 8, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
-            case 4: wave_stage<4, (EPL + 3) / 4, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
-            case 2: wave_stage<2, (EPL + 1) / 2, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
-            case 3: wave_stage<3, (EPL + 2) / 3, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
-            case 5: wave_stage<5, (EPL + 4) / 5, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
-            case 7: wave_stage<7, (EPL + 6) / 7, INV>(buf, twl, Ns, nbf, twm, mns, lane); break;
+            case 8: wave_stage<8, (EPL + 7) / 8, INV>(buf, t, Ns, nbf, mns, lane); break;
+            case 4: wave_stage<4, (EPL + 3) / 4, INV>(buf, t, Ns, nbf, mns, lane); break;
+            case 2: wave_stage<2, (EPL + 1) / 2, INV>(buf, t, Ns, nbf, mns, lane); break;
+            case 3: wave_stage<3, (EPL + 2) / 3, INV>(buf, t, Ns, nbf, mns, lane); break;
+            case 5: wave_stage<5, (EPL + 4) / 5, INV>(buf, t, Ns, nbf, mns, lane); break;
+            case 7: wave_stage<7, (EPL + 6) / 7, INV>(buf, t, Ns, nbf, mns, lane); break;
             default: break;
         }
     }
+}
+
+// ---- fixed lengths: the schedule is a compile-time constant, so every index,
+// stride and twiddle offset folds into the instruction immediates
+template <int N> struct CSched {
+    static constexpr int nst() {
+        int r[ADMM_MAX_STAGES] = {};
+        return fft_schedule(N, r, ADMM_MAX_STAGES);
+    }
+    static constexpr int rad(int s) {
+        int r[ADMM_MAX_STAGES] = {};
+        fft_schedule(N, r, ADMM_MAX_STAGES);
+        return r[s];
+    }
+    static constexpr int ns(int s) {
+        int p = 1;
+        for (int t = 0; t < s; ++t) p *= rad(t);
+        return p;
+    }
+    static constexpr int tso(int s) {
+        int o = 0;
+        for (int t = 0; t < s; ++t) o += ns(t) * (rad(t) - 1);
+        return o;
+    }
+};
+
+template <int N, int S> struct CSt {
+    static constexpr int R = CSched<N>::rad(S);
+    static constexpr int Ns = CSched<N>::ns(S);
+    static constexpr int nbf = N / R;
+    static constexpr int NB = (nbf + 63) / 64;
+    static constexpr int TSO = CSched<N>::tso(S);
+    static constexpr bool full = nbf % 64 == 0;   // every lane has NB butterflies
+};
+
+// Operands of stage S: v[i][r] = x[j + r nbf], j = lane + 64 i.
+template <int N, int S, typename E>
+__device__ __forceinline__ void c_load(const ADMM_LDS E* buf, E (&v)[CSt<N, S>::NB][CSt<N, S>::R], int lane) {
+    using T = CSt<N, S>;
+#pragma unroll
+    for (int i = 0; i < T::NB; ++i) {
+        const int j = lane + 64 * i;
+        if (T::full || j < T::nbf) {
+            if constexpr (T::nbf % 8 == 0) {
+                const ADMM_LDS E* b = buf + pidx(j);
+#pragma unroll
+                for (int r = 0; r < T::R; ++r) v[i][r] = lds_ld(b + r * (T::nbf + T::nbf / 8));
+            } else {
+#pragma unroll
+                for (int r = 0; r < T::R; ++r) v[i][r] = lds_ld(buf + pidx(j + r * T::nbf));
+            }
+        }
+    }
+}
+
+// Twiddles and the R-point DFTs of stage S (stw: the length's stage table).
+template <int N, int S, bool INV, typename E>
+__device__ __forceinline__ void c_bfly(const ADMM_LDS float2* stw, E (&v)[CSt<N, S>::NB][CSt<N, S>::R], int lane) {
+    using T = CSt<N, S>;
+#pragma unroll
+    for (int i = 0; i < T::NB; ++i) {
+        const int j = lane + 64 * i;
+        if (T::full || j < T::nbf) {
+            if constexpr (T::Ns > 1) {
+                const ADMM_LDS float2* tk = stw + T::TSO + (j % T::Ns) * (T::R - 1);
+#pragma unroll
+                for (int r = 1; r < T::R; ++r) {
+                    float2 w = lds_ld(tk + r - 1);
+                    if (INV) w.y = -w.y;
+                    v[i][r] = cmul(v[i][r], w);
+                }
+            }
+            dft<T::R, INV>(v[i]);
+        }
+    }
+}
+
+// Results of stage S: x'[(j / Ns) Ns R + j mod Ns + r Ns] = v[i][r].
+template <int N, int S, typename E>
+__device__ __forceinline__ void c_store(ADMM_LDS E* buf, const E (&v)[CSt<N, S>::NB][CSt<N, S>::R], int lane) {
+    using T = CSt<N, S>;
+#pragma unroll
+    for (int i = 0; i < T::NB; ++i) {
+        const int j = lane + 64 * i;
+        if (T::full || j < T::nbf) {
+            const int d = (j / T::Ns) * T::Ns * T::R + j % T::Ns;
+            if constexpr (T::Ns % 8 == 0) {
+                ADMM_LDS E* b = buf + pidx(d);
+#pragma unroll
+                for (int r = 0; r < T::R; ++r) lds_st(b + r * (T::Ns + T::Ns / 8), v[i][r]);
+            } else if constexpr (T::Ns == 1 && T::R == 8) {
+                ADMM_LDS E* b = buf + 9 * j;   // pidx(8 j + r) = 9 j + r
+#pragma unroll
+                for (int r = 0; r < T::R; ++r) lds_st(b + r, v[i][r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < T::R; ++r) lds_st(buf + pidx(d + r * T::Ns), v[i][r]);
+            }
+        }
+    }
+}
+
+template <int N, int S, bool INV, typename E>
+__device__ __forceinline__ void c_stage(ADMM_LDS E* buf, const ADMM_LDS float2* stw, int lane) {
+    E v[CSt<N, S>::NB][CSt<N, S>::R];
+    lane_exchange_fence();
+    c_load<N, S>(buf, v, lane);
+    c_bfly<N, S, INV>(stw, v, lane);
+    c_store<N, S>(buf, v, lane);
+    lane_exchange_fence();
+}
+
+// Stages [S0, S1) of the fixed-length transform on a wave-owned sequence.
+template <int N, int S0, int S1, bool INV, typename E>
+__device__ __forceinline__ void c_stages(ADMM_LDS E* buf, const ADMM_LDS float2* stw, int lane) {
+    if constexpr (S0 < S1) {
+        c_stage<N, S0, INV>(buf, stw, lane);
+        c_stages<N, S0 + 1, S1, INV>(buf, stw, lane);
+    }
+}
+
+// A whole transform of a wave-owned row of length N: the fixed-length code
+// when N == NF, else the general stages.
+template <int NF, int EPL, bool INV, typename E>
+__device__ __forceinline__ void wave_fft(ADMM_LDS E* buf, const ADMM_LDS float2* stw, const FftPlanDev& f, int lane) {
+    if (f.N == NF)
+        c_stages<NF, 0, CSched<NF>::nst(), INV>(buf, stw, lane);
+    else
+        wave_stages<EPL, INV>(buf, stw, f, 0, f.nst, lane);
 }
 
 // Copy the length-N twiddle table to LDS (before the first barrier of a kernel).
