@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=120, help="oracle iterations per sampled image")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the planner's heuristic tile shapes instead of the autotuner (which runs at plan time, "
+                         "outside the timed region; ADMM_TUNE_CACHE names an optional JSON cache)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event-timing pass")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (HBM counter calibration)")
@@ -141,7 +144,8 @@ def main():
     probs = [WL.config2(i % 8, size=args.size) for i in range(args.batch)]
     ys = [torch.tensor(p.y, dtype=torch.float32, device="cuda") for p in probs]
     xs = [torch.zeros_like(y) for y in ys]
-    plan = A.Plan(probs)
+    plan = A.Plan(probs, tune=not args.no_tune, cache_path=os.environ.get("ADMM_TUNE_CACHE"))
+    tiles = plan.tiles(0)
     graph = not args.no_graph
     run = lambda **kw: plan.batch(ys, xs, max_iters=args.iters, tol=0.0, graph=graph, **kw)
 
@@ -182,7 +186,9 @@ def main():
         "config": {"workload": f"TV-MD batch of {args.batch} x {args.size}x{args.size}, {args.iters} iterations",
                    "batch": args.batch, "H": args.size, "W": args.size, "iters": args.iters,
                    "kernels": "19x19 Gaussian sigma 3 (4) + 15-px motion (4)",
-                   "mask": "valid region minus 40% i.i.d. missing", "graph": graph},
+                   "mask": "valid region minus 40% i.i.d. missing", "graph": graph,
+                   "tiles": {"cols_per_block": tiles[0], "rows_per_block": tiles[1],
+                             "chosen_by": "heuristic" if args.no_tune else "autotuner"}},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     plan.close()

@@ -27,6 +27,7 @@
 #ifndef ADMM_DECONV_H
 #define ADMM_DECONV_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -153,6 +154,35 @@ typedef struct {
 
 /* Copies up to `cap` entries to out (HOST) and returns how many classes exist. */
 int32_t admm_plan_kernel_times(const admm_plan* plan, admm_kernel_time* out, int32_t cap);
+
+/* ---- FFT autotuner (tile shapes of the pass kernels) ----
+ * Like admm_deconv_plan, but the columns per column-pass block (1..4, one
+ * column per wave) and the rows per row-pass block are chosen by timing trial
+ * plans on the device (10 profiled iterations each, zero data, on hip_stream).
+ * cache_path: NULL (always measure) or a JSON file of earlier results, read if
+ * it exists and rewritten with the new entry; an entry for the batch's key
+ * (admm_tune_key with the device's architecture) is used without measuring.
+ * The tile shape does not change the iterates. Concurrent writers of one cache
+ * file may lose each other's entries. Errors: as admm_deconv_plan, and
+ * ADMM_E_INVALID for a cache file that cannot be parsed or written.            */
+admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t count, void* hip_stream,
+                                   const char* cache_path, admm_plan** out);
+
+/* Cache key of a batch: "<arch>|<shape multiset>", e.g. "gfx950|tv512x512*8"
+ * (a hash of the shape list for long ragged batches). Writes at most cap bytes
+ * (NUL-terminated) to out (HOST) and returns the key length, -1 on bad input. */
+int32_t admm_tune_key(const admm_problem* probs, int32_t count, const char* arch, char* out, size_t cap);
+
+/* Cache file access (HOST only, no device): lookup returns 1 and the entry if
+ * `key` is present, 0 if absent (or no file), -1 if the file is malformed;
+ * store inserts or replaces an entry (tc, rows >= 1; timings in microseconds). */
+int32_t admm_tune_cache_lookup(const char* path, const char* key, int32_t* tc, int32_t* rows);
+admm_status admm_tune_cache_store(const char* path, const char* key, int32_t tc, int32_t rows, double col_us,
+                                  double row_us);
+
+/* Tile shape a plan uses for problem `index` (columns per column block, rows
+ * per row block).                                                             */
+admm_status admm_plan_tiles(const admm_plan* plan, int32_t index, int32_t* tc, int32_t* rows);
 
 /* Release every resource of a plan (NULL is ignored).                         */
 void admm_plan_destroy(admm_plan* plan);

@@ -72,12 +72,20 @@ def lib_path():
 
 
 def lib():
-    """Load the HIP library (raises if it has not been built)."""
+    """Load the HIP library (raises if it has not been built).
+
+    torch is imported first: its HIP runtime then provides the library's
+    libamdhip64 (same soname), so the process has one HIP runtime and torch's
+    device pointers and streams are valid in the library's calls."""
     global _LIB
     if _LIB is None:
         path = lib_path()
         if not os.path.exists(path):
             raise ImportError(f"{path} is missing: build it with `python -m paper_1210_2687_amd.build`")
+        try:
+            import torch  # noqa: F401  (loads the process's HIP runtime)
+        except ImportError:
+            pass
         L = ctypes.CDLL(path)
         L.admm_deconv_plan.argtypes = [POINTER(admm_problem), c_int32, c_void_p, POINTER(c_void_p)]
         L.admm_deconv_solve.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(admm_state), POINTER(admm_opts),
@@ -93,6 +101,13 @@ def lib():
         L.admm_validate_problem.argtypes = [POINTER(admm_problem)]
         L.admm_plan_kernel_times.argtypes = [c_void_p, POINTER(admm_kernel_time), c_int32]
         L.admm_plan_kernel_times.restype = c_int32
+        L.admm_deconv_plan_tuned.argtypes = [POINTER(admm_problem), c_int32, c_void_p, c_char_p, POINTER(c_void_p)]
+        L.admm_tune_key.argtypes = [POINTER(admm_problem), c_int32, c_char_p, c_char_p, ctypes.c_size_t]
+        L.admm_tune_key.restype = c_int32
+        L.admm_tune_cache_lookup.argtypes = [c_char_p, c_char_p, POINTER(c_int32), POINTER(c_int32)]
+        L.admm_tune_cache_lookup.restype = c_int32
+        L.admm_tune_cache_store.argtypes = [c_char_p, c_char_p, c_int32, c_int32, c_double, c_double]
+        L.admm_plan_tiles.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]
         vp = c_void_p
         L.admm_conv3x3_pack_weights.argtypes = [vp, c_int32, c_int32, vp, vp, vp]
         L.admm_conv3x3_bf16_fwd.argtypes = [vp, c_int32, c_int32, c_int32, c_int32, vp, vp, c_int32, c_int32,
@@ -105,7 +120,8 @@ def lib():
         L.admm_ws_input.argtypes = [vp, vp, vp, c_int32, c_int32, c_int32, vp, vp]
         L.admm_ws_loss.argtypes = [vp, vp, vp, vp, vp, c_int32, c_int32, c_int32, c_float, vp, vp, vp]
         L.admm_ws_output.argtypes = [vp, vp, vp, c_int32, c_int32, c_int32, vp, vp, vp]
-        for f in ("admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
+        for f in ("admm_deconv_plan", "admm_deconv_plan_tuned", "admm_tune_cache_store", "admm_plan_tiles",
+                  "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
                   "admm_warmstart_map", "admm_fft_radices", "admm_validate_problem",
                   "admm_conv3x3_pack_weights", "admm_conv3x3_bf16_fwd", "admm_conv3x3_bf16_wgrad",
                   "admm_adam_step", "admm_ws_input", "admm_ws_loss", "admm_ws_output"):
@@ -118,7 +134,8 @@ def exported_symbols():
     """Names of the C entry points declared in include/admm_deconv.h."""
     return ["admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
             "admm_warmstart_map", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
-            "admm_validate_problem", "admm_plan_kernel_times",
+            "admm_validate_problem", "admm_plan_kernel_times", "admm_deconv_plan_tuned", "admm_tune_key",
+            "admm_tune_cache_lookup", "admm_tune_cache_store", "admm_plan_tiles",
             "admm_conv3x3_pack_weights", "admm_conv3x3_bf16_fwd", "admm_conv3x3_bf16_wgrad_workspace",
             "admm_conv3x3_bf16_wgrad", "admm_adam_step", "admm_ws_input", "admm_ws_loss", "admm_ws_output"]
 
@@ -171,6 +188,43 @@ def admm_deconv_plan(problems, stream=None):
     out = c_void_p()
     _check(lib().admm_deconv_plan(arr, len(problems), _stream_ptr(stream), ctypes.byref(out)))
     return out
+
+
+def admm_deconv_plan_tuned(problems, stream=None, cache_path=None):
+    """Plan with tile shapes chosen by the autotuner (optionally cached in a JSON file)."""
+    arr = (admm_problem * len(problems))(*problems)
+    out = c_void_p()
+    cp = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().admm_deconv_plan_tuned(arr, len(problems), _stream_ptr(stream), cp, ctypes.byref(out)))
+    return out
+
+
+def admm_tune_key(problems, arch):
+    arr = (admm_problem * len(problems))(*problems)
+    buf = ctypes.create_string_buffer(512)
+    n = lib().admm_tune_key(arr, len(problems), arch.encode(), buf, 512)
+    if n < 0:
+        raise AdmmError(ADMM_E_INVALID, "bad key request")
+    return buf.value.decode()
+
+
+def admm_tune_cache_lookup(path, key):
+    """(tc, rows) for key, None if absent; raises on a malformed file."""
+    tc, rows = c_int32(), c_int32()
+    r = lib().admm_tune_cache_lookup(os.fsencode(path), key.encode(), ctypes.byref(tc), ctypes.byref(rows))
+    if r < 0:
+        raise AdmmError(ADMM_E_INVALID, f"malformed tuning cache {path}")
+    return (tc.value, rows.value) if r == 1 else None
+
+
+def admm_tune_cache_store(path, key, tc, rows, col_us=0.0, row_us=0.0):
+    _check(lib().admm_tune_cache_store(os.fsencode(path), key.encode(), tc, rows, col_us, row_us))
+
+
+def admm_plan_tiles(plan, index):
+    tc, rows = c_int32(), c_int32()
+    _check(lib().admm_plan_tiles(plan, index, ctypes.byref(tc), ctypes.byref(rows)))
+    return tc.value, rows.value
 
 
 def admm_plan_destroy(plan):
@@ -307,14 +361,17 @@ def alloc_state(H, W, nreg=2, device="cuda"):
 class Plan:
     """Convenience owner of a plan handle built from ``workloads.Problem``-like objects."""
 
-    def __init__(self, problems, stream=None):
+    def __init__(self, problems, stream=None, tune=False, cache_path=None):
         self.problems = list(problems)
         self._cprobs = []
         for p in self.problems:
             reg = ADMM_REG_FRAME if getattr(p, "reg", "tv") == "frame" else ADMM_REG_TV
             self._cprobs.append(make_problem(p.kernel, p.mask, p.lam, p.mu1, p.mu2, reg, getattr(p, "levels", 0)))
         self.nregs = [3 * p.levels + 1 if getattr(p, "reg", "tv") == "frame" else 2 for p in self.problems]
-        self.handle = admm_deconv_plan(self._cprobs, stream)
+        if tune:
+            self.handle = admm_deconv_plan_tuned(self._cprobs, stream, cache_path)
+        else:
+            self.handle = admm_deconv_plan(self._cprobs, stream)
 
     def solve(self, y, x, state=None, **kw):
         return admm_deconv_solve(self.handle, y, x, state, nreg=self.nregs[0], **kw)
@@ -327,6 +384,9 @@ class Plan:
 
     def kernel_times(self):
         return admm_plan_kernel_times(self.handle)
+
+    def tiles(self, index=0):
+        return admm_plan_tiles(self.handle, index)
 
     def warmstart_map(self, index, x0, p0, y, state):
         admm_warmstart_map(self.handle, index, x0, p0, y, state)

@@ -115,8 +115,15 @@ void stage_twiddles(int N, float2* out) {
 
 }  // namespace
 
+// Tile shape forced on every problem of a plan (0 = the planner's heuristic):
+// columns per column-pass block and rows per row-pass block.
+struct TileChoice {
+    int tc = 0, b = 0;
+};
+
 struct admm_plan {
     hipStream_t stream = nullptr;
+    TileChoice tile;                      // what the plan was built with
     int count = 0;
     std::vector<admm_problem> probs;      // copies (host pointers cleared)
     std::vector<ProbDesc> hd;             // host copy of the descriptors
@@ -203,7 +210,8 @@ extern "C" void admm_plan_destroy(admm_plan* P) {
     delete P;
 }
 
-static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t count, void* hip_stream);
+static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t count, void* hip_stream,
+                              TileChoice tile);
 
 extern "C" admm_status admm_deconv_plan(const admm_problem* probs, int32_t count, void* hip_stream, admm_plan** out) {
     if (!out) return fail(ADMM_E_INVALID, "null output pointer");
@@ -217,7 +225,7 @@ extern "C" admm_status admm_deconv_plan(const admm_problem* probs, int32_t count
         }
     }
     admm_plan* P = new admm_plan();
-    admm_status s = build_plan(P, probs, count, hip_stream);
+    admm_status s = build_plan(P, probs, count, hip_stream, TileChoice{});
     if (s != ADMM_OK) {
         admm_plan_destroy(P);
         return s;
@@ -226,7 +234,8 @@ extern "C" admm_status admm_deconv_plan(const admm_problem* probs, int32_t count
     return ADMM_OK;
 }
 
-static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t count, void* hip_stream) {
+static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t count, void* hip_stream,
+                              TileChoice tile) {
     auto bail = [](admm_status s) { return s; };
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -289,6 +298,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         if (tcmax < 1)
             return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: column length %d does not fit a block", i, q.H));
         d.TC = std::min(tcmax, d.P);
+        if (tile.tc > 0) d.TC = std::min(d.TC, tile.tc);
         if (const char* e = std::getenv("ADMM_TC")) d.TC = std::max(1, std::min(d.TC, std::atoi(e)));
         // rows per row-pass block
         int bmax = 0;
@@ -302,6 +312,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         if (bmax < 1) return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: row length %d does not fit a block", i, q.W));
         const int bmin = q.reg == ADMM_REG_TV ? std::min(bmax, 4) : 1;
         d.B = std::max(bmin, std::min(bmax, (q.H + per - 1) / per));
+        if (tile.b > 0) d.B = std::min(bmax, tile.b);
         if (const char* e = std::getenv("ADMM_ROWS")) d.B = std::max(1, std::min(bmax, std::atoi(e)));
         d.nrowblk = (q.H + d.B - 1) / d.B;
         d.ncolblk = (d.P + d.TC - 1) / d.TC;
@@ -800,4 +811,334 @@ extern "C" int32_t admm_plan_kernel_times(const admm_plan* P, admm_kernel_time* 
         out[i].total_ms = P->prof_ms[i];
     }
     return 6;
+}
+
+// ------------------------------------------------------------ FFT autotuner
+// Chooses the tile shapes of the two pass kernels by measurement: columns per
+// column-pass block (one column per wave) and rows per row-pass block. The
+// passes are independent (a column tile changes only the column kernel, a
+// row count only the row kernels), so each trial plan carries one candidate
+// of each and both are read from the same profiled run. Results are cached in
+// a JSON object keyed by device architecture and the batch's shape multiset:
+//   {"gfx950|tv512x512*8": {"tc": 4, "rows": 8, "col_us": 16.1, "row_us": 30.6}}
+// The tile shape changes which thread computes what, never the arithmetic of
+// an element, so the iterates do not depend on it.
+namespace {
+
+struct TuneEntry {
+    int tc = 0, rows = 0;
+    double col_us = 0.0, row_us = 0.0;
+};
+
+void skip_ws(const char*& p) {
+    while (*p == ' ' || *p == '\n' || *p == '\r' || *p == '\t') ++p;
+}
+bool parse_str(const char*& p, std::string& out) {
+    skip_ws(p);
+    if (*p != '"') return false;
+    ++p;
+    out.clear();
+    while (*p && *p != '"') {
+        if (*p == '\\') return false;   // keys and fields never need escapes
+        out.push_back(*p++);
+    }
+    if (*p != '"') return false;
+    ++p;
+    return true;
+}
+bool parse_char(const char*& p, char c) {
+    skip_ws(p);
+    if (*p != c) return false;
+    ++p;
+    return true;
+}
+
+// Parse the cache text; false if it is not an object of objects of numbers.
+bool parse_cache(const std::string& text, std::map<std::string, TuneEntry>& out) {
+    const char* p = text.c_str();
+    if (!parse_char(p, '{')) return false;
+    skip_ws(p);
+    if (*p == '}') return true;
+    for (;;) {
+        std::string key;
+        if (!parse_str(p, key) || !parse_char(p, ':') || !parse_char(p, '{')) return false;
+        TuneEntry e;
+        skip_ws(p);
+        if (*p != '}') {
+            for (;;) {
+                std::string f;
+                if (!parse_str(p, f) || !parse_char(p, ':')) return false;
+                skip_ws(p);
+                char* end = nullptr;
+                const double v = std::strtod(p, &end);
+                if (end == p) return false;
+                p = end;
+                if (f == "tc") e.tc = (int)v;
+                else if (f == "rows") e.rows = (int)v;
+                else if (f == "col_us") e.col_us = v;
+                else if (f == "row_us") e.row_us = v;
+                skip_ws(p);
+                if (*p == ',') {
+                    ++p;
+                    continue;
+                }
+                break;
+            }
+        }
+        if (!parse_char(p, '}')) return false;
+        out[key] = e;
+        skip_ws(p);
+        if (*p == ',') {
+            ++p;
+            continue;
+        }
+        break;
+    }
+    return parse_char(p, '}');
+}
+
+std::string format_cache(const std::map<std::string, TuneEntry>& m) {
+    std::string s = "{\n";
+    size_t i = 0;
+    for (const auto& kv : m) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "{\"tc\": %d, \"rows\": %d, \"col_us\": %.3f, \"row_us\": %.3f}", kv.second.tc,
+                      kv.second.rows, kv.second.col_us, kv.second.row_us);
+        s += "  \"" + kv.first + "\": " + buf + (++i < m.size() ? ",\n" : "\n");
+    }
+    return s + "}\n";
+}
+
+// 0: read (or absent: empty map); -1: unreadable or malformed
+int read_cache(const char* path, std::map<std::string, TuneEntry>& out) {
+    out.clear();
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return 0;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    return parse_cache(text, out) ? 0 : -1;
+}
+
+int write_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return -1;
+    const std::string s = format_cache(m);
+    const bool ok = std::fwrite(s.data(), 1, s.size(), f) == s.size();
+    if (std::fclose(f) != 0 || !ok) return -1;
+    return std::rename(tmp.c_str(), path) == 0 ? 0 : -1;
+}
+
+std::string make_key(const admm_problem* probs, int count, const char* arch) {
+    std::vector<std::string> sh;
+    for (int i = 0; i < count; ++i) {
+        char b[48];
+        if (probs[i].reg == ADMM_REG_FRAME)
+            std::snprintf(b, sizeof b, "fa%dx%dj%d", (int)probs[i].H, (int)probs[i].W, (int)probs[i].levels);
+        else
+            std::snprintf(b, sizeof b, "tv%dx%d", (int)probs[i].H, (int)probs[i].W);
+        sh.push_back(b);
+    }
+    std::sort(sh.begin(), sh.end());
+    std::string list;
+    for (size_t i = 0; i < sh.size();) {
+        size_t j = i;
+        while (j < sh.size() && sh[j] == sh[i]) ++j;
+        if (!list.empty()) list += ",";
+        list += sh[i] + "*" + std::to_string(j - i);
+        i = j;
+    }
+    if (list.size() > 160) {   // long ragged batches: a hash of the shape list
+        unsigned long long h = 1469598103934665603ull;
+        for (unsigned char c : list) h = (h ^ c) * 1099511628211ull;
+        char b[40];
+        std::snprintf(b, sizeof b, "h%016llx*%d", h, count);
+        list = b;
+    }
+    return std::string(arch) + "|" + list;
+}
+
+// Time one trial plan: per-launch microseconds of the column kernel and of
+// the row-side kernels (TV row pass, or FA inverse rows + frame + forward rows).
+admm_status time_plan(admm_plan* P, const float* const* y, float* const* x, double* col_us, double* row_us) {
+    admm_opts o{};
+    o.max_iters = 10;
+    o.tol = 0.0;
+    o.check_every = 1 << 20;
+    o.flags = ADMM_FLAG_PROFILE;
+    std::vector<admm_info> infos(P->count);
+    double best_c = 1e300, best_r = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+        admm_status s = run(P, y, x, nullptr, &o, infos.data());
+        if (s != ADMM_OK) return s;
+        if (rep == 0) continue;   // the first run warms caches and code
+        const double c = P->prof_n[0] ? P->prof_ms[0] / P->prof_n[0] * 1e3 : 0.0;
+        double r = 0.0;
+        for (int k = 1; k <= 4; ++k)
+            if (P->prof_n[k]) r += P->prof_ms[k] / P->prof_n[k] * 1e3;
+        best_c = std::min(best_c, c);
+        best_r = std::min(best_r, r);
+    }
+    *col_us = best_c;
+    *row_us = best_r;
+    return ADMM_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t admm_tune_key(const admm_problem* probs, int32_t count, const char* arch, char* out, size_t cap) {
+    if (!probs || count < 1 || !arch) return -1;
+    const std::string k = make_key(probs, count, arch);
+    if (out && cap > 0) std::snprintf(out, cap, "%s", k.c_str());
+    return (int32_t)k.size();
+}
+
+extern "C" int32_t admm_tune_cache_lookup(const char* path, const char* key, int32_t* tc, int32_t* rows) {
+    if (!path || !key) return -1;
+    std::map<std::string, TuneEntry> m;
+    if (read_cache(path, m) != 0) return -1;
+    auto it = m.find(key);
+    if (it == m.end()) return 0;
+    if (tc) *tc = it->second.tc;
+    if (rows) *rows = it->second.rows;
+    return 1;
+}
+
+extern "C" admm_status admm_tune_cache_store(const char* path, const char* key, int32_t tc, int32_t rows,
+                                             double col_us, double row_us) {
+    if (!path || !key || tc < 1 || rows < 1) return fail(ADMM_E_INVALID, "bad cache entry");
+    for (const char* c = key; *c; ++c)
+        if (*c == '"' || *c == '\\' || (unsigned char)*c < 0x20) return fail(ADMM_E_INVALID, "bad cache key");
+    std::map<std::string, TuneEntry> m;
+    if (read_cache(path, m) != 0) return fail(ADMM_E_INVALID, "tuning cache %s is not a cache file", path);
+    TuneEntry e;
+    e.tc = tc;
+    e.rows = rows;
+    e.col_us = col_us;
+    e.row_us = row_us;
+    m[key] = e;
+    if (write_cache(path, m) != 0) return fail(ADMM_E_INVALID, "cannot write tuning cache %s", path);
+    return ADMM_OK;
+}
+
+extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t count, void* hip_stream,
+                                              const char* cache_path, admm_plan** out) {
+    if (!out) return fail(ADMM_E_INVALID, "null output pointer");
+    *out = nullptr;
+    if (!probs || count < 1) return fail(ADMM_E_INVALID, "need at least one problem");
+    for (int i = 0; i < count; ++i) {
+        admm_status s = validate(probs[i]);
+        if (s != ADMM_OK) {
+            g_err = "problem " + std::to_string(i) + ": " + g_err;
+            return s;
+        }
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    const std::string key = make_key(probs, count, arch.c_str());
+
+    TileChoice best;
+    std::map<std::string, TuneEntry> cache;
+    bool have = false;
+    if (cache_path) {
+        if (read_cache(cache_path, cache) != 0)
+            return fail(ADMM_E_INVALID, "tuning cache %s is not a cache file", cache_path);
+        auto it = cache.find(key);
+        if (it != cache.end() && it->second.tc > 0 && it->second.rows > 0) {
+            best.tc = it->second.tc;
+            best.b = it->second.rows;
+            have = true;
+        }
+    }
+    if (!have) {
+        // trial data: one shared zero observation, one output per problem
+        size_t nmax = 0, ntot = 0;
+        for (int i = 0; i < count; ++i) {
+            const size_t n = (size_t)probs[i].H * probs[i].W;
+            nmax = std::max(nmax, n);
+            ntot += n;
+        }
+        float* dy = nullptr;
+        float* dx = nullptr;
+        if (hipMalloc(&dy, nmax * sizeof(float)) != hipSuccess || hipMalloc(&dx, ntot * sizeof(float)) != hipSuccess) {
+            (void)hipFree(dy);
+            return fail(ADMM_E_NOMEM, "autotuner: no device memory for trial data");
+        }
+        std::vector<const float*> yv(count, dy);
+        std::vector<float*> xv(count);
+        size_t off = 0;
+        for (int i = 0; i < count; ++i) {
+            xv[i] = dx + off;
+            off += (size_t)probs[i].H * probs[i].W;
+        }
+        admm_status st = hipMemsetAsync(dy, 0, nmax * sizeof(float), (hipStream_t)hip_stream) == hipSuccess
+                             ? ADMM_OK
+                             : fail(ADMM_E_DEVICE, "autotuner: memset failed");
+        const int tcs[] = {1, 2, 3, 4};
+        const int bs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
+        const int ntc = 4, nb = 10;
+        double best_c = 1e300, best_r = 1e300;
+        TuneEntry rec;
+        for (int k = 0; k < std::max(ntc, nb) && st == ADMM_OK; ++k) {
+            TileChoice t;
+            t.tc = tcs[std::min(k, ntc - 1)];
+            t.b = bs[std::min(k, nb - 1)];
+            admm_plan* P = new admm_plan();
+            admm_status s = build_plan(P, probs, count, hip_stream, t);
+            if (s == ADMM_OK) {
+                double c = 0, r = 0;
+                s = time_plan(P, yv.data(), xv.data(), &c, &r);
+                if (s == ADMM_OK) {
+                    // the requested shapes are recorded: planning with them again
+                    // reproduces this trial (the planner clamps them the same way)
+                    if (k < ntc && c < best_c) {
+                        best_c = c;
+                        best.tc = t.tc;
+                    }
+                    if (k < nb && r < best_r) {
+                        best_r = r;
+                        best.b = t.b;
+                    }
+                }
+            }
+            admm_plan_destroy(P);
+            if (s == ADMM_E_DEVICE || s == ADMM_E_NOMEM) st = s;
+        }
+        (void)hipStreamSynchronize((hipStream_t)hip_stream);
+        (void)hipFree(dy);
+        (void)hipFree(dx);
+        if (st != ADMM_OK) return st;
+        if (best.tc < 1 || best.b < 1) return fail(ADMM_E_UNSUPPORTED, "autotuner: no tile shape could be planned");
+        rec.tc = best.tc;
+        rec.rows = best.b;
+        rec.col_us = best_c;
+        rec.row_us = best_r;
+        if (cache_path) {
+            cache[key] = rec;
+            if (write_cache(cache_path, cache) != 0)
+                return fail(ADMM_E_INVALID, "cannot write tuning cache %s", cache_path);
+        }
+    }
+    admm_plan* P = new admm_plan();
+    admm_status s = build_plan(P, probs, count, hip_stream, best);
+    if (s != ADMM_OK) {
+        admm_plan_destroy(P);
+        return s;
+    }
+    *out = P;
+    return ADMM_OK;
+}
+
+extern "C" admm_status admm_plan_tiles(const admm_plan* P, int32_t index, int32_t* tc, int32_t* rows) {
+    if (!P || index < 0 || index >= P->count) return fail(ADMM_E_INVALID, "bad plan or index");
+    if (tc) *tc = P->hd[index].TC;
+    if (rows) *rows = P->hd[index].B;
+    return ADMM_OK;
 }
