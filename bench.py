@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -97,6 +99,70 @@ def cpu_baseline(iters):
                       f"{iters} iterations each, {dt:.1f} s"}
 
 
+def cnn_flops_per_px(train=False):
+    """Multiply-adds x 2 of the warm-start network per pixel (forward), and of
+    one training step (forward, input gradients of layers 2..6, weight gradients)."""
+    from paper_1210_2687_amd.warmstart import CHANNELS
+    layers = [(CHANNELS[i], CHANNELS[i + 1]) for i in range(len(CHANNELS) - 1)]
+    fwd = sum(2 * 9 * ci * co for ci, co in layers)
+    if not train:
+        return fwd
+    dgrad = sum(2 * 9 * ci * co for ci, co in layers[1:])
+    return 2 * fwd + dgrad
+
+
+def warm_start_eval(n_train, steps, n_eval, train_size, eval_size, log):
+    """Train the warm-start network on GPU-generated targets, then time
+    cold and warm solves to tolerance 1e-4 on unseen problems."""
+    import torch
+    from paper_1210_2687_amd import warmstart as WS
+    t0 = time.perf_counter()
+    parts = [WS.targets(WS.problems(b, min(32, n_train - b), train_size)) for b in range(0, n_train, 32)]
+    data = tuple(torch.cat([d[k] for d in parts]) for k in range(5))
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = WS.WarmStartNet(seed=0)
+    t0 = time.perf_counter()
+    hist = WS.train(net, data, steps=steps, batch=8)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"warm start: targets {t_data:.1f} s, {steps} training steps {t_train:.1f} s, "
+        f"loss {np.mean(hist[:10]):.3e} -> {np.mean(hist[-10:]):.3e}")
+    # network throughput: inference on a 4 x eval_size^2 batch, one training step on 8 x train_size^2
+    ev = WS.problems(10 ** 6, n_eval, eval_size)
+    y, m, e = WS.to_device(ev[:4])
+    for _ in range(2):
+        net.predict(y, m, e)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        net.predict(y, m, e)
+    torch.cuda.synchronize()
+    fwd_s = (time.perf_counter() - t0) / reps
+    fwd_tf = cnn_flops_per_px() * y.numel() / fwd_s / 1e12
+    ii = torch.arange(8, device="cuda")
+    batch = [t[ii].contiguous() for t in data]
+    net.train_step(*batch, lr=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.train_step(*batch, lr=0.0, want_loss=False)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / reps
+    step_tf = cnn_flops_per_px(train=True) * batch[0].numel() / step_s / 1e12
+    rows = WS.evaluate(net, ev)
+    s = WS.summary(rows)
+    s.update({"tol": 1e-4, "check_every": 10, "eval": f"{n_eval} unseen {eval_size}x{eval_size} problems",
+              "train": f"{n_train} problems {train_size}x{train_size}, {steps} Adam steps of 8, "
+                       f"{t_data + t_train:.1f} s incl. target generation",
+              "net_params": net.nparams,
+              "cnn_fwd_tflops": round(fwd_tf, 2), "cnn_train_step_tflops": round(step_tf, 2),
+              "bf16_peak_tflops": 2500.0, "timing": "wall clock per problem; warm includes the network and the "
+                                                    "state mapping; both solve on a hipGraph"})
+    return s
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +173,10 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--cpu-iters", type=int, default=120, help="oracle iterations per sampled image")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start training and evaluation")
+    ap.add_argument("--ws-train", type=int, default=256, help="warm-start training problems (256x256)")
+    ap.add_argument("--ws-steps", type=int, default=2000, help="warm-start training steps")
+    ap.add_argument("--ws-eval", type=int, default=32, help="warm-start evaluation problems (512x512)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the planner's heuristic tile shapes instead of the autotuner (which runs at plan time, "
@@ -177,6 +247,8 @@ def main():
                     "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": alg[dom],
                     "kernel_us": {k: round(v[1] / max(v[0], 1) * 1e3, 3) for k, v in kt.items() if v[0]}}
 
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    ws = None if args.no_warm_start else warm_start_eval(args.ws_train, args.ws_steps, args.ws_eval, 256, 512, log)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_iters)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpx*iter/s", "n_gpus": 1,
@@ -189,7 +261,7 @@ def main():
                    "mask": "valid region minus 40% i.i.d. missing", "graph": graph,
                    "tiles": {"cols_per_block": tiles[0], "rows_per_block": tiles[1],
                              "chosen_by": "heuristic" if args.no_tune else "autotuner"}},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "warm_start": ws,
     }
     plan.close()
     print(json.dumps(out), flush=True)
