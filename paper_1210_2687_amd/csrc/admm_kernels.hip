@@ -262,9 +262,11 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
 
 // ------------------------------------------------------------ row helpers
 // Load transposed half-spectrum rows [rbeg, rbeg + nrows) (wrapping mod H) as
-// full complex rows Y = z^ + i A z^ (Hermitian completion of both halves).
-__device__ __forceinline__ void load_rows_hermitian(float2* X, const float4* __restrict__ S, int H, int W, int P,
-                                                    int rbeg, int nrows, int tid) {
+// full complex rows Y = z^ + i A z^ (Hermitian completion of both halves), row
+// rr at X + rr pitch, padded (pidx) if PAD.
+template <bool PAD>
+__device__ __forceinline__ void load_rows_hermitian(float2* X, int pitch, const float4* __restrict__ S, int H, int W,
+                                                    int P, int rbeg, int nrows, int tid) {
     const int tot = P * nrows;
     const unsigned mr = div_magic((unsigned)nrows);
     for (int i = tid; i < tot; i += NT) {
@@ -272,27 +274,30 @@ __device__ __forceinline__ void load_rows_hermitian(float2* X, const float4* __r
         const int rr = i - k2 * nrows;
         const int r = wrapi(rbeg + rr, H);
         const float4 f = gld(S, (unsigned)(k2 * H + r));
-        float2* row = X + rr * W;
+        float2* row = X + rr * pitch;
         if (k2 == 0 || 2 * k2 == W) {
-            row[k2] = make_float2(f.x, f.z);  // real parts only at DC / Nyquist
+            row[PAD ? pidx(k2) : k2] = make_float2(f.x, f.z);  // real parts only at DC / Nyquist
         } else {
-            row[k2] = make_float2(f.x - f.w, f.y + f.z);
-            if (k2 <= W - P) row[W - k2] = make_float2(f.x + f.w, f.z - f.y);
+            row[PAD ? pidx(k2) : k2] = make_float2(f.x - f.w, f.y + f.z);
+            if (k2 <= W - P) row[PAD ? pidx(W - k2) : W - k2] = make_float2(f.x + f.w, f.z - f.y);
         }
     }
 }
 
 // Split the row DFTs C of (a + i b) in X rows [0, nrows) into the half spectra of
 // a and b and store them transposed at rows [r0, r0 + nrows).
-__device__ __forceinline__ void store_rows_split(const float2* X, float4* __restrict__ S, int H, int W, int P,
-                                                 int r0, int nrows, int tid) {
+template <bool PAD>
+__device__ __forceinline__ void store_rows_split(const float2* X, int pitch, float4* __restrict__ S, int H, int W,
+                                                 int P, int r0, int nrows, int tid) {
     const int tot = P * nrows;
     const unsigned mr = div_magic((unsigned)nrows);
     for (int i = tid; i < tot; i += NT) {
         const int k2 = (int)udiv16((unsigned)i, (unsigned)nrows, mr);
         const int rr = i - k2 * nrows;
-        const float2 c = X[rr * W + k2];
-        const float2 m = X[rr * W + (k2 == 0 ? 0 : W - k2)];
+        const float2* row = X + rr * pitch;
+        const int km = k2 == 0 ? 0 : W - k2;
+        const float2 c = row[PAD ? pidx(k2) : k2];
+        const float2 m = row[PAD ? pidx(km) : km];
         // A^ = (C + conj(Cm)) / 2 ; B^ = (C - conj(Cm)) / (2 i)
         gst(S, (unsigned)(k2 * H + r0 + rr),
             make_float4(0.5f * (c.x + m.x), 0.5f * (c.y - m.y), 0.5f * (c.y + m.y), 0.5f * (m.x - c.x)));
@@ -318,7 +323,8 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     const int nrh = nr + 2;
     const int tid = threadIdx.x;
     const unsigned n = (unsigned)(H * W);   // planes hold at most 2048^2 values: 32-bit offsets
-    float* dl = reinterpret_cast<float*>(X + (size_t)(p.B + 2) * W);   // 2 x W: delta^h of the row (ping-pong)
+    const int pitch = row_pitch(W);                                        // padded rows (pidx)
+    float* dl = reinterpret_cast<float*>(X + (size_t)(p.B + 2) * pitch);   // 2 x W: delta^h of the row (ping-pong)
     float2* twl = reinterpret_cast<float2*>(dl + 2 * W);                 // row twiddles
 
     const float4* Sin = par ? p.spec1 : p.spec0;
@@ -329,9 +335,9 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     float* dv_out = dh_out + n;
 
     load_twiddles(twl, tw + p.fr.tw_off + W, W, tid, NT);   // the stage table
-    load_rows_hermitian(X, Sin, H, W, P, r0 - 1, nrh, tid);
+    load_rows_hermitian<true>(X, pitch, Sin, H, W, P, r0 - 1, nrh, tid);
     __syncthreads();
-    fft_lds<MAXE, true>(X, p.fr, twl, nrh, W, tid, NT);
+    rows_fft<NT * CPT, NT, RB + 2, MAXE, true>(X, pitch, p.fr, twl, nrh, tid);
     // X[rr][c] = z + i A z for row r0 - 1 + rr
 
     const float tau = p.tau, mu2 = p.mu2, c1 = p.inv1pmu1;
@@ -368,16 +374,17 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     for (int rr = 0; rr <= RB; ++rr) {
         if (rr > nr) break;
         const int r = wrapi(r0 - 1 + rr, H);
-        const float2* Xr = X + rr * W;
-        const float2* Xn = X + (rr + 1) * W;
+        const float2* Xr = X + rr * pitch;
+        const float2* Xn = Xr + pitch;
         float* dlr = dl + (rr & 1) * W;
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
             const int c = tid + j * NT;
             if (c < W) {
-                const float zc = Xr[c].x;
-                const float zh = Xr[c + 1 == W ? 0 : c + 1].x - zc;
-                const float zv = Xn[c].x - zc;
+                const float2 xc = Xr[pidx(c)];
+                const float zc = xc.x;
+                const float zh = Xr[pidx(c + 1 == W ? 0 : c + 1)].x - zc;
+                const float zv = Xn[pidx(c)].x - zc;
                 const unsigned g = (unsigned)(r * W + c);
                 const float dh = pdh[j][rr], dv = pdv[j][rr];
                 const float vh = zh - dh, vv = zv - dv;
@@ -390,7 +397,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                 dlr[c] = uh + dhn;
                 dvc[j] = uv + dvn;
                 if (rr > 0) {
-                    const float Az = Xr[c].y;
+                    const float Az = xc.y;
                     const float d1o = pd1[j][rr - 1];
                     const bool obs = pob[j][rr - 1];
                     const float yv = obs ? py[j][rr - 1] : 0.0f;
@@ -438,13 +445,13 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
         }
         __syncthreads();
         if (rr > 0) {
-            float2* Xw = X + rr * W;
+            float2* Xw = X + rr * pitch;
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
                 const int c = tid + j * NT;
                 if (c < W) {
                     const float s = mu2 * ((dlr[c == 0 ? W - 1 : c - 1] - dlr[c]) + (dvp[j] - dvc[j]));
-                    Xw[c] = make_float2(p.mu1 * zet[j], s);
+                    Xw[pidx(c)] = make_float2(p.mu1 * zet[j], s);
                 }
             }
         }
@@ -453,8 +460,8 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     }
     __syncthreads();
     if (flags & F_FORWARD) {
-        fft_lds<MAXE, false>(X + W, p.fr, twl, nr, W, tid, NT);
-        store_rows_split(X + W, Sout, H, W, P, r0, nr, tid);
+        rows_fft<NT * CPT, NT, RB, MAXE, false>(X + pitch, pitch, p.fr, twl, nr, tid);
+        store_rows_split<true>(X + pitch, pitch, Sout, H, W, P, r0, nr, tid);
     }
     if (chk) block_sums_write(acc, reinterpret_cast<double*>(X), partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM);
 }
@@ -486,8 +493,8 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
         for (int i = tid; i < tot; i += NT) X[i] = make_float2(gld(a, i), 0.0f);
     }
     __syncthreads();
-    fft_lds<MAXE, false>(X, p.fr, twl, nr, W, tid, NT);
-    store_rows_split(X, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
+    fft_lds<MAXE, false, false>(X, p.fr, twl, nr, W, tid, NT);
+    store_rows_split<false>(X, W, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
 }
 
 // ------------------------------------------------------------ spectrum rows -> planes
@@ -509,9 +516,9 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     const int tid = threadIdx.x;
     float2* twl = X + (size_t)p.B * W;
     load_twiddles(twl, tw + p.fr.tw_off + W, W, tid, NT);   // the stage table
-    load_rows_hermitian(X, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
+    load_rows_hermitian<false>(X, W, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
     __syncthreads();
-    fft_lds<MAXE, true>(X, p.fr, twl, nr, W, tid, NT);
+    fft_lds<MAXE, true, false>(X, p.fr, twl, nr, W, tid, NT);
     const int tot = nr * W;
     const unsigned off = (unsigned)(r0 * W);
     if (mode == 0) {
@@ -689,7 +696,8 @@ static size_t col_lds(int H, int TC) {
     return (size_t)((H + 1) / 2) * sizeof(float4) + (size_t)TC * pidx_len(H) * sizeof(float4);
 }
 static size_t rowtv_lds(int W, int B) {
-    const size_t b = (size_t)(B + 2) * W * sizeof(float2) + 2 * (size_t)W * sizeof(float) + (size_t)W * sizeof(float2);
+    const size_t b = (size_t)(B + 2) * row_pitch(W) * sizeof(float2) + 2 * (size_t)W * sizeof(float) +
+                     (size_t)W * sizeof(float2);
     const size_t scratch = NT / 64 * ADMM_NSUM * sizeof(double);   // block partial sums reuse the buffer
     return b > scratch ? b : scratch;
 }

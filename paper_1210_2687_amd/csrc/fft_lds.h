@@ -224,6 +224,16 @@ template <int R, bool INV, typename E> __device__ __forceinline__ void dft(E* v)
     else dft_odd<R, INV>(v);
 }
 
+// Padded layout of a sequence in LDS: element e at pidx(e) = e + e / 8, so
+// that the stride-8 element accesses of a first radix-8 stage fall in
+// distinct banks.
+__host__ __device__ constexpr int pidx_len(int n) { return n + (n >> 3) + 1; }
+__device__ __forceinline__ int pidx(int e) { return e + (e >> 3); }
+// Pitch of padded rows that several lanes visit at one column (a transposing
+// load or store): pidx_len rounded up to 4 modulo 32 complex values, so that
+// eight consecutive rows start on eight disjoint groups of banks.
+__host__ __device__ constexpr int row_pitch(int n) { return pidx_len(n) + ((36 - pidx_len(n) % 32) % 32); }
+
 // ----------------------------------------------------------- block-level transforms
 // Used by the row passes: the `ntrans` transforms of length N of one block, at
 // stride `tstride` (elements) in LDS, share the stages; every thread takes
@@ -231,25 +241,26 @@ template <int R, bool INV, typename E> __device__ __forceinline__ void dft(E* v)
 // synchronises between the loads and the stores of a stage. Requirement
 // (checked on the host): ntrans * N / R <= (MAXE / R) * nthr. stw: the stage's
 // twiddle block (entries [k][r - 1]).
-template <int R, int MAXE, bool INV, typename E>
+template <int R, int MAXE, bool INV, bool PAD, typename E>
 __device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS float2* stw, int ntrans, int tstride,
                                             int Ns, int nbf, unsigned mnbf, unsigned mns, int tid, int nthr) {
     constexpr int NB = MAXE / R;
     const int total = ntrans * nbf;
     E v[NB][R];
-    int dst[NB];
+    int dst[NB], row[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int q = tid + i * nthr;
         dst[i] = -1;
+        row[i] = 0;
         if (q < total) {
             const int t = (int)udiv16((unsigned)q, (unsigned)nbf, mnbf);
             const int j = q - t * nbf;
             const int jq = (int)udiv16((unsigned)j, (unsigned)Ns, mns);
             const int k = j - jq * Ns;
-            const ADMM_LDS E* b = buf + t * tstride + j;
+            const ADMM_LDS E* b = buf + t * tstride;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = lds_ld(b + r * nbf);
+            for (int r = 0; r < R; ++r) v[i][r] = lds_ld(b + (PAD ? pidx(j + r * nbf) : j + r * nbf));
             if (Ns > 1) {
                 const ADMM_LDS float2* tk = stw + k * (R - 1);
 #pragma unroll
@@ -260,24 +271,26 @@ __device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS floa
                 }
             }
             dft<R, INV>(v[i]);
-            dst[i] = t * tstride + jq * Ns * R + k;
+            dst[i] = jq * Ns * R + k;
+            row[i] = t * tstride;
         }
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         if (dst[i] >= 0) {
-            ADMM_LDS E* o = buf + dst[i];
+            ADMM_LDS E* o = buf + row[i];
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds_st(o + r * Ns, v[i][r]);
+            for (int r = 0; r < R; ++r) lds_st(o + (PAD ? pidx(dst[i] + r * Ns) : dst[i] + r * Ns), v[i][r]);
         }
     }
     __syncthreads();
 }
 
-// Full transform of `ntrans` length-N sequences in LDS (natural order in and
-// out, unnormalised); stw: the length's stage table in LDS.
-template <int MAXE, bool INV, typename E>
+// Full transform of `ntrans` length-N sequences in LDS at stride `tstride`
+// (natural order in and out, unnormalised); PAD: each sequence in the padded
+// layout (pidx); stw: the length's stage table in LDS.
+template <int MAXE, bool INV, bool PAD, typename E>
 __device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const float2* gstw, int ntrans, int tstride,
                                         int tid, int nthr) {
     ADMM_LDS E* buf = (ADMM_LDS E*)gbuf;
@@ -288,12 +301,12 @@ __device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const floa
         const unsigned mnbf = f.mnbf[s], mns = f.mns[s];
         const ADMM_LDS float2* t = stw + f.tso[s];
         switch (R) {
-            case 8: stockham_stage<8, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
-            case 4: stockham_stage<4, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
-            case 2: stockham_stage<2, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
-            case 3: stockham_stage<3, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
-            case 5: stockham_stage<5, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
-            case 7: stockham_stage<7, MAXE, INV>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 8: stockham_stage<8, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 4: stockham_stage<4, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 2: stockham_stage<2, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 3: stockham_stage<3, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 5: stockham_stage<5, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 7: stockham_stage<7, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
             default: break;
         }
     }
@@ -306,10 +319,7 @@ __device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const floa
 // needs no block barrier: all of a wave's loads of a stage are issued before
 // its stores, and the next stage's loads after those stores. Waves therefore
 // run their columns independently and overlap one another's memory phases.
-// The sequence is stored padded, element e at pidx(e) = e + e / 8, so that the
-// stride-8 element accesses of a first radix-8 stage fall in distinct banks.
-__host__ __device__ constexpr int pidx_len(int n) { return n + (n >> 3) + 1; }
-__device__ __forceinline__ int pidx(int e) { return e + (e >> 3); }
+// The sequence is stored padded (pidx).
 
 // Keeps the compiler from moving LDS accesses across a stage boundary: the
 // stages of a wave-owned transform exchange data between lanes, which the
@@ -503,6 +513,87 @@ __device__ __forceinline__ void wave_fft(ADMM_LDS E* buf, const ADMM_LDS float2*
         c_stages<NF, 0, CSched<NF>::nst(), INV>(buf, stw, lane);
     else
         wave_stages<EPL, INV>(buf, stw, f, 0, f.nst, lane);
+}
+
+// ---- fixed-length block-level transforms (row passes): up to MAXT padded
+// rows at `pitch` in LDS share the stages; butterfly q = tid + i NTHR of a
+// stage belongs to row q / nbf and is butterfly q mod nbf of that row, and
+// with the length fixed every such division is a shift or a constant multiply.
+template <int N, int S, int NTHR, int MAXT, bool INV, typename E>
+__device__ __forceinline__ void b_stage(ADMM_LDS E* buf, int pitch, const ADMM_LDS float2* stw, int ntrans, int tid) {
+    using T = CSt<N, S>;
+    constexpr int NBT = (MAXT * T::nbf + NTHR - 1) / NTHR;
+    E v[NBT][T::R];
+    lane_exchange_fence();
+#pragma unroll
+    for (int i = 0; i < NBT; ++i) {
+        const int q = tid + i * NTHR;
+        const int t = q / T::nbf, j = q % T::nbf;
+        if (t < ntrans) {
+            const ADMM_LDS E* b = buf + t * pitch;
+            if constexpr (T::nbf % 8 == 0) {
+                b += pidx(j);
+#pragma unroll
+                for (int r = 0; r < T::R; ++r) v[i][r] = lds_ld(b + r * (T::nbf + T::nbf / 8));
+            } else {
+#pragma unroll
+                for (int r = 0; r < T::R; ++r) v[i][r] = lds_ld(b + pidx(j + r * T::nbf));
+            }
+            if constexpr (T::Ns > 1) {
+                const ADMM_LDS float2* tk = stw + T::TSO + (j % T::Ns) * (T::R - 1);
+#pragma unroll
+                for (int r = 1; r < T::R; ++r) {
+                    float2 w = lds_ld(tk + r - 1);
+                    if (INV) w.y = -w.y;
+                    v[i][r] = cmul(v[i][r], w);
+                }
+            }
+            dft<T::R, INV>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NBT; ++i) {
+        const int q = tid + i * NTHR;
+        const int t = q / T::nbf, j = q % T::nbf;
+        if (t < ntrans) {
+            ADMM_LDS E* b = buf + t * pitch;
+            const int d = (j / T::Ns) * T::Ns * T::R + j % T::Ns;
+            if constexpr (T::Ns % 8 == 0) {
+                b += pidx(d);
+#pragma unroll
+                for (int r = 0; r < T::R; ++r) lds_st(b + r * (T::Ns + T::Ns / 8), v[i][r]);
+            } else if constexpr (T::Ns == 1 && T::R == 8) {
+                b += 9 * j;   // pidx(8 j + r) = 9 j + r
+#pragma unroll
+                for (int r = 0; r < T::R; ++r) lds_st(b + r, v[i][r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < T::R; ++r) lds_st(b + pidx(d + r * T::Ns), v[i][r]);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, int S0, int S1, int NTHR, int MAXT, bool INV, typename E>
+__device__ __forceinline__ void b_stages(ADMM_LDS E* buf, int pitch, const ADMM_LDS float2* stw, int ntrans, int tid) {
+    if constexpr (S0 < S1) {
+        b_stage<N, S0, NTHR, MAXT, INV>(buf, pitch, stw, ntrans, tid);
+        b_stages<N, S0 + 1, S1, NTHR, MAXT, INV>(buf, pitch, stw, ntrans, tid);
+    }
+}
+
+// Transform `ntrans` <= MAXT padded rows at `pitch`: the fixed-length code when
+// the length is NF, else the run-time schedule (same layout).
+template <int NF, int NTHR, int MAXT, int MAXE, bool INV, typename E>
+__device__ __forceinline__ void rows_fft(E* gbuf, int pitch, const FftPlanDev& f, const float2* gstw, int ntrans,
+                                         int tid) {
+    if (f.N == NF)
+        b_stages<NF, 0, CSched<NF>::nst(), NTHR, MAXT, INV>((ADMM_LDS E*)gbuf, pitch, (const ADMM_LDS float2*)gstw,
+                                                            ntrans, tid);
+    else
+        fft_lds<MAXE, INV, true>(gbuf, f, gstw, ntrans, pitch, tid, NTHR);
 }
 
 // Copy the length-N twiddle table to LDS (before the first barrier of a kernel).
