@@ -43,22 +43,53 @@ def kernel_source_hash():
 def alg_bytes_per_launch(problems):
     """Algorithmic HBM bytes of one launch of each kernel class (plain iteration).
 
-    col:    read the two transposed half spectra (16 B / entry) and Lambda
-            (8 B / entry), write the two half spectra back: 40 B per entry of
-            the H x (W/2+1) half spectrum.
-    row_tv: read the half spectra (16 B / entry), d1, d^h, d^v (12 B / px),
-            y (4 B / px) and the mask (1 B / px); write d1, d^h, d^v
-            (12 B / px) and the next half spectra (16 B / entry).
+    col:     read the two transposed half spectra (16 B / entry) and Lambda
+             (8 B / entry), write the two half spectra back: 40 B per entry of
+             the H x (W/2+1) half spectrum.
+    row_tv:  read the half spectra (16 B / entry), d1, d^h, d^v (12 B / px),
+             y (4 B / px) and the mask (1 B / px); write d1, d^h, d^v
+             (12 B / px) and the next half spectra (16 B / entry).
+    row_inv: read the half spectra (16 B / entry), d1, y, mask (9 B / px);
+             write d1, zeta1, z (12 B / px).
+    frame:   read z (4 B / px) and the 3J+1 frame duals, write the duals and
+             q (4 B / px): 8 + 8 (3J+1) B / px.
+    row_fwd: read zeta1 and q (8 B / px), write the half spectra (16 B / entry).
     Halo re-reads are not counted (they are overhead, not algorithmic).
     """
-    col = row = 0
+    out = {"col": 0, "row_tv": 0, "row_inv": 0, "frame": 0, "row_fwd": 0}
     for p in problems:
         H, W = p.shape
         hp = H * (W // 2 + 1)
         n = H * W
-        col += 40 * hp
-        row += 32 * hp + 29 * n
-    return {"col": col, "row_tv": row}
+        out["col"] += 40 * hp
+        if getattr(p, "reg", "tv") == "frame":
+            out["row_inv"] += 16 * hp + 21 * n
+            out["frame"] += (8 + 8 * (3 * p.levels + 1)) * n
+            out["row_fwd"] += 8 * n + 16 * hp
+        else:
+            out["row_tv"] += 32 * hp + 29 * n
+    return out
+
+
+WORKLOADS = {
+    "tv8x512": "TV-MD batch of 8 x 512x512 (19x19 Gaussian x4, 15-px motion x4), 40% missing",
+    "fa1024": "FA-MD 1024x1024, 13x13 disk, undecimated Haar J = 3, 20% missing 8x8 blocks",
+    "ragged256": "TV-MD ragged batch of 256 problems, sides 128..1024 (7-smooth), kernels 5..31",
+}
+
+
+def workload(name, batch, size):
+    from paper_1210_2687_amd import workloads as WL
+    if name == "tv8x512":
+        return [WL.config2(i % 8, size=size) for i in range(batch)]
+    if name == "fa1024":
+        return [WL.config3(size=1024, levels=3)]
+    if name == "ragged256":
+        # the synthetic observations take about a second each on one core
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            return list(ex.map(WL.config4, range(256)))
+    raise SystemExit(f"bench.py: unknown workload {name}")
 
 
 def read_traffic(expected_hash):
@@ -78,8 +109,9 @@ def read_traffic(expected_hash):
         return None
 
 
-def cpu_baseline(iters):
-    """FP64 oracle on a bounded sample: one Gaussian and one motion member of the batch."""
+def cpu_baseline(iters, name="tv8x512"):
+    """FP64 oracle on a bounded sample of the workload (the TV batch: one Gaussian
+    and one motion member; FA: the problem itself; ragged: two members)."""
     import numpy as np
     import oracle as O
     from paper_1210_2687_amd import workloads as WL
@@ -88,15 +120,23 @@ def cpu_baseline(iters):
         cores = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or os.cpu_count()
     except Exception:
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    sample = [WL.config2(0), WL.config2(4)]
+    if name == "fa1024":
+        sample, what = [WL.config3(size=1024, levels=3)], "the 1024x1024 FA problem"
+    elif name == "ragged256":
+        sample, what = [WL.config4(0), WL.config4(1)], "ragged members 0 and 1"
+    else:
+        sample, what = [WL.config2(0), WL.config2(4)], "2 of the 8 batch images (one 19x19 Gaussian, one 15-px motion)"
     t0 = time.perf_counter()
     for p in sample:
-        O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=iters)
+        if getattr(p, "reg", "tv") == "frame":
+            O.fa_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, p.levels, iters=iters)
+        else:
+            O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=iters)
     dt = time.perf_counter() - t0
     px_it = sum(p.y.size for p in sample) * iters
+    shapes = ", ".join(f"{p.shape[0]}x{p.shape[1]}" for p in sample)
     return {"value": px_it / dt / 1e6, "unit": "Mpx*iter/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"2 of the 8 batch images (one 19x19 Gaussian, one 15-px motion), 512x512, "
-                      f"{iters} iterations each, {dt:.1f} s"}
+            "sample": f"{what} ({shapes}), {iters} iterations each, {dt:.1f} s"}
 
 
 def cnn_flops_per_px(train=False):
@@ -168,10 +208,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--iters", type=int, default=500, help="ADMM iterations per step")
+    ap.add_argument("--workload", default="tv8x512", choices=sorted(WORKLOADS),
+                    help="tv8x512 is the headline; fa1024 and ragged256 measure the other paths")
+    ap.add_argument("--iters", type=int, default=0, help="ADMM iterations per step (0: 500, 200, 100 by workload)")
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--cpu-iters", type=int, default=120, help="oracle iterations per sampled image")
+    ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations per sampled image "
+                    "(0: 120 for the TV batch, 10 for FA, 30 for ragged)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start training and evaluation")
     ap.add_argument("--ws-train", type=int, default=256, help="warm-start training problems (256x256)")
@@ -211,7 +254,11 @@ def main():
         sys.exit(1)
     A.lib()   # fail loudly if the HIP library is missing
 
-    probs = [WL.config2(i % 8, size=args.size) for i in range(args.batch)]
+    if not args.iters:
+        args.iters = {"tv8x512": 500, "fa1024": 200, "ragged256": 100}[args.workload]
+    if not args.cpu_iters:
+        args.cpu_iters = {"tv8x512": 120, "fa1024": 10, "ragged256": 30}[args.workload]
+    probs = workload(args.workload, args.batch, args.size)
     ys = [torch.tensor(p.y, dtype=torch.float32, device="cuda") for p in probs]
     xs = [torch.zeros_like(y) for y in ys]
     plan = A.Plan(probs, tune=not args.no_tune, cache_path=os.environ.get("ADMM_TUNE_CACHE"))
@@ -237,30 +284,36 @@ def main():
         plan.batch(ys, xs, max_iters=args.iters, tol=0.0, graph=False, profile=True)
         kt = plan.kernel_times()
         alg = alg_bytes_per_launch(probs)
-        dom = max(("col", "row_tv"), key=lambda k: kt[k][1])
+        dom = max(("col", "row_tv", "row_inv", "frame", "row_fwd"), key=lambda k: kt[k][1])
         n_launch, tot_ms = kt[dom]
         avg_s = tot_ms / n_launch / 1e3
         achieved = alg[dom] / avg_s / 1e9
-        traffic = read_traffic(kernel_source_hash()) if dom == "row_tv" else None
+        traffic = read_traffic(kernel_source_hash()) if (dom == "row_tv" and args.workload == "tv8x512") else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                     "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": alg[dom],
                     "kernel_us": {k: round(v[1] / max(v[0], 1) * 1e3, 3) for k, v in kt.items() if v[0]}}
 
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
-    ws = None if args.no_warm_start else warm_start_eval(args.ws_train, args.ws_steps, args.ws_eval, 256, 512, log)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_iters)
+    ws = None if (args.no_warm_start or args.workload != "tv8x512") else \
+        warm_start_eval(args.ws_train, args.ws_steps, args.ws_eval, 256, 512, log)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_iters, args.workload)
+    tile_info = {"cols_per_block": tiles[0], "rows_per_block": tiles[1],
+                 "chosen_by": "heuristic" if args.no_tune else "autotuner"}
+    if args.workload == "tv8x512":
+        config = {"workload": f"TV-MD batch of {args.batch} x {args.size}x{args.size}, {args.iters} iterations",
+                  "batch": args.batch, "H": args.size, "W": args.size, "iters": args.iters,
+                  "kernels": "19x19 Gaussian sigma 3 (4) + 15-px motion (4)",
+                  "mask": "valid region minus 40% i.i.d. missing", "graph": graph, "tiles": tile_info}
+    else:
+        config = {"workload": f"{WORKLOADS[args.workload]}, {args.iters} iterations", "problems": len(probs),
+                  "pixels": int(px), "iters": args.iters, "graph": graph, "tiles": tile_info}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpx*iter/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"TV-MD batch of {args.batch} x {args.size}x{args.size}, {args.iters} iterations",
-                   "batch": args.batch, "H": args.size, "W": args.size, "iters": args.iters,
-                   "kernels": "19x19 Gaussian sigma 3 (4) + 15-px motion (4)",
-                   "mask": "valid region minus 40% i.i.d. missing", "graph": graph,
-                   "tiles": {"cols_per_block": tiles[0], "rows_per_block": tiles[1],
-                             "chosen_by": "heuristic" if args.no_tune else "autotuner"}},
+        "config": config,
         "roofline": roofline, "cpu_baseline": cpu, "warm_start": ws,
     }
     plan.close()

@@ -19,15 +19,18 @@
 // The duals are ping-pong buffers: halo reads see only the previous iteration.
 #include "admm_internal.h"
 #include "admm_launch.h"
+#include "fft_lds.h"
 
 namespace admm {
 
-constexpr int NTF = 256;
+constexpr int NTF = 512;
 
 __device__ __forceinline__ int wrapm(int i, int n) {
     i %= n;
     return i < 0 ? i + n : i;
 }
+// i in [-n, 2n): one conditional add or subtract
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 __device__ __forceinline__ double fwave_sum(double v) {
 #pragma unroll
@@ -55,27 +58,33 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
     const int ntx = (W + FT - 1) / FT;
     const int ty = it.start / ntx, tx = it.start - ty * ntx;
     const int r0 = ty * FT, c0 = tx * FT;
-    const size_t n = (size_t)H * W;
+    const unsigned n = (unsigned)(H * W);   // planes hold at most 2048^2 values: 32-bit offsets
     const int tid = threadIdx.x;
+    // windows reach h pixels beyond the tile; a single wrap suffices unless the
+    // image is smaller than a window
+    const bool small = H < FT + 2 * h || W < FT + 2 * h;
+    auto wrap = [&](int i, int m) { return small ? wrapm(i, m) : wrap1(i, m); };
     const float tau = p.tau, mu2 = p.mu2;
     const bool chk = (flags & F_CHECK) && !import_mode;
 
     // LDS carve-up: a_0..a_J, three omega planes, two a' planes
+    // (explicit LDS pointers: indexed arrays of generic pointers would become flat accesses)
     const int L0 = FT + 2 * h, LE = FT + h;
-    float* a[5];
+    ADMM_LDS float* const smem = (ADMM_LDS float*)sm;
+    ADMM_LDS float* a[5];
     int La[5];
     int off = 0;
     for (int j = 0; j <= J; ++j) {
         La[j] = L0 - ((1 << j) - 1);
-        a[j] = sm + off;
+        a[j] = smem + off;
         off += La[j] * La[j];
     }
-    float* wb[3];
+    ADMM_LDS float* wb[3];
     for (int b = 0; b < 3; ++b) {
-        wb[b] = sm + off;
+        wb[b] = smem + off;
         off += LE * LE;
     }
-    float* ap[2] = {sm + off, sm + off + LE * LE};
+    ADMM_LDS float* ap[2] = {smem + off, smem + off + LE * LE};
 
     const float* din = par ? p.dreg1 : p.dreg0;
     float* dout = par ? p.dreg0 : p.dreg1;
@@ -85,16 +94,18 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
 
     if (!import_mode) {
+        const unsigned m0 = div_magic((unsigned)L0);
         for (int idx = tid; idx < L0 * L0; idx += NTF) {
-            const int i = idx / L0, k = idx - (idx / L0) * L0;
-            a[0][idx] = p.zpl[(size_t)wrapm(r0 - h + i, H) * W + wrapm(c0 - h + k, W)];
+            const int i = (int)udiv16((unsigned)idx, (unsigned)L0, m0), k = idx - i * L0;
+            a[0][idx] = gld(p.zpl, (unsigned)(wrap(r0 - h + i, H) * W + wrap(c0 - h + k, W)));
         }
         __syncthreads();
         for (int j = 1; j <= J; ++j) {
             const int s = 1 << (j - 1), Lp = La[j - 1], Lc = La[j];
-            const float* A = a[j - 1];
+            const ADMM_LDS float* A = a[j - 1];
+            const unsigned mc = div_magic((unsigned)Lc);
             for (int idx = tid; idx < Lc * Lc; idx += NTF) {
-                const int i = idx / Lc, k = idx - (idx / Lc) * Lc;
+                const int i = (int)udiv16((unsigned)idx, (unsigned)Lc, mc), k = idx - i * Lc;
                 const float x00 = A[i * Lp + k], x10 = A[(i + s) * Lp + k];
                 const float x01 = A[i * Lp + k + s], x11 = A[(i + s) * Lp + k + s];
                 const float lv0 = 0.5f * (x00 + x10), lv1 = 0.5f * (x01 + x11);
@@ -104,23 +115,28 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
         }
     }
 
-    // One coefficient of band `band` at tile-relative (i, k): prox, dual, omega.
-    auto coef = [&](int band, float Pz, int i, int k) -> float {
-        const int gr = r0 + i, gc = c0 + k;
-        const bool own = i >= 0 && k >= 0 && i < FT && k < FT && gr < H && gc < W;
-        const size_t g = (size_t)band * n + (size_t)wrapm(gr, H) * W + wrapm(gc, W);
+    // One coefficient of band `band` at tile-relative (i, k): its plane offset,
+    // its dual (the loads of up to CH coefficients per thread are issued
+    // together), then prox, dual update and omega = u2 + d2'.
+    auto cidx = [&](int band, int i, int k) -> unsigned {
+        return (unsigned)band * n + (unsigned)(wrap(r0 + i, H) * W + wrap(c0 + k, W));
+    };
+    auto cload = [&](unsigned g) -> float2 {
+        return import_mode ? make_float2(gld(p.st_dreg, g), gld(p.st_ureg, g)) : make_float2(gld(din, g), 0.0f);
+    };
+    auto coef = [&](float Pz, float2 dl, unsigned g, int i, int k) -> float {
+        const bool own = i >= 0 && k >= 0 && i < FT && k < FT && r0 + i < H && c0 + k < W;
         if (import_mode) {
-            const float dn = p.st_dreg[g];
-            if (own) dout[g] = dn;
-            return p.st_ureg[g] + dn;
+            if (own) gst(dout, g, dl.x);
+            return dl.y + dl.x;
         }
-        const float v = Pz - din[g];
+        const float v = Pz - dl.x;
         const float u = softf(v, tau);
         const float dn = u - v;                  // d2 - (P z - u2)
         if (own) {
-            dout[g] = dn;
+            gst(dout, g, dn);
             if (chk) {
-                const float e = Pz - u, f = u - p.uregp[g];
+                const float e = Pz - u, f = u - gld(p.uregp, g);
                 acc[1] += (double)(e * e);
                 acc[3] += (double)(Pz * Pz);
                 acc[5] += (double)(u * u);
@@ -128,52 +144,90 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
                 acc[9] += (double)(dn * dn);
                 acc[11] += (double)fabsf(Pz);
             }
-            if (flags & F_WRITE_UPREV) p.uregp[g] = u;
+            if (flags & F_WRITE_UPREV) gst(p.uregp, g, u);
             if (flags & F_EXPORT) {
-                p.st_ureg[g] = u;
-                p.st_dreg[g] = dn;
+                gst(p.st_ureg, g, u);
+                gst(p.st_dreg, g, dn);
             }
         }
         return u + dn;
     };
+    constexpr int CH = 4;
 
     // coarsest low-low band on [-h, FT)^2 -> a'_J
-    for (int idx = tid; idx < LE * LE; idx += NTF) {
-        const int i = idx / LE - h, k = idx - (idx / LE) * LE - h;
-        ap[0][idx] = coef(3 * J, import_mode ? 0.0f : a[J][idx], i, k);
+    const unsigned mE = div_magic((unsigned)LE);
+    for (int base = tid; base < LE * LE; base += CH * NTF) {
+        unsigned g[CH];
+        float2 dl[CH];
+        int iv[CH], kv[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int idx = min(base + u * NTF, LE * LE - 1);
+            const int ie = (int)udiv16((unsigned)idx, (unsigned)LE, mE);
+            iv[u] = ie - h;
+            kv[u] = idx - ie * LE - h;
+            g[u] = cidx(3 * J, iv[u], kv[u]);
+            if (base + u * NTF < LE * LE) dl[u] = cload(g[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int idx = base + u * NTF;
+            if (idx < LE * LE) ap[0][idx] = coef(import_mode ? 0.0f : a[J][idx], dl[u], g[u], iv[u], kv[u]);
+        }
     }
     __syncthreads();
     int cur = 0;
     for (int j = J; j >= 1; --j) {
         const int s = 1 << (j - 1), e = (1 << j) - 1, Lb = FT + e;
-        const float* A = a[j - 1];
+        const ADMM_LDS float* A = a[j - 1];
         const int Lp = La[j - 1];
-        for (int idx = tid; idx < Lb * Lb; idx += NTF) {
-            const int ii = idx / Lb, kk = idx - (idx / Lb) * Lb;
-            const int i = ii - e, k = kk - e;
-            float lh = 0.f, hl = 0.f, hh = 0.f;
-            if (!import_mode) {
-                const int pi = i + h, pk = k + h;     // position in the a_{j-1} window
-                const float x00 = A[pi * Lp + pk], x10 = A[(pi + s) * Lp + pk];
-                const float x01 = A[pi * Lp + pk + s], x11 = A[(pi + s) * Lp + pk + s];
-                const float lv0 = 0.5f * (x00 + x10), lv1 = 0.5f * (x01 + x11);
-                const float hv0 = 0.5f * (x00 - x10), hv1 = 0.5f * (x01 - x11);
-                lh = 0.5f * (lv0 - lv1);
-                hl = 0.5f * (hv0 + hv1);
-                hh = 0.5f * (hv0 - hv1);
+        const unsigned mb = div_magic((unsigned)Lb);
+        const int b0 = 3 * (j - 1);
+        for (int base = tid; base < Lb * Lb; base += CH * NTF) {
+            unsigned g[CH][3];
+            float2 dl[CH][3];
+            int iv[CH], kv[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int idx = min(base + u * NTF, Lb * Lb - 1);
+                const int ii = (int)udiv16((unsigned)idx, (unsigned)Lb, mb), kk = idx - ii * Lb;
+                iv[u] = ii - e;
+                kv[u] = kk - e;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    g[u][b] = cidx(b0 + b, iv[u], kv[u]);
+                    if (base + u * NTF < Lb * Lb) dl[u][b] = cload(g[u][b]);
+                }
             }
-            const int b0 = 3 * (j - 1);
-            wb[0][idx] = coef(b0 + 0, lh, i, k);
-            wb[1][idx] = coef(b0 + 1, hl, i, k);
-            wb[2][idx] = coef(b0 + 2, hh, i, k);
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int idx = base + u * NTF;
+                if (idx >= Lb * Lb) break;
+                const int i = iv[u], k = kv[u];
+                float lh = 0.f, hl = 0.f, hh = 0.f;
+                if (!import_mode) {
+                    const int pi = i + h, pk = k + h;     // position in the a_{j-1} window
+                    const float x00 = A[pi * Lp + pk], x10 = A[(pi + s) * Lp + pk];
+                    const float x01 = A[pi * Lp + pk + s], x11 = A[(pi + s) * Lp + pk + s];
+                    const float lv0 = 0.5f * (x00 + x10), lv1 = 0.5f * (x01 + x11);
+                    const float hv0 = 0.5f * (x00 - x10), hv1 = 0.5f * (x01 - x11);
+                    lh = 0.5f * (lv0 - lv1);
+                    hl = 0.5f * (hv0 + hv1);
+                    hh = 0.5f * (hv0 - hv1);
+                }
+                wb[0][idx] = coef(lh, dl[u][0], g[u][0], i, k);
+                wb[1][idx] = coef(hl, dl[u][1], g[u][1], i, k);
+                wb[2][idx] = coef(hh, dl[u][2], g[u][2], i, k);
+            }
         }
         __syncthreads();
         // synthesis a'_{j-1} on [-(s-1), FT)^2 from level-j planes on [-e, FT)^2 (stride Lb)
         const int Lc = FT + s - 1;
-        const float* Ap = ap[cur];
-        float* An = ap[cur ^ 1];
+        const ADMM_LDS float* Ap = ap[cur];
+        ADMM_LDS float* An = ap[cur ^ 1];
+        const unsigned mc = div_magic((unsigned)Lc);
         for (int idx = tid; idx < Lc * Lc; idx += NTF) {
-            const int ci = idx / Lc, ck = idx - (idx / Lc) * Lc;
+            const int ci = (int)udiv16((unsigned)idx, (unsigned)Lc, mc), ck = idx - ci * Lc;
             const int ii = ci - (s - 1) + e, kk = ck - (s - 1) + e;     // >= s by construction
             const int q0 = ii * Lb + kk, q1 = ii * Lb + kk - s, q2 = (ii - s) * Lb + kk, q3 = (ii - s) * Lb + kk - s;
             // horizontal adjoints of the rows ii and ii - s
@@ -187,11 +241,12 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
         cur ^= 1;
     }
     // q = mu2 P^T omega on the tile
-    const float* Af = ap[cur];
+    const ADMM_LDS float* Af = ap[cur];
+    const unsigned mf = div_magic((unsigned)FT);
     for (int idx = tid; idx < FT * FT; idx += NTF) {
-        const int i = idx / FT, k = idx - (idx / FT) * FT;
+        const int i = (int)udiv16((unsigned)idx, (unsigned)FT, mf), k = idx - i * FT;
         const int gr = r0 + i, gc = c0 + k;
-        if (gr < H && gc < W) p.tmpB[(size_t)gr * W + gc] = mu2 * Af[idx];
+        if (gr < H && gc < W) gst(p.tmpB, (unsigned)(gr * W + gc), mu2 * Af[idx]);
     }
     if (chk) {
         const int lane = tid & 63, wave = tid >> 6;
@@ -214,11 +269,11 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
 // zeta1 = u1 + d1 and the working data dual, from a caller state (FA import).
 __global__ void k_import_fa(const ProbDesc* __restrict__ pd, int prob) {
     const ProbDesc& p = pd[prob];
-    const size_t n = (size_t)p.H * p.W;
-    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned n = (unsigned)(p.H * p.W);
+    const unsigned g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
-    p.tmpA[g] = p.st_u1[g] + p.st_d1[g];
-    p.d1[g] = p.st_d1[g];
+    gst(p.tmpA, g, gld(p.st_u1, g) + gld(p.st_d1, g));
+    gst(p.d1, g, gld(p.st_d1, g));
 }
 
 size_t lds_frame_bytes(int FT, int J) {
