@@ -267,10 +267,6 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
 
     // about two blocks per compute unit per pass (measured best on 8 x 512^2: TC = 4, B = 8)
     const int target_blocks = 512;
-    int tv_maxw = 0;
-    for (int i = 0; i < count; ++i)
-        if (probs[i].reg == ADMM_REG_TV) tv_maxw = std::max(tv_maxw, (int)probs[i].W);
-    const int tv_rows_cap = row_tv_max_rows(tv_maxw);
     for (int i = 0; i < count; ++i) {
         const admm_problem& q = probs[i];
         ProbDesc& d = P->hd[i];
@@ -303,7 +299,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         // rows per row-pass block
         int bmax = 0;
         if (q.reg == ADMM_REG_TV) {
-            while (bmax + 1 <= std::min(q.H, tv_rows_cap) && fits(bmax + 3, d.fr, row_maxe()) &&
+            while (bmax + 1 <= std::min(q.H, row_tv_max_rows(q.W)) && fits(bmax + 3, d.fr, row_maxe()) &&
                    lds_rowtv_bytes(q.W, bmax + 1) <= cap)
                 ++bmax;
         } else {
@@ -335,16 +331,39 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     P->row_end.assign(count, 0);
     P->frm_beg.assign(count, 0);
     P->frm_end.assign(count, 0);
+    // column and TV row items grouped by size class (each class is one launch of
+    // its own instantiation), largest problems first within a class
+    int col_cb[3], col_cc[3], rtv_cb[3], rtv_cc[3];
+    size_t lds_col_c[3] = {0, 0, 0}, lds_rtv_c[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c) {
+        col_cb[c] = (int)col.size();
+        rtv_cb[c] = (int)rowtv.size();
+        for (int i : order) {
+            ProbDesc& d = P->hd[i];
+            if (size_class(d.H) == c) {
+                P->col_beg[i] = (int)col.size();
+                for (int b = 0; b < d.ncolblk; ++b) col.push_back({i, b * d.TC, b, 0});
+                P->col_end[i] = (int)col.size();
+                lds_col_c[c] = std::max(lds_col_c[c], lds_col_bytes(d.H, d.TC));
+            }
+            if (d.reg == REG_TV && size_class(d.W) == c) {
+                P->row_beg[i] = (int)rowtv.size();
+                for (int b = 0; b < d.nrowblk; ++b) rowtv.push_back({i, b * d.B, b, 0});
+                P->row_end[i] = (int)rowtv.size();
+                lds_rtv_c[c] = std::max(lds_rtv_c[c], lds_rowtv_bytes(d.W, d.B));
+            }
+        }
+        col_cc[c] = (int)col.size() - col_cb[c];
+        rtv_cc[c] = (int)rowtv.size() - rtv_cb[c];
+    }
     int part = 0;
     for (int i : order) {
         ProbDesc& d = P->hd[i];
-        P->col_beg[i] = (int)col.size();
-        for (int b = 0; b < d.ncolblk; ++b) col.push_back({i, b * d.TC, b, 0});
-        P->col_end[i] = (int)col.size();
-        auto& rows = d.reg == REG_TV ? rowtv : rowfa;
-        P->row_beg[i] = (int)rows.size();
-        for (int b = 0; b < d.nrowblk; ++b) rows.push_back({i, b * d.B, b, 0});
-        P->row_end[i] = (int)rows.size();
+        if (d.reg == REG_FRAME) {
+            P->row_beg[i] = (int)rowfa.size();
+            for (int b = 0; b < d.nrowblk; ++b) rowfa.push_back({i, b * d.B, b, 0});
+            P->row_end[i] = (int)rowfa.size();
+        }
         P->frm_beg[i] = (int)frm.size();
         for (int b = 0; b < d.nfrmblk; ++b) frm.push_back({i, b, b, 0});
         P->frm_end[i] = (int)frm.size();
@@ -484,9 +503,13 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     base_ctx.lds_rowtv = P->lds_rowtv;
     base_ctx.lds_row = P->lds_row;
     base_ctx.lds_frm = P->lds_frm;
-    base_ctx.tv_maxw = tv_maxw;
-    for (int i = 0; i < count; ++i) {
-        base_ctx.col_maxh = std::max(base_ctx.col_maxh, (int)probs[i].H);
+    for (int c = 0; c < 3; ++c) {
+        base_ctx.col_beg[c] = col_cb[c];
+        base_ctx.col_cnt[c] = col_cc[c];
+        base_ctx.rtv_beg[c] = rtv_cb[c];
+        base_ctx.rtv_cnt[c] = rtv_cc[c];
+        base_ctx.lds_col_c[c] = lds_col_c[c];
+        base_ctx.lds_rtv_c[c] = lds_rtv_c[c];
     }
     base_ctx.col_items = P->d_items;
     base_ctx.ncol = P->ncol;
@@ -761,6 +784,12 @@ LaunchCtx single(const admm_plan* P, int i) {
     c.nrow = P->row_end[i] - P->row_beg[i];
     c.frm_items = nullptr;
     c.nfrm = 0;
+    for (int k = 0; k < 3; ++k) {
+        c.col_beg[k] = c.rtv_beg[k] = 0;
+        c.col_cnt[k] = c.rtv_cnt[k] = 0;
+    }
+    c.col_cnt[size_class(d.H)] = c.ncol;
+    if (d.reg == REG_TV) c.rtv_cnt[size_class(d.W)] = c.nrow;
     return c;
 }
 

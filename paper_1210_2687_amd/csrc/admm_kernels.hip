@@ -707,34 +707,50 @@ static size_t row_lds(int W, int B) {
     return b > scratch ? b : scratch;
 }
 
+int size_class(int n) { return n <= 512 ? 0 : (n <= 1024 ? 1 : 2); }
+
 hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
     const InfoDev* info = mode == COL_SOLVE ? L.info : nullptr;
-    if (L.col_maxh <= 512)
-        hipLaunchKernelGGL(k_col<8>, dim3(L.ncol), dim3(NTC), L.lds_col, L.stream, L.desc, L.col_items, L.ncol, par,
-                           mode, info, L.tw, L.s2);
-    else if (L.col_maxh <= 1024)
-        hipLaunchKernelGGL(k_col<16>, dim3(L.ncol), dim3(NTC), L.lds_col, L.stream, L.desc, L.col_items, L.ncol, par,
-                           mode, info, L.tw, L.s2);
-    else
-        hipLaunchKernelGGL(k_col<32>, dim3(L.ncol), dim3(NTC), L.lds_col, L.stream, L.desc, L.col_items, L.ncol, par,
-                           mode, info, L.tw, L.s2);
-    return hipGetLastError();
+    for (int c = 0; c < 3; ++c) {
+        const int n = L.col_cnt[c];
+        if (!n) continue;
+        const WorkItem* it = L.col_items + L.col_beg[c];
+        if (c == 0)
+            hipLaunchKernelGGL(k_col<8>, dim3(n), dim3(NTC), L.lds_col_c[0], L.stream, L.desc, it, n, par, mode, info,
+                               L.tw, L.s2);
+        else if (c == 1)
+            hipLaunchKernelGGL(k_col<16>, dim3(n), dim3(NTC), L.lds_col_c[1], L.stream, L.desc, it, n, par, mode, info,
+                               L.tw, L.s2);
+        else
+            hipLaunchKernelGGL(k_col<32>, dim3(n), dim3(NTC), L.lds_col_c[2], L.stream, L.desc, it, n, par, mode, info,
+                               L.tw, L.s2);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags) {
-    if (L.tv_maxw <= NT)
-        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 1, 8>), dim3(L.nrow), dim3(NT), L.lds_rowtv, L.stream, L.desc,
-                           L.row_items, L.nrow, par, flags, L.info, L.tw, L.partials);
-    else if (L.tv_maxw <= 2 * NT)
-        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 2, 6>), dim3(L.nrow), dim3(NT), L.lds_rowtv, L.stream, L.desc,
-                           L.row_items, L.nrow, par, flags, L.info, L.tw, L.partials);
-    else
-        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 4, 2>), dim3(L.nrow), dim3(NT), L.lds_rowtv, L.stream, L.desc,
-                           L.row_items, L.nrow, par, flags, L.info, L.tw, L.partials);
-    return hipGetLastError();
+    for (int c = 0; c < 3; ++c) {
+        const int n = L.rtv_cnt[c];
+        if (!n) continue;
+        const WorkItem* it = L.row_items + L.rtv_beg[c];
+        if (c == 0)
+            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 1, 8>), dim3(n), dim3(NT), L.lds_rtv_c[0], L.stream, L.desc, it, n,
+                               par, flags, L.info, L.tw, L.partials);
+        else if (c == 1)
+            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 2, 6>), dim3(n), dim3(NT), L.lds_rtv_c[1], L.stream, L.desc, it, n,
+                               par, flags, L.info, L.tw, L.partials);
+        else
+            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 4, 2>), dim3(n), dim3(NT), L.lds_rtv_c[2], L.stream, L.desc, it, n,
+                               par, flags, L.info, L.tw, L.partials);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-int row_tv_max_rows(int maxw) { return maxw <= NT ? 8 : (maxw <= 2 * NT ? 6 : 2); }
+int row_tv_max_rows(int w) { return w <= NT ? 8 : (w <= 2 * NT ? 6 : 2); }
 
 hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
     hipLaunchKernelGGL(k_row_fwd<MAXE_ROW>, dim3(L.nrow), dim3(NT), L.lds_row, L.stream, L.desc, L.row_items,

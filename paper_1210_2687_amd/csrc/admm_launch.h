@@ -20,8 +20,12 @@ struct LaunchCtx {
     const float2* tw = nullptr;
     const float* s2 = nullptr;
     size_t lds_col = 0, lds_rowtv = 0, lds_row = 0, lds_frm = 0;
-    int tv_maxw = 0;                       // widest TV problem (selects the row-pass instantiation)
-    int col_maxh = 0;                      // tallest problem (selects the column-pass instantiation)
+    // size classes of the column and TV row passes (0: length <= 512, 1: <= 1024,
+    // 2: <= 2048), each launched with its own instantiation: the items of class c
+    // are [beg[c], beg[c] + cnt[c]) of col_items / row_items
+    int col_beg[3] = {0, 0, 0}, col_cnt[3] = {0, 0, 0};
+    int rtv_beg[3] = {0, 0, 0}, rtv_cnt[3] = {0, 0, 0};
+    size_t lds_col_c[3] = {0, 0, 0}, lds_rtv_c[3] = {0, 0, 0};
 };
 
 hipError_t launch_col(const LaunchCtx& L, int par, int mode);
@@ -42,7 +46,8 @@ size_t lds_rowtv_bytes(int W, int B);
 size_t lds_row_bytes(int W, int B);
 size_t lds_frame_bytes(int FT, int J);
 int col_max_tiles();                       // columns per column-pass block (one per wave)
-int row_tv_max_rows(int maxw);
+int row_tv_max_rows(int w);                  // rows per block of the TV row pass for width w
+int size_class(int n);                      // 0: n <= 512, 1: n <= 1024, 2: larger
 int row_maxe();
 int block_threads();
 
