@@ -155,6 +155,17 @@ typedef struct {
 /* Copies up to `cap` entries to out (HOST) and returns how many classes exist. */
 int32_t admm_plan_kernel_times(const admm_plan* plan, admm_kernel_time* out, int32_t cap);
 
+/* Average duration of one launch of a pass kernel ("col", "row_tv", "frame",
+ * "row_inv" or "row_fwd"; a pass split into size classes counts as one
+ * launch) over `reps` back-to-back launches on the plan's stream, bracketed by
+ * one pair of HIP events, after one untimed launch. For measurement only: it
+ * runs plain iterations' launches on whatever the plan's buffers hold (call
+ * it after a solve or batch, which sets the data pointers) and leaves that
+ * state modified; the next solve starts over. *avg_ms (HOST) receives the
+ * result. Errors: ADMM_E_INVALID (unknown kernel, none in the plan),
+ * ADMM_E_DEVICE.                                                              */
+admm_status admm_plan_time_pass(admm_plan* plan, const char* kernel, int32_t reps, double* avg_ms);
+
 /* ---- FFT autotuner (tile shapes of the pass kernels) ----
  * Like admm_deconv_plan, but the columns per column-pass block (1..4, one
  * column per wave) and the rows per row-pass block are chosen by timing trial

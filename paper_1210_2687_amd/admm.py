@@ -108,6 +108,7 @@ def lib():
         L.admm_tune_cache_lookup.restype = c_int32
         L.admm_tune_cache_store.argtypes = [c_char_p, c_char_p, c_int32, c_int32, c_double, c_double]
         L.admm_plan_tiles.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]
+        L.admm_plan_time_pass.argtypes = [c_void_p, c_char_p, c_int32, POINTER(c_double)]
         vp = c_void_p
         L.admm_conv3x3_pack_weights.argtypes = [vp, c_int32, c_int32, vp, vp, vp]
         L.admm_conv3x3_bf16_fwd.argtypes = [vp, c_int32, c_int32, c_int32, c_int32, vp, vp, c_int32, c_int32,
@@ -121,6 +122,7 @@ def lib():
         L.admm_ws_loss.argtypes = [vp, vp, vp, vp, vp, c_int32, c_int32, c_int32, c_float, vp, vp, vp]
         L.admm_ws_output.argtypes = [vp, vp, vp, c_int32, c_int32, c_int32, vp, vp, vp]
         for f in ("admm_deconv_plan", "admm_deconv_plan_tuned", "admm_tune_cache_store", "admm_plan_tiles",
+                  "admm_plan_time_pass",
                   "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
                   "admm_warmstart_map", "admm_fft_radices", "admm_validate_problem",
                   "admm_conv3x3_pack_weights", "admm_conv3x3_bf16_fwd", "admm_conv3x3_bf16_wgrad",
@@ -135,7 +137,7 @@ def exported_symbols():
     return ["admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
             "admm_warmstart_map", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
             "admm_validate_problem", "admm_plan_kernel_times", "admm_deconv_plan_tuned", "admm_tune_key",
-            "admm_tune_cache_lookup", "admm_tune_cache_store", "admm_plan_tiles",
+            "admm_tune_cache_lookup", "admm_tune_cache_store", "admm_plan_tiles", "admm_plan_time_pass",
             "admm_conv3x3_pack_weights", "admm_conv3x3_bf16_fwd", "admm_conv3x3_bf16_wgrad_workspace",
             "admm_conv3x3_bf16_wgrad", "admm_adam_step", "admm_ws_input", "admm_ws_loss", "admm_ws_output"]
 
@@ -225,6 +227,13 @@ def admm_plan_tiles(plan, index):
     tc, rows = c_int32(), c_int32()
     _check(lib().admm_plan_tiles(plan, index, ctypes.byref(tc), ctypes.byref(rows)))
     return tc.value, rows.value
+
+
+def admm_plan_time_pass(plan, kernel, reps=50):
+    """Average milliseconds of one launch of a pass kernel over `reps` back-to-back launches."""
+    out = c_double()
+    _check(lib().admm_plan_time_pass(plan, kernel.encode(), int(reps), ctypes.byref(out)))
+    return out.value
 
 
 def admm_plan_destroy(plan):
@@ -387,6 +396,9 @@ class Plan:
 
     def tiles(self, index=0):
         return admm_plan_tiles(self.handle, index)
+
+    def time_pass(self, kernel, reps=50):
+        return admm_plan_time_pass(self.handle, kernel, reps)
 
     def warmstart_map(self, index, x0, p0, y, state):
         admm_warmstart_map(self.handle, index, x0, p0, y, state)

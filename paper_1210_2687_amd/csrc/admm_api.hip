@@ -1171,3 +1171,43 @@ extern "C" admm_status admm_plan_tiles(const admm_plan* P, int32_t index, int32_
     if (rows) *rows = P->hd[index].B;
     return ADMM_OK;
 }
+
+extern "C" admm_status admm_plan_time_pass(admm_plan* P, const char* kernel, int32_t reps, double* avg_ms) {
+    if (!P || !kernel || !avg_ms || reps < 1) return fail(ADMM_E_INVALID, "bad argument");
+    const std::string k = kernel;
+    const bool fa = k == "frame" || k == "row_inv" || k == "row_fwd";
+    if (k != "col" && k != "row_tv" && !fa) return fail(ADMM_E_INVALID, "unknown pass kernel %s", kernel);
+    if ((k == "row_tv" && !P->nrowtv) || (fa && !P->nfa))
+        return fail(ADMM_E_INVALID, "the plan has no %s launches", kernel);
+    // every problem active, as in a running solve (a finished solve leaves them inactive)
+    for (int i = 0; i < P->count; ++i) {
+        std::memset(&P->h_info[i], 0, sizeof(InfoDev));
+        P->h_info[i].active = 1;
+    }
+    HIP_TRY(hipMemcpyAsync(P->d_info, P->h_info, sizeof(InfoDev) * P->count, hipMemcpyHostToDevice, P->stream));
+    auto launch = [&]() -> hipError_t {
+        if (k == "col") return launch_col(P->all, 0, COL_SOLVE);
+        if (k == "row_tv") return launch_row_tv(P->tv, 0, F_FORWARD);
+        if (k == "frame") return launch_frame(P->fa, 0, 0, 0, true);
+        if (k == "row_inv") return launch_row_inv(P->fa, 0, 1, 0, true);
+        return launch_row_fwd(P->fa, 0, 0, true);
+    };
+    HIP_TRY(launch());   // warm
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ADMM_E_DEVICE, "hipEventCreate failed");
+    }
+    hipError_t e = hipEventRecord(e0, P->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, P->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(ADMM_E_DEVICE, "timing %s failed: %s", kernel, hipGetErrorString(e));
+    *avg_ms = (double)ms / reps;
+    return ADMM_OK;
+}

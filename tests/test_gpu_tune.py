@@ -69,3 +69,21 @@ def test_iterates_do_not_depend_on_the_tile_shape(tmp_path, tc, rows):
     announce(f"tiles {used}")
     for a, b in zip(got, ref):
         assert np.array_equal(a, b)
+
+
+def test_pass_timing_entry_point():
+    import torch
+    probs = _batch()
+    with A.Plan(probs) as plan:
+        _run(plan, probs, iters=5)
+        for k in ("col", "row_tv", "frame", "row_inv", "row_fwd"):
+            ms = plan.time_pass(k, reps=5)
+            assert 0.0 < ms < 100.0, k
+        with pytest.raises(A.AdmmError):
+            plan.time_pass("nonsense", reps=5)
+        # a solve after the timing launches starts over from its own initial state
+        ref = _run(plan, probs)
+    with A.Plan(probs) as plan2:
+        again = _run(plan2, probs)
+    for a, b in zip(ref, again):
+        assert np.array_equal(a, b)
