@@ -188,3 +188,81 @@ def test_graph_replay_matches_eager_launches():
         za, ia = gpu_solve(plan, q, 3000, tol=1e-4, check_every=10)
         zb, ib = gpu_solve(plan, q, 3000, tol=1e-4, check_every=10, graph=True)
         assert ia["iters"] == ib["iters"] and np.array_equal(za, zb)
+
+
+def test_bench_batch_at_full_size_matches_oracle():
+    # the timed workload itself: 8 x 512^2 in one batch, graph replay, 3 iterations
+    import torch
+    announce("full-size bench batch, 3 iterations")
+    probs = [WL.config2(i) for i in range(8)]
+    with A.Plan(probs, tune=True) as plan:
+        ys = [dev(p.y) for p in probs]
+        xs = [torch.zeros_like(y) for y in ys]
+        plan.batch(ys, xs, max_iters=3, graph=True)
+    for p, x in zip(probs, xs):
+        ref = O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=3)
+        e = rel(host(x), ref["z"])
+        announce(f"  rel err {e:.2e}")
+        assert e <= ITER_TOL
+
+
+def _tiled(base, reps):
+    """The periodic problem made of reps x reps copies of `base`: every operator
+    of the method is shift-invariant on the torus, so its iterates are the
+    copies of the base problem's iterates (a property that holds at any size)."""
+    ry, rx = reps
+    return WL.Problem(y=np.tile(base.y, (ry, rx)), mask=np.tile(base.mask, (ry, rx)), kernel=base.kernel,
+                      lam=base.lam, mu1=base.mu1, mu2=base.mu2, reg=base.reg, levels=base.levels)
+
+
+@pytest.mark.parametrize("reps", [(32, 32), (16, 32), (32, 8)])
+def test_largest_sizes_by_tiling(reps):
+    # 2048 x 2048, 1024 x 2048 and 2048 x 512 TV problems against the oracle on one 64 x 64 tile
+    announce(f"tiled TV {reps}")
+    base = fast_tv_problem(71, 64, 64, 7)
+    big = _tiled(base, reps)
+    K = 30
+    ref = O.tv_md_run(base.y, base.mask, base.kernel, base.lam, base.mu1, base.mu2, iters=K)["z"]
+    with A.Plan([big]) as plan:
+        z, _ = gpu_solve(plan, big, K, graph=True)
+    e = rel(z, np.tile(ref, reps))
+    announce(f"  {big.shape}: rel err {e:.2e}")
+    assert e <= ITER_TOL
+
+
+def test_frame_largest_size_by_tiling():
+    announce("tiled FA 2048 x 1024, J = 3")
+    base = WL.config3(size=64, levels=3)
+    big = _tiled(base, (32, 16))
+    K = 20
+    ref = O.fa_md_run(base.y, base.mask, base.kernel, base.lam, base.mu1, base.mu2, base.levels, iters=K)["z"]
+    with A.Plan([big]) as plan:
+        z, _ = gpu_solve(plan, big, K)
+    e = rel(z, np.tile(ref, (32, 16)))
+    announce(f"  rel err {e:.2e}")
+    assert e <= ITER_TOL
+
+
+def test_all_pixels_missing():
+    # M = 0: the data term vanishes (u1 follows A z, d1 becomes 0 after one
+    # iteration); from a random state the iterates still move, and match
+    announce("all pixels missing, random initial state")
+    import torch
+    base = fast_tv_problem(72, 48, 56, 5)
+    p = WL.Problem(y=base.y, mask=np.zeros_like(base.mask), kernel=base.kernel, lam=base.lam, mu1=base.mu1,
+                   mu2=base.mu2)
+    H, W = p.shape
+    g = np.random.default_rng(72)
+    s0 = O.TVState(u1=g.standard_normal((H, W)), d1=g.standard_normal((H, W)),
+                   uh=0.1 * g.standard_normal((H, W)), uv=0.1 * g.standard_normal((H, W)),
+                   dh=0.01 * g.standard_normal((H, W)), dv=0.01 * g.standard_normal((H, W)))
+    ref = O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=20, state0=s0)
+    st = {"u1": dev(s0.u1), "d1": dev(s0.d1), "ureg": dev(np.stack([s0.uh, s0.uv])),
+          "dreg": dev(np.stack([s0.dh, s0.dv]))}
+    with A.Plan([p]) as plan:
+        z, info = gpu_solve(plan, p, 20, state=st)
+    assert np.all(np.isfinite(z))
+    e = rel(z, ref["z"])
+    announce(f"  rel err {e:.2e}")
+    assert e <= ITER_TOL
+    assert np.all(host(st["d1"]) == 0.0)
