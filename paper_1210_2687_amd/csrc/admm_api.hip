@@ -313,7 +313,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         d.nrowblk = (q.H + d.B - 1) / d.B;
         d.ncolblk = (d.P + d.TC - 1) / d.TC;
         if (q.reg == ADMM_REG_FRAME) {
-            d.frm_tile = q.levels >= 4 ? 16 : 32;
+            d.frm_tile = frame_tile(q.levels);
             d.nfrmblk = ((q.H + d.frm_tile - 1) / d.frm_tile) * ((q.W + d.frm_tile - 1) / d.frm_tile);
         }
     }
@@ -364,9 +364,6 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
             for (int b = 0; b < d.nrowblk; ++b) rowfa.push_back({i, b * d.B, b, 0});
             P->row_end[i] = (int)rowfa.size();
         }
-        P->frm_beg[i] = (int)frm.size();
-        for (int b = 0; b < d.nfrmblk; ++b) frm.push_back({i, b, b, 0});
-        P->frm_end[i] = (int)frm.size();
         d.part_base = part;
         part += d.nrowblk + d.nfrmblk;
         if (d.reg == REG_TV) {
@@ -374,10 +371,26 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
             P->lds_rowtv = std::max(P->lds_rowtv, lds_rowtv_bytes(d.W, d.B));
         } else {
             ++P->nfa;
-            P->lds_frm = std::max(P->lds_frm, lds_frame_bytes(d.frm_tile, d.J));
+            P->lds_frm = std::max(P->lds_frm, lds_frame_bytes(d.J));
         }
         P->lds_row = std::max(P->lds_row, lds_row_bytes(d.W, d.B));
         P->lds_col = std::max(P->lds_col, lds_col_bytes(d.H, d.TC));
+    }
+    // frame items grouped by class (levels, small image), one launch per class
+    int frm_cb[ADMM_FRAME_CLASSES], frm_cc[ADMM_FRAME_CLASSES];
+    size_t lds_frm_c[ADMM_FRAME_CLASSES];
+    for (int c = 0; c < ADMM_FRAME_CLASSES; ++c) {
+        frm_cb[c] = (int)frm.size();
+        lds_frm_c[c] = 0;
+        for (int i : order) {
+            const ProbDesc& d = P->hd[i];
+            if (d.reg != REG_FRAME || frame_class(d.H, d.W, d.J) != c) continue;
+            P->frm_beg[i] = (int)frm.size();
+            for (int b = 0; b < d.nfrmblk; ++b) frm.push_back({i, b, b, 0});
+            P->frm_end[i] = (int)frm.size();
+            lds_frm_c[c] = lds_frame_bytes(d.J);
+        }
+        frm_cc[c] = (int)frm.size() - frm_cb[c];
     }
     P->ncol = (int)col.size();
     P->nrowtv = (int)rowtv.size();
@@ -510,6 +523,11 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         base_ctx.rtv_cnt[c] = rtv_cc[c];
         base_ctx.lds_col_c[c] = lds_col_c[c];
         base_ctx.lds_rtv_c[c] = lds_rtv_c[c];
+    }
+    for (int c = 0; c < ADMM_FRAME_CLASSES; ++c) {
+        base_ctx.frm_beg[c] = frm_cb[c];
+        base_ctx.frm_cnt[c] = frm_cc[c];
+        base_ctx.lds_frm_c[c] = lds_frm_c[c];
     }
     base_ctx.col_items = P->d_items;
     base_ctx.ncol = P->ncol;

@@ -43,48 +43,58 @@ __device__ __forceinline__ float softf(float v, float t) {
     return a > 0.0f ? copysignf(a, v) : 0.0f;
 }
 
-// import_mode: omega = u2 + d2 from the caller's state (no analysis), the
-// working duals are initialised from it; used to start or resume a solve.
+// Window edge of a_j (j = 0 .. J) and the LDS offset of a_j, in floats.
+__host__ __device__ constexpr int fr_la(int J, int j) { return frame_tile(J) + 2 * ((1 << J) - 1) - ((1 << j) - 1); }
+__host__ __device__ constexpr int fr_aoff(int J, int j) {
+    int o = 0;
+    for (int l = 0; l < j; ++l) o += fr_la(J, l) * fr_la(J, l);
+    return o;
+}
+__host__ __device__ constexpr int fr_cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// J levels and the tile size are compile-time, so every window size, LDS offset
+// and loop trip count is a constant. SMALL: the image is smaller than a window
+// and indices wrap by a full modulo. MODE: FR_PLAIN iteration, FR_CHECK
+// iteration that also accumulates the residual sums, or FR_IMPORT: omega =
+// u2 + d2 from the caller's state (no analysis) and the working duals are
+// initialised from it; used to start or resume a solve.
+enum { FR_PLAIN = 0, FR_CHECK = 1, FR_IMPORT = 2 };
+
+template <int J, bool SMALL, int MODE>
 __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
-                                               int nitems, int par, int flags, int import_mode,
-                                               const InfoDev* __restrict__ info, double* __restrict__ partials) {
+                                               int nitems, int par, int flags, const InfoDev* __restrict__ info,
+                                               double* __restrict__ partials) {
+    constexpr bool IMPORT = MODE == FR_IMPORT, chk = MODE == FR_CHECK;
+    constexpr int FT = frame_tile(J);
+    constexpr int h = (1 << J) - 1;
+    constexpr int L0 = FT + 2 * h, LE = FT + h;
+    constexpr int NZ = fr_cdiv(L0 * L0, NTF);       // z window values per thread
+    constexpr int NC = fr_cdiv(LE * LE, NTF);       // coefficients per thread and band (largest window)
+    // the z window is stored to LDS unconditionally (positions past it are
+    // overwritten by the analysis after the next barrier)
+    static_assert(fr_aoff(J, J + 1) + 5 * LE * LE >= NZ * NTF, "LDS smaller than the z prefetch");
     extern __shared__ float sm[];
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
     const WorkItem it = items[wi];
     if (info && !info[it.prob].active) return;
     const ProbDesc& p = pd[it.prob];
-    const int H = p.H, W = p.W, J = p.J, FT = p.frm_tile;
-    const int h = (1 << J) - 1;
+    const int H = p.H, W = p.W;
     const int ntx = (W + FT - 1) / FT;
     const int ty = it.start / ntx, tx = it.start - ty * ntx;
     const int r0 = ty * FT, c0 = tx * FT;
+    const unsigned hlim = (unsigned)min(FT, H - r0), wlim = (unsigned)min(FT, W - c0);   // owned part of the tile
     const unsigned n = (unsigned)(H * W);   // planes hold at most 2048^2 values: 32-bit offsets
     const int tid = threadIdx.x;
-    // windows reach h pixels beyond the tile; a single wrap suffices unless the
-    // image is smaller than a window
-    const bool small = H < FT + 2 * h || W < FT + 2 * h;
-    auto wrap = [&](int i, int m) { return small ? wrapm(i, m) : wrap1(i, m); };
+    auto wrap = [&](int i, int m) { return SMALL ? wrapm(i, m) : wrap1(i, m); };
     const float tau = p.tau, mu2 = p.mu2;
-    const bool chk = (flags & F_CHECK) && !import_mode;
 
-    // LDS carve-up: a_0..a_J, three omega planes, two a' planes
-    // (explicit LDS pointers: indexed arrays of generic pointers would become flat accesses)
-    const int L0 = FT + 2 * h, LE = FT + h;
+    // LDS: a_0 .. a_J, three omega planes and two a' planes of LE^2
     ADMM_LDS float* const smem = (ADMM_LDS float*)sm;
-    ADMM_LDS float* a[5];
-    int La[5];
-    int off = 0;
-    for (int j = 0; j <= J; ++j) {
-        La[j] = L0 - ((1 << j) - 1);
-        a[j] = smem + off;
-        off += La[j] * La[j];
-    }
-    ADMM_LDS float* wb[3];
-    for (int b = 0; b < 3; ++b) {
-        wb[b] = smem + off;
-        off += LE * LE;
-    }
-    ADMM_LDS float* ap[2] = {smem + off, smem + off + LE * LE};
+    constexpr int WB0 = fr_aoff(J, J + 1);
+    ADMM_LDS float* const wb0 = smem + WB0;
+    ADMM_LDS float* const wb1 = wb0 + LE * LE;
+    ADMM_LDS float* const wb2 = wb1 + LE * LE;
+    ADMM_LDS float* const ap[2] = {wb2 + LE * LE, wb2 + 2 * LE * LE};
 
     const float* din = par ? p.dreg1 : p.dreg0;
     float* dout = par ? p.dreg0 : p.dreg1;
@@ -93,50 +103,83 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
 #pragma unroll
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
 
-    if (!import_mode) {
-        const unsigned m0 = div_magic((unsigned)L0);
-        for (int idx = tid; idx < L0 * L0; idx += NTF) {
-            const int i = (int)udiv16((unsigned)idx, (unsigned)L0, m0), k = idx - i * L0;
-            a[0][idx] = gld(p.zpl, (unsigned)(wrap(r0 - h + i, H) * W + wrap(c0 - h + k, W)));
+    auto cidx = [&](int band, int i, int k) -> unsigned {
+        return (unsigned)band * n + (unsigned)(wrap(r0 + i, H) * W + wrap(c0 + k, W));
+    };
+
+    // Every global input of the tile is requested before any of it is used: the
+    // z window, then the duals of the coarsest band and of levels J .. 1 over
+    // their coefficient windows, in the order they are consumed. The loads are
+    // unconditional (indices past a window are clamped to its last element), so
+    // each use waits only for the loads issued before it. A check iteration also
+    // fetches u2 of the previous iteration for the dual residual.
+    float zr[NZ], dcv[NC], dlv[J][3][NC], ucv[NC], ulv[J][3][NC];
+    if (!IMPORT) {
+#pragma unroll
+        for (int u = 0; u < NZ; ++u) {
+            const int idx = min(tid + u * NTF, L0 * L0 - 1);
+            const int i = idx / L0, k = idx - i * L0;
+            zr[u] = gld(p.zpl, (unsigned)(wrap(r0 - h + i, H) * W + wrap(c0 - h + k, W)));
         }
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+            const int idx = min(tid + u * NTF, LE * LE - 1);
+            const int ie = idx / LE;
+            const unsigned g = cidx(3 * J, ie - h, idx - ie * LE - h);
+            dcv[u] = gld(din, g);
+            if (chk) ucv[u] = gld(p.uregp, g);
+        }
+#pragma unroll
+        for (int jj = J - 1; jj >= 0; --jj) {
+            const int e = (2 << jj) - 1, Lb = FT + e;     // level jj + 1
+#pragma unroll
+            for (int u = 0; u < NC; ++u) {
+                if (u * NTF < Lb * Lb) {
+                    const int idx = min(tid + u * NTF, Lb * Lb - 1);
+                    const int ii = idx / Lb;
+                    const unsigned g = cidx(3 * jj, ii - e, idx - ii * Lb - e);
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        dlv[jj][b][u] = gld(din, g + (unsigned)b * n);
+                        if (chk) ulv[jj][b][u] = gld(p.uregp, g + (unsigned)b * n);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NZ; ++u) smem[tid + u * NTF] = zr[u];
         __syncthreads();
+#pragma unroll
         for (int j = 1; j <= J; ++j) {
-            const int s = 1 << (j - 1), Lp = La[j - 1], Lc = La[j];
-            const ADMM_LDS float* A = a[j - 1];
-            const unsigned mc = div_magic((unsigned)Lc);
-            for (int idx = tid; idx < Lc * Lc; idx += NTF) {
-                const int i = (int)udiv16((unsigned)idx, (unsigned)Lc, mc), k = idx - i * Lc;
-                const float x00 = A[i * Lp + k], x10 = A[(i + s) * Lp + k];
-                const float x01 = A[i * Lp + k + s], x11 = A[(i + s) * Lp + k + s];
-                const float lv0 = 0.5f * (x00 + x10), lv1 = 0.5f * (x01 + x11);
-                a[j][idx] = 0.5f * (lv0 + lv1);
+            const int s = 1 << (j - 1), Lp = fr_la(J, j - 1), Lc = fr_la(J, j);
+            const ADMM_LDS float* A = smem + fr_aoff(J, j - 1);
+            ADMM_LDS float* An = smem + fr_aoff(J, j);
+#pragma unroll
+            for (int u = 0; u < fr_cdiv(Lc * Lc, NTF); ++u) {
+                const int idx = tid + u * NTF;
+                if (idx < Lc * Lc) {
+                    const int i = idx / Lc, k = idx - i * Lc;
+                    const float x00 = A[i * Lp + k], x10 = A[(i + s) * Lp + k];
+                    const float x01 = A[i * Lp + k + s], x11 = A[(i + s) * Lp + k + s];
+                    const float lv0 = 0.5f * (x00 + x10), lv1 = 0.5f * (x01 + x11);
+                    An[idx] = 0.5f * (lv0 + lv1);
+                }
             }
             __syncthreads();
         }
     }
 
-    // One coefficient of band `band` at tile-relative (i, k): its plane offset,
-    // its dual (the loads of up to CH coefficients per thread are issued
-    // together), then prox, dual update and omega = u2 + d2'.
-    auto cidx = [&](int band, int i, int k) -> unsigned {
-        return (unsigned)band * n + (unsigned)(wrap(r0 + i, H) * W + wrap(c0 + k, W));
-    };
-    auto cload = [&](unsigned g) -> float2 {
-        return import_mode ? make_float2(gld(p.st_dreg, g), gld(p.st_ureg, g)) : make_float2(gld(din, g), 0.0f);
-    };
-    auto coef = [&](float Pz, float2 dl, unsigned g, int i, int k) -> float {
-        const bool own = i >= 0 && k >= 0 && i < FT && k < FT && r0 + i < H && c0 + k < W;
-        if (import_mode) {
-            if (own) gst(dout, g, dl.x);
-            return dl.y + dl.x;
-        }
-        const float v = Pz - dl.x;
+    // One coefficient at tile-relative (i, k), plane offset g, with its dual:
+    // prox, dual update and omega = u2 + d2'. Only the owner of a coefficient
+    // (its tile) writes it back and counts it in the residual sums.
+    auto coef = [&](float Pz, float dl, float uprev, unsigned g, bool own) -> float {
+        const float v = Pz - dl;
         const float u = softf(v, tau);
         const float dn = u - v;                  // d2 - (P z - u2)
         if (own) {
             gst(dout, g, dn);
             if (chk) {
-                const float e = Pz - u, f = u - gld(p.uregp, g);
+                const float e = Pz - u, f = u - uprev;
                 acc[1] += (double)(e * e);
                 acc[3] += (double)(Pz * Pz);
                 acc[5] += (double)(u * u);
@@ -152,101 +195,83 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
         }
         return u + dn;
     };
-    constexpr int CH = 4;
+    auto coef_import = [&](unsigned g, bool own) -> float {
+        const float d = gld(p.st_dreg, g), u = gld(p.st_ureg, g);
+        if (own) gst(dout, g, d);
+        return u + d;
+    };
+    auto owns = [&](int i, int k) { return (unsigned)i < hlim && (unsigned)k < wlim; };
 
     // coarsest low-low band on [-h, FT)^2 -> a'_J
-    const unsigned mE = div_magic((unsigned)LE);
-    for (int base = tid; base < LE * LE; base += CH * NTF) {
-        unsigned g[CH];
-        float2 dl[CH];
-        int iv[CH], kv[CH];
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int idx = min(base + u * NTF, LE * LE - 1);
-            const int ie = (int)udiv16((unsigned)idx, (unsigned)LE, mE);
-            iv[u] = ie - h;
-            kv[u] = idx - ie * LE - h;
-            g[u] = cidx(3 * J, iv[u], kv[u]);
-            if (base + u * NTF < LE * LE) dl[u] = cload(g[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int idx = base + u * NTF;
-            if (idx < LE * LE) ap[0][idx] = coef(import_mode ? 0.0f : a[J][idx], dl[u], g[u], iv[u], kv[u]);
+    for (int u = 0; u < NC; ++u) {
+        const int idx = tid + u * NTF;
+        if (idx < LE * LE) {
+            const int ie = idx / LE;
+            const int i = ie - h, k = idx - ie * LE - h;
+            const unsigned g = cidx(3 * J, i, k);
+            ap[0][idx] = IMPORT ? coef_import(g, owns(i, k)) : coef(smem[fr_aoff(J, J) + idx], dcv[u], chk ? ucv[u] : 0.0f, g, owns(i, k));
         }
     }
     __syncthreads();
-    int cur = 0;
-    for (int j = J; j >= 1; --j) {
-        const int s = 1 << (j - 1), e = (1 << j) - 1, Lb = FT + e;
-        const ADMM_LDS float* A = a[j - 1];
-        const int Lp = La[j - 1];
-        const unsigned mb = div_magic((unsigned)Lb);
-        const int b0 = 3 * (j - 1);
-        for (int base = tid; base < Lb * Lb; base += CH * NTF) {
-            unsigned g[CH][3];
-            float2 dl[CH][3];
-            int iv[CH], kv[CH];
 #pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int idx = min(base + u * NTF, Lb * Lb - 1);
-                const int ii = (int)udiv16((unsigned)idx, (unsigned)Lb, mb), kk = idx - ii * Lb;
-                iv[u] = ii - e;
-                kv[u] = kk - e;
+    for (int jj = J - 1; jj >= 0; --jj) {
+        const int s = 1 << jj, e = (2 << jj) - 1, Lb = FT + e;   // level j = jj + 1
+        const ADMM_LDS float* A = smem + fr_aoff(J, jj);
+        const int Lp = fr_la(J, jj);
+        const ADMM_LDS float* Ap = ap[(J - 1 - jj) & 1];
+        ADMM_LDS float* An = ap[(J - jj) & 1];
 #pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    g[u][b] = cidx(b0 + b, iv[u], kv[u]);
-                    if (base + u * NTF < Lb * Lb) dl[u][b] = cload(g[u][b]);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int idx = base + u * NTF;
-                if (idx >= Lb * Lb) break;
-                const int i = iv[u], k = kv[u];
-                float lh = 0.f, hl = 0.f, hh = 0.f;
-                if (!import_mode) {
+        for (int u = 0; u < NC; ++u) {
+            const int idx = tid + u * NTF;
+            if (idx < Lb * Lb) {
+                const int ii = idx / Lb;
+                const int i = ii - e, k = idx - ii * Lb - e;
+                const unsigned g0 = cidx(3 * jj, i, k), g1 = g0 + n, g2 = g1 + n;
+                const bool own = owns(i, k);
+                if (IMPORT) {
+                    wb0[idx] = coef_import(g0, own);
+                    wb1[idx] = coef_import(g1, own);
+                    wb2[idx] = coef_import(g2, own);
+                } else {
                     const int pi = i + h, pk = k + h;     // position in the a_{j-1} window
                     const float x00 = A[pi * Lp + pk], x10 = A[(pi + s) * Lp + pk];
                     const float x01 = A[pi * Lp + pk + s], x11 = A[(pi + s) * Lp + pk + s];
                     const float lv0 = 0.5f * (x00 + x10), lv1 = 0.5f * (x01 + x11);
                     const float hv0 = 0.5f * (x00 - x10), hv1 = 0.5f * (x01 - x11);
-                    lh = 0.5f * (lv0 - lv1);
-                    hl = 0.5f * (hv0 + hv1);
-                    hh = 0.5f * (hv0 - hv1);
+                    wb0[idx] = coef(0.5f * (lv0 - lv1), dlv[jj][0][u], chk ? ulv[jj][0][u] : 0.0f, g0, own);
+                    wb1[idx] = coef(0.5f * (hv0 + hv1), dlv[jj][1][u], chk ? ulv[jj][1][u] : 0.0f, g1, own);
+                    wb2[idx] = coef(0.5f * (hv0 - hv1), dlv[jj][2][u], chk ? ulv[jj][2][u] : 0.0f, g2, own);
                 }
-                wb[0][idx] = coef(lh, dl[u][0], g[u][0], i, k);
-                wb[1][idx] = coef(hl, dl[u][1], g[u][1], i, k);
-                wb[2][idx] = coef(hh, dl[u][2], g[u][2], i, k);
             }
         }
         __syncthreads();
         // synthesis a'_{j-1} on [-(s-1), FT)^2 from level-j planes on [-e, FT)^2 (stride Lb)
         const int Lc = FT + s - 1;
-        const ADMM_LDS float* Ap = ap[cur];
-        ADMM_LDS float* An = ap[cur ^ 1];
-        const unsigned mc = div_magic((unsigned)Lc);
-        for (int idx = tid; idx < Lc * Lc; idx += NTF) {
-            const int ci = (int)udiv16((unsigned)idx, (unsigned)Lc, mc), ck = idx - ci * Lc;
-            const int ii = ci - (s - 1) + e, kk = ck - (s - 1) + e;     // >= s by construction
-            const int q0 = ii * Lb + kk, q1 = ii * Lb + kk - s, q2 = (ii - s) * Lb + kk, q3 = (ii - s) * Lb + kk - s;
-            // horizontal adjoints of the rows ii and ii - s
-            const float lvA = 0.5f * ((Ap[q0] + Ap[q1]) + (wb[0][q0] - wb[0][q1]));
-            const float hvA = 0.5f * ((wb[1][q0] + wb[1][q1]) + (wb[2][q0] - wb[2][q1]));
-            const float lvB = 0.5f * ((Ap[q2] + Ap[q3]) + (wb[0][q2] - wb[0][q3]));
-            const float hvB = 0.5f * ((wb[1][q2] + wb[1][q3]) + (wb[2][q2] - wb[2][q3]));
-            An[idx] = 0.5f * ((lvA + lvB) + (hvA - hvB));
+#pragma unroll
+        for (int u = 0; u < fr_cdiv(Lc * Lc, NTF); ++u) {
+            const int idx = tid + u * NTF;
+            if (idx < Lc * Lc) {
+                const int ci = idx / Lc, ck = idx - ci * Lc;
+                const int ii = ci - (s - 1) + e, kk = ck - (s - 1) + e;     // >= s by construction
+                const int q0 = ii * Lb + kk, q1 = ii * Lb + kk - s, q2 = (ii - s) * Lb + kk, q3 = (ii - s) * Lb + kk - s;
+                // horizontal adjoints of the rows ii and ii - s
+                const float lvA = 0.5f * ((Ap[q0] + Ap[q1]) + (wb0[q0] - wb0[q1]));
+                const float hvA = 0.5f * ((wb1[q0] + wb1[q1]) + (wb2[q0] - wb2[q1]));
+                const float lvB = 0.5f * ((Ap[q2] + Ap[q3]) + (wb0[q2] - wb0[q3]));
+                const float hvB = 0.5f * ((wb1[q2] + wb1[q3]) + (wb2[q2] - wb2[q3]));
+                An[idx] = 0.5f * ((lvA + lvB) + (hvA - hvB));
+            }
         }
         __syncthreads();
-        cur ^= 1;
     }
-    // q = mu2 P^T omega on the tile
-    const ADMM_LDS float* Af = ap[cur];
-    const unsigned mf = div_magic((unsigned)FT);
-    for (int idx = tid; idx < FT * FT; idx += NTF) {
-        const int i = (int)udiv16((unsigned)idx, (unsigned)FT, mf), k = idx - i * FT;
-        const int gr = r0 + i, gc = c0 + k;
-        if (gr < H && gc < W) gst(p.tmpB, (unsigned)(gr * W + gc), mu2 * Af[idx]);
+    // q = mu2 P^T omega on the tile (a'_0 is ap[J & 1])
+    const ADMM_LDS float* Af = ap[J & 1];
+#pragma unroll
+    for (int u = 0; u < fr_cdiv(FT * FT, NTF); ++u) {
+        const int idx = tid + u * NTF;
+        const int i = idx / FT, k = idx - i * FT;
+        if ((unsigned)i < hlim && (unsigned)k < wlim) gst(p.tmpB, (unsigned)((r0 + i) * W + c0 + k), mu2 * Af[idx]);
     }
     if (chk) {
         const int lane = tid & 63, wave = tid >> 6;
@@ -276,23 +301,54 @@ __global__ void k_import_fa(const ProbDesc* __restrict__ pd, int prob) {
     gst(p.d1, g, gld(p.st_d1, g));
 }
 
-size_t lds_frame_bytes(int FT, int J) {
-    const int h = (1 << J) - 1, L0 = FT + 2 * h, LE = FT + h;
-    size_t f = 0;
-    for (int j = 0; j <= J; ++j) {
-        const size_t L = L0 - ((1 << j) - 1);
-        f += L * L;
-    }
-    f += 5 * (size_t)LE * LE;
-    size_t b = f * sizeof(float);
+int frame_class(int H, int W, int J) {
+    const int w = frame_tile(J) + 2 * ((1 << J) - 1);
+    return 2 * (J - 1) + ((H < w || W < w) ? 1 : 0);
+}
+
+size_t lds_frame_bytes(int J) {
+    const int LE = frame_tile(J) + (1 << J) - 1;
+    const size_t b = (size_t)(fr_aoff(J, J + 1) + 5 * LE * LE) * sizeof(float);
     const size_t need = NTF / 64 * ADMM_NSUM * sizeof(double);
     return b > need ? b : need;
 }
 
+namespace {
+template <int J, bool SMALL>
+void launch_frame_class(const LaunchCtx& L, int c, int par, int flags, int import_mode, bool gated) {
+    const WorkItem* it = L.frm_items + L.frm_beg[c];
+    const int n = L.frm_cnt[c];
+    const InfoDev* info = gated ? L.info : nullptr;
+    if (import_mode)
+        hipLaunchKernelGGL((k_frame<J, SMALL, FR_IMPORT>), dim3(n), dim3(NTF), L.lds_frm_c[c], L.stream, L.desc, it, n,
+                           par, flags, info, L.partials);
+    else if (flags & F_CHECK)
+        hipLaunchKernelGGL((k_frame<J, SMALL, FR_CHECK>), dim3(n), dim3(NTF), L.lds_frm_c[c], L.stream, L.desc, it, n,
+                           par, flags, info, L.partials);
+    else
+        hipLaunchKernelGGL((k_frame<J, SMALL, FR_PLAIN>), dim3(n), dim3(NTF), L.lds_frm_c[c], L.stream, L.desc, it, n,
+                           par, flags, info, L.partials);
+}
+}  // namespace
+
+// One launch per frame class (levels, small image) that has items.
 hipError_t launch_frame(const LaunchCtx& L, int par, int flags, int import_mode, bool gated) {
-    hipLaunchKernelGGL(k_frame, dim3(L.nfrm), dim3(NTF), L.lds_frm, L.stream, L.desc, L.frm_items, L.nfrm, par,
-                       flags, import_mode, gated ? L.info : nullptr, L.partials);
-    return hipGetLastError();
+    for (int c = 0; c < ADMM_FRAME_CLASSES; ++c) {
+        if (!L.frm_items || L.frm_cnt[c] == 0) continue;
+        switch (c) {
+            case 0: launch_frame_class<1, false>(L, c, par, flags, import_mode, gated); break;
+            case 1: launch_frame_class<1, true>(L, c, par, flags, import_mode, gated); break;
+            case 2: launch_frame_class<2, false>(L, c, par, flags, import_mode, gated); break;
+            case 3: launch_frame_class<2, true>(L, c, par, flags, import_mode, gated); break;
+            case 4: launch_frame_class<3, false>(L, c, par, flags, import_mode, gated); break;
+            case 5: launch_frame_class<3, true>(L, c, par, flags, import_mode, gated); break;
+            case 6: launch_frame_class<4, false>(L, c, par, flags, import_mode, gated); break;
+            default: launch_frame_class<4, true>(L, c, par, flags, import_mode, gated); break;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_import_fa(const LaunchCtx& L, int prob, size_t n) {

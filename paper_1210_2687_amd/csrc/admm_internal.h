@@ -100,6 +100,10 @@ struct FftPlanDev {
     unsigned mns[ADMM_MAX_STAGES];
 };
 
+// Frame tiles: 32 x 32 up to three levels, 16 x 16 at four (the windows reach
+// 2^J - 1 pixels beyond the tile on each side).
+__host__ __device__ constexpr int frame_tile(int J) { return J >= 4 ? 16 : 32; }
+
 // exact division for operands below 2^16 by a divisor with multiplier m = ceil(2^32 / d)
 __host__ __device__ inline unsigned div_magic(unsigned d) { return d <= 1 ? 0u : (unsigned)((0x100000000ull + d - 1) / d); }
 __device__ __forceinline__ unsigned udiv16(unsigned x, unsigned d, unsigned m) { return d == 1 ? x : __umulhi(x, m); }

@@ -5,6 +5,8 @@
 
 namespace admm {
 
+constexpr int ADMM_FRAME_CLASSES = 8;
+
 // Everything a launch needs; item lists are device arrays, counts are the grid sizes.
 struct LaunchCtx {
     hipStream_t stream = nullptr;
@@ -26,6 +28,10 @@ struct LaunchCtx {
     int col_beg[3] = {0, 0, 0}, col_cnt[3] = {0, 0, 0};
     int rtv_beg[3] = {0, 0, 0}, rtv_cnt[3] = {0, 0, 0};
     size_t lds_col_c[3] = {0, 0, 0}, lds_rtv_c[3] = {0, 0, 0};
+    // frame classes (levels 1..4, image smaller than a window or not): items of
+    // class c are [frm_beg[c], frm_beg[c] + frm_cnt[c]) of frm_items
+    int frm_beg[ADMM_FRAME_CLASSES] = {}, frm_cnt[ADMM_FRAME_CLASSES] = {};
+    size_t lds_frm_c[ADMM_FRAME_CLASSES] = {};
 };
 
 hipError_t launch_col(const LaunchCtx& L, int par, int mode);
@@ -44,7 +50,8 @@ hipError_t allow_dynamic_lds(int bytes);
 size_t lds_col_bytes(int H, int TC);
 size_t lds_rowtv_bytes(int W, int B);
 size_t lds_row_bytes(int W, int B);
-size_t lds_frame_bytes(int FT, int J);
+size_t lds_frame_bytes(int J);
+int frame_class(int H, int W, int J);       // 2 (J - 1) + (image smaller than a window)
 int col_max_tiles();                       // columns per column-pass block (one per wave)
 int row_tv_max_rows(int w);                  // rows per block of the TV row pass for width w
 int size_class(int n);                      // 0: n <= 512, 1: n <= 1024, 2: larger
