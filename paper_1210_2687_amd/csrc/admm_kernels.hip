@@ -25,6 +25,7 @@ namespace admm {
 
 constexpr int NT = 512;            // threads per block of the FFT passes
 constexpr int MAXE_ROW = 16;       // float2 elements per thread in the row passes
+constexpr int ROW_BURST = 8;       // plane elements per thread fetched together by the FA row passes
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -263,24 +264,50 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
 // ------------------------------------------------------------ row helpers
 // Load transposed half-spectrum rows [rbeg, rbeg + nrows) (wrapping mod H) as
 // full complex rows Y = z^ + i A z^ (Hermitian completion of both halves), row
-// rr at X + rr pitch, padded (pidx) if PAD.
+// rr at X + rr pitch, padded (pidx) if PAD. The first NLD entries of each
+// thread are fetched in one burst of unconditional loads (indices past the
+// end clamped to the last entry) so that one memory latency covers them; the
+// loop after it takes any remainder (none when P nrows <= NLD NT, which the
+// launch configurations guarantee). The stage table of the row transforms
+// (n entries, when twl is given) is fetched behind the burst.
 template <bool PAD>
+__device__ __forceinline__ void store_hermitian(float2* X, int pitch, int W, int P, int k2, int rr, float4 f) {
+    float2* row = X + rr * pitch;
+    if (k2 == 0 || 2 * k2 == W) {
+        row[PAD ? pidx(k2) : k2] = make_float2(f.x, f.z);  // real parts only at DC / Nyquist
+    } else {
+        row[PAD ? pidx(k2) : k2] = make_float2(f.x - f.w, f.y + f.z);
+        if (k2 <= W - P) row[PAD ? pidx(W - k2) : W - k2] = make_float2(f.x + f.w, f.z - f.y);
+    }
+}
+
+template <bool PAD, int NLD>
 __device__ __forceinline__ void load_rows_hermitian(float2* X, int pitch, const float4* __restrict__ S, int H, int W,
-                                                    int P, int rbeg, int nrows, int tid) {
+                                                    int P, int rbeg, int nrows, int tid, float2* twl = nullptr,
+                                                    const float2* __restrict__ tw = nullptr, int ntw = 0) {
     const int tot = P * nrows;
     const unsigned mr = div_magic((unsigned)nrows);
-    for (int i = tid; i < tot; i += NT) {
+    float4 f[NLD];
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+        const int i = min(tid + u * NT, tot - 1);
+        const int k2 = (int)udiv16((unsigned)i, (unsigned)nrows, mr);
+        const int r = wrapi(rbeg + i - k2 * nrows, H);
+        f[u] = gld(S, (unsigned)(k2 * H + r));
+    }
+    if (twl) load_twiddles(twl, tw, ntw, tid, NT);
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+        const int i = tid + u * NT;
+        if (i < tot) {
+            const int k2 = (int)udiv16((unsigned)i, (unsigned)nrows, mr);
+            store_hermitian<PAD>(X, pitch, W, P, k2, i - k2 * nrows, f[u]);
+        }
+    }
+    for (int i = tid + NLD * NT; i < tot; i += NT) {
         const int k2 = (int)udiv16((unsigned)i, (unsigned)nrows, mr);
         const int rr = i - k2 * nrows;
-        const int r = wrapi(rbeg + rr, H);
-        const float4 f = gld(S, (unsigned)(k2 * H + r));
-        float2* row = X + rr * pitch;
-        if (k2 == 0 || 2 * k2 == W) {
-            row[PAD ? pidx(k2) : k2] = make_float2(f.x, f.z);  // real parts only at DC / Nyquist
-        } else {
-            row[PAD ? pidx(k2) : k2] = make_float2(f.x - f.w, f.y + f.z);
-            if (k2 <= W - P) row[PAD ? pidx(W - k2) : W - k2] = make_float2(f.x + f.w, f.z - f.y);
-        }
+        store_hermitian<PAD>(X, pitch, W, P, k2, rr, gld(S, (unsigned)(k2 * H + wrapi(rbeg + rr, H))));
     }
 }
 
@@ -320,6 +347,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     const ProbDesc& p = pd[it.prob];
     const int H = p.H, W = p.W, P = p.P, r0 = it.start;
     const int nr = min(p.B, H - r0);
+    __builtin_assume(nr >= 1);
     const int nrh = nr + 2;
     const int tid = threadIdx.x;
     const unsigned n = (unsigned)(H * W);   // planes hold at most 2048^2 values: 32-bit offsets
@@ -334,8 +362,9 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     float* dh_out = par ? p.dreg0 : p.dreg1;
     float* dv_out = dh_out + n;
 
-    load_twiddles(twl, tw + p.fr.tw_off + W, W, tid, NT);   // the stage table
-    load_rows_hermitian<true>(X, pitch, Sin, H, W, P, r0 - 1, nrh, tid);
+    // spectrum rows r0 - 1 .. r0 + nr (P <= NT CPT / 2 + 1 entries each), then the stage table
+    constexpr int NLD = ((NT * CPT / 2 + 1) * (RB + 2) + NT - 1) / NT;
+    load_rows_hermitian<true, NLD>(X, pitch, Sin, H, W, P, r0 - 1, nrh, tid, twl, tw + p.fr.tw_off + W, W);
     __syncthreads();
     rows_fft<NT * CPT, NT, RB + 2, MAXE, true>(X, pitch, p.fr, twl, nrh, tid);
     // X[rr][c] = z + i A z for row r0 - 1 + rr
@@ -346,25 +375,23 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
 #pragma unroll
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
 
-    // burst of epilogue loads: duals of rows r0-1 .. r0+nr-1, data of rows r0 .. r0+nr-1
+    // burst of epilogue loads: duals of rows r0-1 .. r0+nr-1, data of rows r0 .. r0+nr-1;
+    // unconditional (rows past nr and columns past W are clamped to valid ones and
+    // never used), so that no load waits for another
     float pdh[CPT][RB + 1], pdv[CPT][RB + 1], pd1[CPT][RB], py[CPT][RB];
-    bool pob[CPT][RB];
+    uint8_t pmk[CPT][RB];
 #pragma unroll
     for (int rr = 0; rr <= RB; ++rr) {
-        if (rr > nr) break;
-        const int r = wrapi(r0 - 1 + rr, H);
+        const int r = wrapi(r0 - 1 + min(rr, nr), H);
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
-            const int c = tid + j * NT;
-            if (c < W) {
-                const unsigned g = (unsigned)(r * W + c);
-                pdh[j][rr] = gld(dh_in, g);
-                pdv[j][rr] = gld(dv_in, g);
-                if (rr > 0) {
-                    pd1[j][rr - 1] = gld(p.d1, g);
-                    pob[j][rr - 1] = gld(p.mask, g) != 0;
-                    py[j][rr - 1] = gld(p.y, g);
-                }
+            const unsigned g = (unsigned)(r * W + min(tid + j * NT, W - 1));
+            pdh[j][rr] = gld(dh_in, g);
+            pdv[j][rr] = gld(dv_in, g);
+            if (rr > 0) {
+                pd1[j][rr - 1] = gld(p.d1, g);
+                pmk[j][rr - 1] = gld(p.mask, g);
+                py[j][rr - 1] = gld(p.y, g);
             }
         }
     }
@@ -377,10 +404,14 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
         const float2* Xr = X + rr * pitch;
         const float2* Xn = Xr + pitch;
         float* dlr = dl + (rr & 1) * W;
+        // every lane computes (lanes past W on the last column, identical values),
+        // only the global stores and the sums are guarded: the loaded values are
+        // then used outside any branch and stay in the burst
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
-            const int c = tid + j * NT;
-            if (c < W) {
+            const bool live = tid + j * NT < W;
+            const int c = live ? tid + j * NT : W - 1;
+            {
                 const float2 xc = Xr[pidx(c)];
                 const float zc = xc.x;
                 const float zh = Xr[pidx(c + 1 == W ? 0 : c + 1)].x - zc;
@@ -399,15 +430,16 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                 if (rr > 0) {
                     const float Az = xc.y;
                     const float d1o = pd1[j][rr - 1];
-                    const bool obs = pob[j][rr - 1];
+                    const bool obs = pmk[j][rr - 1] != 0;
                     const float yv = obs ? py[j][rr - 1] : 0.0f;
                     const float v1 = Az - d1o;
                     const float u1 = obs ? fmaf(yv - v1, c1, v1) : v1;   // (y + mu1 v)/(1 + mu1) or v
                     const float d1n = u1 - v1;                           // d1 - (A z - u1)
+                    zet[j] = u1 + d1n;
+                  if (live) {
                     gst(p.d1, g, d1n);
                     gst(dh_out, g, dhn);
                     gst(dv_out, g, dvn);
-                    zet[j] = u1 + d1n;
                     if (flags & F_WRITE_X) gst(p.x, g, zc);
                     if (chk) {
                         const float u1q = gld(p.u1p, g), uhq = gld(p.uregp, g), uvq = gld(p.uregp, n + g);
@@ -440,6 +472,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                         gst(p.st_dreg, g, dhn);
                         gst(p.st_dreg, n + g, dvn);
                     }
+                  }
                 }
             }
         }
@@ -448,11 +481,9 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
             float2* Xw = X + rr * pitch;
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const int c = tid + j * NT;
-                if (c < W) {
-                    const float s = mu2 * ((dlr[c == 0 ? W - 1 : c - 1] - dlr[c]) + (dvp[j] - dvc[j]));
-                    Xw[pidx(c)] = make_float2(p.mu1 * zet[j], s);
-                }
+                const int c = min(tid + j * NT, W - 1);
+                const float s = mu2 * ((dlr[c == 0 ? W - 1 : c - 1] - dlr[c]) + (dvp[j] - dvc[j]));
+                Xw[pidx(c)] = make_float2(p.mu1 * zet[j], s);
             }
         }
 #pragma unroll
@@ -486,11 +517,22 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
     const int tot = nr * W;
     const float mu1 = p.mu1;
     float2* twl = X + (size_t)p.B * W;
-    load_twiddles(twl, tw + p.fr.tw_off + W, W, tid, NT);   // the stage table
-    if (src == 0) {
-        for (int i = tid; i < tot; i += NT) X[i] = make_float2(mu1 * gld(a, i), gld(b, i));
-    } else {
-        for (int i = tid; i < tot; i += NT) X[i] = make_float2(gld(a, i), 0.0f);
+    // bursts of ROW_BURST unconditional loads per thread (indices clamped), the
+    // stage table behind the first one
+    for (int base = tid; base < tot; base += ROW_BURST * NT) {
+        float va[ROW_BURST], vb[ROW_BURST];
+#pragma unroll
+        for (int u = 0; u < ROW_BURST; ++u) {
+            const int i = min(base + u * NT, tot - 1);
+            va[u] = gld(a, i);
+            vb[u] = src == 0 ? gld(b, i) : 0.0f;
+        }
+        if (base == tid) load_twiddles(twl, tw + p.fr.tw_off + W, W, tid, NT);
+#pragma unroll
+        for (int u = 0; u < ROW_BURST; ++u) {
+            const int i = base + u * NT;
+            if (i < tot) X[i] = src == 0 ? make_float2(mu1 * va[u], vb[u]) : make_float2(va[u], 0.0f);
+        }
     }
     __syncthreads();
     fft_lds<MAXE, false, false>(X, p.fr, twl, nr, W, tid, NT);
@@ -515,8 +557,9 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     const int nr = min(p.B, H - r0);
     const int tid = threadIdx.x;
     float2* twl = X + (size_t)p.B * W;
-    load_twiddles(twl, tw + p.fr.tw_off + W, W, tid, NT);   // the stage table
-    load_rows_hermitian<false>(X, W, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
+    // nr W <= MAXE NT, so P nr <= (MAXE / 2 + 1) NT except for very short rows
+    load_rows_hermitian<false, MAXE / 2 + 1>(X, W, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid, twl,
+                                              tw + p.fr.tw_off + W, W);
     __syncthreads();
     fft_lds<MAXE, true, false>(X, p.fr, twl, nr, W, tid, NT);
     const int tot = nr * W;
@@ -530,12 +573,26 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     double acc[ADMM_NSUM];
 #pragma unroll
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
-    for (int i = tid; i < tot; i += NT) {
+    for (int base = tid; base < tot; base += ROW_BURST * NT) {
+      // one burst of unconditional loads (indices clamped) per ROW_BURST elements
+      float d1b[ROW_BURST], yb[ROW_BURST];
+      uint8_t mb[ROW_BURST];
+#pragma unroll
+      for (int u = 0; u < ROW_BURST; ++u) {
+        const unsigned g = off + (unsigned)min(base + u * NT, tot - 1);
+        d1b[u] = gld(p.d1, g);
+        mb[u] = gld(p.mask, g);
+        yb[u] = gld(p.y, g);
+      }
+#pragma unroll
+      for (int u = 0; u < ROW_BURST; ++u) {
+        const int i = base + u * NT;
+        if (i >= tot) break;
         const unsigned g = off + i;
         const float z = X[i].x, Az = X[i].y;
-        const float d1o = gld(p.d1, g);
-        const bool obs = gld(p.mask, g) != 0;
-        const float yv = obs ? gld(p.y, g) : 0.0f;
+        const float d1o = d1b[u];
+        const bool obs = mb[u] != 0;
+        const float yv = obs ? yb[u] : 0.0f;
         const float v1 = Az - d1o;
         const float u1 = obs ? fmaf(yv - v1, c1, v1) : v1;
         const float d1n = u1 - v1;
@@ -557,6 +614,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
             gst(p.st_u1, g, u1);
             gst(p.st_d1, g, d1n);
         }
+      }
     }
     if (chk) block_sums_write(acc, reinterpret_cast<double*>(X), partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM);
 }
