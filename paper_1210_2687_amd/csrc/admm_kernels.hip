@@ -140,7 +140,7 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
         }
     }
     float2* twg = reinterpret_cast<float2*>(cl);
-    load_twiddles(twg, tw + p.fc.tw_off + H, H, tid, NTC);   // the stage table
+    load_twiddles<(64 * EPL + NTC - 1) / NTC>(twg, tw + p.fc.tw_off + H, H, tid, NTC);   // the stage table
     __syncthreads();
     if (!live) return;
     const ADMM_LDS float2* stw = (const ADMM_LDS float2*)twg;
@@ -281,7 +281,7 @@ __device__ __forceinline__ void store_hermitian(float2* X, int pitch, int W, int
     }
 }
 
-template <bool PAD, int NLD>
+template <bool PAD, int NLD, int NTW = 1>
 __device__ __forceinline__ void load_rows_hermitian(float2* X, int pitch, const float4* __restrict__ S, int H, int W,
                                                     int P, int rbeg, int nrows, int tid, float2* twl = nullptr,
                                                     const float2* __restrict__ tw = nullptr, int ntw = 0) {
@@ -295,7 +295,7 @@ __device__ __forceinline__ void load_rows_hermitian(float2* X, int pitch, const 
         const int r = wrapi(rbeg + i - k2 * nrows, H);
         f[u] = gld(S, (unsigned)(k2 * H + r));
     }
-    if (twl) load_twiddles(twl, tw, ntw, tid, NT);
+    if (twl) load_twiddles<NTW>(twl, tw, ntw, tid, NT);
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
         const int i = tid + u * NT;
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
 
     // spectrum rows r0 - 1 .. r0 + nr (P <= NT CPT / 2 + 1 entries each), then the stage table
     constexpr int NLD = ((NT * CPT / 2 + 1) * (RB + 2) + NT - 1) / NT;
-    load_rows_hermitian<true, NLD>(X, pitch, Sin, H, W, P, r0 - 1, nrh, tid, twl, tw + p.fr.tw_off + W, W);
+    load_rows_hermitian<true, NLD, CPT>(X, pitch, Sin, H, W, P, r0 - 1, nrh, tid, twl, tw + p.fr.tw_off + W, W);
     __syncthreads();
     rows_fft<NT * CPT, NT, RB + 2, MAXE, true>(X, pitch, p.fr, twl, nrh, tid);
     // X[rr][c] = z + i A z for row r0 - 1 + rr
@@ -517,17 +517,27 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
     const int tot = nr * W;
     const float mu1 = p.mu1;
     float2* twl = X + (size_t)p.B * W;
-    // bursts of ROW_BURST unconditional loads per thread (indices clamped), the
-    // stage table behind the first one
+    // the stage table, then bursts of ROW_BURST unconditional loads of both planes
+    // per thread (indices clamped; the second plane is read but not used for
+    // src 1), so that each burst costs one memory latency
+    constexpr int NTW = ADMM_MAX_SIDE / NT;
+    const float2* tws = tw + p.fr.tw_off + W;
+    float2 tv[NTW];
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) tv[u] = gld(tws, (unsigned)min(tid + u * NT, W - 1));
     for (int base = tid; base < tot; base += ROW_BURST * NT) {
         float va[ROW_BURST], vb[ROW_BURST];
 #pragma unroll
         for (int u = 0; u < ROW_BURST; ++u) {
-            const int i = min(base + u * NT, tot - 1);
+            const unsigned i = (unsigned)min(base + u * NT, tot - 1);
             va[u] = gld(a, i);
-            vb[u] = src == 0 ? gld(b, i) : 0.0f;
+            vb[u] = gld(b, i);
         }
-        if (base == tid) load_twiddles(twl, tw + p.fr.tw_off + W, W, tid, NT);
+        if (base == tid) {   // every thread below W takes this pass: tot = nr W >= W
+#pragma unroll
+            for (int u = 0; u < NTW; ++u)
+                if (tid + u * NT < W) twl[tid + u * NT] = tv[u];
+        }
 #pragma unroll
         for (int u = 0; u < ROW_BURST; ++u) {
             const int i = base + u * NT;
@@ -558,7 +568,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     const int tid = threadIdx.x;
     float2* twl = X + (size_t)p.B * W;
     // nr W <= MAXE NT, so P nr <= (MAXE / 2 + 1) NT except for very short rows
-    load_rows_hermitian<false, MAXE / 2 + 1>(X, W, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid, twl,
+    load_rows_hermitian<false, MAXE / 2 + 1, ADMM_MAX_SIDE / NT>(X, W, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid, twl,
                                               tw + p.fr.tw_off + W, W);
     __syncthreads();
     fft_lds<MAXE, true, false>(X, p.fr, twl, nr, W, tid, NT);

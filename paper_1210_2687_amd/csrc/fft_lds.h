@@ -597,8 +597,21 @@ __device__ __forceinline__ void rows_fft(E* gbuf, int pitch, const FftPlanDev& f
 }
 
 // Copy the length-N twiddle table to LDS (before the first barrier of a kernel).
+// The N entries of a stage table into LDS: the first NPT per thread in one
+// burst of unconditional loads (indices clamped to the last entry), any
+// remainder in a loop.
+template <int NPT>
 __device__ __forceinline__ void load_twiddles(float2* twl, const float2* __restrict__ tw, int N, int tid, int nthr) {
-    for (int i = tid; i < N; i += nthr) twl[i] = tw[i];
+    if (N <= 0) return;
+    float2 t[NPT];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) t[u] = tw[min(tid + u * nthr, N - 1)];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        const int i = tid + u * nthr;
+        if (i < N) twl[i] = t[u];
+    }
+    for (int i = tid + NPT * nthr; i < N; i += nthr) twl[i] = tw[i];
 }
 
 }  // namespace admm
