@@ -26,6 +26,10 @@ namespace admm {
 constexpr int NT = 512;            // threads per block of the FFT passes
 constexpr int MAXE_ROW = 16;       // float2 elements per thread in the row passes
 constexpr int ROW_BURST = 8;       // plane elements per thread fetched together by the FA row passes
+// rows of the TV row pass's epilogue inputs requested before its inverse
+// transforms, per size class (as many as keep the kernel at 128 VGPRs or fewer,
+// two blocks per compute unit)
+constexpr int RTV_EARLY[3] = {5, 3, 1};
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -336,7 +340,7 @@ __device__ __forceinline__ void store_rows_split(const float2* X, int pitch, flo
 // inputs of the epilogue are loaded in one burst after the inverse transform
 // (register arrays indexed by the unrolled row loop), so the row steps, which
 // exchange delta^h through LDS, wait on memory once rather than once per row.
-template <int MAXE, int CPT, int RB>
+template <int MAXE, int CPT, int RB, int EARLY>
 __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                int nitems, int par, int flags, const InfoDev* __restrict__ info,
                                                const float2* __restrict__ tw, double* __restrict__ partials) {
@@ -365,23 +369,15 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     // spectrum rows r0 - 1 .. r0 + nr (P <= NT CPT / 2 + 1 entries each), then the stage table
     constexpr int NLD = ((NT * CPT / 2 + 1) * (RB + 2) + NT - 1) / NT;
     load_rows_hermitian<true, NLD, CPT>(X, pitch, Sin, H, W, P, r0 - 1, nrh, tid, twl, tw + p.fr.tw_off + W, W);
-    __syncthreads();
-    rows_fft<NT * CPT, NT, RB + 2, MAXE, true>(X, pitch, p.fr, twl, nrh, tid);
-    // X[rr][c] = z + i A z for row r0 - 1 + rr
 
-    const float tau = p.tau, mu2 = p.mu2, c1 = p.inv1pmu1;
-    const bool chk = flags & F_CHECK;
-    double acc[ADMM_NSUM];
-#pragma unroll
-    for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
-
-    // burst of epilogue loads: duals of rows r0-1 .. r0+nr-1, data of rows r0 .. r0+nr-1;
-    // unconditional (rows past nr and columns past W are clamped to valid ones and
-    // never used), so that no load waits for another
+    // Epilogue inputs: duals of rows r0-1 .. r0+nr-1, data of rows r0 .. r0+nr-1,
+    // fetched unconditionally (rows past nr and columns past W are clamped to
+    // valid ones and never used), so that no load waits for another. The first
+    // EARLY rows are requested before the inverse transforms, whose arithmetic
+    // then covers their latency; the rest after them (register budget).
     float pdh[CPT][RB + 1], pdv[CPT][RB + 1], pd1[CPT][RB], py[CPT][RB];
     uint8_t pmk[CPT][RB];
-#pragma unroll
-    for (int rr = 0; rr <= RB; ++rr) {
+    auto fetch_row = [&](int rr) {
         const int r = wrapi(r0 - 1 + min(rr, nr), H);
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
@@ -394,7 +390,21 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                 py[j][rr - 1] = gld(p.y, g);
             }
         }
-    }
+    };
+#pragma unroll
+    for (int rr = 0; rr < EARLY; ++rr) fetch_row(rr);
+    __syncthreads();
+    rows_fft<NT * CPT, NT, RB + 2, MAXE, true>(X, pitch, p.fr, twl, nrh, tid);
+    // X[rr][c] = z + i A z for row r0 - 1 + rr
+
+    const float tau = p.tau, mu2 = p.mu2, c1 = p.inv1pmu1;
+    const bool chk = flags & F_CHECK;
+    double acc[ADMM_NSUM];
+#pragma unroll
+    for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
+
+#pragma unroll
+    for (int rr = EARLY; rr <= RB; ++rr) fetch_row(rr);   // the rest of the epilogue burst
     float dvp[CPT], zet[CPT], dvc[CPT];
 
 #pragma unroll
@@ -804,13 +814,13 @@ hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags) {
         if (!n) continue;
         const WorkItem* it = L.row_items + L.rtv_beg[c];
         if (c == 0)
-            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 1, 8>), dim3(n), dim3(NT), L.lds_rtv_c[0], L.stream, L.desc, it, n,
+            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0]>), dim3(n), dim3(NT), L.lds_rtv_c[0], L.stream, L.desc, it, n,
                                par, flags, L.info, L.tw, L.partials);
         else if (c == 1)
-            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 2, 6>), dim3(n), dim3(NT), L.lds_rtv_c[1], L.stream, L.desc, it, n,
+            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1]>), dim3(n), dim3(NT), L.lds_rtv_c[1], L.stream, L.desc, it, n,
                                par, flags, L.info, L.tw, L.partials);
         else
-            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 4, 2>), dim3(n), dim3(NT), L.lds_rtv_c[2], L.stream, L.desc, it, n,
+            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 4, 2, RTV_EARLY[2]>), dim3(n), dim3(NT), L.lds_rtv_c[2], L.stream, L.desc, it, n,
                                par, flags, L.info, L.tw, L.partials);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -862,9 +872,9 @@ hipError_t allow_dynamic_lds(int bytes) {
     const void* fns[] = {
         reinterpret_cast<const void*>(&k_col<8>),     reinterpret_cast<const void*>(&k_col<16>),
         reinterpret_cast<const void*>(&k_col<32>),
-        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8>),
-        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6>),
-        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 4, 2>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0]>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1]>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 4, 2, RTV_EARLY[2]>),
         reinterpret_cast<const void*>(&k_row_fwd<MAXE_ROW>),
         reinterpret_cast<const void*>(&k_row_inv<MAXE_ROW>)};
     for (const void* f : fns) {
