@@ -133,3 +133,50 @@ def test_tolerance_batch_stops_each_problem_independently():
         F = lambda z: O.tv_objective(z, p.y, p.mask, p.kernel, p.lam)
         assert abs(F(host(x)) - F(ref["z"])) <= 2e-5 * F(ref["z"])
     assert len(iters) > 1      # problems stopped at their own iterations
+
+
+def _fa_small(seed, H, W, J):
+    g = WL.rng(seed)
+    x = WL.synth_image(g, H, W)
+    h = WL.kernel_disk(2.0)
+    m = WL.valid_mask(H, W, h.shape[0] // 2)
+    m &= (g.uniform(size=(H, W)) >= 0.2).astype(np.uint8)
+    return WL.Problem(y=WL.observe(g, x, h, m, 1e-3), mask=m, kernel=h, lam=5e-4, mu1=0.02, mu2=0.01,
+                      reg="frame", levels=J)
+
+
+# (H, W, J): images narrower than the frame window FT + 2 (2^J - 1) (46 at J = 3 and 4, 38 at
+# J = 2, 34 at J = 1) wrap their windows more than once; mixed with ordinary ones in one batch
+SMALL_MIX = [(40, 56, 3), (32, 32, 4), (24, 36, 2), (20, 28, 1), (64, 48, 3), (48, 40, 1), (50, 60, 4)]
+
+
+def test_frame_classes_small_images_mixed_levels():
+    import torch
+    announce("frame classes: small images, levels 1..4, one batch")
+    probs = [_fa_small(300 + i, H, W, J) for i, (H, W, J) in enumerate(SMALL_MIX)]
+    K = 30
+    with A.Plan(probs) as plan:
+        ys = [dev(p.y) for p in probs]
+        xs = [torch.zeros_like(y) for y in ys]
+        infos = plan.batch(ys, xs, max_iters=K)
+    for p, x, info in zip(probs, xs, infos):
+        assert info["iters"] == K
+        ref = _fa(p, K)["z"]
+        e = rel(host(x), ref)
+        announce(f"  {p.shape} J={p.levels} rel err {e:.3e}")
+        assert e <= ITER_TOL
+
+
+def test_small_image_frame_resume_is_bitwise():
+    import torch
+    announce("frame resume bitwise, image smaller than the window")
+    p = _fa_small(310, 32, 32, 4)
+    with A.Plan([p]) as plan:
+        s1 = A.alloc_state(32, 32, nreg=13)
+        x30, _ = gpu_solve(plan, p, 30, state=s1)
+        s2 = A.alloc_state(32, 32, nreg=13)
+        gpu_solve(plan, p, 12, state=s2)
+        x18b, _ = gpu_solve(plan, p, 18, state=s2)
+    assert np.array_equal(x30, x18b)
+    for key in ("u1", "d1", "ureg", "dreg"):
+        assert torch.equal(s1[key], s2[key]), key
