@@ -596,7 +596,6 @@ __device__ __forceinline__ void rows_fft(E* gbuf, int pitch, const FftPlanDev& f
         fft_lds<MAXE, INV, true>(gbuf, f, gstw, ntrans, pitch, tid, NTHR);
 }
 
-// Copy the length-N twiddle table to LDS (before the first barrier of a kernel).
 // The N entries of a stage table into LDS: the first NPT per thread in one
 // burst of unconditional loads (indices clamped to the last entry), any
 // remainder in a loop.
