@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -121,6 +122,9 @@ struct TileChoice {
     int tc = 0, b = 0;
 };
 
+constexpr int kPeriodsInFlight = 2;      // period graphs queued ahead of the host's stop test
+constexpr int kPeriodIters = 40;         // iterations per period graph (whole check periods)
+
 struct admm_plan {
     hipStream_t stream = nullptr;
     TileChoice tile;                      // what the plan was built with
@@ -144,6 +148,15 @@ struct admm_plan {
     // graph replay of plain iterations: executable per chunk length (even)
     hipStream_t cap_stream = nullptr;
     std::map<int, hipGraphExec_t> graphs;
+    // graph replay of whole check periods (tolerance solves): executable per
+    // (period, periods per graph, state export, tolerance bits); the iteration
+    // counter they advance; active flags mirrored into host-mapped memory; one
+    // event per graph in flight
+    std::map<std::tuple<int, int, int, uint64_t>, hipGraphExec_t> pgraphs;
+    int* d_kbase = nullptr;
+    int* h_active = nullptr;
+    int* h_active_dev = nullptr;
+    hipEvent_t pev[kPeriodsInFlight] = {};
     // profiling: per-class totals of the last profiled run
     double prof_ms[6] = {0, 0, 0, 0, 0, 0};
     int prof_n[6] = {0, 0, 0, 0, 0, 0};
@@ -204,6 +217,10 @@ extern "C" admm_status admm_validate_problem(const admm_problem* prob) {
 extern "C" void admm_plan_destroy(admm_plan* P) {
     if (!P) return;
     for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : P->pgraphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipEvent_t e : P->pev)
+        if (e) (void)hipEventDestroy(e);
+    if (P->h_active) (void)hipHostFree(P->h_active);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     if (P->arena) (void)hipFree(P->arena);
     if (P->h_info) (void)hipHostFree(P->h_info);
@@ -409,6 +426,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     const size_t nitems = col.size() + rowtv.size() + rowfa.size() + frm.size();
     const size_t o_items = take(sizeof(WorkItem) * nitems);
     const size_t o_info = take(sizeof(InfoDev) * count);
+    const size_t o_kbase = take(sizeof(int));
     const size_t o_part = take(sizeof(double) * ADMM_NSUM * std::max(part, 1));
     const size_t o_tw = take(sizeof(float2) * tab_len);
     const size_t o_s2 = take(sizeof(float) * tab_len);
@@ -449,11 +467,18 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
             P->h_info = nullptr;
             return bail(fail(ADMM_E_NOMEM, "pinned host allocation failed: %s", hipGetErrorString(e)));
         }
+        e = hipHostMalloc((void**)&P->h_active, sizeof(int) * count, hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&P->h_active_dev, P->h_active, 0);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(fail(ADMM_E_NOMEM, "mapped host allocation failed: %s", hipGetErrorString(e)));
+        }
     }
     char* A = P->arena;
     P->d_desc = (ProbDesc*)(A + o_desc);
     P->d_items = (WorkItem*)(A + o_items);
     P->d_info = (InfoDev*)(A + o_info);
+    P->d_kbase = (int*)(A + o_kbase);
     P->d_partials = (double*)(A + o_part);
     P->d_tw = (float2*)(A + o_tw);
     P->d_s2 = (float*)(A + o_s2);
@@ -698,9 +723,83 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
         return ADMM_OK;
     };
 
+    // Check periods replayed as graphs (solves to a tolerance): a graph holds g
+    // periods of c iterations, the last two of each with the pre-check and check
+    // flags and then the reduction, which takes its iteration number from a
+    // device counter (base + j c for period j) and mirrors the active flags into
+    // host-mapped memory; the graph ends by advancing the counter by g c. The
+    // host keeps at most kPeriodsInFlight graphs queued and stops launching once
+    // every flag is clear; the kernels skip finished problems, so iterations
+    // launched after the end change nothing. The final iteration and a tail
+    // shorter than a period take the loop below.
+    auto get_period_graph = [&](int g, hipGraphExec_t* exec) -> admm_status {
+        uint64_t tb = 0;
+        std::memcpy(&tb, &tol, sizeof tb);
+        const auto key = std::make_tuple(c, g, st ? 1 : 0, tb);
+        auto it = P->pgraphs.find(key);
+        if (it != P->pgraphs.end()) {
+            *exec = it->second;
+            return ADMM_OK;
+        }
+        if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+        LaunchCtx cA = P->all, cT = P->tv, cF = P->fa;
+        cA.stream = cT.stream = cF.stream = P->cap_stream;
+        HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int q = 1; q <= g && e == hipSuccess; ++q) {
+            for (int j = 1; j <= c && e == hipSuccess; ++j) {
+                int flags = F_FORWARD | (j == c - 1 ? F_WRITE_UPREV : 0);
+                if (j == c) flags |= F_CHECK | F_WRITE_X | (st ? F_EXPORT : 0);
+                e = iteration(cA, cT, cF, (j - 1) & 1, flags, false);
+            }
+            if (e == hipSuccess) e = launch_reduce(cA, count, tol, q * c, 0, P->d_kbase, P->h_active_dev);
+        }
+        if (e == hipSuccess) e = launch_tick(cA, P->d_kbase, g * c, false);
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = hipStreamEndCapture(P->cap_stream, &gr);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return fail(ADMM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        hipGraphExec_t x = nullptr;
+        hipError_t e3 = hipGraphInstantiate(&x, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e3 != hipSuccess) return fail(ADMM_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e3));
+        P->pgraphs[key] = x;
+        *exec = x;
+        return ADMM_OK;
+    };
+
     int par = 0;
     int k = 1;
-    while (k <= K) {
+    bool all_done = false;
+    if (use_graph && tol > 0 && c >= 2 && c % 2 == 0 && c < K) {
+        for (hipEvent_t& e : P->pev)
+            if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (int i = 0; i < count; ++i) P->h_active[i] = 1;
+        HIP_TRY(launch_tick(P->all, P->d_kbase, 0, true));
+        const int gmax = std::max(1, kPeriodIters / c);
+        for (int n = 0; k + c - 1 < K; ++n) {
+            const int g = std::min(gmax, (K - k) / c);   // whole periods that end before K
+            hipEvent_t& ev_n = P->pev[n % kPeriodsInFlight];
+            if (n >= kPeriodsInFlight) {
+                HIP_TRY(hipEventSynchronize(ev_n));   // graph n - kPeriodsInFlight has finished
+                bool any = false;
+                for (int i = 0; i < count; ++i) any = any || ((volatile int*)P->h_active)[i] != 0;
+                if (!any) {
+                    all_done = true;
+                    break;
+                }
+            }
+            hipGraphExec_t exec = nullptr;
+            admm_status gs = get_period_graph(g, &exec);
+            if (gs != ADMM_OK) return gs;
+            HIP_TRY(hipGraphLaunch(exec, sm));
+            HIP_TRY(hipEventRecord(ev_n, sm));
+            k += g * c;
+        }
+    }
+    while (!all_done && k <= K) {
         if (use_graph && par == 0 && is_plain(k)) {
             int run = 0;
             while (k + run <= K && is_plain(k + run)) ++run;

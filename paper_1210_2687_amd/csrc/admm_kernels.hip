@@ -340,7 +340,7 @@ __device__ __forceinline__ void store_rows_split(const float2* X, int pitch, flo
 // inputs of the epilogue are loaded in one burst after the inverse transform
 // (register arrays indexed by the unrolled row loop), so the row steps, which
 // exchange delta^h through LDS, wait on memory once rather than once per row.
-template <int MAXE, int CPT, int RB, int EARLY>
+template <int MAXE, int CPT, int RB, int EARLY, bool CHK>
 __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                int nitems, int par, int flags, const InfoDev* __restrict__ info,
                                                const float2* __restrict__ tw, double* __restrict__ partials) {
@@ -375,7 +375,9 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     // valid ones and never used), so that no load waits for another. The first
     // EARLY rows are requested before the inverse transforms, whose arithmetic
     // then covers their latency; the rest after them (register budget).
+    // A check iteration (CHK) also fetches u of the previous iteration (dual residual).
     float pdh[CPT][RB + 1], pdv[CPT][RB + 1], pd1[CPT][RB], py[CPT][RB];
+    float pq1[CPT][CHK ? RB : 1], pqh[CPT][CHK ? RB : 1], pqv[CPT][CHK ? RB : 1];
     uint8_t pmk[CPT][RB];
     auto fetch_row = [&](int rr) {
         const int r = wrapi(r0 - 1 + min(rr, nr), H);
@@ -388,6 +390,11 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                 pd1[j][rr - 1] = gld(p.d1, g);
                 pmk[j][rr - 1] = gld(p.mask, g);
                 py[j][rr - 1] = gld(p.y, g);
+                if (CHK) {
+                    pq1[j][CHK ? rr - 1 : 0] = gld(p.u1p, g);
+                    pqh[j][CHK ? rr - 1 : 0] = gld(p.uregp, g);
+                    pqv[j][CHK ? rr - 1 : 0] = gld(p.uregp, n + g);
+                }
             }
         }
     };
@@ -398,7 +405,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     // X[rr][c] = z + i A z for row r0 - 1 + rr
 
     const float tau = p.tau, mu2 = p.mu2, c1 = p.inv1pmu1;
-    const bool chk = flags & F_CHECK;
+    constexpr bool chk = CHK;                 // the launch picks the instantiation from F_CHECK
     double acc[ADMM_NSUM];
 #pragma unroll
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
@@ -452,7 +459,8 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                     gst(dv_out, g, dvn);
                     if (flags & F_WRITE_X) gst(p.x, g, zc);
                     if (chk) {
-                        const float u1q = gld(p.u1p, g), uhq = gld(p.uregp, g), uvq = gld(p.uregp, n + g);
+                        const float u1q = pq1[j][CHK ? rr - 1 : 0], uhq = pqh[j][CHK ? rr - 1 : 0],
+                                    uvq = pqv[j][CHK ? rr - 1 : 0];
                         const float e0 = Az - u1, e1h = zh - uh, e1v = zv - uv;
                         const float f6 = u1 - u1q, f7h = uh - uhq, f7v = uv - uvq;
                         const float ry = yv - Az;
@@ -668,8 +676,13 @@ __global__ void k_import_tv(const ProbDesc* __restrict__ pd, int prob) {
 // ------------------------------------------------------------ second-stage reduction
 // One block per problem: sum the block partials in a fixed order (deterministic),
 // form the residuals and objective, update the problem's info and active flag.
+// iter_dev (if given): the iteration number is iter_dev[0] + iter (graph
+// replays of whole check periods); host_active (if given, host-mapped memory)
+// receives each problem's active flag so that the host can see the end of a
+// solve without synchronising.
 __global__ __launch_bounds__(NT) void k_reduce(const ProbDesc* __restrict__ pd, const double* __restrict__ partials,
-                                               InfoDev* __restrict__ info, double tol, int iter, int final_iter) {
+                                               InfoDev* __restrict__ info, double tol, int iter, int final_iter,
+                                               const int* __restrict__ iter_dev, int* __restrict__ host_active) {
     __shared__ double sm[NT / 64][ADMM_NSUM];
     const int prob = blockIdx.x;
     if (!info[prob].active) return;
@@ -703,7 +716,7 @@ __global__ __launch_bounds__(NT) void k_reduce(const ProbDesc* __restrict__ pd, 
         const double dual = sqrt(mu1 * mu1 * s[6] + mu2 * mu2 * s[7]);
         const double dden = fmax(sqrt(mu1 * mu1 * s[8] + mu2 * mu2 * s[9]), 1e-30);
         InfoDev f = info[prob];
-        f.iters = iter;
+        f.iters = iter_dev ? iter_dev[0] + iter : iter;
         f.r_pri = pri / den;
         f.r_dual = dual / dden;
         f.objective = 0.5 * s[10] + (double)p.lam * s[11];
@@ -718,7 +731,15 @@ __global__ __launch_bounds__(NT) void k_reduce(const ProbDesc* __restrict__ pd, 
         }
         if (final_iter) f.active = 0;
         info[prob] = f;
+        if (host_active) host_active[prob] = f.active;
     }
+}
+
+// Iteration counter of graph-replayed check periods: counter[0] += c (one
+// lane; an ordinary vector store).
+__global__ void k_tick(int* __restrict__ counter, int c, int set) {
+    const int t = threadIdx.x;
+    if (t == 0) counter[t] = set ? c : counter[t] + c;
 }
 
 // ------------------------------------------------------------ kernel spectrum
@@ -808,20 +829,29 @@ hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
     return hipSuccess;
 }
 
+namespace {
+template <int CPT, int RB, int EARLY>
+void launch_row_tv_class(const LaunchCtx& L, int c, int par, int flags) {
+    const WorkItem* it = L.row_items + L.rtv_beg[c];
+    const int n = L.rtv_cnt[c];
+    if (flags & F_CHECK)
+        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, CPT, RB, EARLY, true>), dim3(n), dim3(NT), L.lds_rtv_c[c], L.stream,
+                           L.desc, it, n, par, flags, L.info, L.tw, L.partials);
+    else
+        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, CPT, RB, EARLY, false>), dim3(n), dim3(NT), L.lds_rtv_c[c], L.stream,
+                           L.desc, it, n, par, flags, L.info, L.tw, L.partials);
+}
+}  // namespace
+
 hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags) {
     for (int c = 0; c < 3; ++c) {
-        const int n = L.rtv_cnt[c];
-        if (!n) continue;
-        const WorkItem* it = L.row_items + L.rtv_beg[c];
+        if (!L.rtv_cnt[c]) continue;
         if (c == 0)
-            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0]>), dim3(n), dim3(NT), L.lds_rtv_c[0], L.stream, L.desc, it, n,
-                               par, flags, L.info, L.tw, L.partials);
+            launch_row_tv_class<1, 8, RTV_EARLY[0]>(L, c, par, flags);
         else if (c == 1)
-            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1]>), dim3(n), dim3(NT), L.lds_rtv_c[1], L.stream, L.desc, it, n,
-                               par, flags, L.info, L.tw, L.partials);
+            launch_row_tv_class<2, 6, RTV_EARLY[1]>(L, c, par, flags);
         else
-            hipLaunchKernelGGL((k_row_tv<MAXE_ROW, 4, 2, RTV_EARLY[2]>), dim3(n), dim3(NT), L.lds_rtv_c[2], L.stream, L.desc, it, n,
-                               par, flags, L.info, L.tw, L.partials);
+            launch_row_tv_class<4, 2, RTV_EARLY[2]>(L, c, par, flags);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -842,9 +872,15 @@ hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const LaunchCtx& L, int count, double tol, int iter, int final_iter) {
+hipError_t launch_reduce(const LaunchCtx& L, int count, double tol, int iter, int final_iter, const int* iter_dev,
+                         int* host_active) {
     hipLaunchKernelGGL(k_reduce, dim3(count), dim3(NT), 0, L.stream, L.desc, L.partials, L.info, tol, iter,
-                       final_iter);
+                       final_iter, iter_dev, host_active);
+    return hipGetLastError();
+}
+
+hipError_t launch_tick(const LaunchCtx& L, int* counter, int c, bool set) {
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, L.stream, counter, c, set ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -872,9 +908,12 @@ hipError_t allow_dynamic_lds(int bytes) {
     const void* fns[] = {
         reinterpret_cast<const void*>(&k_col<8>),     reinterpret_cast<const void*>(&k_col<16>),
         reinterpret_cast<const void*>(&k_col<32>),
-        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0]>),
-        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1]>),
-        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 4, 2, RTV_EARLY[2]>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0], false>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1], false>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 4, 2, RTV_EARLY[2], false>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0], true>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1], true>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 4, 2, RTV_EARLY[2], true>),
         reinterpret_cast<const void*>(&k_row_fwd<MAXE_ROW>),
         reinterpret_cast<const void*>(&k_row_inv<MAXE_ROW>)};
     for (const void* f : fns) {

@@ -266,3 +266,35 @@ def test_all_pixels_missing():
     announce(f"  rel err {e:.2e}")
     assert e <= ITER_TOL
     assert np.all(host(st["d1"]) == 0.0)
+
+
+def test_tolerance_batch_period_graphs_match_eager():
+    # graph-replayed check periods (device-side stopping flags) against eager
+    # launches with a host check after every period: same stop iterations, iterates,
+    # infos and exported states, problem by problem, on repeated runs
+    import torch
+    announce("tolerance batch: period graphs vs eager")
+    probs = [fast_tv_problem(s, 64, 64 + 16 * s, 7, mu=0.01 * (1 + s)) for s in range(3)]
+    with A.Plan(probs) as plan:
+        ys = [dev(p.y) for p in probs]
+
+        def solve(graph, ce):
+            xs = [torch.zeros_like(y) for y in ys]
+            sts = [A.alloc_state(*p.shape) for p in probs]
+            infos = plan.batch(ys, xs, sts, max_iters=4000, tol=1e-4, check_every=ce, graph=graph)
+            torch.cuda.synchronize()
+            return [host(x) for x in xs], [{k: host(v) for k, v in st.items()} for st in sts], infos
+
+        for ce in (10, 4, 7):
+            xe, se, ie = solve(False, ce)
+            announce(f"  check every {ce}: eager stops at {[i['iters'] for i in ie]}")
+            assert all(i["converged"] for i in ie)
+            if ce == 10:
+                assert len({i["iters"] for i in ie}) > 1        # the problems stop at different iterations
+            for rep in range(2):
+                xg, sg, ig = solve(True, ce)
+                for a, b, sa, sb, fa, fb in zip(xe, xg, se, sg, ie, ig):
+                    assert fa == fb
+                    assert np.array_equal(a, b)
+                    for key in sa:
+                        assert np.array_equal(sa[key], sb[key]), key
