@@ -282,8 +282,12 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
                 tab_len += 2 * N;
             }
 
-    // about two blocks per compute unit per pass (measured best on 8 x 512^2: TC = 4, B = 8)
+    // about two blocks per compute unit per pass (measured best on 8 x 512^2: TC = 4,
+    // B = 8; on one 512^2 problem: TC = 1, B = 2)
     const int target_blocks = 512;
+    long long cols_total = 0;   // column transforms per pass over the batch
+    for (int i = 0; i < count; ++i) cols_total += probs[i].W / 2 + 1;
+    const int tc_batch = (int)std::max(1LL, std::min<long long>(col_max_tiles(), cols_total / target_blocks));
     for (int i = 0; i < count; ++i) {
         const admm_problem& q = probs[i];
         ProbDesc& d = P->hd[i];
@@ -310,7 +314,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         while (tcmax + 1 <= col_max_tiles() && lds_col_bytes(q.H, tcmax + 1) <= cap) ++tcmax;
         if (tcmax < 1)
             return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: column length %d does not fit a block", i, q.H));
-        d.TC = std::min(tcmax, d.P);
+        d.TC = std::min(std::min(tcmax, tc_batch), d.P);
         if (tile.tc > 0) d.TC = std::min(d.TC, tile.tc);
         if (const char* e = std::getenv("ADMM_TC")) d.TC = std::max(1, std::min(d.TC, std::atoi(e)));
         // rows per row-pass block
@@ -323,7 +327,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
             while (bmax + 1 <= q.H && fits(bmax + 1, d.fr, row_maxe()) && lds_row_bytes(q.W, bmax + 1) <= cap) ++bmax;
         }
         if (bmax < 1) return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: row length %d does not fit a block", i, q.W));
-        const int bmin = q.reg == ADMM_REG_TV ? std::min(bmax, 4) : 1;
+        const int bmin = q.reg == ADMM_REG_TV ? std::min(bmax, 2) : 1;   // TV: halo rows cost (B + 2) / B
         d.B = std::max(bmin, std::min(bmax, (q.H + per - 1) / per));
         if (tile.b > 0) d.B = std::min(bmax, tile.b);
         if (const char* e = std::getenv("ADMM_ROWS")) d.B = std::max(1, std::min(bmax, std::atoi(e)));
