@@ -250,14 +250,43 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
         return;
     }
 
-    // general schedule: the whole column goes through LDS
-    for (int e = lane; e < H; e += 64) lds_st(buf + pidx(e), gld(S, e));
+    // general schedule: the whole column goes through LDS. Its entries (GC per
+    // lane at a time), and Lambda and |Delta^v|^2 for the solve (GS at a time),
+    // are fetched in bursts of unconditional loads (indices clamped), not one
+    // round trip each.
+    constexpr int GC = 8;
+#pragma unroll
+    for (int c0 = 0; c0 < EPL; c0 += GC) {
+        float4 t[GC];
+#pragma unroll
+        for (int u = 0; u < GC; ++u) t[u] = gld(S, min(lane + 64 * (c0 + u), H - 1));
+#pragma unroll
+        for (int u = 0; u < GC; ++u) {
+            const int e = lane + 64 * (c0 + u);
+            if (e < H) lds_st(buf + pidx(e), t[u]);
+        }
+        lane_exchange_fence();   // one chunk in registers at a time
+    }
     lane_exchange_fence();
     wave_stages<EPL, false>(buf, stw, p.fc, 0, nst, lane);
     lane_exchange_fence();
-    for (int e = lane; e < H; e += 64) {
-        const float w = p.reg == REG_TV ? s2H[e] + w2 : 1.0f;
-        lds_st(buf + pidx(e), col_solve(lds_ld(buf + pidx(e)), gld(L, e), w, mu1, mu2, ihw, mode));
+    constexpr int GS = 4;   // solve entries per lane per burst (each solve holds a division's temporaries)
+#pragma unroll 1
+    for (int c0 = 0; c0 < EPL; c0 += GS) {
+        float2 lm[GS];
+        float wq[GS];
+#pragma unroll
+        for (int u = 0; u < GS; ++u) {
+            const int e = min(lane + 64 * (c0 + u), H - 1);
+            lm[u] = gld(L, e);
+            wq[u] = p.reg == REG_TV ? s2H[e] + w2 : 1.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < GS; ++u) {
+            const int e = lane + 64 * (c0 + u);
+            if (e < H) lds_st(buf + pidx(e), col_solve(lds_ld(buf + pidx(e)), lm[u], wq[u], mu1, mu2, ihw, mode));
+        }
+        lane_exchange_fence();
     }
     lane_exchange_fence();
     wave_stages<EPL, true>(buf, stw, p.fc, 0, nst, lane);
