@@ -242,7 +242,7 @@ __host__ __device__ constexpr int row_pitch(int n) { return pidx_len(n) + ((36 -
 // (checked on the host): ntrans * N / R <= (MAXE / R) * nthr. stw: the stage's
 // twiddle block (entries [k][r - 1]).
 template <int R, int MAXE, bool INV, bool PAD, typename E>
-__device__ __noinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS float2* stw, int ntrans, int tstride,
+__device__ __forceinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS float2* stw, int ntrans, int tstride,
                                             int Ns, int nbf, unsigned mnbf, unsigned mns, int tid, int nthr) {
     constexpr int NB = MAXE / R;
     const int total = ntrans * nbf;
@@ -330,7 +330,7 @@ __device__ __forceinline__ void lane_exchange_fence() { asm volatile("" ::: "mem
 // One radix-R stage; NB bounds the butterflies per lane. stw: the stage's
 // twiddle block (entries [k][r - 1]).
 template <int R, int NB, bool INV, typename E>
-__device__ __noinline__ void wave_stage(ADMM_LDS E* buf, const ADMM_LDS float2* stw, int Ns, int nbf, unsigned mns,
+__device__ __forceinline__ void wave_stage(ADMM_LDS E* buf, const ADMM_LDS float2* stw, int Ns, int nbf, unsigned mns,
                                         int lane) {
     E v[NB][R];
     int dst[NB];
