@@ -324,7 +324,9 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
                    lds_rowtv_bytes(q.W, bmax + 1) <= cap)
                 ++bmax;
         } else {
-            while (bmax + 1 <= q.H && fits(bmax + 1, d.fr, row_maxe()) && lds_row_bytes(q.W, bmax + 1) <= cap) ++bmax;
+            while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) && fits(bmax + 1, d.fr, row_maxe()) &&
+                   lds_row_bytes(q.W, bmax + 1) <= cap)
+                ++bmax;
         }
         if (bmax < 1) return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: row length %d does not fit a block", i, q.W));
         const int bmin = q.reg == ADMM_REG_TV ? std::min(bmax, 2) : 1;   // TV: halo rows cost (B + 2) / B
@@ -380,11 +382,6 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     int part = 0;
     for (int i : order) {
         ProbDesc& d = P->hd[i];
-        if (d.reg == REG_FRAME) {
-            P->row_beg[i] = (int)rowfa.size();
-            for (int b = 0; b < d.nrowblk; ++b) rowfa.push_back({i, b * d.B, b, 0});
-            P->row_end[i] = (int)rowfa.size();
-        }
         d.part_base = part;
         part += d.nrowblk + d.nfrmblk;
         if (d.reg == REG_TV) {
@@ -412,6 +409,26 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
             lds_frm_c[c] = lds_frame_bytes(d.J);
         }
         frm_cc[c] = (int)frm.size() - frm_cb[c];
+    }
+    // FA row items grouped by size class of the row length, like the TV rows; the
+    // plain row passes of each context use the classes of its own row items
+    int rfa_cb[3], rfa_cc[3];
+    size_t lds_rfa_c[3] = {0, 0, 0}, lds_rtvp_c[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c) {
+        rfa_cb[c] = (int)rowfa.size();
+        for (int i : order) {
+            const ProbDesc& d = P->hd[i];
+            if (size_class(d.W) != c) continue;
+            if (d.reg == REG_FRAME) {
+                P->row_beg[i] = (int)rowfa.size();
+                for (int b = 0; b < d.nrowblk; ++b) rowfa.push_back({i, b * d.B, b, 0});
+                P->row_end[i] = (int)rowfa.size();
+                lds_rfa_c[c] = std::max(lds_rfa_c[c], lds_row_bytes(d.W, d.B));
+            } else {
+                lds_rtvp_c[c] = std::max(lds_rtvp_c[c], lds_row_bytes(d.W, d.B));
+            }
+        }
+        rfa_cc[c] = (int)rowfa.size() - rfa_cb[c];
     }
     P->ncol = (int)col.size();
     P->nrowtv = (int)rowtv.size();
@@ -567,6 +584,14 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     P->fa = base_ctx;
     P->fa.row_items = P->d_items + col.size() + rowtv.size();
     P->fa.nrow = P->nrowfa;
+    for (int c = 0; c < 3; ++c) {
+        P->tv.rrow_beg[c] = rtv_cb[c];
+        P->tv.rrow_cnt[c] = rtv_cc[c];
+        P->tv.lds_rrow_c[c] = lds_rtvp_c[c];
+        P->fa.rrow_beg[c] = rfa_cb[c];
+        P->fa.rrow_cnt[c] = rfa_cc[c];
+        P->fa.lds_rrow_c[c] = lds_rfa_c[c];
+    }
     P->fa.frm_items = P->d_items + col.size() + rowtv.size() + rowfa.size();
     P->fa.nfrm = P->nfrm;
 
@@ -906,10 +931,11 @@ LaunchCtx single(const admm_plan* P, int i) {
     c.frm_items = nullptr;
     c.nfrm = 0;
     for (int k = 0; k < 3; ++k) {
-        c.col_beg[k] = c.rtv_beg[k] = 0;
-        c.col_cnt[k] = c.rtv_cnt[k] = 0;
+        c.col_beg[k] = c.rtv_beg[k] = c.rrow_beg[k] = 0;
+        c.col_cnt[k] = c.rtv_cnt[k] = c.rrow_cnt[k] = 0;
     }
     c.col_cnt[size_class(d.H)] = c.ncol;
+    c.rrow_cnt[size_class(d.W)] = c.nrow;
     if (d.reg == REG_TV) c.rtv_cnt[size_class(d.W)] = c.nrow;
     return c;
 }

@@ -30,6 +30,8 @@ constexpr int ROW_BURST = 8;       // plane elements per thread fetched together
 // transforms, per size class (as many as keep the kernel at 128 VGPRs or fewer,
 // two blocks per compute unit)
 constexpr int RTV_EARLY[3] = {5, 3, 1};
+// most rows per block of the plain row passes, per size class (W <= 512, 1024, 2048)
+constexpr int ROW_RB[3] = {16, 8, 4};
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -545,8 +547,9 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
 }
 
 // ------------------------------------------------------------ plane -> spectrum rows
-// Forward row DFT of (a + i b) for rows [r0, r0 + nr) of two planes.
-template <int MAXE>
+// Forward row DFT of (a + i b) for rows [r0, r0 + nr) of two planes. CPT columns
+// per thread (W <= CPT NT), at most RB rows, rows padded (pidx) at row_pitch(W).
+template <int CPT, int RB>
 __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                 int nitems, int par, int src, const InfoDev* __restrict__ info,
                                                 const float2* __restrict__ tw) {
@@ -558,49 +561,59 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
     const int H = p.H, W = p.W, P = p.P, r0 = it.start;
     const int nr = min(p.B, H - r0);
     const int tid = threadIdx.x;
+    const int pitch = row_pitch(W);                           // padded rows (pidx)
+    float2* twl = X + (size_t)p.B * pitch;                    // the stage table
     // src 0: (mu1 * zeta1, s) from (tmpA, tmpB); src 1: (x, 0) from tmpA (blur)
     const float* a = p.tmpA + (size_t)r0 * W;
     const float* b = p.tmpB + (size_t)r0 * W;
-    const int tot = nr * W;
     const float mu1 = p.mu1;
-    float2* twl = X + (size_t)p.B * W;
-    // the stage table, then bursts of ROW_BURST unconditional loads of both planes
-    // per thread (indices clamped; the second plane is read but not used for
-    // src 1), so that each burst costs one memory latency
-    constexpr int NTW = ADMM_MAX_SIDE / NT;
+    // the stage table, then bursts of RCH rows of both planes per thread
+    // (unconditional loads, rows and columns clamped; the second plane is read
+    // but not used for src 1), so that each burst costs one memory latency
+    constexpr int RCH = CPT >= ROW_BURST ? 1 : ROW_BURST / CPT;
     const float2* tws = tw + p.fr.tw_off + W;
-    float2 tv[NTW];
+    float2 tv[CPT];
 #pragma unroll
-    for (int u = 0; u < NTW; ++u) tv[u] = gld(tws, (unsigned)min(tid + u * NT, W - 1));
-    for (int base = tid; base < tot; base += ROW_BURST * NT) {
-        float va[ROW_BURST], vb[ROW_BURST];
+    for (int u = 0; u < CPT; ++u) tv[u] = gld(tws, (unsigned)min(tid + u * NT, W - 1));
+    for (int rb = 0; rb < nr; rb += RCH) {
+        float va[RCH][CPT], vb[RCH][CPT];
 #pragma unroll
-        for (int u = 0; u < ROW_BURST; ++u) {
-            const unsigned i = (unsigned)min(base + u * NT, tot - 1);
-            va[u] = gld(a, i);
-            vb[u] = gld(b, i);
+        for (int k = 0; k < RCH; ++k) {
+            const int rr = min(rb + k, nr - 1);
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const unsigned g = (unsigned)(rr * W + min(tid + j * NT, W - 1));
+                va[k][j] = gld(a, g);
+                vb[k][j] = gld(b, g);
+            }
         }
-        if (base == tid) {   // every thread below W takes this pass: tot = nr W >= W
+        if (rb == 0) {
 #pragma unroll
-            for (int u = 0; u < NTW; ++u)
+            for (int u = 0; u < CPT; ++u)
                 if (tid + u * NT < W) twl[tid + u * NT] = tv[u];
         }
 #pragma unroll
-        for (int u = 0; u < ROW_BURST; ++u) {
-            const int i = base + u * NT;
-            if (i < tot) X[i] = src == 0 ? make_float2(mu1 * va[u], vb[u]) : make_float2(va[u], 0.0f);
+        for (int k = 0; k < RCH; ++k) {
+            const int rr = rb + k;
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int c = tid + j * NT;
+                if (rr < nr && c < W)
+                    X[rr * pitch + pidx(c)] = src == 0 ? make_float2(mu1 * va[k][j], vb[k][j]) : make_float2(va[k][j], 0.0f);
+            }
         }
     }
     __syncthreads();
-    fft_lds<MAXE, false, false>(X, p.fr, twl, nr, W, tid, NT);
-    store_rows_split<false>(X, W, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
+    rows_fft<NT * CPT, NT, RB, MAXE_ROW, false>(X, pitch, p.fr, twl, nr, tid);
+    store_rows_split<true>(X, pitch, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
 }
 
 // ------------------------------------------------------------ spectrum rows -> planes
 // Inverse row DFT of (z^ + i A z^) for rows [r0, r0 + nr).
 //   mode 0 (blur): write z (the real part) to tmpB.
 //   mode 1 (FA data step): z -> zpl, mask prox and data dual (eq. (40)), zeta1 -> tmpA.
-template <int MAXE>
+// Rows padded as in k_row_fwd.
+template <int CPT, int RB>
 __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                 int nitems, int par, int mode, int flags,
                                                 const InfoDev* __restrict__ info, const float2* __restrict__ tw,
@@ -613,16 +626,23 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     const int H = p.H, W = p.W, P = p.P, r0 = it.start;
     const int nr = min(p.B, H - r0);
     const int tid = threadIdx.x;
-    float2* twl = X + (size_t)p.B * W;
-    // nr W <= MAXE NT, so P nr <= (MAXE / 2 + 1) NT except for very short rows
-    load_rows_hermitian<false, MAXE / 2 + 1, ADMM_MAX_SIDE / NT>(X, W, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid, twl,
-                                              tw + p.fr.tw_off + W, W);
+    const int pitch = row_pitch(W);
+    float2* twl = X + (size_t)p.B * pitch;
+    // spectrum rows r0 .. r0 + nr - 1 (P <= NT CPT / 2 + 1 entries each), then the stage table
+    constexpr int NLD = ((NT * CPT / 2 + 1) * RB + NT - 1) / NT;
+    load_rows_hermitian<true, NLD, CPT>(X, pitch, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid, twl,
+                                        tw + p.fr.tw_off + W, W);
     __syncthreads();
-    fft_lds<MAXE, true, false>(X, p.fr, twl, nr, W, tid, NT);
-    const int tot = nr * W;
+    rows_fft<NT * CPT, NT, RB, MAXE_ROW, true>(X, pitch, p.fr, twl, nr, tid);
     const unsigned off = (unsigned)(r0 * W);
     if (mode == 0) {
-        for (int i = tid; i < tot; i += NT) gst(p.tmpB, off + i, X[i].x);
+        for (int rr = 0; rr < nr; ++rr) {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int c = tid + j * NT;
+                if (c < W) gst(p.tmpB, off + (unsigned)(rr * W + c), X[rr * pitch + pidx(c)].x);
+            }
+        }
         return;
     }
     const float c1 = p.inv1pmu1;
@@ -630,48 +650,58 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     double acc[ADMM_NSUM];
 #pragma unroll
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
-    for (int base = tid; base < tot; base += ROW_BURST * NT) {
-      // one burst of unconditional loads (indices clamped) per ROW_BURST elements
-      float d1b[ROW_BURST], yb[ROW_BURST];
-      uint8_t mb[ROW_BURST];
+    constexpr int RCH = CPT >= ROW_BURST ? 1 : ROW_BURST / CPT;
+    for (int rb = 0; rb < nr; rb += RCH) {
+        // one burst of unconditional loads (rows and columns clamped) per RCH rows
+        float d1b[RCH][CPT], yb[RCH][CPT];
+        uint8_t mb[RCH][CPT];
 #pragma unroll
-      for (int u = 0; u < ROW_BURST; ++u) {
-        const unsigned g = off + (unsigned)min(base + u * NT, tot - 1);
-        d1b[u] = gld(p.d1, g);
-        mb[u] = gld(p.mask, g);
-        yb[u] = gld(p.y, g);
-      }
+        for (int k = 0; k < RCH; ++k) {
+            const int rr = min(rb + k, nr - 1);
 #pragma unroll
-      for (int u = 0; u < ROW_BURST; ++u) {
-        const int i = base + u * NT;
-        if (i >= tot) break;
-        const unsigned g = off + i;
-        const float z = X[i].x, Az = X[i].y;
-        const float d1o = d1b[u];
-        const bool obs = mb[u] != 0;
-        const float yv = obs ? yb[u] : 0.0f;
-        const float v1 = Az - d1o;
-        const float u1 = obs ? fmaf(yv - v1, c1, v1) : v1;
-        const float d1n = u1 - v1;
-        gst(p.d1, g, d1n);
-        gst(p.tmpA, g, u1 + d1n);
-        gst(p.zpl, g, z);
-        if (flags & F_WRITE_X) gst(p.x, g, z);
-        if (chk) {
-            const float e0 = Az - u1, f6 = u1 - gld(p.u1p, g), ry = yv - Az;
-            acc[0] += (double)(e0 * e0);
-            acc[2] += (double)(Az * Az);
-            acc[4] += (double)(u1 * u1);
-            acc[6] += (double)(f6 * f6);
-            acc[8] += (double)(d1n * d1n);
-            acc[10] += obs ? (double)(ry * ry) : 0.0;
+            for (int j = 0; j < CPT; ++j) {
+                const unsigned g = off + (unsigned)(rr * W + min(tid + j * NT, W - 1));
+                d1b[k][j] = gld(p.d1, g);
+                mb[k][j] = gld(p.mask, g);
+                yb[k][j] = gld(p.y, g);
+            }
         }
-        if (flags & F_WRITE_UPREV) gst(p.u1p, g, u1);
-        if (flags & F_EXPORT) {
-            gst(p.st_u1, g, u1);
-            gst(p.st_d1, g, d1n);
+#pragma unroll
+        for (int k = 0; k < RCH; ++k) {
+            const int rr = rb + k;
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int c = tid + j * NT;
+                if (rr >= nr || c >= W) continue;
+                const unsigned g = off + (unsigned)(rr * W + c);
+                const float2 xv = X[rr * pitch + pidx(c)];
+                const float z = xv.x, Az = xv.y;
+                const float d1o = d1b[k][j];
+                const bool obs = mb[k][j] != 0;
+                const float yv = obs ? yb[k][j] : 0.0f;
+                const float v1 = Az - d1o;
+                const float u1 = obs ? fmaf(yv - v1, c1, v1) : v1;
+                const float d1n = u1 - v1;
+                gst(p.d1, g, d1n);
+                gst(p.tmpA, g, u1 + d1n);
+                gst(p.zpl, g, z);
+                if (flags & F_WRITE_X) gst(p.x, g, z);
+                if (chk) {
+                    const float e0 = Az - u1, f6 = u1 - gld(p.u1p, g), ry = yv - Az;
+                    acc[0] += (double)(e0 * e0);
+                    acc[2] += (double)(Az * Az);
+                    acc[4] += (double)(u1 * u1);
+                    acc[6] += (double)(f6 * f6);
+                    acc[8] += (double)(d1n * d1n);
+                    acc[10] += obs ? (double)(ry * ry) : 0.0;
+                }
+                if (flags & F_WRITE_UPREV) gst(p.u1p, g, u1);
+                if (flags & F_EXPORT) {
+                    gst(p.st_u1, g, u1);
+                    gst(p.st_d1, g, d1n);
+                }
+            }
         }
-      }
     }
     if (chk) block_sums_write(acc, reinterpret_cast<double*>(X), partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM);
 }
@@ -830,7 +860,7 @@ static size_t rowtv_lds(int W, int B) {
     return b > scratch ? b : scratch;
 }
 static size_t row_lds(int W, int B) {
-    const size_t b = (size_t)(B + 1) * W * sizeof(float2);            // rows + twiddles
+    const size_t b = ((size_t)B * row_pitch(W) + W) * sizeof(float2);   // padded rows + twiddles
     const size_t scratch = NT / 64 * ADMM_NSUM * sizeof(double);    // block sums reuse the rows
     return b > scratch ? b : scratch;
 }
@@ -889,17 +919,51 @@ hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags) {
 
 int row_tv_max_rows(int w) { return w <= NT ? 8 : (w <= 2 * NT ? 6 : 2); }
 
+// The plain row passes (FA rows, blur, state import) per size class of the row
+// length: CPT columns per thread, at most ROW_RB[c] rows per block.
 hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
-    hipLaunchKernelGGL(k_row_fwd<MAXE_ROW>, dim3(L.nrow), dim3(NT), L.lds_row, L.stream, L.desc, L.row_items,
-                       L.nrow, par, src, gated ? L.info : nullptr, L.tw);
-    return hipGetLastError();
+    const InfoDev* info = gated ? L.info : nullptr;
+    for (int c = 0; c < 3; ++c) {
+        const int n = L.rrow_cnt[c];
+        if (!n) continue;
+        const WorkItem* it = L.row_items + L.rrow_beg[c];
+        if (c == 0)
+            hipLaunchKernelGGL((k_row_fwd<1, ROW_RB[0]>), dim3(n), dim3(NT), L.lds_rrow_c[0], L.stream, L.desc, it, n,
+                               par, src, info, L.tw);
+        else if (c == 1)
+            hipLaunchKernelGGL((k_row_fwd<2, ROW_RB[1]>), dim3(n), dim3(NT), L.lds_rrow_c[1], L.stream, L.desc, it, n,
+                               par, src, info, L.tw);
+        else
+            hipLaunchKernelGGL((k_row_fwd<4, ROW_RB[2]>), dim3(n), dim3(NT), L.lds_rrow_c[2], L.stream, L.desc, it, n,
+                               par, src, info, L.tw);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool gated) {
-    hipLaunchKernelGGL(k_row_inv<MAXE_ROW>, dim3(L.nrow), dim3(NT), L.lds_row, L.stream, L.desc, L.row_items,
-                       L.nrow, par, mode, flags, gated ? L.info : nullptr, L.tw, L.partials);
-    return hipGetLastError();
+    const InfoDev* info = gated ? L.info : nullptr;
+    for (int c = 0; c < 3; ++c) {
+        const int n = L.rrow_cnt[c];
+        if (!n) continue;
+        const WorkItem* it = L.row_items + L.rrow_beg[c];
+        if (c == 0)
+            hipLaunchKernelGGL((k_row_inv<1, ROW_RB[0]>), dim3(n), dim3(NT), L.lds_rrow_c[0], L.stream, L.desc, it, n,
+                               par, mode, flags, info, L.tw, L.partials);
+        else if (c == 1)
+            hipLaunchKernelGGL((k_row_inv<2, ROW_RB[1]>), dim3(n), dim3(NT), L.lds_rrow_c[1], L.stream, L.desc, it, n,
+                               par, mode, flags, info, L.tw, L.partials);
+        else
+            hipLaunchKernelGGL((k_row_inv<4, ROW_RB[2]>), dim3(n), dim3(NT), L.lds_rrow_c[2], L.stream, L.desc, it, n,
+                               par, mode, flags, info, L.tw, L.partials);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
+
+int row_max_rows(int w) { return ROW_RB[size_class(w)]; }
 
 hipError_t launch_reduce(const LaunchCtx& L, int count, double tol, int iter, int final_iter, const int* iter_dev,
                          int* host_active) {
@@ -943,8 +1007,12 @@ hipError_t allow_dynamic_lds(int bytes) {
         reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0], true>),
         reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1], true>),
         reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 4, 2, RTV_EARLY[2], true>),
-        reinterpret_cast<const void*>(&k_row_fwd<MAXE_ROW>),
-        reinterpret_cast<const void*>(&k_row_inv<MAXE_ROW>)};
+        reinterpret_cast<const void*>(&k_row_fwd<1, ROW_RB[0]>),
+        reinterpret_cast<const void*>(&k_row_fwd<2, ROW_RB[1]>),
+        reinterpret_cast<const void*>(&k_row_fwd<4, ROW_RB[2]>),
+        reinterpret_cast<const void*>(&k_row_inv<1, ROW_RB[0]>),
+        reinterpret_cast<const void*>(&k_row_inv<2, ROW_RB[1]>),
+        reinterpret_cast<const void*>(&k_row_inv<4, ROW_RB[2]>)};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;

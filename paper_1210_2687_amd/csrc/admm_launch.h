@@ -28,6 +28,9 @@ struct LaunchCtx {
     int col_beg[3] = {0, 0, 0}, col_cnt[3] = {0, 0, 0};
     int rtv_beg[3] = {0, 0, 0}, rtv_cnt[3] = {0, 0, 0};
     size_t lds_col_c[3] = {0, 0, 0}, lds_rtv_c[3] = {0, 0, 0};
+    // size classes of the plain row passes (FA rows, blur, state import) over row_items
+    int rrow_beg[3] = {0, 0, 0}, rrow_cnt[3] = {0, 0, 0};
+    size_t lds_rrow_c[3] = {0, 0, 0};
     // frame classes (levels 1..4, image smaller than a window or not): items of
     // class c are [frm_beg[c], frm_beg[c] + frm_cnt[c]) of frm_items
     int frm_beg[ADMM_FRAME_CLASSES] = {}, frm_cnt[ADMM_FRAME_CLASSES] = {};
@@ -56,6 +59,7 @@ size_t lds_frame_bytes(int J);
 int frame_class(int H, int W, int J);       // 2 (J - 1) + (image smaller than a window)
 int col_max_tiles();                       // columns per column-pass block (one per wave)
 int row_tv_max_rows(int w);                  // rows per block of the TV row pass for width w
+int row_max_rows(int w);                     // rows per block of the plain row passes for width w
 int size_class(int n);                      // 0: n <= 512, 1: n <= 1024, 2: larger
 int row_maxe();
 int block_threads();
