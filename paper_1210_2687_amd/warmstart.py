@@ -177,7 +177,7 @@ def targets(probs, tol=1e-6, max_iters=8000, check_every=20):
         H, W = probs[0].shape
         states = [A.alloc_state(H, W) for _ in probs]
         infos = plan.batch([y[i] for i in range(len(probs))], xs, states, max_iters=max_iters, tol=tol,
-                           check_every=check_every)
+                           check_every=check_every, graph=True)
     xt = torch.stack(xs)
     pt = torch.stack([-(p.mu2 / p.lam) * s["dreg"] for p, s in zip(probs, states)])
     return y, m, e, xt, pt, infos
