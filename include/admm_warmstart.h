@@ -36,26 +36,29 @@ extern "C" {
 admm_status admm_conv3x3_pack_weights(const float* w, int32_t cin, int32_t cout, uint16_t* wfwd,
                                       uint16_t* wbwd, void* stream);
 
-/* y = act(conv3x3(x, w) + bias), act = ReLU if relu != 0; if gate is not NULL
- * the result is zeroed wherever gate <= 0 (gate has cout channels).
+/* y = act(conv3x3_d(x, w) + bias), act = ReLU if relu != 0; if gate is not
+ * NULL the result is zeroed wherever gate <= 0 (gate has cout channels).
+ * conv3x3_d: taps at offsets dilation * (-1, 0, 1) in rows and columns, zero
+ * padding; dilation in 1..8 (else ADMM_E_INVALID).
  * x: [N][H][W][cin], cin in {8,16,32}; y: [N][H][W][cout], cout in {16,32};
  * wpacked from admm_conv3x3_pack_weights (forward layout for a forward
- * convolution; the input-gradient layout, with cin/cout swapped, computes
- * dL/dx from dL/dy); bias: FP32 [cout] or NULL.                               */
+ * convolution; the input-gradient layout, with cin/cout swapped and the same
+ * dilation, computes dL/dx from dL/dy); bias: FP32 [cout] or NULL.            */
 admm_status admm_conv3x3_bf16_fwd(const uint16_t* x, int32_t N, int32_t H, int32_t W, int32_t cin,
                                   const uint16_t* wpacked, const float* bias, int32_t cout, int32_t relu,
-                                  const uint16_t* gate, uint16_t* y, void* stream);
+                                  const uint16_t* gate, uint16_t* y, int32_t dilation, void* stream);
 
 /* Workspace bytes for admm_conv3x3_bf16_wgrad with the given pixel chunk.     */
 size_t admm_conv3x3_bf16_wgrad_workspace(int32_t N, int32_t H, int32_t W, int32_t cin, int32_t cout,
                                          int32_t chunk);
 
-/* dw[9][cout][cin] = sum_p dy[p][cout] x[p + off(tap)][cin] and db = sum_p dy
- * (FP32 outputs, overwritten). Split over pixel chunks of `chunk` (multiple of
- * 32) with a fixed-order second pass: deterministic.                          */
+/* dw[9][cout][cin] = sum_p dy[p][cout] x[p + dilation off(tap)][cin] and
+ * db = sum_p dy (FP32 outputs, overwritten; dilation in 1..8). Split over pixel
+ * chunks of `chunk` (multiple of 32) with a fixed-order second pass:
+ * deterministic.                                                              */
 admm_status admm_conv3x3_bf16_wgrad(const uint16_t* x, const uint16_t* dy, int32_t N, int32_t H, int32_t W,
                                     int32_t cin, int32_t cout, int32_t chunk, float* workspace, size_t ws_bytes,
-                                    float* dw, float* db, void* stream);
+                                    float* dw, float* db, int32_t dilation, void* stream);
 
 /* One Adam step (Kingma & Ba) at step t >= 1 on n FP32 parameters.          */
 admm_status admm_adam_step(float* p, const float* g, float* m, float* v, int32_t n, float lr, float beta1,

@@ -112,11 +112,11 @@ def lib():
         vp = c_void_p
         L.admm_conv3x3_pack_weights.argtypes = [vp, c_int32, c_int32, vp, vp, vp]
         L.admm_conv3x3_bf16_fwd.argtypes = [vp, c_int32, c_int32, c_int32, c_int32, vp, vp, c_int32, c_int32,
-                                            vp, vp, vp]
+                                            vp, vp, c_int32, vp]
         L.admm_conv3x3_bf16_wgrad_workspace.argtypes = [c_int32] * 6
         L.admm_conv3x3_bf16_wgrad_workspace.restype = ctypes.c_size_t
         L.admm_conv3x3_bf16_wgrad.argtypes = [vp, vp, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, vp,
-                                              ctypes.c_size_t, vp, vp, vp]
+                                              ctypes.c_size_t, vp, vp, c_int32, vp]
         L.admm_adam_step.argtypes = [vp, vp, vp, vp, c_int32, c_float, c_float, c_float, c_float, c_int32, vp]
         L.admm_ws_input.argtypes = [vp, vp, vp, c_int32, c_int32, c_int32, vp, vp]
         L.admm_ws_loss.argtypes = [vp, vp, vp, vp, vp, c_int32, c_int32, c_int32, c_float, vp, vp, vp]
@@ -316,19 +316,19 @@ def admm_conv3x3_pack_weights(w, cin, cout, wfwd, wbwd=None):
     _check(lib().admm_conv3x3_pack_weights(_ptr(w), cin, cout, _ptr(wfwd), _ptr(wbwd), _stream()))
 
 
-def admm_conv3x3_bf16_fwd(x, N, H, W, cin, wpacked, bias, cout, relu, gate, y):
+def admm_conv3x3_bf16_fwd(x, N, H, W, cin, wpacked, bias, cout, relu, gate, y, dil=1):
     _check(lib().admm_conv3x3_bf16_fwd(_ptr(x), N, H, W, cin, _ptr(wpacked), _ptr(bias), cout, int(relu),
-                                       _ptr(gate), _ptr(y), _stream()))
+                                       _ptr(gate), _ptr(y), int(dil), _stream()))
 
 
 def admm_conv3x3_bf16_wgrad_workspace(N, H, W, cin, cout, chunk):
     return lib().admm_conv3x3_bf16_wgrad_workspace(N, H, W, cin, cout, chunk)
 
 
-def admm_conv3x3_bf16_wgrad(x, dy, N, H, W, cin, cout, chunk, workspace, dw, db):
+def admm_conv3x3_bf16_wgrad(x, dy, N, H, W, cin, cout, chunk, workspace, dw, db, dil=1):
     _check(lib().admm_conv3x3_bf16_wgrad(_ptr(x), _ptr(dy), N, H, W, cin, cout, chunk, _ptr(workspace),
                                          workspace.numel() * workspace.element_size(), _ptr(dw), _ptr(db),
-                                         _stream()))
+                                         int(dil), _stream()))
 
 
 def admm_adam_step(p, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):

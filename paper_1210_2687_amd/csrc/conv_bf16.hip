@@ -2,10 +2,10 @@
 //
 // The warm start is not part of the paper: a small CNN predicts an initial
 // image x0 and TV dual field p0, which only set u_0, d_0 (Theorem 1 allows any).
-// Layers are 3x3 convolutions, stride 1, zero padding, NHWC bf16 activations,
-// FP32 accumulation on v_mfma_f32_16x16x32_bf16:
+// Layers are 3x3 convolutions with dilation d (1 <= d <= 8), stride 1, zero
+// padding, NHWC bf16 activations, FP32 accumulation on v_mfma_f32_16x16x32_bf16:
 //
-//   out[p][m] = bias[m] + sum_{tap, k} in[p + off(tap)][k] * W[tap][m][k],
+//   out[p][m] = bias[m] + sum_{tap, k} in[p + d off(tap)][k] * W[tap][m][k],
 //   off(tap) = (tap / 3 - 1, tap % 3 - 1)
 //
 // as an implicit GEMM with M = output channels (16 per tile), N = 16 pixels
@@ -19,7 +19,7 @@
 // dgrad is the same kernel applied to dY with weights flipped in space and
 // transposed in channels (W'[8 - tap][k][m] = W[tap][m][k]); its epilogue
 // multiplies by (x > 0), the derivative of the ReLU that produced the layer
-// input x. wgrad reduces dW[tap][m][k] = sum_p dY[p][m] x[p + off(tap)][k] over
+// input x. wgrad reduces dW[tap][m][k] = sum_p dY[p][m] x[p + d off(tap)][k] over
 // pixel chunks (split K) with LDS transposes, then a fixed-order second pass.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,6 +32,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int CW = 4;             // waves per block
 constexpr int PIX_PER_WAVE = 64;  // 4 N tiles of 16 pixels along a row
+constexpr int DIL_MAX = 8;        // largest dilation (the wgrad input tile's halo)
 
 __device__ __forceinline__ bf16x8 zero8() {
     bf16x8 z;
@@ -45,7 +46,8 @@ __device__ __forceinline__ bf16x8 zero8() {
 template <int CIN, int MT>
 __global__ __launch_bounds__(CW * 64) void k_conv3x3(const __bf16* __restrict__ x, const __bf16* __restrict__ wA,
                                                      const float* __restrict__ bias, const __bf16* __restrict__ gate,
-                                                     __bf16* __restrict__ y, int N, int H, int W, int relu) {
+                                                     __bf16* __restrict__ y, int N, int H, int W, int relu,
+                                                     int dil) {
     constexpr int TPK = 32 / CIN;                 // taps per K step
     constexpr int KS = (9 + TPK - 1) / TPK;       // K steps
     constexpr int COUT = MT * 16;
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(CW * 64) void k_conv3x3(const __bf16* __restrict__ 
         // which tap / channel group this lane feeds at K step s
         const int tap = s * TPK + g / (CIN / 8);
         const int ch0 = (g % (CIN / 8)) * 8;
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const int dy = (tap / 3 - 1) * dil, dx = (tap % 3 - 1) * dil;
         const int rr = r + dy;
         const bool rowok = tap < 9 && rr >= 0 && rr < H;
         bf16x8 a[MT];
@@ -123,13 +125,14 @@ __global__ __launch_bounds__(CW * 64) void k_conv3x3(const __bf16* __restrict__ 
 template <int CIN, int MT>
 __global__ __launch_bounds__(CW * 64) void k_wgrad_part(const __bf16* __restrict__ x, const __bf16* __restrict__ dy,
                                                         float* __restrict__ part, float* __restrict__ dbpart, int N,
-                                                        int H, int W, int chunk) {
+                                                        int H, int W, int chunk, int dil) {
     constexpr int COUT = MT * 16;
     constexpr int KT = CIN / 16 > 0 ? CIN / 16 : 1;      // k tiles of 16 channels (CIN 8 uses one, half empty)
     constexpr int PX = 32;                               // pixels per K step
-    // transposed tiles: dyT[m][px], xT[3 rows][k][PX + 2]
+    constexpr int PXW = PX + 2 * DIL_MAX;               // pixels of an input row with its halo
+    // transposed tiles: dyT[m][px], xT[3 rows (r - d, r, r + d)][k][px], px = column - cb + d
     __shared__ __bf16 dyT[COUT][PX];
-    __shared__ __bf16 xT[3][KT * 16][PX + 2];
+    __shared__ __bf16 xT[3][KT * 16][PXW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, col = lane & 15;
     const long long npx = (long long)N * H * W;
@@ -158,13 +161,13 @@ __global__ __launch_bounds__(CW * 64) void k_wgrad_part(const __bf16* __restrict
             if (px < valid) v = dy[pp * COUT + m];
             dyT[m][px] = v;
         }
-        for (int i = tid; i < 3 * KT * 16 * (PX + 2); i += CW * 64) {
-            const int row = i / (KT * 16 * (PX + 2));
-            const int rem = i - row * (KT * 16 * (PX + 2));
-            const int k = rem / (PX + 2), px = rem - (rem / (PX + 2)) * (PX + 2);
-            const int rr = r + row - 1, cc = cb + px - 1;
+        for (int i = tid; i < 3 * KT * 16 * PXW; i += CW * 64) {
+            const int row = i / (KT * 16 * PXW);
+            const int rem = i - row * (KT * 16 * PXW);
+            const int k = rem / PXW, px = rem - (rem / PXW) * PXW;
+            const int rr = r + (row - 1) * dil, cc = cb + px - dil;
             __bf16 v = (__bf16)0.0f;
-            if (k < CIN && rr >= 0 && rr < H && cc >= 0 && cc < W && px - 1 < valid + 1)
+            if (k < CIN && rr >= 0 && rr < H && cc >= 0 && cc < W && px < valid + 2 * dil)
                 v = x[(((long long)n * H + rr) * W + cc) * CIN + k];
             xT[row][k][px] = v;
         }
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(CW * 64) void k_wgrad_part(const __bf16* __restrict
         for (int q = 0; q < 3; ++q) {
             const int tap = wave + 4 * q;
             if (tap >= 9) continue;
-            const int dyo = tap / 3, dxo = tap % 3;     // row index into xT, pixel shift 0..2
+            const int dyo = tap / 3, dxo = (tap % 3) * dil;     // row index into xT, pixel shift 0, d, 2d
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt) {
                 bf16x8 b;
@@ -354,8 +357,9 @@ using namespace admm;
 
 extern "C" admm_status admm_conv3x3_bf16_fwd(const uint16_t* x, int32_t N, int32_t H, int32_t W, int32_t cin,
                                              const uint16_t* wpacked, const float* bias, int32_t cout,
-                                             int32_t relu, const uint16_t* gate, uint16_t* y, void* stream) {
-    if (!x || !wpacked || !y || N < 1 || H < 1 || W < 1) return ADMM_E_INVALID;
+                                             int32_t relu, const uint16_t* gate, uint16_t* y, int32_t dilation,
+                                             void* stream) {
+    if (!x || !wpacked || !y || N < 1 || H < 1 || W < 1 || dilation < 1 || dilation > DIL_MAX) return ADMM_E_INVALID;
     if (!(cin == 8 || cin == 16 || cin == 32) || !(cout == 16 || cout == 32)) return ADMM_E_UNSUPPORTED;
     const long long jobs = (long long)N * H * ((W + PIX_PER_WAVE - 1) / PIX_PER_WAVE);
     const dim3 grid((unsigned)((jobs + CW - 1) / CW)), blk(CW * 64);
@@ -365,7 +369,7 @@ extern "C" admm_status admm_conv3x3_bf16_fwd(const uint16_t* x, int32_t N, int32
     const __bf16* gb = (const __bf16*)gate;
     __bf16* yb = (__bf16*)y;
 #define CONV_CASE(CI, MTV) \
-    if (cin == CI && cout == MTV * 16) hipLaunchKernelGGL((k_conv3x3<CI, MTV>), grid, blk, 0, s, xb, wb, bias, gb, yb, N, H, W, relu);
+    if (cin == CI && cout == MTV * 16) hipLaunchKernelGGL((k_conv3x3<CI, MTV>), grid, blk, 0, s, xb, wb, bias, gb, yb, N, H, W, relu, dilation);
     CONV_CASE(8, 1) CONV_CASE(8, 2) CONV_CASE(16, 1) CONV_CASE(16, 2) CONV_CASE(32, 1) CONV_CASE(32, 2)
 #undef CONV_CASE
     return hipGetLastError() == hipSuccess ? ADMM_OK : ADMM_E_DEVICE;
@@ -380,8 +384,9 @@ extern "C" size_t admm_conv3x3_bf16_wgrad_workspace(int32_t N, int32_t H, int32_
 
 extern "C" admm_status admm_conv3x3_bf16_wgrad(const uint16_t* x, const uint16_t* dy, int32_t N, int32_t H, int32_t W,
                                                int32_t cin, int32_t cout, int32_t chunk, float* workspace,
-                                               size_t ws_bytes, float* dw, float* db, void* stream) {
-    if (!x || !dy || !dw || !db || !workspace || N < 1 || H < 1 || W < 1 || chunk < 32 || chunk % 32)
+                                               size_t ws_bytes, float* dw, float* db, int32_t dilation, void* stream) {
+    if (!x || !dy || !dw || !db || !workspace || N < 1 || H < 1 || W < 1 || chunk < 32 || chunk % 32 ||
+        dilation < 1 || dilation > DIL_MAX)
         return ADMM_E_INVALID;
     if (!(cin == 8 || cin == 16 || cin == 32) || !(cout == 16 || cout == 32)) return ADMM_E_UNSUPPORTED;
     if (ws_bytes < admm_conv3x3_bf16_wgrad_workspace(N, H, W, cin, cout, chunk)) return ADMM_E_INVALID;
@@ -393,7 +398,7 @@ extern "C" admm_status admm_conv3x3_bf16_wgrad(const uint16_t* x, const uint16_t
     const __bf16* xb = (const __bf16*)x;
     const __bf16* dyb = (const __bf16*)dy;
 #define WG_CASE(CI, MTV) \
-    if (cin == CI && cout == MTV * 16) hipLaunchKernelGGL((k_wgrad_part<CI, MTV>), dim3(nblk), dim3(CW * 64), 0, s, xb, dyb, part, dbp, N, H, W, chunk);
+    if (cin == CI && cout == MTV * 16) hipLaunchKernelGGL((k_wgrad_part<CI, MTV>), dim3(nblk), dim3(CW * 64), 0, s, xb, dyb, part, dbp, N, H, W, chunk, dilation);
     WG_CASE(8, 1) WG_CASE(8, 2) WG_CASE(16, 1) WG_CASE(16, 2) WG_CASE(32, 1) WG_CASE(32, 2)
 #undef WG_CASE
     const int nw = 9 * cout * cin;

@@ -8,8 +8,8 @@ perfect prediction is a fixed point, and by Theorem 1 of the paper any
 prediction still converges to a minimiser: the network changes the iteration
 count, never the answer. A non-finite prediction falls back to a cold start.
 
-Network: layers 8 -> 32 -> 32 -> 32 -> 32 -> 32 -> 16 channels, ReLU after all
-but the last; input [m y, m, e0..e3, 0, 0] with a 4-number kernel embedding e;
+Network: layers 8 -> 32 -> 32 -> 32 -> 32 -> 32 -> 16 channels, 3x3 kernels
+dilated 1, 2, 4, 8, 4, 1 (a 41 x 41 receptive field), ReLU after all but the last; input [m y, m, e0..e3, 0, 0] with a 4-number kernel embedding e;
 outputs 0..2 give x0 = m y + out0 and p0 = (out1, out2). Activations are
 NHWC bf16, weights FP32 masters with bf16 copies, accumulation FP32, all in
 the library's BF16 MFMA kernels; the loss is mean over pixels of
@@ -27,6 +27,7 @@ from . import admm as A
 from . import workloads as WL
 
 CHANNELS = (8, 32, 32, 32, 32, 32, 16)
+DILATIONS = (1, 2, 4, 8, 4, 1)    # per layer: a 41 x 41 receptive field (13 x 13 undilated)
 
 
 def kernel_embedding(h):
@@ -44,9 +45,11 @@ def kernel_embedding(h):
 class WarmStartNet:
     """Weights, Adam state and scratch of the warm-start CNN (device tensors)."""
 
-    def __init__(self, seed=0, alpha=0.25):
+    def __init__(self, seed=0, alpha=0.25, dilations=DILATIONS):
         import torch
         self.alpha = alpha
+        self.dil = tuple(int(d) for d in dilations)
+        assert len(self.dil) == len(CHANNELS) - 1
         g = np.random.default_rng(seed)
         self.w, self.b, self.mw, self.vw, self.mb, self.vb = [], [], [], [], [], []
         self.wf, self.wb = [], []
@@ -102,7 +105,7 @@ class WarmStartNet:
             # every layer input is kept for the backward pass; inference ping-pongs
             o = self._buf(f"a{li + 1}" if keep else f"p{li % 2}_{cout}", (N, H, W, cout), torch.bfloat16)
             A.admm_conv3x3_bf16_fwd(acts[-1], N, H, W, CHANNELS[li], self.wf[li], self.b[li], cout,
-                                    1 if li < nl - 1 else 0, None, o)
+                                    1 if li < nl - 1 else 0, None, o, dil=self.dil[li])
             acts.append(o)
         return (acts[-1], acts) if keep else acts[-1]
 
@@ -126,11 +129,11 @@ class WarmStartNet:
             ws = self._buf(f"ws{li}", (wsb // 4 + 1,), torch.float32)
             dws[li] = self._buf(f"dw{li}", (9, cout, cin), torch.float32)
             dbs[li] = self._buf(f"db{li}", (cout,), torch.float32)
-            A.admm_conv3x3_bf16_wgrad(acts[li], dy, N, H, W, cin, cout, chunk, ws, dws[li], dbs[li])
+            A.admm_conv3x3_bf16_wgrad(acts[li], dy, N, H, W, cin, cout, chunk, ws, dws[li], dbs[li], dil=self.dil[li])
             if li > 0:
                 # dL/d(input of layer li) through the ReLU that produced it
                 dx = self._buf(f"dx{li % 2}_{cin}", (N, H, W, cin), torch.bfloat16)
-                A.admm_conv3x3_bf16_fwd(dy, N, H, W, cout, self.wb[li], None, cin, 0, acts[li], dx)
+                A.admm_conv3x3_bf16_fwd(dy, N, H, W, cout, self.wb[li], None, cin, 0, acts[li], dx, dil=self.dil[li])
                 dy = dx
         return lpart, dws, dbs
 

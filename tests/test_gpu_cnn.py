@@ -57,20 +57,22 @@ def packed(w, cin_p, cout_p):
     return wf, wb
 
 
-@pytest.mark.parametrize("cin,cout,N,H,W,relu", [(8, 32, 2, 20, 37, 1), (32, 32, 1, 33, 70, 1),
-                                                  (32, 16, 2, 17, 16, 0), (16, 32, 1, 9, 130, 1)])
-def test_conv_forward(cin, cout, N, H, W, relu):
+@pytest.mark.parametrize("cin,cout,N,H,W,relu,dil", [(8, 32, 2, 20, 37, 1, 1), (32, 32, 1, 33, 70, 1, 1),
+                                                      (32, 16, 2, 17, 16, 0, 1), (16, 32, 1, 9, 130, 1, 1),
+                                                      (8, 32, 2, 20, 37, 1, 2), (32, 32, 1, 33, 70, 1, 4),
+                                                      (32, 16, 2, 17, 16, 0, 8)])
+def test_conv_forward(cin, cout, N, H, W, relu, dil):
     import torch
-    announce(f"conv fwd cin={cin} cout={cout} {N}x{H}x{W}")
+    announce(f"conv fwd cin={cin} cout={cout} {N}x{H}x{W} dilation {dil}")
     g = np.random.default_rng(cin * 100 + cout)
     x = bf16(g.standard_normal((N, H, W, cin)))
     w = bf16(0.2 * g.standard_normal((9, cout, cin)))
     b = g.standard_normal(cout).astype(np.float32)
     wf, _ = packed(w, cin, cout)
     y = torch.zeros(N, H, W, cout, dtype=torch.bfloat16, device="cuda")
-    A.admm_conv3x3_bf16_fwd(to_bf16_dev(x), N, H, W, cin, wf, to_f32_dev(b), cout, relu, None, y)
+    A.admm_conv3x3_bf16_fwd(to_bf16_dev(x), N, H, W, cin, wf, to_f32_dev(b), cout, relu, None, y, dil=dil)
     torch.cuda.synchronize()
-    ref = O.conv3x3_fwd(x, oracle_w(w), b)
+    ref = O.conv3x3_fwd(x, oracle_w(w), b, dil=dil)
     if relu:
         ref = O.relu(ref)
     ok, worst = close_bf16(host(y), ref)
@@ -78,29 +80,31 @@ def test_conv_forward(cin, cout, N, H, W, relu):
     assert ok
 
 
-@pytest.mark.parametrize("cin,cout,N,H,W", [(32, 32, 2, 19, 45), (32, 16, 1, 24, 33)])
-def test_conv_input_gradient_with_relu_gate(cin, cout, N, H, W):
+@pytest.mark.parametrize("cin,cout,N,H,W,dil", [(32, 32, 2, 19, 45, 1), (32, 16, 1, 24, 33, 1),
+                                                 (32, 32, 2, 19, 45, 4), (32, 16, 1, 24, 33, 8)])
+def test_conv_input_gradient_with_relu_gate(cin, cout, N, H, W, dil):
     import torch
-    announce(f"conv dgrad cin={cin} cout={cout}")
+    announce(f"conv dgrad cin={cin} cout={cout} dilation {dil}")
     g = np.random.default_rng(7 + cin + cout)
     w = bf16(0.2 * g.standard_normal((9, cout, cin)))
     dy = bf16(g.standard_normal((N, H, W, cout)))
     gate = bf16(g.standard_normal((N, H, W, cin)))
     _, wb = packed(w, cin, cout)
     dx = torch.zeros(N, H, W, cin, dtype=torch.bfloat16, device="cuda")
-    A.admm_conv3x3_bf16_fwd(to_bf16_dev(dy), N, H, W, cout, wb, None, cin, 0, to_bf16_dev(gate), dx)
+    A.admm_conv3x3_bf16_fwd(to_bf16_dev(dy), N, H, W, cout, wb, None, cin, 0, to_bf16_dev(gate), dx, dil=dil)
     torch.cuda.synchronize()
-    ref = O.conv3x3_dgrad(dy, oracle_w(w)) * (gate > 0)
+    ref = O.conv3x3_dgrad(dy, oracle_w(w), dil=dil) * (gate > 0)
     ok, worst = close_bf16(host(dx), ref)
     announce(f"  worst rel {worst:.2e}")
     assert ok
 
 
-@pytest.mark.parametrize("cin,cout,N,H,W,chunk", [(8, 32, 2, 21, 37, 256), (32, 32, 1, 30, 70, 1024),
-                                                  (32, 16, 3, 16, 16, 96)])
-def test_conv_weight_gradient(cin, cout, N, H, W, chunk):
+@pytest.mark.parametrize("cin,cout,N,H,W,chunk,dil", [(8, 32, 2, 21, 37, 256, 1), (32, 32, 1, 30, 70, 1024, 1),
+                                                      (32, 16, 3, 16, 16, 96, 1), (8, 32, 2, 21, 37, 256, 2),
+                                                      (32, 32, 1, 30, 70, 1024, 8), (32, 16, 3, 16, 16, 96, 4)])
+def test_conv_weight_gradient(cin, cout, N, H, W, chunk, dil):
     import torch
-    announce(f"conv wgrad cin={cin} cout={cout} chunk={chunk}")
+    announce(f"conv wgrad cin={cin} cout={cout} chunk={chunk} dilation {dil}")
     g = np.random.default_rng(11 + cin + cout)
     x = bf16(g.standard_normal((N, H, W, cin)))
     dy = bf16(g.standard_normal((N, H, W, cout)))
@@ -108,9 +112,9 @@ def test_conv_weight_gradient(cin, cout, N, H, W, chunk):
                      dtype=torch.float32, device="cuda")
     dw = torch.zeros(9, cout, cin, dtype=torch.float32, device="cuda")
     db = torch.zeros(cout, dtype=torch.float32, device="cuda")
-    A.admm_conv3x3_bf16_wgrad(to_bf16_dev(x), to_bf16_dev(dy), N, H, W, cin, cout, chunk, ws, dw, db)
+    A.admm_conv3x3_bf16_wgrad(to_bf16_dev(x), to_bf16_dev(dy), N, H, W, cin, cout, chunk, ws, dw, db, dil=dil)
     torch.cuda.synchronize()
-    dwo, dbo = O.conv3x3_wgrad(x, dy)
+    dwo, dbo = O.conv3x3_wgrad(x, dy, dil=dil)
     ref = dwo.transpose(0, 1, 3, 2).reshape(9, cout, cin)
     e = np.abs(host(dw) - ref).max() / np.abs(ref).max()
     eb = np.abs(host(db) - dbo).max() / np.abs(dbo).max()

@@ -87,7 +87,7 @@ def _oracle_backprop(net, y, m, e, xt, pt):
         cout, cin = w.shape[1], w.shape[2]
         wo = _bf16(w).reshape(3, 3, cout, cin).transpose(0, 1, 3, 2)
         ws.append(wo)
-        z = O.conv3x3_fwd(acts[-1], wo, host(net.b[li]))
+        z = O.conv3x3_fwd(acts[-1], wo, host(net.b[li]), dil=net.dil[li])
         acts.append(_bf16(O.relu(z) if li < nl - 1 else z))
     out = acts[-1]
     npx = N * H * W
@@ -98,11 +98,11 @@ def _oracle_backprop(net, y, m, e, xt, pt):
     dy = _bf16(g)
     dws, dbs = [None] * nl, [None] * nl
     for li in range(nl - 1, -1, -1):
-        dw, db = O.conv3x3_wgrad(acts[li], dy)
+        dw, db = O.conv3x3_wgrad(acts[li], dy, dil=net.dil[li])
         dws[li] = dw.transpose(0, 1, 3, 2).reshape(9, dw.shape[3], dw.shape[2])
         dbs[li] = db
         if li > 0:
-            dy = _bf16(O.conv3x3_dgrad(dy, ws[li]) * (acts[li] > 0))
+            dy = _bf16(O.conv3x3_dgrad(dy, ws[li], dil=net.dil[li]) * (acts[li] > 0))
     return dws, dbs
 
 

@@ -1,6 +1,7 @@
 """Pins for oracle/cnn.py: torch CPU library routines and finite differences."""
 
 import numpy as np
+import pytest
 import torch
 
 import oracle as O
@@ -51,6 +52,41 @@ def test_conv_grads_central_differences():
         e = np.zeros_like(w)
         e[idw] = h
         assert abs((L(x, w + e) - L(x, w - e)) / (2 * h) - dw[idw]) < 1e-7
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_dilated_conv_and_grads_match_torch(d):
+    x = torch.from_numpy(_rand((2, 9, 11, 3), 20 + d)).requires_grad_()
+    w = torch.from_numpy(_rand((3, 3, 3, 4), 30 + d)).requires_grad_()
+    b = torch.from_numpy(_rand((4,), 40 + d)).requires_grad_()
+    R = torch.from_numpy(_rand((2, 9, 11, 4), 50 + d))
+    y = torch.nn.functional.conv2d(x.permute(0, 3, 1, 2), w.permute(3, 2, 0, 1), b, padding=d, dilation=d)
+    np.testing.assert_allclose(O.conv3x3_fwd(x.detach().numpy(), w.detach().numpy(), b.detach().numpy(), dil=d),
+                               y.permute(0, 2, 3, 1).detach().numpy(), atol=1e-12)
+    (y.permute(0, 2, 3, 1) * R).sum().backward()
+    np.testing.assert_allclose(O.conv3x3_dgrad(R.numpy(), w.detach().numpy(), dil=d), x.grad.numpy(), atol=1e-12)
+    dw, db = O.conv3x3_wgrad(x.detach().numpy(), R.numpy(), dil=d)
+    np.testing.assert_allclose(dw, w.grad.numpy(), atol=1e-12)
+    np.testing.assert_allclose(db, b.grad.numpy(), atol=1e-12)
+
+
+def test_dilated_conv_is_plain_conv_with_zero_stuffed_kernel():
+    # a 3x3 kernel at dilation 2 is the 5x5 kernel with the taps at even offsets,
+    # written here as the sum of two dilation-1 convolutions of shifted inputs
+    x = _rand((1, 8, 10, 2), 60)
+    w = _rand((3, 3, 2, 3), 61)
+    y2 = O.conv3x3_fwd(x, w, dil=2)
+    xp = np.pad(x, ((0, 0), (2, 2), (2, 2), (0, 0)))
+    ref = np.zeros_like(y2)
+    for ky in range(3):
+        for kx in range(3):
+            ref += xp[:, 2 * ky:2 * ky + 8, 2 * kx:2 * kx + 10, :] @ w[ky, kx]
+    np.testing.assert_allclose(y2, ref, atol=1e-12)
+    # brute force at one output pixel
+    r, c = 3, 4
+    v = sum(x[0, r + 2 * (ky - 1), c + 2 * (kx - 1)] @ w[ky, kx] for ky in range(3) for kx in range(3)
+            if 0 <= r + 2 * (ky - 1) < 8 and 0 <= c + 2 * (kx - 1) < 10)
+    np.testing.assert_allclose(y2[0, r, c], v, atol=1e-12)
 
 
 def test_adam_first_step_closed_form_and_torch():
