@@ -70,9 +70,13 @@ typedef struct {
     uint32_t flags;          /* ADMM_FLAG_* below                                      */
 } admm_opts;
 
-/* ADMM_FLAG_GRAPH: runs of iterations that need no host decision are replayed
- * from hipGraphs captured once per plan (captured on an internal stream,
- * launched on the plan's stream); results are identical to eager launches.
+/* ADMM_FLAG_GRAPH: iterations are replayed from hipGraphs captured once per
+ * plan (captured on an internal stream, launched on the plan's stream). With
+ * tol > 0 and an even check period, whole check periods, residual checks
+ * included, are replayed and the stopping test is read from host-mapped
+ * memory with at most two graphs queued; iterations queued past a problem's
+ * stop leave it unchanged. Iterates, states and infos are identical to eager
+ * launches.
  * ADMM_FLAG_PROFILE: time every kernel launch with HIP events (eager launches
  * only; read the totals with admm_plan_kernel_times).                        */
 #define ADMM_FLAG_GRAPH 1u
