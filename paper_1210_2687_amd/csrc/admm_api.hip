@@ -144,7 +144,6 @@ struct admm_plan {
     float2* d_tw = nullptr;
     float* d_s2 = nullptr;
     LaunchCtx all, tv, fa;
-    size_t lds_col = 0, lds_rowtv = 0, lds_row = 0, lds_frm = 0;
     // graph replay of plain iterations: executable per chunk length (even)
     hipStream_t cap_stream = nullptr;
     std::map<int, hipGraphExec_t> graphs;
@@ -384,15 +383,10 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         ProbDesc& d = P->hd[i];
         d.part_base = part;
         part += d.nrowblk + d.nfrmblk;
-        if (d.reg == REG_TV) {
+        if (d.reg == REG_TV)
             ++P->ntv;
-            P->lds_rowtv = std::max(P->lds_rowtv, lds_rowtv_bytes(d.W, d.B));
-        } else {
+        else
             ++P->nfa;
-            P->lds_frm = std::max(P->lds_frm, lds_frame_bytes(d.J));
-        }
-        P->lds_row = std::max(P->lds_row, lds_row_bytes(d.W, d.B));
-        P->lds_col = std::max(P->lds_col, lds_col_bytes(d.H, d.TC));
     }
     // frame items grouped by class (levels, small image), one launch per class
     int frm_cb[ADMM_FRAME_CLASSES], frm_cc[ADMM_FRAME_CLASSES];
@@ -558,10 +552,6 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     base_ctx.partials = P->d_partials;
     base_ctx.tw = P->d_tw;
     base_ctx.s2 = P->d_s2;
-    base_ctx.lds_col = P->lds_col;
-    base_ctx.lds_rowtv = P->lds_rowtv;
-    base_ctx.lds_row = P->lds_row;
-    base_ctx.lds_frm = P->lds_frm;
     for (int c = 0; c < 3; ++c) {
         base_ctx.col_beg[c] = col_cb[c];
         base_ctx.col_cnt[c] = col_cc[c];

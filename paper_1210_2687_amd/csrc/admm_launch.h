@@ -21,7 +21,6 @@ struct LaunchCtx {
     double* partials = nullptr;
     const float2* tw = nullptr;
     const float* s2 = nullptr;
-    size_t lds_col = 0, lds_rowtv = 0, lds_row = 0, lds_frm = 0;
     // size classes of the column and TV row passes (0: length <= 512, 1: <= 1024,
     // 2: <= 2048), each launched with its own instantiation: the items of class c
     // are [beg[c], beg[c] + cnt[c]) of col_items / row_items
