@@ -275,12 +275,18 @@ def test_tolerance_batch_period_graphs_match_eager():
     import torch
     announce("tolerance batch: period graphs vs eager")
     probs = [fast_tv_problem(s, 64, 64 + 16 * s, 7, mu=0.01 * (1 + s)) for s in range(3)]
+    g = WL.rng(81)                                   # and one FA-MD problem (its frame check mode)
+    xf = WL.synth_image(g, 48, 48)
+    hf = WL.kernel_disk(2.0)
+    mf = WL.valid_mask(48, 48, hf.shape[0] // 2)
+    probs.append(WL.Problem(y=WL.observe(g, xf, hf, mf, 1e-3), mask=mf, kernel=hf, lam=5e-4, mu1=0.02, mu2=0.01,
+                            reg="frame", levels=2))
     with A.Plan(probs) as plan:
         ys = [dev(p.y) for p in probs]
 
         def solve(graph, ce):
             xs = [torch.zeros_like(y) for y in ys]
-            sts = [A.alloc_state(*p.shape) for p in probs]
+            sts = [A.alloc_state(*p.shape, nreg=nr) for p, nr in zip(probs, plan.nregs)]
             infos = plan.batch(ys, xs, sts, max_iters=4000, tol=1e-4, check_every=ce, graph=graph)
             torch.cuda.synchronize()
             return [host(x) for x in xs], [{k: host(v) for k, v in st.items()} for st in sts], infos
@@ -288,7 +294,7 @@ def test_tolerance_batch_period_graphs_match_eager():
         for ce in (10, 4, 7):
             xe, se, ie = solve(False, ce)
             announce(f"  check every {ce}: eager stops at {[i['iters'] for i in ie]}")
-            assert all(i["converged"] for i in ie)
+            assert all(i["converged"] for i in ie[:3])
             if ce == 10:
                 assert len({i["iters"] for i in ie}) > 1        # the problems stop at different iterations
             for rep in range(2):
