@@ -1,0 +1,391 @@
+"""Write the golden trajectories of tiny TV-MD and FA-MD problems.
+
+These fixtures pin the FP64 oracle to a computation that shares none of its
+code and none of its arithmetic route. Here every operator is an explicit
+dense matrix built from its definition, and every z-step is a dense linear
+solve. No FFT, no diagonalisation, and no Parseval identity is assumed.
+FA-MD runs in exact rational arithmetic. Its steps, the Haar filters
+included, are rational on any grid. TV-MD needs the square root of the vector
+soft threshold, so it runs in 60-digit decimal arithmetic.
+
+Steps, in the paper's order (Almeida & Figueiredo, Sec. IV):
+
+* z-step of Alg. 2 / Alg. 3, written as the normal equations it solves:
+      (mu1 A^T A + mu2 R^T R) z = mu1 A^T zeta1 + mu2 R^T zeta2
+  with R = (D^h; D^v) for TV (eq. (33)) and R = P for FA (eqs. (24)-(25));
+* data step (the mask prox of eq. (40), used as eq. (49) in TV-MD):
+  u1 = (M^T y + mu1 (A z - d1)) / (m + mu1),
+  d1 <- d1 - (A z - u1);
+* regulariser step: vector soft threshold of (D z - d_TV) by lambda / mu2
+  (TV, Sec. III-C), component-wise soft threshold of (P z - d2) by
+  lambda / mu2 (FA, eq. (16)); d <- d - (R z - u).
+
+Conventions (the same readings the oracle states):
+* A is periodic convolution, (A x)[r, c] = sum h[a+l, b+l] x[r-a, c-b];
+* D^h, D^v are periodic forward differences;
+* P is the undecimated Haar frame, levels j = 1..J at dilation 2^(j-1),
+  filters (x[i] + x[i+s]) / 2 and (x[i] - x[i+s]) / 2 on each axis.
+  The z-trajectory does not depend on the band order or on the filter
+  direction (either one permutes, shifts or negates whole bands, which the
+  soft threshold and P^T undo).
+
+Inputs are dyadic rationals, so that the FP64 oracle receives them exactly.
+
+Run ``python tests/golden/make_golden.py`` to rewrite the ``.txt`` files.
+"""
+
+import os
+from decimal import Decimal, getcontext
+from fractions import Fraction as Q
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+getcontext().prec = 60
+
+
+# ----------------------------------------------------------------- problems
+# Each problem: grid H x W, kernel (odd side, dyadic taps summing to 1),
+# mask (0/1, row-major), y (dyadic, row-major), lambda, mu1, mu2, iterations.
+
+def _tv_problem():
+    H, W = 5, 6
+    h = [[0, 1, 0],
+         [2, 5, 1],
+         [0, 3, 4]]                                      # sum 16; asymmetric
+    h = [[Q(v, 16) for v in row] for row in h]
+    mask = [1, 1, 0, 1, 1, 1,
+            1, 0, 1, 1, 1, 0,
+            1, 1, 1, 1, 0, 1,
+            0, 1, 1, 1, 1, 1,
+            1, 1, 1, 0, 1, 1]
+    yv = [3, 7, 0, 5, 6, 2,
+          4, 0, 8, 1, 7, 0,
+          2, 6, 3, 8, 0, 5,
+          0, 1, 7, 4, 2, 6,
+          5, 3, 1, 0, 8, 4]
+    y = [Q(v, 8) for v in yv]
+    return dict(name="tv_md_5x6", reg="tv", H=H, W=W, kernel=h, mask=mask, y=y,
+                lam=Q(1, 64), mu1=Q(1, 2), mu2=Q(1, 4), iters=8, record=[1, 2, 3, 5, 8])
+
+
+def _fa_problem():
+    H, W = 4, 6
+    h = [[1, 0, 2],
+         [0, 6, 3],
+         [1, 2, 1]]                                      # sum 16; asymmetric
+    h = [[Q(v, 16) for v in row] for row in h]
+    mask = [1, 1, 1, 0, 1, 1,
+            1, 0, 1, 1, 1, 1,
+            1, 1, 1, 1, 0, 1,
+            0, 1, 1, 1, 1, 1]
+    yv = [6, 1, 4, 0, 7, 3,
+          2, 0, 5, 8, 1, 6,
+          7, 3, 0, 2, 0, 4,
+          0, 5, 6, 1, 3, 8]
+    y = [Q(v, 8) for v in yv]
+    return dict(name="fa_md_4x6_J2", reg="fa", J=2, H=H, W=W, kernel=h, mask=mask, y=y,
+                lam=Q(1, 32), mu1=Q(1, 2), mu2=Q(1, 4), iters=8, record=[1, 2, 3, 5, 8])
+
+
+def _grid(H, W, seed, top):
+    """Deterministic small integers in [0, top] from a linear congruential sequence."""
+    v, out = seed, []
+    for _ in range(H * W):
+        v = (1103515245 * v + 12345) % (1 << 31)
+        out.append((v >> 16) % (top + 1))
+    return out
+
+
+def _tv_problem_8x10():
+    H, W = 8, 10
+    h = [[0, 1, 1, 0, 0],
+         [1, 2, 3, 1, 0],
+         [0, 3, 30, 4, 1],
+         [0, 1, 4, 2, 0],
+         [1, 0, 1, 1, 7]]                                # sum 64; asymmetric
+    h = [[Q(v, 64) for v in row] for row in h]
+    mask = [0 if v == 0 else 1 for v in _grid(H, W, 11, 4)]
+    y = [Q(v, 16) * m for v, m in zip(_grid(H, W, 12, 16), mask)]
+    return dict(name="tv_md_8x10", reg="tv", H=H, W=W, kernel=h, mask=mask, y=y,
+                lam=Q(1, 128), mu1=Q(1, 4), mu2=Q(1, 8), iters=8, record=[1, 2, 3, 5, 8])
+
+
+def _fa_problem_8x8():
+    H, W = 8, 8
+    h = [[1, 2, 0],
+         [0, 8, 3],
+         [1, 0, 1]]                                      # sum 16; asymmetric
+    h = [[Q(v, 16) for v in row] for row in h]
+    mask = [0 if v == 0 else 1 for v in _grid(H, W, 21, 4)]
+    y = [Q(v, 16) * m for v, m in zip(_grid(H, W, 22, 16), mask)]
+    return dict(name="fa_md_8x8_J3", reg="fa", J=3, H=H, W=W, kernel=h, mask=mask, y=y,
+                lam=Q(1, 64), mu1=Q(1, 2), mu2=Q(1, 8), iters=8, record=[1, 2, 3, 5, 8])
+
+
+PROBLEMS = (_tv_problem, _fa_problem, _tv_problem_8x10, _fa_problem_8x8)
+
+
+# ----------------------------------------------------------------- dense algebra
+
+def zeros(n, m, zero):
+    return [[zero] * m for _ in range(n)]
+
+
+def matvec(M, x):
+    return [sum((a * b for a, b in zip(row, x)), x[0] * 0) for row in M]
+
+
+def transpose(M):
+    return [list(col) for col in zip(*M)]
+
+
+def matmul(A, B):
+    Bt = transpose(B)
+    return [[sum((a * b for a, b in zip(row, col)), row[0] * 0) for col in Bt] for row in A]
+
+
+def add(*vs):
+    return [sum(t[1:], t[0]) for t in zip(*vs)]
+
+
+def scale(s, v):
+    return [s * a for a in v]
+
+
+def lu_factor(M):
+    """Gaussian elimination with partial pivoting: (rows of U, multipliers, pivot order).
+
+    Exact for Fractions; the z-step matrix is factored once per problem.
+    """
+    n = len(M)
+    U = [list(r) for r in M]
+    perm = list(range(n))
+    L = [[None] * n for _ in range(n)]
+    for k in range(n):
+        p = max(range(k, n), key=lambda i: abs(U[i][k]))
+        if U[p][k] == 0:
+            raise ZeroDivisionError("singular system")
+        U[k], U[p] = U[p], U[k]
+        L[k], L[p] = L[p], L[k]
+        perm[k], perm[p] = perm[p], perm[k]
+        for i in range(k + 1, n):
+            f = U[i][k] / U[k][k]
+            L[i][k] = f
+            if f != 0:
+                U[i] = [a - f * c for a, c in zip(U[i], U[k])]
+    return U, L, perm
+
+
+def lu_solve(fac, b):
+    U, L, perm = fac
+    n = len(U)
+    x = [b[perm[i]] for i in range(n)]
+    for i in range(n):
+        for k in range(i):
+            if L[i][k]:
+                x[i] = x[i] - L[i][k] * x[k]
+    for i in range(n - 1, -1, -1):
+        s = x[i]
+        for j in range(i + 1, n):
+            if U[i][j]:
+                s = s - U[i][j] * x[j]
+        x[i] = s / U[i][i]
+    return x
+
+
+# ----------------------------------------------------------------- operators as matrices
+
+def conv_matrix(h, H, W, one):
+    n, k = H * W, len(h)
+    l = k // 2
+    A = zeros(n, n, one * 0)
+    for r in range(H):
+        for c in range(W):
+            for a in range(-l, l + 1):
+                for b in range(-l, l + 1):
+                    q = ((r - a) % H) * W + (c - b) % W
+                    A[r * W + c][q] += one * h[a + l][b + l]
+    return A
+
+
+def diff_matrices(H, W, one):
+    n = H * W
+    Dh, Dv = zeros(n, n, one * 0), zeros(n, n, one * 0)
+    for r in range(H):
+        for c in range(W):
+            p = r * W + c
+            Dh[p][r * W + (c + 1) % W] += one
+            Dh[p][p] -= one
+            Dv[p][((r + 1) % H) * W + c] += one
+            Dv[p][p] -= one
+    return Dh, Dv
+
+
+def haar_bands(H, W, J, one):
+    """The 3J + 1 band matrices of the undecimated Haar frame (each n x n)."""
+    half = one / 2
+
+    def axis_op(N, s, sign):
+        M = zeros(N, N, one * 0)
+        for i in range(N):
+            M[i][i] += half
+            M[i][(i + s) % N] += sign * half
+        return M
+
+    def vert(op):    # acts along rows index r
+        n = H * W
+        M = zeros(n, n, one * 0)
+        for r in range(H):
+            for rr in range(H):
+                if op[r][rr] != 0:
+                    for c in range(W):
+                        M[r * W + c][rr * W + c] += op[r][rr]
+        return M
+
+    def horz(op):    # acts along column index c
+        n = H * W
+        M = zeros(n, n, one * 0)
+        for r in range(H):
+            for c in range(W):
+                for cc in range(W):
+                    if op[c][cc] != 0:
+                        M[r * W + c][r * W + cc] += op[c][cc]
+        return M
+
+    n = H * W
+    a = [[one if i == j else one * 0 for j in range(n)] for i in range(n)]
+    bands = []
+    for j in range(1, J + 1):
+        s = 2 ** (j - 1)
+        Lv, Hv = vert(axis_op(H, s, 1)), vert(axis_op(H, s, -1))
+        Lh, Hh = horz(axis_op(W, s, 1)), horz(axis_op(W, s, -1))
+        lv, hv = matmul(Lv, a), matmul(Hv, a)
+        bands += [matmul(Hh, lv), matmul(Lh, hv), matmul(Hh, hv)]
+        a = matmul(Lh, lv)
+    bands.append(a)
+    return bands
+
+
+# ----------------------------------------------------------------- the iterations
+
+def run(pb):
+    reg = pb["reg"]
+    one = Q(1) if reg == "fa" else Decimal(1)
+    cv = (lambda q: q) if reg == "fa" else (lambda q: Decimal(q.numerator) / Decimal(q.denominator))
+    H, W = pb["H"], pb["W"]
+    n = H * W
+    h = [[cv(v) for v in row] for row in pb["kernel"]]
+    m = [one * v for v in pb["mask"]]
+    y = [cv(v) for v in pb["y"]]
+    lam, mu1, mu2 = cv(pb["lam"]), cv(pb["mu1"]), cv(pb["mu2"])
+    tau = lam / mu2
+    zero = one * 0
+
+    A = conv_matrix(h, H, W, one)
+    At = transpose(A)
+    if reg == "tv":
+        R = list(diff_matrices(H, W, one))
+    else:
+        R = haar_bands(H, W, pb["J"], one)
+    Rt = [transpose(B) for B in R]
+    # normal matrix of the z-step: mu1 A^T A + mu2 sum_b R_b^T R_b
+    N = [scale(mu1, row) for row in matmul(At, A)]
+    for B, Bt in zip(R, Rt):
+        BtB = matmul(Bt, B)
+        N = [add(row, scale(mu2, brow)) for row, brow in zip(N, BtB)]
+
+    fac = lu_factor(N)
+    u1, d1 = [zero] * n, [zero] * n
+    ur = [[zero] * n for _ in R]
+    dr = [[zero] * n for _ in R]
+    out = {}
+    z = None
+    for k in range(1, pb["iters"] + 1):
+        rhs = scale(mu1, matvec(At, add(u1, d1)))
+        for Bt, ub, db in zip(Rt, ur, dr):
+            rhs = add(rhs, scale(mu2, matvec(Bt, add(ub, db))))
+        z = lu_solve(fac, rhs)
+        Az = matvec(A, z)
+        v1 = [a - d for a, d in zip(Az, d1)]
+        u1 = [(mi * yi + mu1 * vi) / (mi + mu1) for mi, yi, vi in zip(m, y, v1)]
+        d1 = [d - (a - u) for d, a, u in zip(d1, Az, u1)]
+        Rz = [matvec(B, z) for B in R]
+        vr = [[a - d for a, d in zip(Rb, db)] for Rb, db in zip(Rz, dr)]
+        if reg == "tv":
+            vh, vv = vr
+            uh, uv = [], []
+            for a, b in zip(vh, vv):
+                rho2 = a * a + b * b
+                rho = rho2.sqrt() if rho2 > 0 else zero
+                if rho > tau:
+                    f = (rho - tau) / rho
+                    uh.append(a * f)
+                    uv.append(b * f)
+                else:
+                    uh.append(zero)
+                    uv.append(zero)
+            ur = [uh, uv]
+        else:
+            ur = [[(abs(a) - tau) * (1 if a > 0 else -1) if abs(a) > tau else zero for a in vb] for vb in vr]
+        dr = [[d - (a - u) for d, a, u in zip(db, Rb, ub)] for db, Rb, ub in zip(dr, Rz, ur)]
+        if k in pb["record"]:
+            out[k] = list(z)
+    # objective at the last z: 1/2 ||M (y - A z)||^2 + lambda * regulariser
+    Az = matvec(A, z)
+    fit = sum(((mi * (yi - a)) ** 2 for mi, yi, a in zip(m, y, Az)), zero) / 2
+    Rz = [matvec(B, z) for B in R]
+    if reg == "tv":
+        pen = zero
+        for a, b in zip(*Rz):
+            s2 = a * a + b * b
+            pen += s2.sqrt() if s2 > 0 else zero
+    else:
+        pen = sum((abs(a) for Rb in Rz for a in Rb), zero)
+    return out, fit + lam * pen
+
+
+def _dec(v):
+    if isinstance(v, Q):
+        v = Decimal(v.numerator) / Decimal(v.denominator)
+    if v == 0:
+        return "0"
+    return format(v, ".25e")
+
+
+def write(pb, zs, obj):
+    path = os.path.join(HERE, pb["name"] + ".txt")
+    cite = ("TV-MD: Alg. 3 with the z-step of eq. (33) and the data step of eq. (49), Sec. IV-D"
+            if pb["reg"] == "tv" else
+            "FA-MD: Alg. 2 with the z-step of eqs. (24)-(25), data step eq. (40), soft threshold eq. (16), Sec. IV-C")
+    arith = "60-digit decimal" if pb["reg"] == "tv" else "exact rational"
+    lines = [
+        f"# {cite}.",
+        f"# Cold start, dense explicit operators, {arith} arithmetic; written by tests/golden/make_golden.py.",
+        "# Values are row-major; inputs are exact fractions; z values carry 26 significant digits.",
+        f"reg {pb['reg']}",
+        f"levels {pb.get('J', 0)}",
+        f"shape {pb['H']} {pb['W']}",
+        "kernel " + " ".join(str(v) for row in pb["kernel"] for v in row),
+        "mask " + " ".join(str(v) for v in pb["mask"]),
+        "y " + " ".join(str(v) for v in pb["y"]),
+        f"lambda {pb['lam']}",
+        f"mu1 {pb['mu1']}",
+        f"mu2 {pb['mu2']}",
+        f"iters {pb['iters']}",
+    ]
+    for k in sorted(zs):
+        lines.append(f"z {k} " + " ".join(_dec(v) for v in zs[k]))
+    lines.append(f"objective {pb['iters']} {_dec(obj)}")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return path
+
+
+def main():
+    for make in PROBLEMS:
+        pb = make()
+        zs, obj = run(pb)
+        print(write(pb, zs, obj))
+
+
+if __name__ == "__main__":
+    main()
