@@ -353,21 +353,27 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     P->row_end.assign(count, 0);
     P->frm_beg.assign(count, 0);
     P->frm_end.assign(count, 0);
-    // column and TV row items grouped by size class (each class is one launch of
-    // its own instantiation), largest problems first within a class
-    int col_cb[3], col_cc[3], rtv_cb[3], rtv_cc[3];
-    size_t lds_col_c[3] = {0, 0, 0}, lds_rtv_c[3] = {0, 0, 0};
-    for (int c = 0; c < 3; ++c) {
+    // column items grouped by column class and TV row items by size class (each
+    // class is one launch of its own instantiation), largest problems first
+    // within a class
+    int col_cb[ADMM_COL_CLASSES], col_cc[ADMM_COL_CLASSES], rtv_cb[3], rtv_cc[3];
+    size_t lds_col_c[ADMM_COL_CLASSES] = {}, lds_rtv_c[3] = {0, 0, 0};
+    for (int c = 0; c < ADMM_COL_CLASSES; ++c) {
         col_cb[c] = (int)col.size();
+        for (int i : order) {
+            ProbDesc& d = P->hd[i];
+            if (col_class(d) != c) continue;
+            P->col_beg[i] = (int)col.size();
+            for (int b = 0; b < d.ncolblk; ++b) col.push_back({i, b * d.TC, b, 0});
+            P->col_end[i] = (int)col.size();
+            lds_col_c[c] = std::max(lds_col_c[c], lds_col_bytes(d.H, d.TC));
+        }
+        col_cc[c] = (int)col.size() - col_cb[c];
+    }
+    for (int c = 0; c < 3; ++c) {
         rtv_cb[c] = (int)rowtv.size();
         for (int i : order) {
             ProbDesc& d = P->hd[i];
-            if (size_class(d.H) == c) {
-                P->col_beg[i] = (int)col.size();
-                for (int b = 0; b < d.ncolblk; ++b) col.push_back({i, b * d.TC, b, 0});
-                P->col_end[i] = (int)col.size();
-                lds_col_c[c] = std::max(lds_col_c[c], lds_col_bytes(d.H, d.TC));
-            }
             if (d.reg == REG_TV && size_class(d.W) == c) {
                 P->row_beg[i] = (int)rowtv.size();
                 for (int b = 0; b < d.nrowblk; ++b) rowtv.push_back({i, b * d.B, b, 0});
@@ -375,7 +381,6 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
                 lds_rtv_c[c] = std::max(lds_rtv_c[c], lds_rowtv_bytes(d.W, d.B));
             }
         }
-        col_cc[c] = (int)col.size() - col_cb[c];
         rtv_cc[c] = (int)rowtv.size() - rtv_cb[c];
     }
     int part = 0;
@@ -552,12 +557,14 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     base_ctx.partials = P->d_partials;
     base_ctx.tw = P->d_tw;
     base_ctx.s2 = P->d_s2;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < ADMM_COL_CLASSES; ++c) {
         base_ctx.col_beg[c] = col_cb[c];
         base_ctx.col_cnt[c] = col_cc[c];
+        base_ctx.lds_col_c[c] = lds_col_c[c];
+    }
+    for (int c = 0; c < 3; ++c) {
         base_ctx.rtv_beg[c] = rtv_cb[c];
         base_ctx.rtv_cnt[c] = rtv_cc[c];
-        base_ctx.lds_col_c[c] = lds_col_c[c];
         base_ctx.lds_rtv_c[c] = lds_rtv_c[c];
     }
     for (int c = 0; c < ADMM_FRAME_CLASSES; ++c) {
@@ -920,11 +927,12 @@ LaunchCtx single(const admm_plan* P, int i) {
     c.nrow = P->row_end[i] - P->row_beg[i];
     c.frm_items = nullptr;
     c.nfrm = 0;
+    for (int k = 0; k < ADMM_COL_CLASSES; ++k) c.col_beg[k] = c.col_cnt[k] = 0;
     for (int k = 0; k < 3; ++k) {
-        c.col_beg[k] = c.rtv_beg[k] = c.rrow_beg[k] = 0;
-        c.col_cnt[k] = c.rtv_cnt[k] = c.rrow_cnt[k] = 0;
+        c.rtv_beg[k] = c.rrow_beg[k] = 0;
+        c.rtv_cnt[k] = c.rrow_cnt[k] = 0;
     }
-    c.col_cnt[size_class(d.H)] = c.ncol;
+    c.col_cnt[col_class(d)] = c.ncol;
     c.rrow_cnt[size_class(d.W)] = c.nrow;
     if (d.reg == REG_TV) c.rtv_cnt[size_class(d.W)] = c.nrow;
     return c;

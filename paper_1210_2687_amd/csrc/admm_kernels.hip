@@ -98,8 +98,12 @@ __device__ __forceinline__ float4 col_solve(float4 f, float2 lam, float w, float
     return make_float4(ax * ihw, ay * ihw, 0.f, 0.f);
 }
 
-// EPL: most column entries per lane (H <= 64 EPL).
-template <int EPL>
+// EPL: most column entries per lane (H <= 64 EPL). GEN: the instantiation for
+// general schedules (first or last stage not radix 8); the other one takes the
+// columns whose schedule starts and ends with radix 8. Separate instantiations
+// keep the registers of the fused path out of the general one (which needs
+// fewer, so more waves fit a SIMD).
+template <int EPL, bool GEN>
 __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                              int nitems, int par, int mode, const InfoDev* __restrict__ info,
                                              const float2* __restrict__ tw, const float* __restrict__ s2tab) {
@@ -111,7 +115,7 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
     const int H = p.H, c0 = it.start;
     const int nc = min(p.TC, p.P - c0);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool fused = p.fc.ends8;
+    constexpr bool fused = !GEN;   // the host puts each column in the class of its schedule
     const int nbf = H >> 3;
     const int col = c0 + wave;
     const bool live = wave < nc;
@@ -867,21 +871,29 @@ static size_t row_lds(int W, int B) {
 
 int size_class(int n) { return n <= 512 ? 0 : (n <= 1024 ? 1 : 2); }
 
+int col_class(const ProbDesc& d) { return 2 * size_class(d.H) + (d.fc.ends8 ? 0 : 1); }
+
+namespace {
+template <int EPL, bool GEN>
+void launch_col_class(const LaunchCtx& L, int c, int par, int mode, const InfoDev* info) {
+    const int n = L.col_cnt[c];
+    hipLaunchKernelGGL((k_col<EPL, GEN>), dim3(n), dim3(NTC), L.lds_col_c[c], L.stream, L.desc,
+                       L.col_items + L.col_beg[c], n, par, mode, info, L.tw, L.s2);
+}
+}  // namespace
+
 hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
     const InfoDev* info = mode == COL_SOLVE ? L.info : nullptr;
-    for (int c = 0; c < 3; ++c) {
-        const int n = L.col_cnt[c];
-        if (!n) continue;
-        const WorkItem* it = L.col_items + L.col_beg[c];
-        if (c == 0)
-            hipLaunchKernelGGL(k_col<8>, dim3(n), dim3(NTC), L.lds_col_c[0], L.stream, L.desc, it, n, par, mode, info,
-                               L.tw, L.s2);
-        else if (c == 1)
-            hipLaunchKernelGGL(k_col<16>, dim3(n), dim3(NTC), L.lds_col_c[1], L.stream, L.desc, it, n, par, mode, info,
-                               L.tw, L.s2);
-        else
-            hipLaunchKernelGGL(k_col<32>, dim3(n), dim3(NTC), L.lds_col_c[2], L.stream, L.desc, it, n, par, mode, info,
-                               L.tw, L.s2);
+    for (int c = 0; c < ADMM_COL_CLASSES; ++c) {
+        if (!L.col_cnt[c]) continue;
+        switch (c) {
+            case 0: launch_col_class<8, false>(L, c, par, mode, info); break;
+            case 1: launch_col_class<8, true>(L, c, par, mode, info); break;
+            case 2: launch_col_class<16, false>(L, c, par, mode, info); break;
+            case 3: launch_col_class<16, true>(L, c, par, mode, info); break;
+            case 4: launch_col_class<32, false>(L, c, par, mode, info); break;
+            default: launch_col_class<32, true>(L, c, par, mode, info); break;
+        }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -999,8 +1011,9 @@ hipError_t launch_warmstart(const LaunchCtx& L, int prob, size_t n, const float*
 // 160 KiB per compute unit). Returns the first error, if any.
 hipError_t allow_dynamic_lds(int bytes) {
     const void* fns[] = {
-        reinterpret_cast<const void*>(&k_col<8>),     reinterpret_cast<const void*>(&k_col<16>),
-        reinterpret_cast<const void*>(&k_col<32>),
+        reinterpret_cast<const void*>(&k_col<8, false>),  reinterpret_cast<const void*>(&k_col<8, true>),
+        reinterpret_cast<const void*>(&k_col<16, false>), reinterpret_cast<const void*>(&k_col<16, true>),
+        reinterpret_cast<const void*>(&k_col<32, false>), reinterpret_cast<const void*>(&k_col<32, true>),
         reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0], false>),
         reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1], false>),
         reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 4, 2, RTV_EARLY[2], false>),

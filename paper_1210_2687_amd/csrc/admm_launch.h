@@ -6,6 +6,10 @@
 namespace admm {
 
 constexpr int ADMM_FRAME_CLASSES = 8;
+// column classes: 2 x (size class of the column length) + 1 for a general
+// schedule (first or last stage not radix 8: the column cannot stay in
+// registers around the solve), each launched with its own instantiation
+constexpr int ADMM_COL_CLASSES = 6;
 
 // Everything a launch needs; item lists are device arrays, counts are the grid sizes.
 struct LaunchCtx {
@@ -21,12 +25,14 @@ struct LaunchCtx {
     double* partials = nullptr;
     const float2* tw = nullptr;
     const float* s2 = nullptr;
-    // size classes of the column and TV row passes (0: length <= 512, 1: <= 1024,
-    // 2: <= 2048), each launched with its own instantiation: the items of class c
-    // are [beg[c], beg[c] + cnt[c]) of col_items / row_items
-    int col_beg[3] = {0, 0, 0}, col_cnt[3] = {0, 0, 0};
+    // classes of the column pass (col_class) and size classes of the TV row pass
+    // (0: length <= 512, 1: <= 1024, 2: <= 2048), each launched with its own
+    // instantiation: the items of class c are [beg[c], beg[c] + cnt[c]) of
+    // col_items / row_items
+    int col_beg[ADMM_COL_CLASSES] = {}, col_cnt[ADMM_COL_CLASSES] = {};
+    size_t lds_col_c[ADMM_COL_CLASSES] = {};
     int rtv_beg[3] = {0, 0, 0}, rtv_cnt[3] = {0, 0, 0};
-    size_t lds_col_c[3] = {0, 0, 0}, lds_rtv_c[3] = {0, 0, 0};
+    size_t lds_rtv_c[3] = {0, 0, 0};
     // size classes of the plain row passes (FA rows, blur, state import) over row_items
     int rrow_beg[3] = {0, 0, 0}, rrow_cnt[3] = {0, 0, 0};
     size_t lds_rrow_c[3] = {0, 0, 0};
@@ -60,6 +66,7 @@ int col_max_tiles();                       // columns per column-pass block (one
 int row_tv_max_rows(int w);                  // rows per block of the TV row pass for width w
 int row_max_rows(int w);                     // rows per block of the plain row passes for width w
 int size_class(int n);                      // 0: n <= 512, 1: n <= 1024, 2: larger
+int col_class(const ProbDesc& d);           // 2 size_class(H) + (general column schedule)
 int row_maxe();
 int block_threads();
 
