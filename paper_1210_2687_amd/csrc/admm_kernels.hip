@@ -87,7 +87,9 @@ constexpr int NTC = 256;
 __device__ __forceinline__ float4 col_solve(float4 f, float2 lam, float w, float mu1, float mu2, float ihw, int mode) {
     if (mode == COL_SOLVE) {
         const float l2 = fmaf(lam.x, lam.x, lam.y * lam.y);
-        const float K = ihw / fmaf(mu1, l2, mu2 * w);
+        // hardware reciprocal (about 1 ulp) instead of a correctly rounded
+        // division: the denominator is positive and far from the range limits
+        const float K = ihw * __builtin_amdgcn_rcpf(fmaf(mu1, l2, mu2 * w));
         const float rx = fmaf(lam.x, f.x, lam.y * f.y) + f.z;
         const float ry = fmaf(lam.x, f.y, -(lam.y * f.x)) + f.w;
         const float zx = K * rx, zy = K * ry;
