@@ -173,7 +173,10 @@ admm_status admm_plan_time_pass(admm_plan* plan, const char* kernel, int32_t rep
 /* ---- FFT autotuner (tile shapes of the pass kernels) ----
  * Like admm_deconv_plan, but the columns per column-pass block (1..4, one
  * column per wave) and the rows per row-pass block are chosen by timing trial
- * plans on the device (10 profiled iterations each, zero data, on hip_stream).
+ * plans on the device (whole iterations replayed from graphs, zero data, on
+ * hip_stream): first the column tiles at the default row count, then the row
+ * counts at the best tile; 8 to 40 iterations per run by batch size, the best
+ * of three runs after a warm-up run.
  * cache_path: NULL (always measure) or a JSON file of earlier results, read if
  * it exists and rewritten with the new entry; an entry for the batch's key
  * (admm_tune_key with the device's architecture) is used without measuring.

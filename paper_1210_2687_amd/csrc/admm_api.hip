@@ -989,11 +989,12 @@ extern "C" int32_t admm_plan_kernel_times(const admm_plan* P, admm_kernel_time* 
 
 // ------------------------------------------------------------ FFT autotuner
 // Chooses the tile shapes of the two pass kernels by measurement: columns per
-// column-pass block (one column per wave) and rows per row-pass block. The
-// passes are independent (a column tile changes only the column kernel, a
-// row count only the row kernels), so each trial plan carries one candidate
-// of each and both are read from the same profiled run. Results are cached in
-// a JSON object keyed by device architecture and the batch's shape multiset:
+// column-pass block (one column per wave) and rows per row-pass block. Each
+// trial plan is timed on whole iterations replayed from graphs, as solves run:
+// first the column tiles with the planner's row count, then the row counts
+// with the best tile. Results are cached in a JSON object keyed by device
+// architecture and the batch's shape multiset, with the per-launch times of
+// the two passes under the choice for the record:
 //   {"gfx950|tv512x512*8": {"tc": 4, "rows": 8, "col_us": 16.1, "row_us": 30.6}}
 // The tile shape changes which thread computes what, never the arithmetic of
 // an element, so the iterates do not depend on it.
@@ -1161,6 +1162,43 @@ admm_status time_plan(admm_plan* P, const float* const* y, float* const* x, doub
     return ADMM_OK;
 }
 
+// Time one trial plan the way solves run: whole iterations replayed from
+// graphs, one event pair around each run on the plan's stream; the lowest
+// per-iteration time of three runs after a warm-up run. Per-launch event pairs
+// (time_plan) carry the dispatch of every launch, a few microseconds of jitter
+// against tile differences below one, so they only describe the choice made.
+admm_status time_iterations(admm_plan* P, const float* const* y, float* const* x, double* us) {
+    size_t px = 0;
+    for (int i = 0; i < P->count; ++i) px += (size_t)P->hd[i].H * P->hd[i].W;
+    admm_opts o{};
+    o.max_iters = (int)std::max<size_t>(8, std::min<size_t>(40, (size_t)2e8 / std::max<size_t>(px, 1)));
+    o.tol = 0.0;
+    o.check_every = 1 << 20;
+    o.flags = ADMM_FLAG_GRAPH;
+    std::vector<admm_info> infos(P->count);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    admm_status s = ADMM_OK;
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+        s = fail(ADMM_E_DEVICE, "autotuner: event creation failed");
+    double best = 1e300;
+    for (int rep = 0; rep < 4 && s == ADMM_OK; ++rep) {
+        if (hipEventRecord(ev[0], P->stream) != hipSuccess) {
+            s = fail(ADMM_E_DEVICE, "autotuner: event record failed");
+            break;
+        }
+        s = run(P, y, x, nullptr, &o, infos.data());
+        float ms = 0.f;
+        if (s == ADMM_OK && (hipEventRecord(ev[1], P->stream) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                             hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+            s = fail(ADMM_E_DEVICE, "autotuner: event timing failed");
+        if (s == ADMM_OK && rep > 0) best = std::min(best, 1e3 * ms / o.max_iters);
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    *us = best;
+    return s;
+}
+
 }  // namespace
 
 extern "C" int32_t admm_tune_key(const admm_problem* probs, int32_t count, const char* arch, char* out, size_t cap) {
@@ -1255,33 +1293,44 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
         admm_status st = hipMemsetAsync(dy, 0, nmax * sizeof(float), (hipStream_t)hip_stream) == hipSuccess
                              ? ADMM_OK
                              : fail(ADMM_E_DEVICE, "autotuner: memset failed");
+        // two searches, each on the time per whole iteration: the column tile
+        // with the planner's row count, then the row count with that tile
         const int tcs[] = {1, 2, 3, 4};
         const int bs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
         const int ntc = 4, nb = 10;
-        double best_c = 1e300, best_r = 1e300;
         TuneEntry rec;
-        for (int k = 0; k < std::max(ntc, nb) && st == ADMM_OK; ++k) {
-            TileChoice t;
-            t.tc = tcs[std::min(k, ntc - 1)];
-            t.b = bs[std::min(k, nb - 1)];
+        auto trial = [&](TileChoice t, double* us) -> admm_status {
             admm_plan* P = new admm_plan();
             admm_status s = build_plan(P, probs, count, hip_stream, t);
-            if (s == ADMM_OK) {
-                double c = 0, r = 0;
-                s = time_plan(P, yv.data(), xv.data(), &c, &r);
-                if (s == ADMM_OK) {
-                    // the requested shapes are recorded: planning with them again
-                    // reproduces this trial (the planner clamps them the same way)
-                    if (k < ntc && c < best_c) {
-                        best_c = c;
-                        best.tc = t.tc;
-                    }
-                    if (k < nb && r < best_r) {
-                        best_r = r;
-                        best.b = t.b;
-                    }
-                }
+            if (s == ADMM_OK) s = time_iterations(P, yv.data(), xv.data(), us);
+            admm_plan_destroy(P);
+            return s;
+        };
+        double best_t = 1e300;
+        for (int k = 0; k < ntc + nb && st == ADMM_OK; ++k) {
+            TileChoice t;
+            t.tc = k < ntc ? tcs[k] : best.tc;
+            t.b = k < ntc ? 0 : bs[k - ntc];
+            if (k == ntc) best_t = 1e300;   // row counts compete among themselves
+            if (k >= ntc && best.tc < 1) break;
+            double us = 0.0;
+            const admm_status s = trial(t, &us);
+            // the requested shapes are recorded: planning with them again
+            // reproduces this trial (the planner clamps them the same way)
+            if (s == ADMM_OK && us < best_t) {
+                best_t = us;
+                if (k < ntc)
+                    best.tc = t.tc;
+                else
+                    best.b = t.b;
             }
+            if (s == ADMM_E_DEVICE || s == ADMM_E_NOMEM) st = s;
+        }
+        double best_c = 0.0, best_r = 0.0;   // per-pass figures of the choice, for the record
+        if (st == ADMM_OK && best.tc >= 1 && best.b >= 1) {
+            admm_plan* P = new admm_plan();
+            admm_status s = build_plan(P, probs, count, hip_stream, best);
+            if (s == ADMM_OK) s = time_plan(P, yv.data(), xv.data(), &best_c, &best_r);
             admm_plan_destroy(P);
             if (s == ADMM_E_DEVICE || s == ADMM_E_NOMEM) st = s;
         }
