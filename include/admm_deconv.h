@@ -175,8 +175,9 @@ admm_status admm_plan_time_pass(admm_plan* plan, const char* kernel, int32_t rep
  * column per wave) and the rows per row-pass block are chosen by timing trial
  * plans on the device (whole iterations replayed from graphs, zero data, on
  * hip_stream): first the column tiles at the default row count, then the row
- * counts at the best tile; 8 to 40 iterations per run by batch size, the best
- * of three runs after a warm-up run.
+ * counts at the best tile. A trial's time per iteration is the difference of
+ * runs of K and 3K iterations (K = 4 to 20 by batch size, best of three runs
+ * of each after a warm-up) over 2K, free of the per-run work.
  * cache_path: NULL (always measure) or a JSON file of earlier results, read if
  * it exists and rewritten with the new entry; an entry for the batch's key
  * (admm_tune_key with the device's architecture) is used without measuring.

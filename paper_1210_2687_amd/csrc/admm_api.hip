@@ -1163,15 +1163,18 @@ admm_status time_plan(admm_plan* P, const float* const* y, float* const* x, doub
 }
 
 // Time one trial plan the way solves run: whole iterations replayed from
-// graphs, one event pair around each run on the plan's stream; the lowest
-// per-iteration time of three runs after a warm-up run. Per-launch event pairs
-// (time_plan) carry the dispatch of every launch, a few microseconds of jitter
-// against tile differences below one, so they only describe the choice made.
+// graphs, one event pair around each run on the plan's stream. Runs of K and
+// 3K iterations are timed (best of three after a warm-up run of each) and the
+// difference divided by 2K: the per-run work (state reset, descriptor upload,
+// the final iteration and its reduction) cancels, which for large batches is
+// a large share of a short run. Per-launch event pairs (time_plan) carry the
+// dispatch of every launch, a few microseconds of jitter against tile
+// differences below one, so they only describe the choice made.
 admm_status time_iterations(admm_plan* P, const float* const* y, float* const* x, double* us) {
     size_t px = 0;
     for (int i = 0; i < P->count; ++i) px += (size_t)P->hd[i].H * P->hd[i].W;
+    const int K = (int)std::max<size_t>(4, std::min<size_t>(20, (size_t)1e8 / std::max<size_t>(px, 1)));
     admm_opts o{};
-    o.max_iters = (int)std::max<size_t>(8, std::min<size_t>(40, (size_t)2e8 / std::max<size_t>(px, 1)));
     o.tol = 0.0;
     o.check_every = 1 << 20;
     o.flags = ADMM_FLAG_GRAPH;
@@ -1180,22 +1183,26 @@ admm_status time_iterations(admm_plan* P, const float* const* y, float* const* x
     admm_status s = ADMM_OK;
     if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
         s = fail(ADMM_E_DEVICE, "autotuner: event creation failed");
-    double best = 1e300;
+    double best[2] = {1e300, 1e300};
     for (int rep = 0; rep < 4 && s == ADMM_OK; ++rep) {
-        if (hipEventRecord(ev[0], P->stream) != hipSuccess) {
-            s = fail(ADMM_E_DEVICE, "autotuner: event record failed");
-            break;
+        for (int len = 0; len < 2 && s == ADMM_OK; ++len) {
+            o.max_iters = len ? 3 * K : K;
+            if (hipEventRecord(ev[0], P->stream) != hipSuccess) {
+                s = fail(ADMM_E_DEVICE, "autotuner: event record failed");
+                break;
+            }
+            s = run(P, y, x, nullptr, &o, infos.data());
+            float ms = 0.f;
+            if (s == ADMM_OK && (hipEventRecord(ev[1], P->stream) != hipSuccess ||
+                                 hipEventSynchronize(ev[1]) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+                s = fail(ADMM_E_DEVICE, "autotuner: event timing failed");
+            if (s == ADMM_OK && rep > 0) best[len] = std::min(best[len], 1e3 * (double)ms);
         }
-        s = run(P, y, x, nullptr, &o, infos.data());
-        float ms = 0.f;
-        if (s == ADMM_OK && (hipEventRecord(ev[1], P->stream) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
-                             hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
-            s = fail(ADMM_E_DEVICE, "autotuner: event timing failed");
-        if (s == ADMM_OK && rep > 0) best = std::min(best, 1e3 * ms / o.max_iters);
     }
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
-    *us = best;
+    *us = best[1] > best[0] ? (best[1] - best[0]) / (2.0 * K) : best[1] / (3.0 * K);
     return s;
 }
 
