@@ -270,3 +270,40 @@ def config5_problem(index, size=256):
     m = valid_mask(H, W, k // 2)
     y = observe(g, x, h, m, 2e-3)
     return Problem(y=y, mask=m, kernel=h, lam=2e-4, mu1=1e-3, mu2=1e-3, x_true=x)
+
+
+def boundary_pair(index, observed=480, k=25, family="uniform", sigma=1e-3, lam=2e-4, mu=1e-3):
+    """The same observation posed twice, for the unknown-boundary comparison of Sec. V.
+
+    The image lives on an (observed + k - 1)^2 domain; y is its blur restricted
+    to the central observed^2 pixels that the kernel reaches without crossing
+    the image edge (the valid region), plus noise. Returned:
+
+    * ``md``: the mask-decoupled problem on the full domain, mask = the valid
+      region, y embedded in it (the boundary pixels are unknown);
+    * ``bc``: the same y as a problem on the observed^2 domain alone, mask = 1,
+      which makes the periodic-boundary model the method falls back to when
+      M = I (Sec. IV-A);
+    * ``x_obs``: the true image on the observed region (ISNR reference);
+    * ``y_obs``: the observed^2 data.
+
+    Both sides are 7-smooth for the default sizes (480 and 504).
+    """
+    g = rng(1000 * 6 + index)
+    l = k // 2
+    H = W = observed + 2 * l
+    if family == "uniform":
+        h = kernel_uniform(k)
+    elif family == "gaussian":
+        h = kernel_gaussian(k, k / 6.0)
+    else:
+        h = kernel_motion(k, float(k), g.uniform(0, math.pi))
+    x = synth_image(g, H, W, grf_scale=32.0)
+    m = valid_mask(H, W, l)
+    y = observe(g, x, h, m, sigma)
+    mu1 = mu2 = mu
+    md = Problem(y=y, mask=m, kernel=h, lam=lam, mu1=mu1, mu2=mu2, x_true=x)
+    y_obs = y[l:H - l, l:W - l].copy()
+    bc = Problem(y=y_obs, mask=np.ones_like(y_obs, dtype=np.uint8), kernel=h, lam=lam, mu1=mu1, mu2=mu2,
+                 x_true=None)
+    return md, bc, x[l:H - l, l:W - l].copy(), y_obs
