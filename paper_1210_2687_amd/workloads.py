@@ -272,8 +272,39 @@ def config5_problem(index, size=256):
     return Problem(y=y, mask=m, kernel=h, lam=2e-4, mu1=1e-3, mu2=1e-3, x_true=x)
 
 
-def boundary_pair(index, observed=480, k=25, family="uniform", sigma=1e-3, lam=2e-4, mu=1e-3):
-    """The same observation posed twice, for the unknown-boundary comparison of Sec. V.
+def edge_taper(y, h):
+    """Edge tapering of an observation before a periodic-boundary solve (the "ET" baseline).
+
+    Written from the published description of edge tapering: the output is a
+    weighted sum of y and its periodic blur by h, with weights equal to one in
+    the centre and falling to zero at the image edges over a width set by the
+    autocorrelation of the kernel. Per axis, the weight at distance d from the
+    nearer edge is 1 - a(d) / a(0), a the autocorrelation of the kernel's
+    projection on that axis; the 2-D weight is the product of the two axes'.
+    Near the edges the data then agree with the periodic model's wrap-around.
+    """
+    y = np.asarray(y, dtype=np.float64)
+    h = np.asarray(h, dtype=np.float64)
+
+    def axis_weight(proj, N):
+        a = np.correlate(proj, proj, mode="full")[len(proj) - 1:]   # lags 0 .. k-1
+        a = a / a[0]
+        d = np.minimum(np.arange(N), N - 1 - np.arange(N))
+        w = np.ones(N)
+        near = d < len(a)
+        w[near] = 1.0 - a[d[near]]
+        return w
+
+    wv = axis_weight(h.sum(axis=1), y.shape[0])
+    wh = axis_weight(h.sum(axis=0), y.shape[1])
+    w = wv[:, None] * wh[None, :]
+    blurred = ndimage.convolve(y, h, mode="wrap")
+    return w * y + (1.0 - w) * blurred
+
+
+def boundary_pair(index, observed=480, k=25, family="uniform", sigma=1e-3, lam=2e-4, mu=1e-3,
+                  reg="tv", levels=3):
+    """The same observation posed three ways, for the unknown-boundary comparison of Sec. V.
 
     The image lives on an (observed + k - 1)^2 domain; y is its blur restricted
     to the central observed^2 pixels that the kernel reaches without crossing
@@ -284,10 +315,12 @@ def boundary_pair(index, observed=480, k=25, family="uniform", sigma=1e-3, lam=2
     * ``bc``: the same y as a problem on the observed^2 domain alone, mask = 1,
       which makes the periodic-boundary model the method falls back to when
       M = I (Sec. IV-A);
+    * ``et``: as ``bc`` with the observation edge-tapered (``edge_taper``);
     * ``x_obs``: the true image on the observed region (ISNR reference);
     * ``y_obs``: the observed^2 data.
 
-    Both sides are 7-smooth for the default sizes (480 and 504).
+    Both sides are 7-smooth for the default sizes (480 and 504). ``reg``:
+    "tv" or "frame" (with ``levels``).
     """
     g = rng(1000 * 6 + index)
     l = k // 2
@@ -301,9 +334,10 @@ def boundary_pair(index, observed=480, k=25, family="uniform", sigma=1e-3, lam=2
     x = synth_image(g, H, W, grf_scale=32.0)
     m = valid_mask(H, W, l)
     y = observe(g, x, h, m, sigma)
-    mu1 = mu2 = mu
-    md = Problem(y=y, mask=m, kernel=h, lam=lam, mu1=mu1, mu2=mu2, x_true=x)
+    J = levels if reg == "frame" else 0
+    md = Problem(y=y, mask=m, kernel=h, lam=lam, mu1=mu, mu2=mu, x_true=x, reg=reg, levels=J)
     y_obs = y[l:H - l, l:W - l].copy()
-    bc = Problem(y=y_obs, mask=np.ones_like(y_obs, dtype=np.uint8), kernel=h, lam=lam, mu1=mu1, mu2=mu2,
-                 x_true=None)
-    return md, bc, x[l:H - l, l:W - l].copy(), y_obs
+    ones = np.ones_like(y_obs, dtype=np.uint8)
+    bc = Problem(y=y_obs, mask=ones, kernel=h, lam=lam, mu1=mu, mu2=mu, reg=reg, levels=J)
+    et = Problem(y=edge_taper(y_obs, h), mask=ones, kernel=h, lam=lam, mu1=mu, mu2=mu, reg=reg, levels=J)
+    return md, bc, et, x[l:H - l, l:W - l].copy(), y_obs
