@@ -98,6 +98,12 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
 
     const float* din = par ? p.dreg1 : p.dreg0;
     float* dout = par ? p.dreg0 : p.dreg1;
+    // descriptor fields read once (the coefficient stores would make the
+    // compiler reload each of them, and wait for it, after every store)
+    float* const UREGP = p.uregp;
+    float* const SUREG = p.st_ureg;
+    float* const SDREG = p.st_dreg;
+    float* const TB = p.tmpB;
 
     double acc[ADMM_NSUM];
 #pragma unroll
@@ -127,7 +133,7 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
             const int ie = idx / LE;
             const unsigned g = cidx(3 * J, ie - h, idx - ie * LE - h);
             dcv[u] = gld(din, g);
-            if (chk) ucv[u] = gld(p.uregp, g);
+            if (chk) ucv[u] = gld(UREGP, g);
         }
 #pragma unroll
         for (int jj = J - 1; jj >= 0; --jj) {
@@ -141,7 +147,7 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
 #pragma unroll
                     for (int b = 0; b < 3; ++b) {
                         dlv[jj][b][u] = gld(din, g + (unsigned)b * n);
-                        if (chk) ulv[jj][b][u] = gld(p.uregp, g + (unsigned)b * n);
+                        if (chk) ulv[jj][b][u] = gld(UREGP, g + (unsigned)b * n);
                     }
                 }
             }
@@ -187,16 +193,16 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
                 acc[9] += (double)(dn * dn);
                 acc[11] += (double)fabsf(Pz);
             }
-            if (flags & F_WRITE_UPREV) gst(p.uregp, g, u);
+            if (flags & F_WRITE_UPREV) gst(UREGP, g, u);
             if (flags & F_EXPORT) {
-                gst(p.st_ureg, g, u);
-                gst(p.st_dreg, g, dn);
+                gst(SUREG, g, u);
+                gst(SDREG, g, dn);
             }
         }
         return u + dn;
     };
     auto coef_import = [&](unsigned g, bool own) -> float {
-        const float d = gld(p.st_dreg, g), u = gld(p.st_ureg, g);
+        const float d = gld(SDREG, g), u = gld(SUREG, g);
         if (own) gst(dout, g, d);
         return u + d;
     };
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
     for (int u = 0; u < fr_cdiv(FT * FT, NTF); ++u) {
         const int idx = tid + u * NTF;
         const int i = idx / FT, k = idx - i * FT;
-        if ((unsigned)i < hlim && (unsigned)k < wlim) gst(p.tmpB, (unsigned)((r0 + i) * W + c0 + k), mu2 * Af[idx]);
+        if ((unsigned)i < hlim && (unsigned)k < wlim) gst(TB, (unsigned)((r0 + i) * W + c0 + k), mu2 * Af[idx]);
     }
     if (chk) {
         const int lane = tid & 63, wave = tid >> 6;

@@ -398,6 +398,20 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
 
     const float4* Sin = par ? p.spec1 : p.spec0;
     float4* Sout = par ? p.spec0 : p.spec1;
+    // Descriptor fields used after the epilogue's global stores, read once: the
+    // compiler cannot tell that those stores leave the descriptor unchanged and
+    // would reload each field (and wait for it) on every row.
+    float* const D1 = p.d1;
+    float* const XO = p.x;
+    float* const U1P = p.u1p;
+    float* const UREGP = p.uregp;
+    float* const SU1 = p.st_u1;
+    float* const SD1 = p.st_d1;
+    float* const SUREG = p.st_ureg;
+    float* const SDREG = p.st_dreg;
+    const uint8_t* const MK = p.mask;
+    const float* const YV = p.y;
+    const float mu1 = p.mu1;
     const float* dh_in = par ? p.dreg1 : p.dreg0;
     const float* dv_in = dh_in + n;
     float* dh_out = par ? p.dreg0 : p.dreg1;
@@ -424,13 +438,13 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
             pdh[j][rr] = gld(dh_in, g);
             pdv[j][rr] = gld(dv_in, g);
             if (rr > 0) {
-                pd1[j][rr - 1] = gld(p.d1, g);
-                pmk[j][rr - 1] = gld(p.mask, g);
-                py[j][rr - 1] = gld(p.y, g);
+                pd1[j][rr - 1] = gld(D1, g);
+                pmk[j][rr - 1] = gld(MK, g);
+                py[j][rr - 1] = gld(YV, g);
                 if (CHK) {
-                    pq1[j][CHK ? rr - 1 : 0] = gld(p.u1p, g);
-                    pqh[j][CHK ? rr - 1 : 0] = gld(p.uregp, g);
-                    pqv[j][CHK ? rr - 1 : 0] = gld(p.uregp, n + g);
+                    pq1[j][CHK ? rr - 1 : 0] = gld(U1P, g);
+                    pqh[j][CHK ? rr - 1 : 0] = gld(UREGP, g);
+                    pqv[j][CHK ? rr - 1 : 0] = gld(UREGP, n + g);
                 }
             }
         }
@@ -491,10 +505,10 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                     const float d1n = u1 - v1;                           // d1 - (A z - u1)
                     zet[j] = u1 + d1n;
                   if (live) {
-                    gst(p.d1, g, d1n);
+                    gst(D1, g, d1n);
                     gst(dh_out, g, dhn);
                     gst(dv_out, g, dvn);
-                    if (flags & F_WRITE_X) gst(p.x, g, zc);
+                    if (flags & F_WRITE_X) gst(XO, g, zc);
                     if (chk) {
                         const float u1q = pq1[j][CHK ? rr - 1 : 0], uhq = pqh[j][CHK ? rr - 1 : 0],
                                     uvq = pqv[j][CHK ? rr - 1 : 0];
@@ -515,17 +529,17 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
                         acc[11] += (double)sqrtf(fmaf(zh, zh, zv * zv));
                     }
                     if (flags & F_WRITE_UPREV) {
-                        gst(p.u1p, g, u1);
-                        gst(p.uregp, g, uh);
-                        gst(p.uregp, n + g, uv);
+                        gst(U1P, g, u1);
+                        gst(UREGP, g, uh);
+                        gst(UREGP, n + g, uv);
                     }
                     if (flags & F_EXPORT) {
-                        gst(p.st_u1, g, u1);
-                        gst(p.st_d1, g, d1n);
-                        gst(p.st_ureg, g, uh);
-                        gst(p.st_ureg, n + g, uv);
-                        gst(p.st_dreg, g, dhn);
-                        gst(p.st_dreg, n + g, dvn);
+                        gst(SU1, g, u1);
+                        gst(SD1, g, d1n);
+                        gst(SUREG, g, uh);
+                        gst(SUREG, n + g, uv);
+                        gst(SDREG, g, dhn);
+                        gst(SDREG, n + g, dvn);
                     }
                   }
                 }
@@ -538,7 +552,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
             for (int j = 0; j < CPT; ++j) {
                 const int c = min(tid + j * NT, W - 1);
                 const float s = mu2 * ((dlr[c == 0 ? W - 1 : c - 1] - dlr[c]) + (dvp[j] - dvc[j]));
-                Xw[pidx(c)] = make_float2(p.mu1 * zet[j], s);
+                Xw[pidx(c)] = make_float2(mu1 * zet[j], s);
             }
         }
 #pragma unroll
@@ -642,17 +656,29 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     rows_fft<NT * CPT, NT, RB, MAXE_ROW, true>(X, pitch, p.fr, twl, nr, tid);
     const unsigned off = (unsigned)(r0 * W);
     if (mode == 0) {
+        float* const TB = p.tmpB;   // read once: the stores below would make the compiler reload it
         for (int rr = 0; rr < nr; ++rr) {
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
                 const int c = tid + j * NT;
-                if (c < W) gst(p.tmpB, off + (unsigned)(rr * W + c), X[rr * pitch + pidx(c)].x);
+                if (c < W) gst(TB, off + (unsigned)(rr * W + c), X[rr * pitch + pidx(c)].x);
             }
         }
         return;
     }
     const float c1 = p.inv1pmu1;
     const bool chk = flags & F_CHECK;
+    // descriptor fields read once (the row loop's global stores would make the
+    // compiler reload each of them, and wait for it, on every row)
+    float* const D1 = p.d1;
+    float* const TA = p.tmpA;
+    float* const ZP = p.zpl;
+    float* const XO = p.x;
+    float* const U1P = p.u1p;
+    float* const SU1 = p.st_u1;
+    float* const SD1 = p.st_d1;
+    const uint8_t* const MK = p.mask;
+    const float* const YV = p.y;
     double acc[ADMM_NSUM];
 #pragma unroll
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
@@ -667,9 +693,9 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
                 const unsigned g = off + (unsigned)(rr * W + min(tid + j * NT, W - 1));
-                d1b[k][j] = gld(p.d1, g);
-                mb[k][j] = gld(p.mask, g);
-                yb[k][j] = gld(p.y, g);
+                d1b[k][j] = gld(D1, g);
+                mb[k][j] = gld(MK, g);
+                yb[k][j] = gld(YV, g);
             }
         }
 #pragma unroll
@@ -688,12 +714,12 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
                 const float v1 = Az - d1o;
                 const float u1 = obs ? fmaf(yv - v1, c1, v1) : v1;
                 const float d1n = u1 - v1;
-                gst(p.d1, g, d1n);
-                gst(p.tmpA, g, u1 + d1n);
-                gst(p.zpl, g, z);
-                if (flags & F_WRITE_X) gst(p.x, g, z);
+                gst(D1, g, d1n);
+                gst(TA, g, u1 + d1n);
+                gst(ZP, g, z);
+                if (flags & F_WRITE_X) gst(XO, g, z);
                 if (chk) {
-                    const float e0 = Az - u1, f6 = u1 - gld(p.u1p, g), ry = yv - Az;
+                    const float e0 = Az - u1, f6 = u1 - gld(U1P, g), ry = yv - Az;
                     acc[0] += (double)(e0 * e0);
                     acc[2] += (double)(Az * Az);
                     acc[4] += (double)(u1 * u1);
@@ -701,10 +727,10 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
                     acc[8] += (double)(d1n * d1n);
                     acc[10] += obs ? (double)(ry * ry) : 0.0;
                 }
-                if (flags & F_WRITE_UPREV) gst(p.u1p, g, u1);
+                if (flags & F_WRITE_UPREV) gst(U1P, g, u1);
                 if (flags & F_EXPORT) {
-                    gst(p.st_u1, g, u1);
-                    gst(p.st_d1, g, d1n);
+                    gst(SU1, g, u1);
+                    gst(SD1, g, d1n);
                 }
             }
         }
