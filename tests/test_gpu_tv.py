@@ -243,6 +243,40 @@ def test_frame_largest_size_by_tiling():
     assert e <= ITER_TOL
 
 
+@pytest.mark.parametrize("base_shape,reps", [((125, 49), (16, 40)), ((49, 125), (21, 16)), ((8, 64), (1, 32)),
+                                             ((125, 8), (16, 1))])
+def test_general_lengths_and_thin_shapes_by_tiling(base_shape, reps):
+    # 2000 x 1960 and 1029 x 2000: general schedules (not ending in radix 8) in the
+    # largest size class of both passes; 8 x 2048 and 2000 x 8: eight-entry
+    # columns and eight-entry rows at the other extreme
+    H, W = base_shape
+    announce(f"tiled TV {base_shape} x {reps} = {(H * reps[0], W * reps[1])}")
+    base = fast_tv_problem(73, H, W, 7)
+    big = _tiled(base, reps)
+    K = 25
+    ref = O.tv_md_run(base.y, base.mask, base.kernel, base.lam, base.mu1, base.mu2, iters=K)["z"]
+    with A.Plan([big]) as plan:
+        z, _ = gpu_solve(plan, big, K, graph=True)
+    e = rel(z, np.tile(ref, reps))
+    announce(f"  {big.shape}: rel err {e:.2e}")
+    assert e <= ITER_TOL
+
+
+def test_frame_general_lengths_by_tiling():
+    announce("tiled FA 2000 x 1960, J = 2")
+    base0 = fast_tv_problem(74, 125, 49, 7)
+    base = WL.Problem(y=base0.y, mask=base0.mask, kernel=base0.kernel, lam=base0.lam, mu1=base0.mu1,
+                      mu2=base0.mu2, reg="frame", levels=2)
+    big = _tiled(base, (16, 40))
+    K = 20
+    ref = O.fa_md_run(base.y, base.mask, base.kernel, base.lam, base.mu1, base.mu2, base.levels, iters=K)["z"]
+    with A.Plan([big]) as plan:
+        z, _ = gpu_solve(plan, big, K)
+    e = rel(z, np.tile(ref, (16, 40)))
+    announce(f"  rel err {e:.2e}")
+    assert e <= ITER_TOL
+
+
 def test_all_pixels_missing():
     # M = 0: the data term vanishes (u1 follows A z, d1 becomes 0 after one
     # iteration); from a random state the iterates still move, and match
