@@ -277,6 +277,50 @@ def test_frame_general_lengths_by_tiling():
     assert e <= ITER_TOL
 
 
+@pytest.mark.parametrize("reg", ["tv", "frame"])
+def test_largest_kernel_on_small_images(reg):
+    # 31 x 31 kernels on 40 x 36 and 32 x 32 domains (valid regions 10 x 6 and 2 x 2)
+    for H, W in ((40, 36), (32, 32)):
+        announce(f"k = 31 on {H} x {W}, {reg}")
+        base = fast_tv_problem(75, H, W, 31)
+        p = WL.Problem(y=base.y, mask=base.mask, kernel=base.kernel, lam=base.lam, mu1=base.mu1, mu2=base.mu2,
+                       reg=reg, levels=2 if reg == "frame" else 0)
+        K = 30
+        if reg == "frame":
+            ref = O.fa_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, p.levels, iters=K)["z"]
+        else:
+            ref = O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=K)["z"]
+        with A.Plan([p]) as plan:
+            z, _ = gpu_solve(plan, p, K)
+        e = rel(z, ref)
+        announce(f"  rel err {e:.2e}")
+        assert e <= ITER_TOL
+
+
+def test_batch_of_smallest_and_largest_problems():
+    # one plan holding an 8 x 8 problem, a 2000 x 1960 one (tiled, general
+    # schedules) and a 2048 x 2048 one (tiled, radix-8 schedules): every size
+    # class of both passes in the same launches
+    import torch
+    announce("batch: 8 x 8, 2000 x 1960, 2048 x 2048")
+    small = fast_tv_problem(76, 8, 8, 3)
+    b1 = fast_tv_problem(73, 125, 49, 7)
+    b2 = fast_tv_problem(71, 64, 64, 7)
+    probs = [small, _tiled(b1, (16, 40)), _tiled(b2, (32, 32))]
+    K = 20
+    refs = [O.tv_md_run(q.y, q.mask, q.kernel, q.lam, q.mu1, q.mu2, iters=K)["z"] for q in (small, b1, b2)]
+    refs = [refs[0], np.tile(refs[1], (16, 40)), np.tile(refs[2], (32, 32))]
+    with A.Plan(probs) as plan:
+        ys = [dev(q.y) for q in probs]
+        xs = [torch.zeros_like(y) for y in ys]
+        infos = plan.batch(ys, xs, max_iters=K, graph=True)
+    for q, x, info, ref in zip(probs, xs, infos, refs):
+        e = rel(host(x), ref)
+        announce(f"  {q.shape}: rel err {e:.2e}")
+        assert info["iters"] == K
+        assert e <= ITER_TOL
+
+
 def test_all_pixels_missing():
     # M = 0: the data term vanishes (u1 follows A z, d1 becomes 0 after one
     # iteration); from a random state the iterates still move, and match
