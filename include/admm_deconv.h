@@ -175,9 +175,12 @@ admm_status admm_plan_time_pass(admm_plan* plan, const char* kernel, int32_t rep
  * column per wave) and the rows per row-pass block are chosen by timing trial
  * plans on the device (whole iterations replayed from graphs, zero data, on
  * hip_stream): first the column tiles at the default row count, then the row
- * counts at the best tile. A trial's time per iteration is the difference of
- * runs of K and 3K iterations (K = 4 to 20 by batch size, best of three runs
- * of each after a warm-up) over 2K, free of the per-run work.
+ * counts at the best tile, then, for batches whose row lengths fall in several
+ * size classes (<= 512, <= 1024, <= 2048), each class's row count with the
+ * others held (kept on a gain above 0.5%). A trial's time per iteration is
+ * the difference of runs of K and 3K iterations (K = 4 to 20 by batch size,
+ * best of three runs of each after a warm-up) over 2K, free of the per-run
+ * work.
  * cache_path: NULL (always measure) or a JSON file of earlier results, read if
  * it exists and rewritten with the new entry; an entry for the batch's key
  * (admm_tune_key with the device's architecture) is used without measuring.
@@ -194,7 +197,10 @@ int32_t admm_tune_key(const admm_problem* probs, int32_t count, const char* arch
 
 /* Cache file access (HOST only, no device): lookup returns 1 and the entry if
  * `key` is present, 0 if absent (or no file), -1 if the file is malformed;
- * store inserts or replaces an entry (tc, rows >= 1; timings in microseconds). */
+ * store inserts or replaces an entry (tc, rows >= 1; timings in microseconds).
+ * Entries the autotuner writes may also hold per-class row counts
+ * ("rows_512", "rows_1024", "rows_2048"), which lookup does not report and
+ * store does not write.                                                        */
 int32_t admm_tune_cache_lookup(const char* path, const char* key, int32_t* tc, int32_t* rows);
 admm_status admm_tune_cache_store(const char* path, const char* key, int32_t tc, int32_t rows, double col_us,
                                   double row_us);

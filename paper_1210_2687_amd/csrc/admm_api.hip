@@ -120,6 +120,7 @@ void stage_twiddles(int N, float2* out) {
 // columns per column-pass block and rows per row-pass block.
 struct TileChoice {
     int tc = 0, b = 0;
+    int bc[3] = {0, 0, 0};   // rows per row block by size class of the row length (0: use b)
 };
 
 constexpr int kPeriodsInFlight = 2;      // period graphs queued ahead of the host's stop test
@@ -330,7 +331,8 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         if (bmax < 1) return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: row length %d does not fit a block", i, q.W));
         const int bmin = q.reg == ADMM_REG_TV ? std::min(bmax, 2) : 1;   // TV: halo rows cost (B + 2) / B
         d.B = std::max(bmin, std::min(bmax, (q.H + per - 1) / per));
-        if (tile.b > 0) d.B = std::min(bmax, tile.b);
+        const int breq = tile.bc[size_class(q.W)] > 0 ? tile.bc[size_class(q.W)] : tile.b;
+        if (breq > 0) d.B = std::min(bmax, breq);
         if (const char* e = std::getenv("ADMM_ROWS")) d.B = std::max(1, std::min(bmax, std::atoi(e)));
         d.nrowblk = (q.H + d.B - 1) / d.B;
         d.ncolblk = (d.P + d.TC - 1) / d.TC;
@@ -992,16 +994,20 @@ extern "C" int32_t admm_plan_kernel_times(const admm_plan* P, admm_kernel_time* 
 // column-pass block (one column per wave) and rows per row-pass block. Each
 // trial plan is timed on whole iterations replayed from graphs, as solves run:
 // first the column tiles with the planner's row count, then the row counts
-// with the best tile. Results are cached in a JSON object keyed by device
-// architecture and the batch's shape multiset, with the per-launch times of
-// the two passes under the choice for the record:
+// with the best tile, then, when the batch's rows fall in several size
+// classes, the row count of each class with the others held. Results are
+// cached in a JSON object keyed by device architecture and the batch's shape
+// multiset, with the per-launch times of the two passes under the choice for
+// the record; per-class row counts appear only where they differ from "rows":
 //   {"gfx950|tv512x512*8": {"tc": 4, "rows": 8, "col_us": 16.1, "row_us": 30.6}}
+//   {"gfx950|h...*256": {"tc": 4, "rows": 5, "rows_512": 8, "col_us": 896, "row_us": 1597}}
 // The tile shape changes which thread computes what, never the arithmetic of
 // an element, so the iterates do not depend on it.
 namespace {
 
 struct TuneEntry {
     int tc = 0, rows = 0;
+    int rows_c[3] = {0, 0, 0};   // per size class of the row length, 0: rows ("rows_512", "rows_1024", "rows_2048")
     double col_us = 0.0, row_us = 0.0;
 };
 
@@ -1050,6 +1056,9 @@ bool parse_cache(const std::string& text, std::map<std::string, TuneEntry>& out)
                 p = end;
                 if (f == "tc") e.tc = (int)v;
                 else if (f == "rows") e.rows = (int)v;
+                else if (f == "rows_512") e.rows_c[0] = (int)v;
+                else if (f == "rows_1024") e.rows_c[1] = (int)v;
+                else if (f == "rows_2048") e.rows_c[2] = (int)v;
                 else if (f == "col_us") e.col_us = v;
                 else if (f == "row_us") e.row_us = v;
                 skip_ws(p);
@@ -1076,9 +1085,13 @@ std::string format_cache(const std::map<std::string, TuneEntry>& m) {
     std::string s = "{\n";
     size_t i = 0;
     for (const auto& kv : m) {
-        char buf[160];
-        std::snprintf(buf, sizeof buf, "{\"tc\": %d, \"rows\": %d, \"col_us\": %.3f, \"row_us\": %.3f}", kv.second.tc,
-                      kv.second.rows, kv.second.col_us, kv.second.row_us);
+        char buf[256];
+        std::string extra;
+        static const char* names[3] = {"rows_512", "rows_1024", "rows_2048"};
+        for (int c = 0; c < 3; ++c)
+            if (kv.second.rows_c[c] > 0) extra += ", \"" + std::string(names[c]) + "\": " + std::to_string(kv.second.rows_c[c]);
+        std::snprintf(buf, sizeof buf, "{\"tc\": %d, \"rows\": %d%s, \"col_us\": %.3f, \"row_us\": %.3f}",
+                      kv.second.tc, kv.second.rows, extra.c_str(), kv.second.col_us, kv.second.row_us);
         s += "  \"" + kv.first + "\": " + buf + (++i < m.size() ? ",\n" : "\n");
     }
     return s + "}\n";
@@ -1273,6 +1286,7 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
         if (it != cache.end() && it->second.tc > 0 && it->second.rows > 0) {
             best.tc = it->second.tc;
             best.b = it->second.rows;
+            for (int c = 0; c < 3; ++c) best.bc[c] = it->second.rows_c[c];
             have = true;
         }
     }
@@ -1300,8 +1314,10 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
         admm_status st = hipMemsetAsync(dy, 0, nmax * sizeof(float), (hipStream_t)hip_stream) == hipSuccess
                              ? ADMM_OK
                              : fail(ADMM_E_DEVICE, "autotuner: memset failed");
-        // two searches, each on the time per whole iteration: the column tile
-        // with the planner's row count, then the row count with that tile
+        // searches on the time per whole iteration: the column tile with the
+        // planner's row count, then the row count with that tile, then (batches
+        // whose rows fall in several size classes) the row count of each class
+        // with the others held
         const int tcs[] = {1, 2, 3, 4};
         const int bs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
         const int ntc = 4, nb = 10;
@@ -1333,6 +1349,25 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
             }
             if (s == ADMM_E_DEVICE || s == ADMM_E_NOMEM) st = s;
         }
+        bool cls[3] = {false, false, false};
+        for (int i = 0; i < count; ++i) cls[size_class(probs[i].W)] = true;
+        if (cls[0] + cls[1] + cls[2] > 1 && best.tc >= 1 && best.b >= 1) {
+            for (int c = 0; c < 3 && st == ADMM_OK; ++c) {
+                if (!cls[c]) continue;
+                for (int k = 0; k < nb && st == ADMM_OK; ++k) {
+                    if (bs[k] == best.b) continue;   // the common count is the incumbent
+                    TileChoice t = best;
+                    t.bc[c] = bs[k];
+                    double us = 0.0;
+                    const admm_status s = trial(t, &us);
+                    if (s == ADMM_OK && us < 0.995 * best_t) {   // a clear gain over the common count
+                        best_t = us;
+                        best.bc[c] = bs[k];
+                    }
+                    if (s == ADMM_E_DEVICE || s == ADMM_E_NOMEM) st = s;
+                }
+            }
+        }
         double best_c = 0.0, best_r = 0.0;   // per-pass figures of the choice, for the record
         if (st == ADMM_OK && best.tc >= 1 && best.b >= 1) {
             admm_plan* P = new admm_plan();
@@ -1348,6 +1383,7 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
         if (best.tc < 1 || best.b < 1) return fail(ADMM_E_UNSUPPORTED, "autotuner: no tile shape could be planned");
         rec.tc = best.tc;
         rec.rows = best.b;
+        for (int c = 0; c < 3; ++c) rec.rows_c[c] = best.bc[c];
         rec.col_us = best_c;
         rec.row_us = best_r;
         if (cache_path) {
