@@ -120,6 +120,11 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
     // each use waits only for the loads issued before it. A check iteration also
     // fetches u2 of the previous iteration for the dual residual.
     float zr[NZ], dcv[NC], dlv[J][3][NC], ucv[NC], ulv[J][3][NC];
+    // plane offsets of the coefficients this thread loads, kept for their stores
+    // in plain iterations (the check instantiation recomputes them: it holds
+    // the previous u2 as well, and the offsets would cost it occupancy)
+    constexpr bool KEEP = MODE == FR_PLAIN;
+    unsigned gcs[NC], gls[J][NC];
     if (!IMPORT) {
 #pragma unroll
         for (int u = 0; u < NZ; ++u) {
@@ -132,6 +137,7 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
             const int idx = min(tid + u * NTF, LE * LE - 1);
             const int ie = idx / LE;
             const unsigned g = cidx(3 * J, ie - h, idx - ie * LE - h);
+            if (KEEP) gcs[u] = g;
             dcv[u] = gld(din, g);
             if (chk) ucv[u] = gld(UREGP, g);
         }
@@ -144,6 +150,7 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
                     const int idx = min(tid + u * NTF, Lb * Lb - 1);
                     const int ii = idx / Lb;
                     const unsigned g = cidx(3 * jj, ii - e, idx - ii * Lb - e);
+                    if (KEEP) gls[jj][u] = g;
 #pragma unroll
                     for (int b = 0; b < 3; ++b) {
                         dlv[jj][b][u] = gld(din, g + (unsigned)b * n);
@@ -215,7 +222,7 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
         if (idx < LE * LE) {
             const int ie = idx / LE;
             const int i = ie - h, k = idx - ie * LE - h;
-            const unsigned g = cidx(3 * J, i, k);
+            const unsigned g = KEEP ? gcs[u] : cidx(3 * J, i, k);   // the loaded offset (same element)
             ap[0][idx] = IMPORT ? coef_import(g, owns(i, k)) : coef(smem[fr_aoff(J, J) + idx], dcv[u], chk ? ucv[u] : 0.0f, g, owns(i, k));
         }
     }
@@ -233,7 +240,7 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
             if (idx < Lb * Lb) {
                 const int ii = idx / Lb;
                 const int i = ii - e, k = idx - ii * Lb - e;
-                const unsigned g0 = cidx(3 * jj, i, k), g1 = g0 + n, g2 = g1 + n;
+                const unsigned g0 = KEEP ? gls[jj][u] : cidx(3 * jj, i, k), g1 = g0 + n, g2 = g1 + n;
                 const bool own = owns(i, k);
                 if (IMPORT) {
                     wb0[idx] = coef_import(g0, own);
