@@ -174,8 +174,8 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
                     const int i = idx / Lc, k = idx - i * Lc;
                     const float x00 = A[i * Lp + k], x10 = A[(i + s) * Lp + k];
                     const float x01 = A[i * Lp + k + s], x11 = A[(i + s) * Lp + k + s];
-                    const float lv0 = 0.5f * (x00 + x10), lv1 = 0.5f * (x01 + x11);
-                    An[idx] = 0.5f * (lv0 + lv1);
+                    // the two filter halvings as one quarter (exact: powers of two)
+                    An[idx] = 0.25f * ((x00 + x10) + (x01 + x11));
                 }
             }
             __syncthreads();
@@ -250,11 +250,11 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
                     const int pi = i + h, pk = k + h;     // position in the a_{j-1} window
                     const float x00 = A[pi * Lp + pk], x10 = A[(pi + s) * Lp + pk];
                     const float x01 = A[pi * Lp + pk + s], x11 = A[(pi + s) * Lp + pk + s];
-                    const float lv0 = 0.5f * (x00 + x10), lv1 = 0.5f * (x01 + x11);
-                    const float hv0 = 0.5f * (x00 - x10), hv1 = 0.5f * (x01 - x11);
-                    wb0[idx] = coef(0.5f * (lv0 - lv1), dlv[jj][0][u], chk ? ulv[jj][0][u] : 0.0f, g0, own);
-                    wb1[idx] = coef(0.5f * (hv0 + hv1), dlv[jj][1][u], chk ? ulv[jj][1][u] : 0.0f, g1, own);
-                    wb2[idx] = coef(0.5f * (hv0 - hv1), dlv[jj][2][u], chk ? ulv[jj][2][u] : 0.0f, g2, own);
+                    const float lv0 = x00 + x10, lv1 = x01 + x11;   // vertical filters, halvings deferred
+                    const float hv0 = x00 - x10, hv1 = x01 - x11;
+                    wb0[idx] = coef(0.25f * (lv0 - lv1), dlv[jj][0][u], chk ? ulv[jj][0][u] : 0.0f, g0, own);
+                    wb1[idx] = coef(0.25f * (hv0 + hv1), dlv[jj][1][u], chk ? ulv[jj][1][u] : 0.0f, g1, own);
+                    wb2[idx] = coef(0.25f * (hv0 - hv1), dlv[jj][2][u], chk ? ulv[jj][2][u] : 0.0f, g2, own);
                 }
             }
         }
@@ -269,11 +269,11 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
                 const int ii = ci - (s - 1) + e, kk = ck - (s - 1) + e;     // >= s by construction
                 const int q0 = ii * Lb + kk, q1 = ii * Lb + kk - s, q2 = (ii - s) * Lb + kk, q3 = (ii - s) * Lb + kk - s;
                 // horizontal adjoints of the rows ii and ii - s
-                const float lvA = 0.5f * ((Ap[q0] + Ap[q1]) + (wb0[q0] - wb0[q1]));
-                const float hvA = 0.5f * ((wb1[q0] + wb1[q1]) + (wb2[q0] - wb2[q1]));
-                const float lvB = 0.5f * ((Ap[q2] + Ap[q3]) + (wb0[q2] - wb0[q3]));
-                const float hvB = 0.5f * ((wb1[q2] + wb1[q3]) + (wb2[q2] - wb2[q3]));
-                An[idx] = 0.5f * ((lvA + lvB) + (hvA - hvB));
+                const float lvA = (Ap[q0] + Ap[q1]) + (wb0[q0] - wb0[q1]);   // halvings deferred
+                const float hvA = (wb1[q0] + wb1[q1]) + (wb2[q0] - wb2[q1]);
+                const float lvB = (Ap[q2] + Ap[q3]) + (wb0[q2] - wb0[q3]);
+                const float hvB = (wb1[q2] + wb1[q3]) + (wb2[q2] - wb2[q3]);
+                An[idx] = 0.25f * ((lvA + lvB) + (hvA - hvB));
             }
         }
         __syncthreads();
