@@ -76,3 +76,18 @@ def test_malformed_cache_is_an_error(tmp_path, text):
 def test_store_rejects_bad_entries(tmp_path, key, tc, rows):
     with pytest.raises(A.AdmmError):
         A.admm_tune_cache_store(str(tmp_path / "t.json"), key, tc, rows)
+
+
+def test_per_class_row_counts_survive_other_writes(tmp_path):
+    # the autotuner may record row counts per size class of the row length
+    # ("rows_512", "rows_1024", "rows_2048"); lookup reports the common
+    # (tc, rows), and rewriting the file for another key keeps those fields
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"gfx950|h0123456789abcdef*256": {"tc": 4, "rows": 5, "rows_512": 8,
+                                                                 "col_us": 896.0, "row_us": 1597.0}}))
+    assert A.admm_tune_cache_lookup(str(path), "gfx950|h0123456789abcdef*256") == (4, 5)
+    A.admm_tune_cache_store(str(path), "gfx950|tv64x64*1", 1, 2)
+    data = json.load(open(path))
+    assert data["gfx950|h0123456789abcdef*256"]["rows_512"] == 8
+    assert "rows_1024" not in data["gfx950|h0123456789abcdef*256"]
+    assert data["gfx950|tv64x64*1"] == {"tc": 1, "rows": 2, "col_us": 0.0, "row_us": 0.0}
