@@ -36,7 +36,11 @@ u^(1) = A x0, d^(1) = M^T (y - M A x0) / mu1, u_TV = D x0, d_TV = -(lambda/mu2) 
 Parity pins: tests/test_oracle_admm.py (closed-form first two iterations, the
 dense 8x8 z-solve, brute-force minimisers of the smoothed objective on 8x8
 problems, lambda-large closed forms, mu- and initialisation-independence of
-the limit, the M = I special case, the d^(1) = 0 off-mask invariant).
+the limit, the M = I special case, the d^(1) = 0 off-mask invariant) and
+tests/test_oracle_golden.py (iterates, objectives and both residuals of tiny
+TV-MD and FA-MD problems against dense exact / 60-digit computations, with
+planted mistakes in the residuals: a dropped block, mu in place of mu^2,
+d_{k-1} in place of d_k, a band left out).
 """
 
 from dataclasses import dataclass, field

@@ -31,6 +31,10 @@ Conventions (the same readings the oracle states):
 
 Inputs are dyadic rationals, so that the FP64 oracle receives them exactly.
 
+At every recorded iteration k >= 2 the files also hold the primal and dual
+residuals of the stopping rule (definitions in ``residuals``), from the same
+exact state: u_k, u_{k-1}, d_k and G z_k.
+
 Run ``python tests/golden/make_golden.py`` to rewrite the ``.txt`` files.
 """
 
@@ -267,6 +271,46 @@ def haar_bands(H, W, J, one):
 
 # ----------------------------------------------------------------- the iterations
 
+def _sq(vs):
+    return sum((v * v for v in vs), vs[0] * 0)
+
+
+def _sqrt(v):
+    """Square root in 60-digit decimal arithmetic (exact inputs are converted first)."""
+    if isinstance(v, Q):
+        v = Decimal(v.numerator) / Decimal(v.denominator)
+    return v.sqrt() if v > 0 else Decimal(0)
+
+
+def residuals(Az, Rz, u1, ur, d1, dr, u1_prev, ur_prev, mu1, mu2):
+    """Primal and dual residuals of a check iteration, from their definitions.
+
+    With G the stacked operator (A over the regulariser's blocks) and
+    Upsilon = diag(mu1 on the data block, mu2 on every regulariser block):
+        r_pri  = ||G z - u|| / max(||G z||, ||u||)
+        r_dual = ||Upsilon (u_k - u_{k-1})|| / ||Upsilon d_k||
+    (the stopping rule is not the paper's, which stops on the relative change
+    of the objective in Sec. V; these are the readings the oracle takes).
+    """
+    pri2 = _sq([a - u for a, u in zip(Az, u1)])
+    gz2 = _sq(Az)
+    un2 = _sq(u1)
+    du2 = _sq([a - b for a, b in zip(u1, u1_prev)])
+    dn2 = _sq(d1)
+    reg = {"pri": pri2 * 0, "gz": pri2 * 0, "un": pri2 * 0, "du": pri2 * 0, "dn": pri2 * 0}
+    for Rb, ub, db, pb_ in zip(Rz, ur, dr, ur_prev):
+        reg["pri"] += _sq([a - u for a, u in zip(Rb, ub)])
+        reg["gz"] += _sq(Rb)
+        reg["un"] += _sq(ub)
+        reg["du"] += _sq([a - b for a, b in zip(ub, pb_)])
+        reg["dn"] += _sq(db)
+    pri = _sqrt(pri2 + reg["pri"])
+    den = max(_sqrt(gz2 + reg["gz"]), _sqrt(un2 + reg["un"]))
+    dual = _sqrt(mu1 * mu1 * du2 + mu2 * mu2 * reg["du"])
+    dden = _sqrt(mu1 * mu1 * dn2 + mu2 * mu2 * reg["dn"])
+    return pri / den, dual / dden
+
+
 def run(pb):
     reg = pb["reg"]
     one = Q(1) if reg == "fa" else Decimal(1)
@@ -298,8 +342,10 @@ def run(pb):
     ur = [[zero] * n for _ in R]
     dr = [[zero] * n for _ in R]
     out = {}
+    res = {}
     z = None
     for k in range(1, pb["iters"] + 1):
+        u1_prev, ur_prev = u1, ur
         rhs = scale(mu1, matvec(At, add(u1, d1)))
         for Bt, ub, db in zip(Rt, ur, dr):
             rhs = add(rhs, scale(mu2, matvec(Bt, add(ub, db))))
@@ -329,6 +375,8 @@ def run(pb):
         dr = [[d - (a - u) for d, a, u in zip(db, Rb, ub)] for db, Rb, ub in zip(dr, Rz, ur)]
         if k in pb["record"]:
             out[k] = list(z)
+            if k >= 2:
+                res[k] = residuals(Az, Rz, u1, ur, d1, dr, u1_prev, ur_prev, mu1, mu2)
     # objective at the last z: 1/2 ||M (y - A z)||^2 + lambda * regulariser
     Az = matvec(A, z)
     fit = sum(((mi * (yi - a)) ** 2 for mi, yi, a in zip(m, y, Az)), zero) / 2
@@ -340,7 +388,7 @@ def run(pb):
             pen += s2.sqrt() if s2 > 0 else zero
     else:
         pen = sum((abs(a) for Rb in Rz for a in Rb), zero)
-    return out, fit + lam * pen
+    return out, fit + lam * pen, res
 
 
 def _dec(v):
@@ -351,7 +399,7 @@ def _dec(v):
     return format(v, ".25e")
 
 
-def write(pb, zs, obj):
+def write(pb, zs, obj, res):
     path = os.path.join(HERE, pb["name"] + ".txt")
     cite = ("TV-MD: Alg. 3 with the z-step of eq. (33) and the data step of eq. (49), Sec. IV-D"
             if pb["reg"] == "tv" else
@@ -374,6 +422,8 @@ def write(pb, zs, obj):
     ]
     for k in sorted(zs):
         lines.append(f"z {k} " + " ".join(_dec(v) for v in zs[k]))
+    for k in sorted(res):
+        lines.append(f"residual {k} {_dec(res[k][0])} {_dec(res[k][1])}")
     lines.append(f"objective {pb['iters']} {_dec(obj)}")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -383,8 +433,8 @@ def write(pb, zs, obj):
 def main():
     for make in PROBLEMS:
         pb = make()
-        zs, obj = run(pb)
-        print(write(pb, zs, obj))
+        zs, obj, res = run(pb)
+        print(write(pb, zs, obj, res))
 
 
 if __name__ == "__main__":

@@ -11,8 +11,9 @@ NAMES = ("tv_md_5x6", "fa_md_4x6_J2", "tv_md_8x10", "fa_md_8x8_J3")
 
 def load(name):
     """Parse ``tests/golden/<name>.txt``: inputs as float64 arrays (exact: dyadic
-    fractions), the stored iterates z_k and the objective at the last iterate."""
-    out = {"zs": {}}
+    fractions), the stored iterates z_k, the (r_pri, r_dual) residuals of the
+    recorded iterations k >= 2 and the objective at the last iterate."""
+    out = {"zs": {}, "residuals": {}}
     with open(os.path.join(GOLDEN, name + ".txt")) as f:
         for line in f:
             if line.startswith("#") or not line.strip():
@@ -20,6 +21,8 @@ def load(name):
             key, *vals = line.split()
             if key == "z":
                 out["zs"][int(vals[0])] = np.array([float(v) for v in vals[1:]])
+            elif key == "residual":
+                out["residuals"][int(vals[0])] = (float(vals[1]), float(vals[2]))
             elif key == "objective":
                 out["objective"] = (int(vals[0]), float(vals[1]))
             elif key in ("reg",):

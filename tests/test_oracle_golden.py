@@ -85,13 +85,105 @@ def test_small_fixtures_regenerate_identically():
     spec.loader.exec_module(G)
     for make in (G._tv_problem, G._fa_problem):
         pb = make()
-        zs, obj = G.run(pb)
+        zs, obj, res = G.run(pb)
         g = load(pb["name"])
         assert sorted(zs) == sorted(g["zs"])
         for k in zs:
             fresh = np.array([float(G._dec(v)) for v in zs[k]]).reshape(g["shape"])
             assert np.array_equal(fresh, g["zs"][k])
         assert float(G._dec(obj)) == g["objective"][1]
+        assert sorted(res) == sorted(g["residuals"])
+        for k, (rp, rd) in res.items():
+            assert (float(G._dec(rp)), float(G._dec(rd))) == g["residuals"][k]
+
+
+# ------------------------------------------- the residuals of the stopping rule
+
+def _oracle_history(g):
+    """(r_pri, r_dual) of every iteration (a negative tolerance never stops the run)."""
+    if g["reg"] == "tv":
+        out = O.tv_md_run(g["y"], g["mask"], g["kernel"], g["lambda"], g["mu1"], g["mu2"],
+                          iters=g["iters"], tol=-1.0, check_every=1)
+    else:
+        out = O.fa_md_run(g["y"], g["mask"], g["kernel"], g["lambda"], g["mu1"], g["mu2"], g["levels"],
+                          iters=g["iters"], tol=-1.0, check_every=1)
+    return {k: (rp, rd) for k, rp, rd in out["history"]}
+
+
+def _residual_err(g):
+    hist = _oracle_history(g)
+    return max(max(abs(hist[k][0] - rp) / rp, abs(hist[k][1] - rd) / rd)
+               for k, (rp, rd) in g["residuals"].items())
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_oracle_residuals_match_exact_values(name):
+    # tv_residuals / fa_residuals against r_pri and r_dual computed from their
+    # definitions on the exact state (u_k, u_{k-1}, d_k, G z_k) at k = 2, 3, 5, 8
+    g = load(name)
+    assert sorted(g["residuals"]) == [2, 3, 5, 8]
+    assert _residual_err(g) <= TOL
+
+
+_tv_res = oadmm.tv_residuals
+_fa_res = oadmm.fa_residuals
+
+
+def _tv_res_dropped_block(aux, st, sp, mu1, mu2):
+    # primal residual without the TV block
+    Az, zh, zv = aux
+    rp, rd = _tv_res(aux, st, sp, mu1, mu2)
+    pri = np.sqrt(np.sum((Az - st.u1) ** 2))
+    den = max(np.sqrt(np.sum(Az ** 2) + np.sum(zh ** 2) + np.sum(zv ** 2)),
+              np.sqrt(np.sum(st.u1 ** 2) + np.sum(st.uh ** 2) + np.sum(st.uv ** 2)))
+    return pri / den, rd
+
+
+def _mu_not_squared(res):
+    # Upsilon applied as sqrt(Upsilon): the dual residual weighs the blocks by mu, not mu^2
+    return lambda aux, st, sp, mu1, mu2: (res(aux, st, sp, mu1, mu2)[0],
+                                          res(aux, st, sp, np.sqrt(mu1), np.sqrt(mu2))[1])
+
+
+def _tv_res_previous_dual(aux, st, sp, mu1, mu2):
+    # the dual residual normalised by d_{k-1} instead of d_k
+    rp, rd = _tv_res(aux, st, sp, mu1, mu2)
+    dn_k = np.sqrt(mu1 ** 2 * np.sum(st.d1 ** 2) + mu2 ** 2 * (np.sum(st.dh ** 2) + np.sum(st.dv ** 2)))
+    dn_p = np.sqrt(mu1 ** 2 * np.sum(sp.d1 ** 2) + mu2 ** 2 * (np.sum(sp.dh ** 2) + np.sum(sp.dv ** 2)))
+    return rp, rd * dn_k / max(dn_p, 1e-30)
+
+
+def _fa_res_dropped_frame(aux, st, sp, mu1, mu2):
+    Az, Pz = aux
+    rp, rd = _fa_res(aux, st, sp, mu1, mu2)
+    pri = np.sqrt(np.sum((Az - st.u1) ** 2))
+    den = max(np.sqrt(np.sum(Az ** 2) + np.sum(Pz ** 2)), np.sqrt(np.sum(st.u1 ** 2) + np.sum(st.u2 ** 2)))
+    return pri / den, rd
+
+
+def _fa_res_no_coarse_band(aux, st, sp, mu1, mu2):
+    # the coarsest band left out of the dual residual
+    Az, Pz = aux
+    rp, _ = _fa_res(aux, st, sp, mu1, mu2)
+    dual = np.sqrt(mu1 ** 2 * np.sum((st.u1 - sp.u1) ** 2) + mu2 ** 2 * np.sum((st.u2[:-1] - sp.u2[:-1]) ** 2))
+    dn = np.sqrt(mu1 ** 2 * np.sum(st.d1 ** 2) + mu2 ** 2 * np.sum(st.d2 ** 2))
+    return rp, dual / dn
+
+
+@pytest.mark.parametrize("mutation", ["tv_dropped_block", "tv_mu_not_squared", "tv_previous_dual",
+                                      "fa_dropped_frame", "fa_mu_not_squared", "fa_no_coarse_band"])
+def test_planted_residual_mistake_is_caught(mutation, monkeypatch):
+    if mutation.startswith("tv"):
+        fn = {"tv_dropped_block": _tv_res_dropped_block, "tv_mu_not_squared": _mu_not_squared(_tv_res),
+              "tv_previous_dual": _tv_res_previous_dual}[mutation]
+        monkeypatch.setattr(oadmm, "tv_residuals", fn)
+        names = ("tv_md_5x6", "tv_md_8x10")
+    else:
+        fn = {"fa_dropped_frame": _fa_res_dropped_frame, "fa_mu_not_squared": _mu_not_squared(_fa_res),
+              "fa_no_coarse_band": _fa_res_no_coarse_band}[mutation]
+        monkeypatch.setattr(oadmm, "fa_residuals", fn)
+        names = ("fa_md_4x6_J2", "fa_md_8x8_J3")
+    assert all(_residual_err(load(n)) > 1e-4 for n in names)
 
 
 # ------------------------------------------- the pins catch planted mistakes
