@@ -1,0 +1,105 @@
+"""GPU parity on every shipped size class, with full-spectrum (non-tiled) data.
+
+Tiled problems have spectra on a coarse lattice only, so they leave most
+twiddles multiplying zeros. Here every image is a non-periodic synthetic one
+(shapes, a smooth random field, noise, i.i.d. missing pixels), and each test
+names the kernel instantiations it runs:
+
+* column pass: one instantiation per size class of the column length
+  (<= 512, <= 1024, <= 2048) and schedule (first and last stage radix 8:
+  fixed; otherwise general);
+* TV row pass: one per size class of the row length (rows per block 8, 6, 2);
+* FA row passes and frame step: per size class of the row length and J.
+
+Bar (TV-MD Alg. 3 with the data step of eq. (49); FA-MD Sec. IV-C): relative
+L2 error of z_k <= 1e-4 and every element within 1e-4 of max |z_k|.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1210_2687_amd import admm as A
+from paper_1210_2687_amd import workloads as WL
+from gpu_util import dev, host, announce, check_iterate, full_problem, gpu_solve
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(p, ks):
+    ks = sorted(ks)
+    if p.reg == "frame":
+        return O.fa_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, p.levels, iters=ks[-1], record=ks)
+    return O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=ks[-1], record=ks)
+
+
+def _single(p, ks, graph=True):
+    ref = _oracle(p, ks)
+    with A.Plan([p]) as plan:
+        for k in ks:
+            z, info = gpu_solve(plan, p, k, graph=graph)
+            assert info["iters"] == k
+            check_iterate(z, ref["zs"][k], what=f"{p.shape} k={k}")
+
+
+def _batch(probs, ks):
+    import torch
+    refs = [_oracle(p, ks) for p in probs]
+    with A.Plan(probs) as plan:
+        ys = [dev(p.y) for p in probs]
+        for k in ks:
+            xs = [torch.zeros_like(y) for y in ys]
+            infos = plan.batch(ys, xs, max_iters=k, graph=True)
+            for p, x, info, ref in zip(probs, xs, infos, refs):
+                assert info["iters"] == k
+                check_iterate(host(x), ref["zs"][k], what=f"{p.shape} k={k}")
+
+
+def test_tv_general_schedules_of_the_middle_class():
+    # 600 x 1000: columns of length 600 (general schedule, 513..1024), rows of
+    # length 1000 (general schedule, TV row class 513..1024)
+    announce("TV 600 x 1000, 13 x 13 Gaussian, k = 2, 10, 30")
+    _single(full_problem(201, 600, 1000, 13), [2, 10, 30])
+
+
+def test_tv_general_schedules_of_the_largest_class():
+    # one batch: 720 x 1960 (columns 720: general, middle class; rows 1960:
+    # general, largest TV row class) and 1960 x 720 (columns 1960: general,
+    # largest class; rows 720: middle class)
+    announce("TV batch 720 x 1960 + 1960 x 720, k = 2, 4")
+    _batch([full_problem(202, 720, 1960, 9, "motion"), full_problem(203, 1960, 720, 7, "uniform")], [2, 4])
+
+
+def test_tv_2048_square():
+    # 2048^2: fixed-length schedules of the largest class in both passes
+    announce("TV 2048 x 2048, 9 x 9 Gaussian, k = 2, 3")
+    _single(full_problem(204, 2048, 2048, 9), [2, 3])
+
+
+def test_tv_fixed_lengths_of_the_middle_class():
+    # 1024 x 768, middle class: columns of length 1024 (compile-time schedule,
+    # first and last stage radix 8, kept in registers around the solve), rows
+    # of length 768 (run-time schedule in the middle class's instantiation)
+    announce("TV 1024 x 768, 15 x 15 motion, k = 2, 6")
+    _single(full_problem(205, 1024, 768, 15, "motion"), [2, 6])
+
+
+def test_fa_config3_full_size():
+    # the frame workload itself: FA-MD 1024^2, J = 3, 13 x 13 disk, 20% missing 8 x 8 blocks
+    announce("FA 1024 x 1024 J = 3 (the frame workload), k = 2, 5")
+    _single(WL.config3(size=1024, levels=3), [2, 5], graph=False)
+
+
+def test_fa_general_lengths_of_the_largest_row_class():
+    # 600 x 1250, J = 2: columns 600 (general, middle class); rows 1250
+    # (general, largest class of the plain row passes)
+    announce("FA 600 x 1250 J = 2, k = 2, 4")
+    _single(full_problem(206, 600, 1250, 7, reg="frame", levels=2), [2, 4], graph=False)
+
+
+def test_tv_config2_member_at_its_iteration_count():
+    # one member of the 8 x 512^2 batch (15-px motion blur, 40% missing) after
+    # the workload's 500 iterations: FP32 drift over a full solve
+    announce("TV config-2 member 4 (512^2 motion), k = 100, 500")
+    p = WL.config2(4)
+    _single(p, [100, 500])
