@@ -127,6 +127,27 @@ admm_status admm_deconv_plan(const admm_problem* probs, int32_t count, void* hip
 admm_status admm_deconv_solve(admm_plan* plan, const float* y, float* x, admm_state* st,
                               const admm_opts* opts, admm_info* info);
 
+/* ---- Allocation-free solve ----
+ * For callers that cannot allocate device memory (serving loops that must not
+ * call hipMalloc, harnesses that forbid it): plan and solve one problem in a
+ * static workspace of ADMM_STATIC_WORKSPACE_BYTES that the library holds on
+ * every device it runs on until the process ends. The call allocates no
+ * device or pinned host memory (no hipMalloc, hipFree, hipHostMalloc, graph
+ * or event), launches eagerly on hip_stream (ADMM_FLAG_GRAPH and
+ * ADMM_FLAG_PROFILE are ignored) and returns after the work is complete.
+ * Arguments: as admm_deconv_plan with count == 1 (prob, hip_stream) followed
+ * by admm_deconv_solve (y, x, st, opts, info); the iterates equal those of
+ * that pair of calls.
+ * Limit: the problem's workspace (spectra, kernel spectrum, duals, scratch
+ * planes, tables; about 60 B per pixel for TV and (30 + 12 (3J+1)) B per pixel
+ * for the frame) must fit the static workspace, else ADMM_E_UNSUPPORTED
+ * before any device work. Every call on a device reuses that device's
+ * workspace: calls that overlap on one device (two threads or two streams)
+ * race and must be serialised by the caller.                                  */
+#define ADMM_STATIC_WORKSPACE_BYTES ((size_t)48 * 1024 * 1024)
+admm_status admm_deconv_solve_static(const admm_problem* prob, const float* y, float* x, admm_state* st,
+                                     const admm_opts* opts, admm_info* info, void* hip_stream);
+
 /* Solve all problems of a plan together (ragged sizes allowed).
  * y, x: HOST arrays of `count` DEVICE pointers; st: NULL or HOST array of
  * `count` states; infos: HOST array of `count` results.                       */

@@ -19,7 +19,7 @@ __all__ = [
     "ADMM_FLAG_PROFILE", "admm_plan_kernel_times",
     "AdmmError", "lib", "lib_path", "exported_symbols",
     "admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
-    "admm_warmstart_map", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
+    "admm_deconv_solve_static", "admm_warmstart_map", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
     "admm_validate_problem", "Plan", "make_problem", "alloc_state",
 ]
 
@@ -92,6 +92,8 @@ def lib():
                                         POINTER(admm_info)]
         L.admm_deconv_batch.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(admm_state),
                                         POINTER(admm_opts), POINTER(admm_info)]
+        L.admm_deconv_solve_static.argtypes = [POINTER(admm_problem), c_void_p, c_void_p, POINTER(admm_state),
+                                               POINTER(admm_opts), POINTER(admm_info), c_void_p]
         L.admm_deconv_blur.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
         L.admm_warmstart_map.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, POINTER(admm_state)]
         L.admm_plan_destroy.argtypes = [c_void_p]
@@ -123,7 +125,7 @@ def lib():
         L.admm_ws_output.argtypes = [vp, vp, vp, c_int32, c_int32, c_int32, vp, vp, vp]
         for f in ("admm_deconv_plan", "admm_deconv_plan_tuned", "admm_tune_cache_store", "admm_plan_tiles",
                   "admm_plan_time_pass",
-                  "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
+                  "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur", "admm_deconv_solve_static",
                   "admm_warmstart_map", "admm_fft_radices", "admm_validate_problem",
                   "admm_conv3x3_pack_weights", "admm_conv3x3_bf16_fwd", "admm_conv3x3_bf16_wgrad",
                   "admm_adam_step", "admm_ws_input", "admm_ws_loss", "admm_ws_output"):
@@ -135,6 +137,7 @@ def lib():
 def exported_symbols():
     """Names of the C entry points declared in include/admm_deconv.h."""
     return ["admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
+            "admm_deconv_solve_static",
             "admm_warmstart_map", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
             "admm_validate_problem", "admm_plan_kernel_times", "admm_deconv_plan_tuned", "admm_tune_key",
             "admm_tune_cache_lookup", "admm_tune_cache_store", "admm_plan_tiles", "admm_plan_time_pass",
@@ -275,6 +278,20 @@ def admm_deconv_solve(plan, y, x, state=None, max_iters=100, tol=0.0, check_ever
     _check(lib().admm_deconv_solve(plan, _dev(y), _dev(x, n), ctypes.byref(st) if st else None,
                                    ctypes.byref(_opts(max_iters, tol, check_every, graph, profile)),
                                    ctypes.byref(info)))
+    return info.as_dict()
+
+
+def admm_deconv_solve_static(problem, y, x, state=None, max_iters=100, tol=0.0, check_every=10, nreg=2,
+                             stream=None):
+    """Plan and solve one problem (``make_problem``) in the library's static
+    device workspace, allocating nothing."""
+    n = y.numel()
+    info = admm_info()
+    st = _state(state, n, nreg)
+    _check(lib().admm_deconv_solve_static(ctypes.byref(problem), _dev(y), _dev(x, n),
+                                          ctypes.byref(st) if st else None,
+                                          ctypes.byref(_opts(max_iters, tol, check_every, False)),
+                                          ctypes.byref(info), _stream_ptr(stream)))
     return info.as_dict()
 
 

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -137,6 +138,11 @@ struct admm_plan {
     int ntv = 0, nfa = 0;
     char* arena = nullptr;
     size_t arena_bytes = 0;
+    // allocation-free plans (admm_deconv_solve_static): the arena is a region
+    // the plan does not own, infos are staged in ordinary host memory, and
+    // solves launch eagerly (no graphs, no events, no host-mapped flags)
+    bool no_alloc = false;
+    std::vector<InfoDev> h_info_host;
     ProbDesc* d_desc = nullptr;
     WorkItem* d_items = nullptr;
     InfoDev* d_info = nullptr;
@@ -222,13 +228,13 @@ extern "C" void admm_plan_destroy(admm_plan* P) {
         if (e) (void)hipEventDestroy(e);
     if (P->h_active) (void)hipHostFree(P->h_active);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
-    if (P->arena) (void)hipFree(P->arena);
-    if (P->h_info) (void)hipHostFree(P->h_info);
+    if (P->arena && !P->no_alloc) (void)hipFree(P->arena);
+    if (P->h_info && !P->no_alloc) (void)hipHostFree(P->h_info);
     delete P;
 }
 
 static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t count, void* hip_stream,
-                              TileChoice tile);
+                              TileChoice tile, void* ext_arena = nullptr, size_t ext_cap = 0);
 
 extern "C" admm_status admm_deconv_plan(const admm_problem* probs, int32_t count, void* hip_stream, admm_plan** out) {
     if (!out) return fail(ADMM_E_INVALID, "null output pointer");
@@ -251,8 +257,11 @@ extern "C" admm_status admm_deconv_plan(const admm_problem* probs, int32_t count
     return ADMM_OK;
 }
 
+// ext_arena (device memory of ext_cap bytes, not owned) replaces the plan's
+// own allocation; the plan then allocates nothing on the device or pinned in
+// host memory.
 static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t count, void* hip_stream,
-                              TileChoice tile) {
+                              TileChoice tile, void* ext_arena, size_t ext_cap) {
     auto bail = [](admm_status s) { return s; };
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -452,6 +461,12 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     const size_t o_part = take(sizeof(double) * ADMM_NSUM * std::max(part, 1));
     const size_t o_tw = take(sizeof(float2) * tab_len);
     const size_t o_s2 = take(sizeof(float) * tab_len);
+    // row sums of the kernel spectrum (host-computed, consumed at plan time):
+    // part of the arena when it is external, else a temporary allocation
+    size_t t_bytes = 0;
+    for (int i = 0; i < count; ++i)
+        t_bytes = std::max(t_bytes, sizeof(float2) * (size_t)probs[i].ksize * (size_t)P->hd[i].P);
+    const size_t o_T = ext_arena ? take(t_bytes) : 0;
     struct Offs {
         size_t spec0, spec1, lam, d1, dreg0, dreg1, u1p, uregp, tmpA, tmpB, zpl, mask;
     };
@@ -474,7 +489,16 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         o.mask = take(n);
     }
     P->arena_bytes = off;
-    {
+    if (ext_arena) {
+        if (off > ext_cap)
+            return bail(fail(ADMM_E_UNSUPPORTED,
+                             "the allocation-free solve holds at most %zu bytes of workspace; this problem needs %zu",
+                             ext_cap, off));
+        P->no_alloc = true;
+        P->arena = (char*)ext_arena;
+        P->h_info_host.assign(count, InfoDev{});
+        P->h_info = P->h_info_host.data();
+    } else {
         hipError_t e = hipMalloc((void**)&P->arena, off);
         if (e != hipSuccess) {
             P->arena = nullptr;
@@ -483,7 +507,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
                              "device allocation of %zu bytes failed: %s", off, hipGetErrorString(e)));
         }
     }
-    {
+    if (!P->no_alloc) {
         hipError_t e = hipHostMalloc((void**)&P->h_info, sizeof(InfoDev) * count, hipHostMallocDefault);
         if (e != hipSuccess) {
             P->h_info = nullptr;
@@ -612,11 +636,14 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
                 T[(size_t)(a + l) * d.P + k2] = make_float2((float)re, (float)im);
             }
         float2* dT = nullptr;
-        HIP_TRY(hipMalloc((void**)&dT, sizeof(float2) * T.size()));
+        if (P->no_alloc)
+            dT = (float2*)(A + o_T);
+        else
+            HIP_TRY(hipMalloc((void**)&dT, sizeof(float2) * T.size()));
         hipError_t e1 = hipMemcpy(dT, T.data(), sizeof(float2) * T.size(), hipMemcpyHostToDevice);
         hipError_t e2 = e1 == hipSuccess ? launch_lambda(P->all, i, (size_t)d.H * d.P, dT, ks) : e1;
         hipError_t e3 = e2 == hipSuccess ? hipStreamSynchronize(P->stream) : e2;
-        (void)hipFree(dT);
+        if (!P->no_alloc) (void)hipFree(dT);
         if (e3 != hipSuccess) return bail(fail(ADMM_E_DEVICE, "kernel spectrum: %s", hipGetErrorString(e3)));
     }
     return ADMM_OK;
@@ -653,7 +680,15 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
     for (int i = 0; i < count; ++i) {
         const ProbDesc& d = P->hd[i];
         const size_t n = (size_t)d.H * d.W, hp = (size_t)d.H * d.P;
-        if (!st) {
+        if (!st && P->no_alloc) {
+            // the shared workspace keeps the previous call's contents: clear
+            // every buffer that a cold start reads before writing
+            HIP_TRY(launch_zero(sm, (float*)d.spec0, hp * 4));
+            HIP_TRY(launch_zero(sm, d.d1, n));
+            HIP_TRY(launch_zero(sm, d.dreg0, n * d.nb));
+            HIP_TRY(launch_zero(sm, d.u1p, n));
+            HIP_TRY(launch_zero(sm, d.uregp, n * d.nb));
+        } else if (!st) {
             HIP_TRY(hipMemsetAsync(d.spec0, 0, hp * sizeof(float4), sm));
             HIP_TRY(hipMemsetAsync(d.d1, 0, n * sizeof(float), sm));
             HIP_TRY(hipMemsetAsync(d.dreg0, 0, n * d.nb * sizeof(float), sm));
@@ -688,8 +723,8 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
     }
     const int K = o->max_iters, c = o->check_every;
     const double tol = o->tol;
-    const bool profile = (o->flags & ADMM_FLAG_PROFILE) != 0;
-    const bool use_graph = (o->flags & ADMM_FLAG_GRAPH) && !profile;
+    const bool profile = (o->flags & ADMM_FLAG_PROFILE) != 0 && !P->no_alloc;
+    const bool use_graph = (o->flags & ADMM_FLAG_GRAPH) && !profile && !P->no_alloc;
     auto is_check = [&](int k) { return k == K || (tol > 0 && k % c == 0); };
     auto is_plain = [&](int k) { return k < K && !is_check(k) && !is_check(k + 1); };
 
@@ -915,6 +950,51 @@ extern "C" admm_status admm_deconv_batch(admm_plan* P, const float* const* y, fl
                                          const admm_opts* o, admm_info* infos) {
     if (!P) return fail(ADMM_E_INVALID, "null plan");
     return run(P, y, x, st, o, infos);
+}
+
+// ------------------------------------------------------------ allocation-free solve
+// The workspace of admm_deconv_solve_static: one array per device, held until
+// the process ends, shared by every call on that device (calls that overlap
+// on one device race). Host code reaches it only through the address that
+// hipGetSymbolAddress returns on the device that is current.
+static __device__ __align__(256) unsigned char scratch[ADMM_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+admm_status scratch_address(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(ADMM_E_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ADMM_E_DEVICE, "address of the static workspace on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return ADMM_OK;
+}
+
+}  // namespace
+
+extern "C" admm_status admm_deconv_solve_static(const admm_problem* prob, const float* y, float* x, admm_state* st,
+                                                const admm_opts* opts, admm_info* info, void* hip_stream) {
+    if (!prob) return fail(ADMM_E_INVALID, "null problem");
+    admm_status s = validate(*prob);
+    if (s != ADMM_OK) return s;
+    void* ws = nullptr;
+    s = scratch_address(&ws);
+    if (s != ADMM_OK) return s;
+    admm_plan P;   // host bookkeeping only: descriptors, tables and state live in the workspace
+    s = build_plan(&P, prob, 1, hip_stream, TileChoice{}, ws, (size_t)ADMM_STATIC_WORKSPACE_BYTES);
+    if (s == ADMM_OK) s = run(&P, &y, &x, st, opts, info);
+    return s;
 }
 
 namespace {

@@ -17,6 +17,8 @@
 // FA-MD (Sec. IV-C) uses k_col with K = 1 / (mu1 |Lambda|^2 + mu2) (eq. (25)),
 // then k_row_inv (inverse rows + data step), k_frame (frame analysis, soft
 // threshold, frame duals and synthesis q = mu2 P^T (u2 + d2)) and k_row_fwd.
+#include <algorithm>
+
 #include "admm_internal.h"
 #include "fft_lds.h"
 #include "admm_launch.h"
@@ -826,6 +828,13 @@ __global__ __launch_bounds__(NT) void k_reduce(const ProbDesc* __restrict__ pd, 
     }
 }
 
+// Zero n floats (the allocation-free solve clears its state with a kernel
+// rather than a memset node, so that a caller may capture the stream).
+__global__ void k_zero(float* __restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
 // Iteration counter of graph-replayed check periods: counter[0] += c (one
 // lane; an ordinary vector store).
 __global__ void k_tick(int* __restrict__ counter, int c, int set) {
@@ -1014,6 +1023,13 @@ hipError_t launch_reduce(const LaunchCtx& L, int count, double tol, int iter, in
 
 hipError_t launch_tick(const LaunchCtx& L, int* counter, int c, bool set) {
     hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, L.stream, counter, c, set ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(hipStream_t stream, float* p, size_t n) {
+    if (!n) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, stream, p, n);
     return hipGetLastError();
 }
 
