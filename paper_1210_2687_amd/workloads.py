@@ -15,9 +15,9 @@ Recipe (all draws from ``numpy.random.Generator(PCG64(seed))``):
 * image: background U[0,1]; Poisson(8 n / 128^2) shapes (cap 400), each an
   axis-aligned rectangle (sides U[0.05,0.4] min(H,W)) or a rotated ellipse
   (semi-axes U[0.03,0.25] min(H,W)), intensity U[0,1], painted in order;
-  optional Gaussian random field (white noise smoothed by a Gaussian of std
-  ``grf_scale`` px, periodic, zero mean, unit std, times 0.2) added, then
-  clipped to [0,1];
+  optional Gaussian random field (white noise smoothed by a periodic Gaussian
+  of std ``grf_scale`` px truncated at 4 std, zero mean, unit std, times 0.2)
+  added, then clipped to [0,1];
 * kernels: uniform 1/k^2; Gaussian exp(-(a^2+b^2)/(2 s^2)); linear motion (a
   centred segment of length L at angle theta, 64 samples splatted bilinearly);
   disk (pixel coverage of a radius-r disk by 16x16 supersampling); all
@@ -63,32 +63,66 @@ class Problem:
         return self.y.shape
 
 
+def _gauss_taps(sigma):
+    """Sampled Gaussian of std sigma truncated at 4 sigma, unit sum (taps -r..r)."""
+    r = int(4.0 * sigma + 0.5)
+    t = np.exp(-0.5 * (np.arange(-r, r + 1, dtype=np.float64) / sigma) ** 2)
+    return t / t.sum(), r
+
+
+def _smooth_periodic(noise, sigma):
+    """Separable periodic Gaussian smoothing (the same truncated kernel on each
+    axis, wrapped onto the grid), applied as a product of transfer functions."""
+    H, W = noise.shape
+    taps, r = _gauss_taps(sigma)
+
+    def transfer(n, half):
+        k = np.zeros(n)
+        np.add.at(k, np.arange(-r, r + 1) % n, taps)
+        return np.fft.rfft(k) if half else np.fft.fft(k)
+
+    spec = np.fft.rfft2(noise) * (transfer(H, False)[:, None] * transfer(W, True)[None, :])
+    return np.fft.irfft2(spec, s=(H, W))
+
+
 def synth_image(g, H, W, grf_scale=None):
     """Piecewise-constant rectangles/ellipses on a uniform background, optional GRF."""
     x = np.full((H, W), g.uniform())
     n = H * W
     nshape = min(400, int(g.poisson(8.0 * n / 128.0 ** 2)))
-    rr, cc = np.mgrid[0:H, 0:W]
     s = float(min(H, W))
+
+    def box(lo, hi, n):
+        # integer pixel range [i0, i1) that contains every pixel i with lo <= i <= hi
+        return max(0, int(math.floor(lo))), min(n, int(math.floor(hi)) + 1)
+
     for _ in range(nshape):
         val = g.uniform()
         if g.uniform() < 0.5:
             hh, ww = g.uniform(0.05, 0.4, size=2) * s
             r0 = g.uniform(0, H)
             c0 = g.uniform(0, W)
+            i0, i1 = box(r0, r0 + hh, H)
+            j0, j1 = box(c0, c0 + ww, W)
+            rr, cc = np.mgrid[i0:i1, j0:j1]
             sel = (rr >= r0) & (rr < r0 + hh) & (cc >= c0) & (cc < c0 + ww)
         else:
             a, b = g.uniform(0.03, 0.25, size=2) * s
             r0 = g.uniform(0, H)
             c0 = g.uniform(0, W)
             th = g.uniform(0, math.pi)
+            R = max(a, b)          # the ellipse lies inside this circle about its centre
+            i0, i1 = box(r0 - R, r0 + R, H)
+            j0, j1 = box(c0 - R, c0 + R, W)
+            rr, cc = np.mgrid[i0:i1, j0:j1]
             dr, dc = rr - r0, cc - c0
             u = dc * math.cos(th) + dr * math.sin(th)
             v = -dc * math.sin(th) + dr * math.cos(th)
             sel = (u / a) ** 2 + (v / b) ** 2 <= 1.0
-        x[sel] = val
+        if sel.size:
+            x[i0:i1, j0:j1][sel] = val
     if grf_scale:
-        f = ndimage.gaussian_filter(g.standard_normal((H, W)), grf_scale, mode="wrap")
+        f = _smooth_periodic(g.standard_normal((H, W)), grf_scale)
         f = (f - f.mean()) / max(f.std(), 1e-12)
         x = np.clip(x + 0.2 * f, 0.0, 1.0)
     return x
@@ -146,9 +180,23 @@ def valid_mask(H, W, l):
     return m
 
 
+def _blur_periodic(x, h):
+    """(h (*) x)[r, c] = sum_{a,b} h[a+l, b+l] x[(r-a) mod H, (c-b) mod W]: the
+    periodic blur of the whole image, as a product of spectra (the kernel
+    wrapped onto the grid with its centre tap at the origin)."""
+    H, W = x.shape
+    k = h.shape[0]
+    l = k // 2
+    kp = np.zeros((H, W))
+    a = (np.arange(k) - l) % H
+    b = (np.arange(k) - l) % W
+    np.add.at(kp, (a[:, None], b[None, :]), h)
+    return np.fft.irfft2(np.fft.rfft2(x) * np.fft.rfft2(kp), s=(H, W))
+
+
 def observe(g, x, h, mask, sigma):
     """y = m * (periodic blur of the full image + N(0, sigma^2)); zero off the mask."""
-    blurred = ndimage.convolve(x, h, mode="wrap")
+    blurred = _blur_periodic(x, h)
     y = blurred + sigma * g.standard_normal(x.shape)
     return np.where(mask > 0, y, 0.0)
 

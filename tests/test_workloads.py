@@ -1,6 +1,7 @@
 """Host checks of the synthetic-input module (no GPU, no solver)."""
 
 import numpy as np
+import pytest
 from scipy import ndimage
 
 from paper_1210_2687_amd import workloads as WL
@@ -31,3 +32,23 @@ def test_boundary_pair_shapes_and_valid_region():
     # blur of the true image computed without periodic extension (up to noise)
     full = ndimage.convolve(md.x_true, md.kernel, mode="constant")[12:108, 12:108]
     assert np.max(np.abs(full - y_obs)) < 6e-3
+
+
+@pytest.mark.parametrize("H,W,k", [(64, 64, 19), (33, 70, 31), (32, 32, 31), (9, 12, 9), (96, 160, 7)])
+def test_observation_blur_is_the_periodic_convolution(H, W, k):
+    # the generator's spectral blur against scipy's direct periodic convolution
+    # (the same definition as the model's A), asymmetric kernels included
+    from scipy import ndimage
+    g = np.random.default_rng(H * W + k)
+    x = g.uniform(size=(H, W))
+    h = np.abs(g.standard_normal((k, k)))
+    ref = ndimage.convolve(x, h, mode="wrap")
+    assert np.max(np.abs(WL._blur_periodic(x, h) - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("H,W,sigma", [(64, 64, 16.0), (8, 8, 32.0), (33, 70, 5.0)])
+def test_random_field_smoothing_is_the_periodic_gaussian_filter(H, W, sigma):
+    from scipy import ndimage
+    n = np.random.default_rng(int(sigma)).standard_normal((H, W))
+    ref = ndimage.gaussian_filter(n, sigma, mode="wrap")
+    assert np.max(np.abs(WL._smooth_periodic(n, sigma) - ref)) <= 1e-13 * np.max(np.abs(ref))
