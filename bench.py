@@ -1,16 +1,29 @@
 #!/usr/bin/env python3
-"""Throughput benchmark of the batched mask-decoupled ADMM (TV-MD) on one MI355X.
+"""Benchmark of the batched mask-decoupled ADMM (TV-MD, FA-MD) on one MI355X.
 
-Workload (default): 8 unknown 512x512 images (rectangles/ellipses plus a
-smooth random field), images 0-3 blurred by a 19x19 Gaussian (sigma 3), 4-7 by
-a 15-px linear motion blur, observed on the valid region minus 40% i.i.d.
-missing pixels, sigma 2e-3, lambda 2e-4, mu1 = mu2 = 1e-3. One step = one
-batched solve of 500 ADMM iterations from a cold start (plan, y, x and all
-workspaces resident on the GPU before timing starts).
+Headline (the timed steps): 8 unknown 512x512 images (rectangles/ellipses
+plus a smooth random field), images 0-3 blurred by a 19x19 Gaussian
+(sigma 3), 4-7 by a 15-px linear motion blur, observed on the valid region
+minus 40% i.i.d. missing pixels, sigma 2e-3, lambda 2e-4, mu1 = mu2 = 1e-3.
+One step = one batched solve of 500 ADMM iterations from a cold start (plan,
+y, x and all workspaces resident on the GPU before timing starts).
 
-Prints one JSON line with the throughput in megapixel-iterations per second,
-the roofline of the dominant kernel (algorithmic bytes over its measured
-launch time) and the FP64 oracle timed on the host as a CPU baseline.
+The same JSON line also carries, under "configs", the other workloads:
+  c1          128^2 TV-MD, 9x9 uniform, 200 iterations (GPU time; the FP64
+              oracle's wall time is in cpu_baseline)
+  c3          FA-MD 1024^2, J = 3, 13x13 disk, 20% missing 8x8 blocks, time to
+              residual tolerance 1e-4
+  c4          ragged batch of 256 TV-MD problems (sides 128..1024, kernels
+              5..31), 200 iterations
+  beyond_cache  64 x 512^2 TV-MD, 500 iterations (working set ~0.9 GB, far
+              beyond the 256 MB memory-side cache)
+  c5          learned warm start: 20k training problems at 256^2 (targets from
+              the GPU ADMM), 512 unseen 512^2 problems, p50 time to 1e-4 cold
+              vs warm
+with a roofline per workload: algorithmic bytes per iteration (this
+schedule's two-launch TV iteration, the FA iteration's four launches) over
+the measured time per iteration, and for the headline the dominant kernel's
+launch duration as well. ``--quick`` runs the headline alone.
 """
 
 import argparse
@@ -19,6 +32,8 @@ import json
 import os
 import sys
 import time
+from concurrent.futures import ProcessPoolExecutor
+from functools import partial
 
 import numpy as np
 
@@ -30,6 +45,10 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "row_tv_tv8x512_traffic.txt")
 KERNEL_SOURCES = ["paper_1210_2687_amd/csrc/admm_kernels.hip", "paper_1210_2687_amd/csrc/fft_lds.h",
                   "paper_1210_2687_amd/csrc/admm_internal.h"]
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -71,25 +90,11 @@ def alg_bytes_per_launch(problems):
     return out
 
 
-WORKLOADS = {
-    "tv8x512": "TV-MD batch of 8 x 512x512 (19x19 Gaussian x4, 15-px motion x4), 40% missing",
-    "fa1024": "FA-MD 1024x1024, 13x13 disk, undecimated Haar J = 3, 20% missing 8x8 blocks",
-    "ragged256": "TV-MD ragged batch of 256 problems, sides 128..1024 (7-smooth), kernels 5..31",
-}
-
-
-def workload(name, batch, size):
-    from paper_1210_2687_amd import workloads as WL
-    if name == "tv8x512":
-        return [WL.config2(i % 8, size=size) for i in range(batch)]
-    if name == "fa1024":
-        return [WL.config3(size=1024, levels=3)]
-    if name == "ragged256":
-        # the synthetic observations take about a second each on one core
-        from concurrent.futures import ProcessPoolExecutor
-        with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
-            return list(ex.map(WL.config4, range(256)))
-    raise SystemExit(f"bench.py: unknown workload {name}")
+def iteration_roofline(problems, us_per_iter):
+    b = sum(alg_bytes_per_launch(problems).values())
+    gbs = b / (us_per_iter * 1e-6) / 1e9
+    return {"bound": "hbm", "alg_bytes_per_iter": int(b), "us_per_iter": round(us_per_iter, 3),
+            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def read_traffic(expected_hash):
@@ -109,34 +114,153 @@ def read_traffic(expected_hash):
         return None
 
 
-def cpu_baseline(iters, name="tv8x512"):
-    """FP64 oracle on a bounded sample of the workload (the TV batch: one Gaussian
-    and one motion member; FA: the problem itself; ragged: two members)."""
-    import numpy as np
-    import oracle as O
+# ------------------------------------------------------------------ host data
+def _c2_member(i, size):
     from paper_1210_2687_amd import workloads as WL
-    try:
-        import threadpoolctl
-        cores = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or os.cpu_count()
-    except Exception:
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    if name == "fa1024":
-        sample, what = [WL.config3(size=1024, levels=3)], "the 1024x1024 FA problem"
-    elif name == "ragged256":
-        sample, what = [WL.config4(0), WL.config4(1)], "ragged members 0 and 1"
-    else:
-        sample, what = [WL.config2(0), WL.config2(4)], "2 of the 8 batch images (one 19x19 Gaussian, one 15-px motion)"
+    return WL.config2(i % 8, size=size)
+
+
+def host_data(args):
+    """Every synthetic input, generated in a process pool before the GPU is touched."""
+    from paper_1210_2687_amd import workloads as WL
+    from paper_1210_2687_amd import warmstart as WS
+    data = {}
+    workers = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
-    for p in sample:
-        if getattr(p, "reg", "tv") == "frame":
-            O.fa_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, p.levels, iters=iters)
-        else:
-            O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=iters)
-    dt = time.perf_counter() - t0
-    px_it = sum(p.y.size for p in sample) * iters
-    shapes = ", ".join(f"{p.shape[0]}x{p.shape[1]}" for p in sample)
-    return {"value": px_it / dt / 1e6, "unit": "Mpx*iter/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{what} ({shapes}), {iters} iterations each, {dt:.1f} s"}
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        data["c2"] = list(ex.map(partial(_c2_member, size=args.size), range(args.batch)))
+        if args.workload == "fa1024" or not args.quick:
+            data["c3"] = WL.config3(size=1024, levels=3)
+        if args.workload == "ragged256" or not args.quick:
+            data["c4"] = list(ex.map(WL.config4, range(256), chunksize=4))
+        if args.workload == "tv64x512" or not args.quick:
+            data["c64"] = [data["c2"][i % len(data["c2"])] for i in range(64)]
+        if not args.quick:
+            data["c1"] = WL.config1()
+            if args.ws_train:
+                data["c5_train"] = list(ex.map(partial(WS.light_problem, size=256), range(args.ws_train),
+                                               chunksize=64))
+                data["c5_eval"] = list(ex.map(partial(WS.light_problem, size=512),
+                                              range(10 ** 6, 10 ** 6 + args.ws_eval), chunksize=8))
+    log(f"host data generated in {time.perf_counter() - t0:.1f} s with {workers} processes")
+    return data
+
+
+# ------------------------------------------------------------------ GPU workloads
+def timed_batch(probs, iters, steps, warmup, tune, graph=True):
+    """Plan (autotuned tiles unless tune is False), warm up, time `steps` cold-start
+    batched solves of `iters` iterations. Returns (plan, ys, xs, result dict)."""
+    import torch
+    from paper_1210_2687_amd import admm as A
+    ys = [torch.tensor(p.y, dtype=torch.float32, device="cuda") for p in probs]
+    xs = [torch.zeros_like(y) for y in ys]
+    t0 = time.perf_counter()
+    plan = A.Plan(probs, tune=tune, cache_path=os.environ.get("ADMM_TUNE_CACHE"))
+    t_plan = time.perf_counter() - t0
+    run = lambda: plan.batch(ys, xs, max_iters=iters, tol=0.0, graph=graph)
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    px = sum(p.y.size for p in probs)
+    tc, rows = plan.tiles(0)
+    res = {"value": px * iters / dt / 1e6, "ms_per_step": dt * 1e3, "pixels": int(px), "iters": iters,
+           "us_per_iter": dt * 1e6 / iters, "plan_s": round(t_plan, 2),
+           "tiles": {"cols_per_block": tc, "rows_per_block": rows, "chosen_by": "autotuner" if tune else "heuristic"}}
+    return plan, ys, xs, res
+
+
+def kernel_breakdown(plan, ys, xs, iters):
+    """Per-launch microseconds of each kernel class from an event-timed eager run."""
+    plan.batch(ys, xs, max_iters=iters, tol=0.0, graph=False, profile=True)
+    kt = plan.kernel_times()
+    return {k: round(v[1] / v[0] * 1e3, 3) for k, v in kt.items() if v[0]}
+
+
+def dominant_roofline(plan, probs, kt, reps=50):
+    """The dominant pass kernel's launch duration: `reps` back-to-back launches
+    between one pair of HIP events on the plan's stream."""
+    alg = alg_bytes_per_launch(probs)
+    dom = max((k for k in ("col", "row_tv", "row_inv", "frame", "row_fwd") if k in kt), key=lambda k: kt[k])
+    avg_s = plan.time_pass(dom, reps) / 1e3
+    achieved = alg[dom] / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 3),
+            "alg_bytes_per_launch": int(alg[dom]), "timing": f"{reps} back-to-back launches between one HIP event pair"}
+
+
+def run_throughput(name, probs, iters, steps, warmup, tune, desc):
+    log(f"{name}: {desc}")
+    plan, ys, xs, r = timed_batch(probs, iters, steps, warmup, tune)
+    kt = kernel_breakdown(plan, ys, xs, min(iters, 100))
+    out = {"workload": desc, "value": round(r["value"], 1), "unit": "Mpx*iter/s", "ms_per_step": round(r["ms_per_step"], 3),
+           "steps": steps, "problems": len(probs), "pixels": r["pixels"], "iters": iters, "tiles": r["tiles"],
+           "plan_s": r["plan_s"], "roofline_iteration": iteration_roofline(probs, r["us_per_iter"]),
+           "roofline_dominant": dominant_roofline(plan, probs, kt), "kernel_us_event_per_launch": kt}
+    plan.close()
+    log(f"{name}: {out['value']:.1f} Mpx*iter/s, iteration at {out['roofline_iteration']['frac']:.3f} of HBM peak")
+    return out
+
+
+def run_c1(p, steps=5):
+    import torch
+    from paper_1210_2687_amd import admm as A
+    log("c1: 128^2 TV-MD, 200 iterations")
+    y = torch.tensor(p.y, dtype=torch.float32, device="cuda")
+    x = torch.zeros_like(y)
+    with A.Plan([p]) as plan:
+        plan.solve(y, x, max_iters=200, graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = plan.solve(y, x, max_iters=200, graph=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+    return {"workload": "TV-MD 128x128, 9x9 uniform, valid 120x120, 200 iterations, cold start",
+            "gpu_ms": round(dt * 1e3, 3), "value": round(p.y.size * 200 / dt / 1e6, 1), "unit": "Mpx*iter/s",
+            "objective": info["objective"], "oracle": "FP64 oracle wall time: cpu_baseline.config1_oracle_s"}
+
+
+def run_c3(p, tol=1e-4, max_iters=5000, c=10):
+    import torch
+    from paper_1210_2687_amd import admm as A
+    log("c3: FA-MD 1024^2 J=3, time to tolerance 1e-4")
+    y = torch.tensor(p.y, dtype=torch.float32, device="cuda")
+    x = torch.zeros_like(y)
+    with A.Plan([p], tune=True, cache_path=os.environ.get("ADMM_TUNE_CACHE")) as plan:
+        plan.solve(y, x, max_iters=4 * c + 1, tol=tol, check_every=c, graph=True)    # graphs captured, untimed
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = plan.solve(y, x, max_iters=max_iters, tol=tol, check_every=c, graph=True)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        dt = float(np.median(times))
+        kt = kernel_breakdown(plan, [y], [x], 50)
+        dom = dominant_roofline(plan, [p], kt)
+        # throughput at a fixed iteration count (graph replay), for the iteration roofline
+        K = 400
+        plan.solve(y, x, max_iters=K, graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve(y, x, max_iters=K, graph=True)
+        torch.cuda.synchronize()
+        us_it = (time.perf_counter() - t0) * 1e6 / K
+    it = info["iters"]
+    out = {"workload": "FA-MD 1024x1024, undecimated Haar J = 3, 13x13 disk r = 6, valid region minus 20% of 8x8 "
+                       "blocks, sigma 1e-3, lambda 2e-4, mu 1e-3, tolerance 1e-4 on both residuals (checked every 10)",
+           "time_to_tol_ms": round(dt * 1e3, 2), "iters": it, "converged": info["converged"],
+           "r_pri": info["r_pri"], "r_dual": info["r_dual"], "objective": info["objective"],
+           "value": round(p.y.size * it / dt / 1e6, 1), "unit": "Mpx*iter/s",
+           "roofline_iteration": iteration_roofline([p], us_it), "roofline_dominant": dom,
+           "kernel_us_event_per_launch": kt}
+    log(f"c3: {it} iterations in {dt * 1e3:.1f} ms, iteration at {out['roofline_iteration']['frac']:.3f} of HBM peak")
+    return out
 
 
 def cnn_flops_per_px(train=False):
@@ -151,26 +275,34 @@ def cnn_flops_per_px(train=False):
     return 2 * fwd + dgrad
 
 
-def warm_start_eval(n_train, steps, n_eval, train_size, eval_size, log):
-    """Train the warm-start network on GPU-generated targets, then time
-    cold and warm solves to tolerance 1e-4 on unseen problems."""
+def run_c5(train_probs, eval_probs, steps, target_batch=500, target_iters=3000):
+    """Train the warm-start network on GPU-generated targets, then time cold and
+    warm solves to tolerance 1e-4 on unseen problems."""
     import torch
     from paper_1210_2687_amd import warmstart as WS
+    n_train, n_eval = len(train_probs), len(eval_probs)
+    log(f"c5: targets for {n_train} problems of 256^2 (tol 1e-6, at most {target_iters} iterations)")
     t0 = time.perf_counter()
-    parts = [WS.targets(WS.problems(b, min(32, n_train - b), train_size)) for b in range(0, n_train, 32)]
+    parts, conv = [], 0
+    for b in range(0, n_train, target_batch):
+        y, m, e, xt, pt, infos = WS.targets(train_probs[b:b + target_batch], tol=1e-6, max_iters=target_iters)
+        parts.append((y, m, e, xt, pt))
+        conv += sum(i["converged"] for i in infos)
+        if (b // target_batch) % 8 == 7:
+            log(f"c5: targets {b + target_batch}/{n_train}")
     data = tuple(torch.cat([d[k] for d in parts]) for k in range(5))
+    del parts
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
+    log(f"c5: targets done in {t_data:.1f} s ({conv}/{n_train} reached 1e-6); training {steps} steps")
     net = WS.WarmStartNet(seed=0)
     t0 = time.perf_counter()
     hist = WS.train(net, data, steps=steps, batch=8)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    log(f"warm start: targets {t_data:.1f} s, {steps} training steps {t_train:.1f} s, "
-        f"loss {np.mean(hist[:10]):.3e} -> {np.mean(hist[-10:]):.3e}")
-    # network throughput: inference on a 4 x eval_size^2 batch, one training step on 8 x train_size^2
-    ev = WS.problems(10 ** 6, n_eval, eval_size)
-    y, m, e = WS.to_device(ev[:4])
+    log(f"c5: trained in {t_train:.1f} s, loss {np.mean(hist[:10]):.3e} -> {np.mean(hist[-10:]):.3e}")
+    # network throughput: inference on 4 unseen 512^2 problems, one training step on 8 x 256^2
+    y, m, e = WS.to_device(eval_probs[:4])
     for _ in range(2):
         net.predict(y, m, e)
     torch.cuda.synchronize()
@@ -191,16 +323,50 @@ def warm_start_eval(n_train, steps, n_eval, train_size, eval_size, log):
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t0) / reps
     step_tf = cnn_flops_per_px(train=True) * batch[0].numel() / step_s / 1e12
-    rows = WS.evaluate(net, ev)
+    del data, batch
+    log(f"c5: timing cold and warm solves of {n_eval} unseen problems of 512^2")
+    rows = WS.evaluate(net, eval_probs, log=log)
     s = WS.summary(rows)
-    s.update({"tol": 1e-4, "check_every": 10, "eval": f"{n_eval} unseen {eval_size}x{eval_size} problems",
-              "train": f"{n_train} problems {train_size}x{train_size}, {steps} Adam steps of 8, "
-                       f"{t_data + t_train:.1f} s incl. target generation",
-              "net_params": net.nparams,
+    s.update({"workload": "learned warm start (6 conv3x3 layers, 32 channels, BF16 MFMA) vs cold start, TV-MD",
+              "tol": 1e-4, "check_every": 10, "eval": f"{n_eval} unseen 512x512 problems, one at a time",
+              "train": f"{n_train} problems 256x256, targets from the GPU ADMM (tol 1e-6, at most {target_iters} "
+                       f"iterations; {conv} reached it), {steps} Adam steps of 8",
+              "targets_s": round(t_data, 1), "train_s": round(t_train, 1),
+              "final_objective_check": "cold and warm continued to tolerance 5e-6 (batches of 64)",
+              "net_params": net.nparams, "loss_first_last": [float(np.mean(hist[:10])), float(np.mean(hist[-10:]))],
               "cnn_fwd_tflops": round(fwd_tf, 2), "cnn_train_step_tflops": round(step_tf, 2),
               "bf16_peak_tflops": 2500.0, "timing": "wall clock per problem; warm includes the network and the "
                                                     "state mapping; both solve on a hipGraph"})
+    log(f"c5: p50 cold {s['p50_cold_ms']:.1f} ms, warm {s['p50_warm_ms']:.1f} ms ({s['p50_speedup']:.2f}x)")
     return s
+
+
+# ------------------------------------------------------------------ CPU baseline (the oracle)
+def cpu_baseline(iters, sample, c1=None):
+    """The FP64 oracle on a bounded sample of the headline workload (and, if
+    given, the whole 128^2 workload: its headline is the oracle's wall time)."""
+    import oracle as O
+    try:
+        import threadpoolctl
+        cores = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or os.cpu_count()
+    except Exception:
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    log(f"cpu baseline: FP64 oracle on {len(sample)} images x {iters} iterations")
+    t0 = time.perf_counter()
+    for p in sample:
+        O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=iters)
+    dt = time.perf_counter() - t0
+    px_it = sum(p.y.size for p in sample) * iters
+    shapes = ", ".join(f"{p.shape[0]}x{p.shape[1]}" for p in sample)
+    out = {"value": px_it / dt / 1e6, "unit": "Mpx*iter/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"{len(sample)} of the 8 headline images (one 19x19 Gaussian, one 15-px motion) ({shapes}), "
+                     f"{iters} iterations each, {dt:.1f} s"}
+    if c1 is not None:
+        t0 = time.perf_counter()
+        O.tv_md_run(c1.y, c1.mask, c1.kernel, c1.lam, c1.mu1, c1.mu2, iters=200)
+        out["config1_oracle_s"] = round(time.perf_counter() - t0, 3)
+        out["config1"] = "TV-MD 128x128, 9x9 uniform, 200 iterations, the whole run"
+    return out
 
 
 def main():
@@ -208,23 +374,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="tv8x512", choices=sorted(WORKLOADS),
-                    help="tv8x512 is the headline; fa1024 and ragged256 measure the other paths")
-    ap.add_argument("--iters", type=int, default=0, help="ADMM iterations per step (0: 500, 200, 100 by workload)")
+    ap.add_argument("--workload", default="tv8x512", choices=["tv8x512", "tv64x512", "fa1024", "ragged256"],
+                    help="the headline is tv8x512; with --quick, the others run alone (profiling)")
+    ap.add_argument("--quick", action="store_true", help="only the chosen workload, no other configs")
+    ap.add_argument("--iters", type=int, default=500, help="ADMM iterations per headline step")
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations per sampled image "
-                    "(0: 120 for the TV batch, 10 for FA, 30 for ragged)")
+    ap.add_argument("--cpu-iters", type=int, default=100, help="oracle iterations per sampled headline image")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start training and evaluation")
-    ap.add_argument("--ws-train", type=int, default=256, help="warm-start training problems (256x256)")
-    ap.add_argument("--ws-steps", type=int, default=2000, help="warm-start training steps")
-    ap.add_argument("--ws-eval", type=int, default=32, help="warm-start evaluation problems (512x512)")
+    ap.add_argument("--ws-train", type=int, default=20000, help="warm-start training problems (256x256; 0: skip)")
+    ap.add_argument("--ws-steps", type=int, default=8000, help="warm-start Adam steps of 8")
+    ap.add_argument("--ws-eval", type=int, default=512, help="warm-start evaluation problems (512x512)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the planner's heuristic tile shapes instead of the autotuner (which runs at plan time, "
                          "outside the timed region; ADMM_TUNE_CACHE names an optional JSON cache)")
-    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event-timing pass")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -245,83 +409,75 @@ def main():
               "problems shard across GPUs by whole images, which is not measured here.", file=sys.stderr)
         sys.exit(2)
 
+    data = host_data(args)
+
     import torch
     from paper_1210_2687_amd import admm as A
-    from paper_1210_2687_amd import workloads as WL
-
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     A.lib()   # fail loudly if the HIP library is missing
-
-    if not args.iters:
-        args.iters = {"tv8x512": 500, "fa1024": 200, "ragged256": 100}[args.workload]
-    if not args.cpu_iters:
-        args.cpu_iters = {"tv8x512": 120, "fa1024": 10, "ragged256": 30}[args.workload]
-    probs = workload(args.workload, args.batch, args.size)
-    ys = [torch.tensor(p.y, dtype=torch.float32, device="cuda") for p in probs]
-    xs = [torch.zeros_like(y) for y in ys]
-    plan = A.Plan(probs, tune=not args.no_tune, cache_path=os.environ.get("ADMM_TUNE_CACHE"))
-    tiles = plan.tiles(0)
+    tune = not args.no_tune
     graph = not args.no_graph
-    run = lambda **kw: plan.batch(ys, xs, max_iters=args.iters, tol=0.0, graph=graph, **kw)
 
-    for _ in range(args.warmup):
-        run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        run()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt / args.steps * 1e3
-    px = sum(p.y.size for p in probs)
-    value = px * args.iters / (dt / args.steps) / 1e6
+    configs = {}
+    if args.quick and args.workload != "tv8x512":
+        # one other workload alone, for profiling
+        if args.workload == "fa1024":
+            configs["c3"] = run_c3(data["c3"])
+        elif args.workload == "ragged256":
+            configs["c4"] = run_throughput("c4", data["c4"], 200, args.steps, args.warmup, tune,
+                                           "TV-MD ragged batch of 256 problems, sides 128..1024 (7-smooth), "
+                                           "kernels 5..31, 200 iterations")
+        else:
+            configs["beyond_cache"] = run_throughput("beyond_cache", data["c64"], 500, args.steps, args.warmup, tune,
+                                                     "TV-MD batch of 64 x 512x512, 500 iterations")
+        print(json.dumps({"metric": METRIC, "configs": configs}), flush=True)
+        return
 
-    roofline = None
-    kt = {}
-    if not args.no_profile:
-        plan.batch(ys, xs, max_iters=args.iters, tol=0.0, graph=False, profile=True)
-        kt = plan.kernel_times()
-        alg = alg_bytes_per_launch(probs)
-        dom = max(("col", "row_tv", "row_inv", "frame", "row_fwd"), key=lambda k: kt[k][1])
-        # the dominant kernel's launch duration: 50 back-to-back launches between one
-        # pair of HIP events on the plan's stream (an event pair per launch, as in the
-        # profiled pass above, adds each launch's dispatch to its interval)
-        reps = 50
-        avg_s = plan.time_pass(dom, reps) / 1e3
-        achieved = alg[dom] / avg_s / 1e9
-        traffic = read_traffic(kernel_source_hash()) if (dom == "row_tv" and args.workload == "tv8x512") else None
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                    "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": alg[dom],
-                    "timing": f"{reps} back-to-back launches between one HIP event pair",
-                    "kernel_us_event_per_launch": {k: round(v[1] / max(v[0], 1) * 1e3, 3) for k, v in kt.items()
-                                                   if v[0]}}
+    # ---- headline
+    probs = data["c2"]
+    log(f"headline: TV-MD batch of {args.batch} x {args.size}^2, {args.iters} iterations, "
+        f"{args.warmup} warm-up + {args.steps} timed steps")
+    plan, ys, xs, r = timed_batch(probs, args.iters, args.steps, args.warmup, tune, graph)
+    kt = kernel_breakdown(plan, ys, xs, min(args.iters, 100))
+    roofline = dominant_roofline(plan, probs, kt)
+    traffic = read_traffic(kernel_source_hash()) if roofline["kernel"] == "row_tv" else None
+    roofline["traffic"] = traffic
+    roofline["kernel_us_event_per_launch"] = kt
+    roofline_it = iteration_roofline(probs, r["us_per_iter"])
+    plan.close()
+    log(f"headline: {r['value']:.1f} Mpx*iter/s; {roofline['kernel']} at {roofline['frac']:.3f}, "
+        f"iteration at {roofline_it['frac']:.3f} of HBM peak")
 
-    log = lambda msg: print(msg, file=sys.stderr, flush=True)
-    ws = None if (args.no_warm_start or args.workload != "tv8x512") else \
-        warm_start_eval(args.ws_train, args.ws_steps, args.ws_eval, 256, 512, log)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_iters, args.workload)
-    tile_info = {"cols_per_block": tiles[0], "rows_per_block": tiles[1],
-                 "chosen_by": "heuristic" if args.no_tune else "autotuner"}
-    if args.workload == "tv8x512":
-        config = {"workload": f"TV-MD batch of {args.batch} x {args.size}x{args.size}, {args.iters} iterations",
-                  "batch": args.batch, "H": args.size, "W": args.size, "iters": args.iters,
-                  "kernels": "19x19 Gaussian sigma 3 (4) + 15-px motion (4)",
-                  "mask": "valid region minus 40% i.i.d. missing", "graph": graph, "tiles": tile_info}
-    else:
-        config = {"workload": f"{WORKLOADS[args.workload]}, {args.iters} iterations", "problems": len(probs),
-                  "pixels": int(px), "iters": args.iters, "graph": graph, "tiles": tile_info}
+    if not args.quick:
+        configs["c1"] = run_c1(data["c1"])
+        configs["c3"] = run_c3(data["c3"])
+        configs["beyond_cache"] = run_throughput("beyond_cache", data["c64"], 500, 3, 1, tune,
+                                                 "TV-MD batch of 64 x 512x512 (the 8 headline images repeated), "
+                                                 "500 iterations")
+        configs["c4"] = run_throughput("c4", data["c4"], 200, 2, 1, tune,
+                                       "TV-MD ragged batch of 256 problems, sides 128..1024 (7-smooth), kernels "
+                                       "Gaussian/uniform/motion 5..31, lambda log-uniform 1e-5..1e-3, 200 iterations")
+        if args.ws_train:
+            configs["c5"] = run_c5(data.pop("c5_train"), data.pop("c5_eval"), args.ws_steps)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_iters, [probs[0], probs[4 % len(probs)]], None if args.quick else data["c1"])
+
+    config = {"workload": f"TV-MD batch of {args.batch} x {args.size}x{args.size}, {args.iters} iterations",
+              "batch": args.batch, "H": args.size, "W": args.size, "iters": args.iters,
+              "kernels": "19x19 Gaussian sigma 3 (4) + 15-px motion (4)",
+              "mask": "valid region minus 40% i.i.d. missing", "graph": graph, "tiles": r["tiles"]}
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "Mpx*iter/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "metric": METRIC, "value": round(r["value"], 1), "unit": "Mpx*iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": config,
-        "roofline": roofline, "cpu_baseline": cpu, "warm_start": ws,
+        "roofline": roofline, "roofline_iteration": roofline_it, "cpu_baseline": cpu, "configs": configs,
     }
-    plan.close()
     print(json.dumps(out), flush=True)
 
 

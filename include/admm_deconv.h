@@ -166,6 +166,15 @@ admm_status admm_deconv_blur(admm_plan* plan, int32_t index, const float* x, flo
 admm_status admm_warmstart_map(admm_plan* plan, int32_t index, const float* x0,
                                const float* p0, const float* y, admm_state* st);
 
+/* Dual field of a TV state, the inverse of the d_TV part of admm_warmstart_map
+ * (KKT form of the optimal duals, not in the paper): p0 = -(mu2 / lambda) d_TV
+ * with the plan's mu2 and lambda of problem `index`. At a minimiser
+ * |p0_i| <= 1 per pixel, so p0 is the target the warm-start network learns.
+ * dreg: DEVICE 2*H*W [horizontal, vertical] (a state's dreg); p0: DEVICE
+ * 2*H*W output (may alias dreg). Errors: ADMM_E_INVALID for a null pointer, an
+ * index out of range, a frame problem or lambda <= 0.                          */
+admm_status admm_warmstart_dual(admm_plan* plan, int32_t index, const float* dreg, float* p0);
+
 /* Per-kernel GPU time of the most recent solve/batch run with ADMM_FLAG_PROFILE.
  * Kernel classes: "col" (column DFT + circulant solve), "row_tv" (fused TV row
  * pass), "row_inv" (FA inverse rows + data step), "frame" (FA frame step),

@@ -96,6 +96,7 @@ def lib():
                                                POINTER(admm_opts), POINTER(admm_info), c_void_p]
         L.admm_deconv_blur.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
         L.admm_warmstart_map.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, POINTER(admm_state)]
+        L.admm_warmstart_dual.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
         L.admm_plan_destroy.argtypes = [c_void_p]
         L.admm_plan_destroy.restype = None
         L.admm_last_error.restype = c_char_p
@@ -126,7 +127,7 @@ def lib():
         for f in ("admm_deconv_plan", "admm_deconv_plan_tuned", "admm_tune_cache_store", "admm_plan_tiles",
                   "admm_plan_time_pass",
                   "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur", "admm_deconv_solve_static",
-                  "admm_warmstart_map", "admm_fft_radices", "admm_validate_problem",
+                  "admm_warmstart_map", "admm_warmstart_dual", "admm_fft_radices", "admm_validate_problem",
                   "admm_conv3x3_pack_weights", "admm_conv3x3_bf16_fwd", "admm_conv3x3_bf16_wgrad",
                   "admm_adam_step", "admm_ws_input", "admm_ws_loss", "admm_ws_output"):
             getattr(L, f).restype = c_int32
@@ -138,7 +139,7 @@ def exported_symbols():
     """Names of the C entry points declared in include/admm_deconv.h."""
     return ["admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
             "admm_deconv_solve_static",
-            "admm_warmstart_map", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
+            "admm_warmstart_map", "admm_warmstart_dual", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
             "admm_validate_problem", "admm_plan_kernel_times", "admm_deconv_plan_tuned", "admm_tune_key",
             "admm_tune_cache_lookup", "admm_tune_cache_store", "admm_plan_tiles", "admm_plan_time_pass",
             "admm_conv3x3_pack_weights", "admm_conv3x3_bf16_fwd", "admm_conv3x3_bf16_wgrad_workspace",
@@ -377,6 +378,11 @@ def admm_warmstart_map(plan, index, x0, p0, y, state):
                                     ctypes.byref(st)))
 
 
+def admm_warmstart_dual(plan, index, dreg, p0):
+    n = p0.numel()
+    _check(lib().admm_warmstart_dual(plan, int(index), _dev(dreg, n), _dev(p0, n)))
+
+
 def alloc_state(H, W, nreg=2, device="cuda"):
     """Zero ADMM state planes (u1, d1: H x W; ureg, dreg: nreg x H x W)."""
     import torch
@@ -419,6 +425,9 @@ class Plan:
 
     def warmstart_map(self, index, x0, p0, y, state):
         admm_warmstart_map(self.handle, index, x0, p0, y, state)
+
+    def warmstart_dual(self, index, dreg, p0):
+        admm_warmstart_dual(self.handle, index, dreg, p0)
 
     def close(self):
         if self.handle:

@@ -1058,6 +1058,18 @@ extern "C" admm_status admm_warmstart_map(admm_plan* P, int32_t index, const flo
     return ADMM_OK;
 }
 
+extern "C" admm_status admm_warmstart_dual(admm_plan* P, int32_t index, const float* dreg, float* p0) {
+    if (!P || !dreg || !p0) return fail(ADMM_E_INVALID, "null argument");
+    if (index < 0 || index >= P->count) return fail(ADMM_E_INVALID, "index %d out of range", index);
+    const ProbDesc& d = P->hd[index];
+    if (d.reg != REG_TV) return fail(ADMM_E_INVALID, "the dual field is defined for TV problems");
+    const double lam = P->probs[index].lambda;
+    if (!(lam > 0.0)) return fail(ADMM_E_INVALID, "lambda must be > 0 to scale the dual field (got %g)", lam);
+    HIP_TRY(launch_scale(P->stream, dreg, p0, 2 * (size_t)d.H * d.W, (float)(-(double)d.mu2 / lam)));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    return ADMM_OK;
+}
+
 extern "C" int32_t admm_plan_kernel_times(const admm_plan* P, admm_kernel_time* out, int32_t cap) {
     if (!P) return 0;
     for (int i = 0; i < 6 && out && i < cap; ++i) {

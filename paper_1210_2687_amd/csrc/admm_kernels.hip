@@ -890,6 +890,13 @@ __global__ void k_warmstart(const ProbDesc* __restrict__ pd, int prob, const flo
     dreg[n + g] = sc * pv;
 }
 
+// p = s d for the 2 n entries of a TV dual pair (s = -mu2 / lambda: the dual
+// field whose warm-start mapping reproduces d_TV)
+__global__ void k_scale2(const float* __restrict__ d, float* __restrict__ p, size_t n2, float s) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = s * d[i];
+}
+
 // ------------------------------------------------------------ host launchers
 static size_t col_lds(int H, int TC) {
     return (size_t)((H + 1) / 2) * sizeof(float4) + (size_t)TC * pidx_len(H) * sizeof(float4);
@@ -1030,6 +1037,13 @@ hipError_t launch_zero(hipStream_t stream, float* p, size_t n) {
     if (!n) return hipSuccess;
     const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(hipStream_t stream, const float* d, float* p, size_t n, float s) {
+    if (!n) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_scale2, dim3((unsigned)blocks), dim3(256), 0, stream, d, p, n, s);
     return hipGetLastError();
 }
 

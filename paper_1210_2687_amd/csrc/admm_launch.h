@@ -51,6 +51,7 @@ hipError_t launch_reduce(const LaunchCtx& L, int count, double tol, int iter, in
                          const int* iter_dev = nullptr, int* host_active = nullptr);
 hipError_t launch_tick(const LaunchCtx& L, int* counter, int c, bool set);   // counter = set ? c : counter + c
 hipError_t launch_zero(hipStream_t stream, float* p, size_t n);
+hipError_t launch_scale(hipStream_t stream, const float* d, float* p, size_t n, float s);
 hipError_t launch_import_tv(const LaunchCtx& L, int prob, size_t n);
 hipError_t launch_import_fa(const LaunchCtx& L, int prob, size_t n);
 hipError_t launch_lambda(const LaunchCtx& L, int prob, size_t HP, const float2* T, int ks);

@@ -163,6 +163,14 @@ def problems(first, count, size):
     return [WL.config5_problem(first + i, size=size) for i in range(count)]
 
 
+def light_problem(index, size):
+    """``WL.config5_problem`` without the true image and with a float32
+    observation (what the solver and the network read; a quarter of the host
+    memory, for data sets of tens of thousands of problems)."""
+    p = WL.config5_problem(index, size=size)
+    return WL.Problem(y=p.y.astype(np.float32), mask=p.mask, kernel=p.kernel, lam=p.lam, mu1=p.mu1, mu2=p.mu2)
+
+
 def to_device(probs):
     import torch
     y = torch.tensor(np.stack([p.y for p in probs]), dtype=torch.float32, device="cuda")
@@ -172,17 +180,23 @@ def to_device(probs):
 
 
 def targets(probs, tol=1e-6, max_iters=8000, check_every=20):
-    """Training targets from the GPU ADMM itself: x* and p* = -(mu2 / lambda) d_TV*."""
+    """Training targets from the GPU ADMM itself, all problems in one batch:
+    x* and the dual field p* = -(mu2 / lambda) d_TV* (admm_warmstart_dual).
+    Returns (y, m, e, xt, pt, infos); a target whose solve stopped at
+    max_iters before tol is kept (it is an iterate of the same convergent
+    method) and counted as unconverged in its info."""
     import torch
     y, m, e = to_device(probs)
+    N = len(probs)
+    H, W = probs[0].shape
+    xt = torch.zeros((N, H, W), dtype=torch.float32, device="cuda")
+    pt = torch.empty((N, 2, H, W), dtype=torch.float32, device="cuda")
     with A.Plan(probs) as plan:
-        xs = [torch.zeros_like(y[i]) for i in range(len(probs))]
-        H, W = probs[0].shape
         states = [A.alloc_state(H, W) for _ in probs]
-        infos = plan.batch([y[i] for i in range(len(probs))], xs, states, max_iters=max_iters, tol=tol,
-                           check_every=check_every, graph=True)
-    xt = torch.stack(xs)
-    pt = torch.stack([-(p.mu2 / p.lam) * s["dreg"] for p, s in zip(probs, states)])
+        infos = plan.batch([y[i] for i in range(N)], [xt[i] for i in range(N)], states, max_iters=max_iters,
+                           tol=tol, check_every=check_every, graph=True)
+        for i, st in enumerate(states):
+            plan.warmstart_dual(i, st["dreg"], pt[i])
     return y, m, e, xt, pt, infos
 
 
@@ -233,26 +247,61 @@ def solve_warm(plan, net, y, m, e, tol, max_iters, check_every):
     return x, info, time.perf_counter() - t0, ok
 
 
-def evaluate(net, probs, tol=1e-4, max_iters=8000, check_every=10, final_tol=5e-6, final_iters=40000):
+def final_objectives(net, probs, y, m, e, tol, max_iters, check_every=50, batch=64):
+    """Objectives of cold and warm runs to a tight tolerance, problems in
+    batches of ``batch`` (throughput mode: only the values are compared)."""
+    import torch
+    out = []
+    for b in range(0, len(probs), batch):
+        chunk = probs[b:b + batch]
+        n = len(chunk)
+        ys = [y[b + i] for i in range(n)]
+        with A.Plan(chunk) as plan:
+            xs = [torch.zeros_like(t) for t in ys]
+            ic = plan.batch(ys, xs, None, max_iters=max_iters, tol=tol, check_every=check_every, graph=True)
+            x0, p0 = net.predict(y[b:b + n], m[b:b + n], e[b:b + n])
+            ok = [bool(torch.isfinite(x0[i]).all().item() and torch.isfinite(p0[i]).all().item()) for i in range(n)]
+            sts = [A.alloc_state(*p.shape) for p in chunk]
+            for i in range(n):
+                if ok[i]:
+                    plan.warmstart_map(i, x0[i].contiguous(), p0[i].contiguous(), ys[i], sts[i])
+            xs = [torch.zeros_like(t) for t in ys]
+            iw = plan.batch(ys, xs, sts, max_iters=max_iters, tol=tol, check_every=check_every, graph=True)
+        out += list(zip(ic, iw))
+    return out
+
+
+def evaluate(net, probs, tol=1e-4, max_iters=8000, check_every=10, final_tol=5e-6, final_iters=40000,
+             final_batch=64, log=None):
     """Per-problem cold and warm time-to-tolerance (seconds, warm including the
     network and the state mapping), iterations, and the objectives F of cold
     and warm runs continued to final_tol (the minimiser's F is unique; at tol
-    both are still up to about tol away from it)."""
+    both are still up to about tol away from it). Each problem gets its own
+    plan; the graphs of both paths are captured by short untimed runs before
+    the timed solves."""
     y, m, e = to_device(probs)
     rows = []
+    warm_k = 4 * check_every + 1      # long enough to capture the period graphs the timed runs replay
     for i, p in enumerate(probs):
         with A.Plan([p]) as plan:
-            if i == 0:   # first use of every kernel, buffer and graph of both paths
-                solve_cold(plan, y[i], tol, max_iters, check_every)
-                solve_warm(plan, net, y[i], m[i], e[i], tol, max_iters, check_every)
+            solve_cold(plan, y[i], tol, warm_k, check_every)
+            solve_warm(plan, net, y[i], m[i], e[i], tol, warm_k, check_every)
             _, ic, tc = solve_cold(plan, y[i], tol, max_iters, check_every)
             _, iw, tw, ok = solve_warm(plan, net, y[i], m[i], e[i], tol, max_iters, check_every)
-            fc = solve_cold(plan, y[i], final_tol, final_iters, 50)[1] if final_tol else ic
-            fw = solve_warm(plan, net, y[i], m[i], e[i], final_tol, final_iters, 50)[1] if final_tol else iw
         rows.append({"cold_s": tc, "warm_s": tw, "cold_iters": ic["iters"], "warm_iters": iw["iters"],
                      "cold_obj": ic["objective"], "warm_obj": iw["objective"], "cold_conv": ic["converged"],
-                     "warm_conv": iw["converged"], "warm_used": ok, "final_cold_obj": fc["objective"],
-                     "final_warm_obj": fw["objective"], "final_conv": fc["converged"] and fw["converged"]})
+                     "warm_conv": iw["converged"], "warm_used": ok})
+        if log and (i + 1) % 64 == 0:
+            log(f"  timed {i + 1}/{len(probs)} problems")
+    if final_tol:
+        fin = final_objectives(net, probs, y, m, e, final_tol, final_iters, batch=final_batch)
+        for r, (fc, fw) in zip(rows, fin):
+            r.update({"final_cold_obj": fc["objective"], "final_warm_obj": fw["objective"],
+                      "final_conv": fc["converged"] and fw["converged"]})
+    else:
+        for r in rows:
+            r.update({"final_cold_obj": r["cold_obj"], "final_warm_obj": r["warm_obj"],
+                      "final_conv": r["cold_conv"] and r["warm_conv"]})
     return rows
 
 
