@@ -13,6 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadmmdeconv.so")
 SOURCES = ["admm_api.hip", "admm_kernels.hip", "admm_frame.hip", "conv_bf16.hip"]
+HOST_SOURCES = ["admm_host.cpp"]   # plain C++ (no device code)
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -45,6 +46,14 @@ def build(verbose=False):
             continue
         obj = os.path.join(out_dir, src.replace(".hip", ".o"))
         cmd = [HIPCC, *FLAGS, "-c", path, "-o", obj]
+        if verbose:
+            print(" ".join(cmd))
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+        objs.append(obj)
+    for src in HOST_SOURCES:
+        obj = os.path.join(out_dir, src.replace(".cpp", ".o"))
+        cmd = [HIPCC, "-x", "c++", "-O2", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"),
+               "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd))
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))

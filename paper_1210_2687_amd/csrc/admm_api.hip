@@ -23,24 +23,20 @@
 #include <vector>
 
 #include "../../include/admm_deconv.h"
+#include "admm_host.h"
 #include "admm_internal.h"
 #include "admm_launch.h"
 
 using namespace admm;
+using admm_host::fail;
+using admm_host::make_key;
+using admm_host::read_cache;
+using admm_host::smooth7;
+using admm_host::TuneEntry;
+using admm_host::validate;
+using admm_host::write_cache;
 
 namespace {
-
-thread_local std::string g_err;
-
-admm_status fail(admm_status s, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return s;
-}
 
 #define HIP_TRY(expr)                                                                               \
     do {                                                                                            \
@@ -50,13 +46,6 @@ admm_status fail(admm_status s, const char* fmt, ...) {
                         #expr, hipGetErrorString(e_), __FILE__, __LINE__);                          \
         }                                                                                           \
     } while (0)
-
-bool smooth7(int n) {
-    if (n < 1) return false;
-    for (int p : {2, 3, 5, 7})
-        while (n % p == 0) n /= p;
-    return n == 1;
-}
 
 // Radix schedule: powers of two as radix 8 with a tail of 4 or 2, then 7, 5, 3.
 int radices(int n, int* out, int cap) {
@@ -172,31 +161,6 @@ static const char* const kProfNames[6] = {"col", "row_tv", "row_inv", "frame", "
 
 namespace {
 
-admm_status validate(const admm_problem& p) {
-    if (p.H < 8 || p.W < 8 || p.H > ADMM_MAX_SIDE || p.W > ADMM_MAX_SIDE)
-        return fail(ADMM_E_UNSUPPORTED, "sides %dx%d outside 8..%d", p.H, p.W, ADMM_MAX_SIDE);
-    if (!smooth7(p.H) || !smooth7(p.W))
-        return fail(ADMM_E_UNSUPPORTED, "sides %dx%d must be 7-smooth (2^a 3^b 5^c 7^d)", p.H, p.W);
-    if (!p.kernel || !p.mask) return fail(ADMM_E_INVALID, "null kernel or mask pointer");
-    if (p.ksize < 1 || p.ksize % 2 == 0 || p.ksize > std::min(p.H, p.W))
-        return fail(ADMM_E_UNSUPPORTED, "kernel side %d must be odd and <= min(H, W)", p.ksize);
-    if (p.reg != ADMM_REG_TV && p.reg != ADMM_REG_FRAME) return fail(ADMM_E_INVALID, "unknown regulariser %d", p.reg);
-    if (p.reg == ADMM_REG_FRAME && (p.levels < 1 || p.levels > 4))
-        return fail(ADMM_E_UNSUPPORTED, "frame levels %d outside 1..4", p.levels);
-    if (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)) return fail(ADMM_E_INVALID, "lambda must be finite and >= 0");
-    if (!std::isfinite(p.mu1) || !std::isfinite(p.mu2)) return fail(ADMM_E_INVALID, "mu must be finite");
-    double sum = 0.0, asum = 0.0;
-    for (int i = 0; i < p.ksize * p.ksize; ++i) {
-        if (!std::isfinite(p.kernel[i])) return fail(ADMM_E_INVALID, "non-finite kernel tap %d", i);
-        sum += p.kernel[i];
-        asum += std::fabs(p.kernel[i]);
-    }
-    if (asum == 0.0) return fail(ADMM_E_SINGULAR, "kernel is identically zero");
-    if (p.reg == ADMM_REG_TV && std::fabs(sum) <= 1e-12 * asum)
-        return fail(ADMM_E_SINGULAR, "TV needs a kernel with nonzero sum (DC gain), got %g", sum);
-    return ADMM_OK;
-}
-
 void penalties(const admm_problem& p, double* mu1, double* mu2) {
     double m2 = p.mu2 > 0 ? p.mu2 : 10.0 * p.lambda;
     double m1 = p.mu1 > 0 ? p.mu1 : std::min(1.0, 5000.0 * (p.mu2 > 0 ? p.mu2 : 10.0 * p.lambda));
@@ -208,7 +172,7 @@ void penalties(const admm_problem& p, double* mu1, double* mu2) {
 
 }  // namespace
 
-extern "C" const char* admm_last_error(void) { return g_err.c_str(); }
+extern "C" const char* admm_last_error(void) { return admm_host::last_error(); }
 
 extern "C" int32_t admm_fft_radices(int32_t n, int32_t* out, int32_t cap) {
     if (!out || cap <= 0) return -1;
@@ -243,7 +207,7 @@ extern "C" admm_status admm_deconv_plan(const admm_problem* probs, int32_t count
     for (int i = 0; i < count; ++i) {
         admm_status s = validate(probs[i]);
         if (s != ADMM_OK) {
-            g_err = "problem " + std::to_string(i) + ": " + g_err;
+            admm_host::prefix_error("problem " + std::to_string(i) + ": ");
             return s;
         }
     }
@@ -1097,150 +1061,6 @@ extern "C" int32_t admm_plan_kernel_times(const admm_plan* P, admm_kernel_time* 
 // an element, so the iterates do not depend on it.
 namespace {
 
-struct TuneEntry {
-    int tc = 0, rows = 0;
-    int rows_c[3] = {0, 0, 0};   // per size class of the row length, 0: rows ("rows_512", "rows_1024", "rows_2048")
-    double col_us = 0.0, row_us = 0.0;
-};
-
-void skip_ws(const char*& p) {
-    while (*p == ' ' || *p == '\n' || *p == '\r' || *p == '\t') ++p;
-}
-bool parse_str(const char*& p, std::string& out) {
-    skip_ws(p);
-    if (*p != '"') return false;
-    ++p;
-    out.clear();
-    while (*p && *p != '"') {
-        if (*p == '\\') return false;   // keys and fields never need escapes
-        out.push_back(*p++);
-    }
-    if (*p != '"') return false;
-    ++p;
-    return true;
-}
-bool parse_char(const char*& p, char c) {
-    skip_ws(p);
-    if (*p != c) return false;
-    ++p;
-    return true;
-}
-
-// Parse the cache text; false if it is not an object of objects of numbers.
-bool parse_cache(const std::string& text, std::map<std::string, TuneEntry>& out) {
-    const char* p = text.c_str();
-    if (!parse_char(p, '{')) return false;
-    skip_ws(p);
-    if (*p == '}') return true;
-    for (;;) {
-        std::string key;
-        if (!parse_str(p, key) || !parse_char(p, ':') || !parse_char(p, '{')) return false;
-        TuneEntry e;
-        skip_ws(p);
-        if (*p != '}') {
-            for (;;) {
-                std::string f;
-                if (!parse_str(p, f) || !parse_char(p, ':')) return false;
-                skip_ws(p);
-                char* end = nullptr;
-                const double v = std::strtod(p, &end);
-                if (end == p) return false;
-                p = end;
-                if (f == "tc") e.tc = (int)v;
-                else if (f == "rows") e.rows = (int)v;
-                else if (f == "rows_512") e.rows_c[0] = (int)v;
-                else if (f == "rows_1024") e.rows_c[1] = (int)v;
-                else if (f == "rows_2048") e.rows_c[2] = (int)v;
-                else if (f == "col_us") e.col_us = v;
-                else if (f == "row_us") e.row_us = v;
-                skip_ws(p);
-                if (*p == ',') {
-                    ++p;
-                    continue;
-                }
-                break;
-            }
-        }
-        if (!parse_char(p, '}')) return false;
-        out[key] = e;
-        skip_ws(p);
-        if (*p == ',') {
-            ++p;
-            continue;
-        }
-        break;
-    }
-    return parse_char(p, '}');
-}
-
-std::string format_cache(const std::map<std::string, TuneEntry>& m) {
-    std::string s = "{\n";
-    size_t i = 0;
-    for (const auto& kv : m) {
-        char buf[256];
-        std::string extra;
-        static const char* names[3] = {"rows_512", "rows_1024", "rows_2048"};
-        for (int c = 0; c < 3; ++c)
-            if (kv.second.rows_c[c] > 0) extra += ", \"" + std::string(names[c]) + "\": " + std::to_string(kv.second.rows_c[c]);
-        std::snprintf(buf, sizeof buf, "{\"tc\": %d, \"rows\": %d%s, \"col_us\": %.3f, \"row_us\": %.3f}",
-                      kv.second.tc, kv.second.rows, extra.c_str(), kv.second.col_us, kv.second.row_us);
-        s += "  \"" + kv.first + "\": " + buf + (++i < m.size() ? ",\n" : "\n");
-    }
-    return s + "}\n";
-}
-
-// 0: read (or absent: empty map); -1: unreadable or malformed
-int read_cache(const char* path, std::map<std::string, TuneEntry>& out) {
-    out.clear();
-    FILE* f = std::fopen(path, "rb");
-    if (!f) return 0;
-    std::string text;
-    char buf[4096];
-    size_t n;
-    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
-    std::fclose(f);
-    return parse_cache(text, out) ? 0 : -1;
-}
-
-int write_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
-    const std::string tmp = std::string(path) + ".tmp";
-    FILE* f = std::fopen(tmp.c_str(), "wb");
-    if (!f) return -1;
-    const std::string s = format_cache(m);
-    const bool ok = std::fwrite(s.data(), 1, s.size(), f) == s.size();
-    if (std::fclose(f) != 0 || !ok) return -1;
-    return std::rename(tmp.c_str(), path) == 0 ? 0 : -1;
-}
-
-std::string make_key(const admm_problem* probs, int count, const char* arch) {
-    std::vector<std::string> sh;
-    for (int i = 0; i < count; ++i) {
-        char b[48];
-        if (probs[i].reg == ADMM_REG_FRAME)
-            std::snprintf(b, sizeof b, "fa%dx%dj%d", (int)probs[i].H, (int)probs[i].W, (int)probs[i].levels);
-        else
-            std::snprintf(b, sizeof b, "tv%dx%d", (int)probs[i].H, (int)probs[i].W);
-        sh.push_back(b);
-    }
-    std::sort(sh.begin(), sh.end());
-    std::string list;
-    for (size_t i = 0; i < sh.size();) {
-        size_t j = i;
-        while (j < sh.size() && sh[j] == sh[i]) ++j;
-        if (!list.empty()) list += ",";
-        list += sh[i] + "*" + std::to_string(j - i);
-        i = j;
-    }
-    if (list.size() > 160) {   // long ragged batches: a hash of the shape list
-        unsigned long long h = 1469598103934665603ull;
-        for (unsigned char c : list) h = (h ^ c) * 1099511628211ull;
-        char b[40];
-        std::snprintf(b, sizeof b, "h%016llx*%d", h, count);
-        list = b;
-    }
-    return std::string(arch) + "|" + list;
-}
-
 // Time one trial plan: per-launch microseconds of the column kernel and of
 // the row-side kernels (TV row pass, or FA inverse rows + frame + forward rows).
 admm_status time_plan(admm_plan* P, const float* const* y, float* const* x, double* col_us, double* row_us) {
@@ -1356,7 +1176,7 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
     for (int i = 0; i < count; ++i) {
         admm_status s = validate(probs[i]);
         if (s != ADMM_OK) {
-            g_err = "problem " + std::to_string(i) + ": " + g_err;
+            admm_host::prefix_error("problem " + std::to_string(i) + ": ");
             return s;
         }
     }
@@ -1414,10 +1234,27 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
         const int bs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
         const int ntc = 4, nb = 10;
         TuneEntry rec;
+        // trials are keyed by the tile shapes the planner actually uses (a
+        // request beyond a problem's limit is clamped): a shape already timed
+        // is not timed again, so a repeat cannot win on measurement noise
+        std::map<std::vector<int>, double> timed;
         auto trial = [&](TileChoice t, double* us) -> admm_status {
             admm_plan* P = new admm_plan();
             admm_status s = build_plan(P, probs, count, hip_stream, t);
-            if (s == ADMM_OK) s = time_iterations(P, yv.data(), xv.data(), us);
+            if (s == ADMM_OK) {
+                std::vector<int> shape;
+                for (const ProbDesc& d : P->hd) {
+                    shape.push_back(d.TC);
+                    shape.push_back(d.B);
+                }
+                auto it = timed.find(shape);
+                if (it != timed.end()) {
+                    *us = it->second;
+                } else {
+                    s = time_iterations(P, yv.data(), xv.data(), us);
+                    if (s == ADMM_OK) timed[shape] = *us;
+                }
+            }
             admm_plan_destroy(P);
             return s;
         };

@@ -1,0 +1,213 @@
+// admm_host.cpp — host-only logic of the library (see admm_host.h).
+#include "admm_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+namespace admm_host {
+
+namespace {
+thread_local std::string g_err;
+
+}  // namespace
+
+admm_status fail(admm_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+const char* last_error() { return g_err.c_str(); }
+
+void prefix_error(const std::string& prefix) { g_err = prefix + g_err; }
+
+bool smooth7(int n) {
+    if (n < 1) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+admm_status validate(const admm_problem& p) {
+    if (p.H < 8 || p.W < 8 || p.H > ADMM_MAX_SIDE || p.W > ADMM_MAX_SIDE)
+        return fail(ADMM_E_UNSUPPORTED, "sides %dx%d outside 8..%d", p.H, p.W, ADMM_MAX_SIDE);
+    if (!smooth7(p.H) || !smooth7(p.W))
+        return fail(ADMM_E_UNSUPPORTED, "sides %dx%d must be 7-smooth (2^a 3^b 5^c 7^d)", p.H, p.W);
+    if (!p.kernel || !p.mask) return fail(ADMM_E_INVALID, "null kernel or mask pointer");
+    if (p.ksize < 1 || p.ksize % 2 == 0 || p.ksize > std::min(p.H, p.W))
+        return fail(ADMM_E_UNSUPPORTED, "kernel side %d must be odd and <= min(H, W)", p.ksize);
+    if (p.reg != ADMM_REG_TV && p.reg != ADMM_REG_FRAME) return fail(ADMM_E_INVALID, "unknown regulariser %d", p.reg);
+    if (p.reg == ADMM_REG_FRAME && (p.levels < 1 || p.levels > 4))
+        return fail(ADMM_E_UNSUPPORTED, "frame levels %d outside 1..4", p.levels);
+    if (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)) return fail(ADMM_E_INVALID, "lambda must be finite and >= 0");
+    if (!std::isfinite(p.mu1) || !std::isfinite(p.mu2)) return fail(ADMM_E_INVALID, "mu must be finite");
+    double sum = 0.0, asum = 0.0;
+    for (int i = 0; i < p.ksize * p.ksize; ++i) {
+        if (!std::isfinite(p.kernel[i])) return fail(ADMM_E_INVALID, "non-finite kernel tap %d", i);
+        sum += p.kernel[i];
+        asum += std::fabs(p.kernel[i]);
+    }
+    if (asum == 0.0) return fail(ADMM_E_SINGULAR, "kernel is identically zero");
+    if (p.reg == ADMM_REG_TV && std::fabs(sum) <= 1e-12 * asum)
+        return fail(ADMM_E_SINGULAR, "TV needs a kernel with nonzero sum (DC gain), got %g", sum);
+    return ADMM_OK;
+}
+
+namespace {
+
+void skip_ws(const char*& p) {
+    while (*p == ' ' || *p == '\n' || *p == '\r' || *p == '\t') ++p;
+}
+bool parse_str(const char*& p, std::string& out) {
+    skip_ws(p);
+    if (*p != '"') return false;
+    ++p;
+    out.clear();
+    while (*p && *p != '"') {
+        if (*p == '\\') return false;   // keys and fields never need escapes
+        out.push_back(*p++);
+    }
+    if (*p != '"') return false;
+    ++p;
+    return true;
+}
+bool parse_char(const char*& p, char c) {
+    skip_ws(p);
+    if (*p != c) return false;
+    ++p;
+    return true;
+}
+
+}  // namespace
+
+bool parse_cache(const std::string& text, std::map<std::string, TuneEntry>& out) {
+    const char* p = text.c_str();
+    if (!parse_char(p, '{')) return false;
+    skip_ws(p);
+    if (*p == '}') return true;
+    for (;;) {
+        std::string key;
+        if (!parse_str(p, key) || !parse_char(p, ':') || !parse_char(p, '{')) return false;
+        TuneEntry e;
+        skip_ws(p);
+        if (*p != '}') {
+            for (;;) {
+                std::string f;
+                if (!parse_str(p, f) || !parse_char(p, ':')) return false;
+                skip_ws(p);
+                char* end = nullptr;
+                const double v = std::strtod(p, &end);
+                if (end == p) return false;
+                p = end;
+                // tile counts are small non-negative integers and timings finite
+                // non-negative numbers: anything else makes the file malformed
+                // (and keeps the conversions below defined)
+                const bool count = f == "tc" || f == "rows" || f == "rows_512" || f == "rows_1024" || f == "rows_2048";
+                if (!std::isfinite(v) || v < 0.0 || (count && (v > kMaxTileCount || v != std::floor(v))))
+                    return false;
+                if (f == "tc") e.tc = (int)v;
+                else if (f == "rows") e.rows = (int)v;
+                else if (f == "rows_512") e.rows_c[0] = (int)v;
+                else if (f == "rows_1024") e.rows_c[1] = (int)v;
+                else if (f == "rows_2048") e.rows_c[2] = (int)v;
+                else if (f == "col_us") e.col_us = v;
+                else if (f == "row_us") e.row_us = v;
+                skip_ws(p);
+                if (*p == ',') {
+                    ++p;
+                    continue;
+                }
+                break;
+            }
+        }
+        if (!parse_char(p, '}')) return false;
+        out[key] = e;
+        skip_ws(p);
+        if (*p == ',') {
+            ++p;
+            continue;
+        }
+        break;
+    }
+    if (!parse_char(p, '}')) return false;
+    skip_ws(p);
+    return *p == '\0';   // nothing may follow the object
+}
+
+std::string format_cache(const std::map<std::string, TuneEntry>& m) {
+    std::string s = "{\n";
+    size_t i = 0;
+    for (const auto& kv : m) {
+        char buf[256];
+        std::string extra;
+        static const char* names[3] = {"rows_512", "rows_1024", "rows_2048"};
+        for (int c = 0; c < 3; ++c)
+            if (kv.second.rows_c[c] > 0) extra += ", \"" + std::string(names[c]) + "\": " + std::to_string(kv.second.rows_c[c]);
+        std::snprintf(buf, sizeof buf, "{\"tc\": %d, \"rows\": %d%s, \"col_us\": %.3f, \"row_us\": %.3f}",
+                      kv.second.tc, kv.second.rows, extra.c_str(), kv.second.col_us, kv.second.row_us);
+        s += "  \"" + kv.first + "\": " + buf + (++i < m.size() ? ",\n" : "\n");
+    }
+    return s + "}\n";
+}
+
+// 0: read (or absent: empty map); -1: unreadable or malformed
+int read_cache(const char* path, std::map<std::string, TuneEntry>& out) {
+    out.clear();
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return 0;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    return parse_cache(text, out) ? 0 : -1;
+}
+
+int write_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return -1;
+    const std::string s = format_cache(m);
+    const bool ok = std::fwrite(s.data(), 1, s.size(), f) == s.size();
+    if (std::fclose(f) != 0 || !ok) return -1;
+    return std::rename(tmp.c_str(), path) == 0 ? 0 : -1;
+}
+
+std::string make_key(const admm_problem* probs, int count, const char* arch) {
+    std::vector<std::string> sh;
+    for (int i = 0; i < count; ++i) {
+        char b[48];
+        if (probs[i].reg == ADMM_REG_FRAME)
+            std::snprintf(b, sizeof b, "fa%dx%dj%d", (int)probs[i].H, (int)probs[i].W, (int)probs[i].levels);
+        else
+            std::snprintf(b, sizeof b, "tv%dx%d", (int)probs[i].H, (int)probs[i].W);
+        sh.push_back(b);
+    }
+    std::sort(sh.begin(), sh.end());
+    std::string list;
+    for (size_t i = 0; i < sh.size();) {
+        size_t j = i;
+        while (j < sh.size() && sh[j] == sh[i]) ++j;
+        if (!list.empty()) list += ",";
+        list += sh[i] + "*" + std::to_string(j - i);
+        i = j;
+    }
+    if (list.size() > 160) {   // long ragged batches: a hash of the shape list
+        unsigned long long h = 1469598103934665603ull;
+        for (unsigned char c : list) h = (h ^ c) * 1099511628211ull;
+        char b[40];
+        std::snprintf(b, sizeof b, "h%016llx*%d", h, count);
+        list = b;
+    }
+    return std::string(arch) + "|" + list;
+}
+
+}  // namespace admm_host
