@@ -220,6 +220,33 @@ admm_status admm_plan_time_pass(admm_plan* plan, const char* kernel, int32_t rep
 admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t count, void* hip_stream,
                                    const char* cache_path, admm_plan** out);
 
+/* Explicit tile shapes and radix schedules (what the autotuner chooses), for
+ * callers that measured their own or reproduce a cached choice.
+ * cols_per_block: 1..4 columns per column-pass block, 0 = planner's choice;
+ * rows_per_block: rows per row-pass block, 0 = planner's choice (both are
+ *   clamped to what a problem's lengths allow);
+ * row_schedule: radix schedule variant of the row transforms, 0..3;
+ * col_schedule: variant of the column transforms, 0..2 (see
+ *   admm_fft_schedule). A variant that gives a length the same schedule as
+ *   variant 0 is variant 0 for that length.
+ * Schedules change the rounding of the transforms, never what they compute. */
+typedef struct {
+    int32_t cols_per_block;
+    int32_t rows_per_block;
+    int32_t row_schedule;
+    int32_t col_schedule;
+} admm_tiles;
+
+/* Like admm_deconv_plan, with the tile shapes and schedules of `tiles` (HOST).
+ * Errors: as admm_deconv_plan, and ADMM_E_INVALID for values out of range.    */
+admm_status admm_deconv_plan_with(const admm_problem* probs, int32_t count, void* hip_stream,
+                                  const admm_tiles* tiles, admm_plan** out);
+
+/* Radix schedule variants a plan uses for problem `index` (row and column
+ * transforms; 0 is admm_fft_radices' schedule).                               */
+admm_status admm_plan_schedules(const admm_plan* plan, int32_t index, int32_t* row_schedule,
+                                int32_t* col_schedule);
+
 /* Cache key of a batch: "<arch>|<shape multiset>", e.g. "gfx950|tv512x512*8"
  * (a hash of the shape list for long ragged batches). Writes at most cap bytes
  * (NUL-terminated) to out (HOST) and returns the key length, -1 on bad input. */
@@ -229,8 +256,9 @@ int32_t admm_tune_key(const admm_problem* probs, int32_t count, const char* arch
  * `key` is present, 0 if absent (or no file), -1 if the file is malformed;
  * store inserts or replaces an entry (tc, rows >= 1; timings in microseconds).
  * Entries the autotuner writes may also hold per-class row counts
- * ("rows_512", "rows_1024", "rows_2048"), which lookup does not report and
- * store does not write.                                                        */
+ * ("rows_512", "rows_1024", "rows_2048") and radix schedule variants
+ * ("rsched", "csched"), which lookup does not report and store does not
+ * write.                                                        */
 int32_t admm_tune_cache_lookup(const char* path, const char* key, int32_t* tc, int32_t* rows);
 admm_status admm_tune_cache_store(const char* path, const char* key, int32_t tc, int32_t rows, double col_us,
                                   double row_us);
@@ -250,6 +278,14 @@ const char* admm_last_error(void);
  * writes up to `cap` radices to out and returns their count, or -1 if n is not
  * a supported 7-smooth length.                                                 */
 int32_t admm_fft_radices(int32_t n, int32_t* out, int32_t cap);
+
+/* admm_fft_schedule: the radix schedule of variant `variant` for length n
+ * (the autotuner's radix dimension), in stage order: 0 = admm_fft_radices;
+ * 1 = powers of two as radix 4 (one 2 for an odd exponent), then 7, 5, 3;
+ * 2 = the odd radices first, then radix 8 with a 4 or 2 tail; 3 = powers of
+ * two as radix 16 with one 8, 4 or 2, then 7, 5, 3 (row transforms only).
+ * Returns the stage count, or -1 for an unsupported length or variant.      */
+int32_t admm_fft_schedule(int32_t n, int32_t variant, int32_t* out, int32_t cap);
 
 /* admm_validate_problem: the plan-time checks for one problem, no allocation. */
 admm_status admm_validate_problem(const admm_problem* prob);

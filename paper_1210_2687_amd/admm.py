@@ -20,7 +20,8 @@ __all__ = [
     "AdmmError", "lib", "lib_path", "exported_symbols",
     "admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
     "admm_deconv_solve_static", "admm_warmstart_map", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
-    "admm_validate_problem", "Plan", "make_problem", "alloc_state",
+    "admm_validate_problem", "admm_fft_schedule", "admm_deconv_plan_with", "admm_plan_schedules",
+    "Plan", "make_problem", "alloc_state",
 ]
 
 ADMM_OK, ADMM_E_INVALID, ADMM_E_UNSUPPORTED, ADMM_E_SINGULAR, ADMM_E_NOMEM, ADMM_E_DEVICE, ADMM_E_DIVERGED = range(7)
@@ -58,6 +59,11 @@ class admm_info(ctypes.Structure):
 
 class admm_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 16), ("launches", c_int32), ("reserved", c_int32), ("total_ms", c_double)]
+
+
+class admm_tiles(ctypes.Structure):
+    _fields_ = [("cols_per_block", c_int32), ("rows_per_block", c_int32), ("row_schedule", c_int32),
+                ("col_schedule", c_int32)]
 
 
 class admm_state(ctypes.Structure):
@@ -111,6 +117,10 @@ def lib():
         L.admm_tune_cache_lookup.restype = c_int32
         L.admm_tune_cache_store.argtypes = [c_char_p, c_char_p, c_int32, c_int32, c_double, c_double]
         L.admm_plan_tiles.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]
+        L.admm_plan_schedules.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]
+        L.admm_deconv_plan_with.argtypes = [POINTER(admm_problem), c_int32, c_void_p, POINTER(admm_tiles),
+                                            POINTER(c_void_p)]
+        L.admm_fft_schedule.argtypes = [c_int32, c_int32, POINTER(c_int32), c_int32]
         L.admm_plan_time_pass.argtypes = [c_void_p, c_char_p, c_int32, POINTER(c_double)]
         vp = c_void_p
         L.admm_conv3x3_pack_weights.argtypes = [vp, c_int32, c_int32, vp, vp, vp]
@@ -125,6 +135,7 @@ def lib():
         L.admm_ws_loss.argtypes = [vp, vp, vp, vp, vp, c_int32, c_int32, c_int32, c_float, vp, vp, vp]
         L.admm_ws_output.argtypes = [vp, vp, vp, c_int32, c_int32, c_int32, vp, vp, vp]
         for f in ("admm_deconv_plan", "admm_deconv_plan_tuned", "admm_tune_cache_store", "admm_plan_tiles",
+                  "admm_plan_schedules", "admm_deconv_plan_with", "admm_fft_schedule",
                   "admm_plan_time_pass",
                   "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur", "admm_deconv_solve_static",
                   "admm_warmstart_map", "admm_warmstart_dual", "admm_fft_radices", "admm_validate_problem",
@@ -142,6 +153,7 @@ def exported_symbols():
             "admm_warmstart_map", "admm_warmstart_dual", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
             "admm_validate_problem", "admm_plan_kernel_times", "admm_deconv_plan_tuned", "admm_tune_key",
             "admm_tune_cache_lookup", "admm_tune_cache_store", "admm_plan_tiles", "admm_plan_time_pass",
+            "admm_deconv_plan_with", "admm_plan_schedules", "admm_fft_schedule",
             "admm_conv3x3_pack_weights", "admm_conv3x3_bf16_fwd", "admm_conv3x3_bf16_wgrad_workspace",
             "admm_conv3x3_bf16_wgrad", "admm_adam_step", "admm_ws_input", "admm_ws_loss", "admm_ws_output"]
 
@@ -177,6 +189,12 @@ def make_problem(kernel, mask, lam, mu1=-1.0, mu2=-1.0, reg=ADMM_REG_TV, levels=
     return p
 
 
+def admm_fft_schedule(n, variant):
+    buf = (c_int32 * 16)()
+    k = lib().admm_fft_schedule(n, variant, buf, 16)
+    return None if k < 0 else list(buf[:k])
+
+
 def admm_validate_problem(prob):
     return lib().admm_validate_problem(ctypes.byref(prob))
 
@@ -203,6 +221,22 @@ def admm_deconv_plan_tuned(problems, stream=None, cache_path=None):
     cp = None if cache_path is None else os.fsencode(cache_path)
     _check(lib().admm_deconv_plan_tuned(arr, len(problems), _stream_ptr(stream), cp, ctypes.byref(out)))
     return out
+
+
+def admm_deconv_plan_with(problems, cols_per_block=0, rows_per_block=0, row_schedule=0, col_schedule=0,
+                          stream=None):
+    """Plan with explicit tile shapes and radix schedule variants."""
+    arr = (admm_problem * len(problems))(*problems)
+    t = admm_tiles(int(cols_per_block), int(rows_per_block), int(row_schedule), int(col_schedule))
+    out = c_void_p()
+    _check(lib().admm_deconv_plan_with(arr, len(problems), _stream_ptr(stream), ctypes.byref(t), ctypes.byref(out)))
+    return out
+
+
+def admm_plan_schedules(plan, index):
+    r, c = c_int32(), c_int32()
+    _check(lib().admm_plan_schedules(plan, index, ctypes.byref(r), ctypes.byref(c)))
+    return r.value, c.value
 
 
 def admm_tune_key(problems, arch):
@@ -393,14 +427,16 @@ def alloc_state(H, W, nreg=2, device="cuda"):
 class Plan:
     """Convenience owner of a plan handle built from ``workloads.Problem``-like objects."""
 
-    def __init__(self, problems, stream=None, tune=False, cache_path=None):
+    def __init__(self, problems, stream=None, tune=False, cache_path=None, tiles=None):
         self.problems = list(problems)
         self._cprobs = []
         for p in self.problems:
             reg = ADMM_REG_FRAME if getattr(p, "reg", "tv") == "frame" else ADMM_REG_TV
             self._cprobs.append(make_problem(p.kernel, p.mask, p.lam, p.mu1, p.mu2, reg, getattr(p, "levels", 0)))
         self.nregs = [3 * p.levels + 1 if getattr(p, "reg", "tv") == "frame" else 2 for p in self.problems]
-        if tune:
+        if tiles is not None:
+            self.handle = admm_deconv_plan_with(self._cprobs, stream=stream, **tiles)
+        elif tune:
             self.handle = admm_deconv_plan_tuned(self._cprobs, stream, cache_path)
         else:
             self.handle = admm_deconv_plan(self._cprobs, stream)
@@ -419,6 +455,9 @@ class Plan:
 
     def tiles(self, index=0):
         return admm_plan_tiles(self.handle, index)
+
+    def schedules(self, index=0):
+        return admm_plan_schedules(self.handle, index)
 
     def time_pass(self, kernel, reps=50):
         return admm_plan_time_pass(self.handle, kernel, reps)

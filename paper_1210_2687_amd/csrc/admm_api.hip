@@ -47,10 +47,25 @@ namespace {
         }                                                                                           \
     } while (0)
 
-// Radix schedule: powers of two as radix 8 with a tail of 4 or 2, then 7, 5, 3.
-int radices(int n, int* out, int cap) {
+// Radix schedule: powers of two as radix 8 with a tail of 4 or 2, then 7, 5, 3
+// (variant 0), or one of the alternatives of fft_schedule_variant.
+int radices(int n, int* out, int cap, int variant = 0) {
     if (!smooth7(n)) return -1;
-    return fft_schedule(n, out, cap);
+    return fft_schedule_variant(n, variant, out, cap);
+}
+
+// The variant a plan uses for a length-n transform: the requested one, unless
+// it gives the same schedule as variant 0 or none at all (then 0, whose
+// compile-time transforms serve the common lengths); radix 16 only in the row
+// passes (wave-level column stages hold at most 8 operands per butterfly).
+int effective_variant(int n, int variant, bool column) {
+    if (variant <= 0 || variant >= FFT_VARIANTS || (column && variant == 3)) return 0;
+    int a[ADMM_MAX_STAGES] = {}, b[ADMM_MAX_STAGES] = {};
+    const int na = radices(n, a, ADMM_MAX_STAGES, variant);
+    const int nb = radices(n, b, ADMM_MAX_STAGES, 0);
+    if (na < 1) return 0;
+    if (na == nb && std::equal(a, a + na, b)) return 0;
+    return variant;
 }
 
 // Does a block of NT threads with MAXE registers per thread fit `ntrans`
@@ -69,10 +84,11 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // tw_off: the length's slot in the table arrays (2 N entries: the natural
 // twiddles exp(-2 pi i k / N), then the stage table)
-void fill_plan(FftPlanDev& f, int N, int tw_off) {
+void fill_plan(FftPlanDev& f, int N, int tw_off, int variant) {
     f.N = N;
     f.tw_off = tw_off;
-    f.nst = radices(N, f.rad, ADMM_MAX_STAGES);
+    f.variant = variant;
+    f.nst = radices(N, f.rad, ADMM_MAX_STAGES, variant);
     f.ends8 = f.nst >= 1 && f.rad[0] == 8 && f.rad[f.nst - 1] == 8;
     int Ns = 1, off = 0;
     for (int s = 0; s < f.nst; ++s) {
@@ -87,10 +103,11 @@ void fill_plan(FftPlanDev& f, int N, int tw_off) {
     }
 }
 
-// The stage table of length N (N - 1 entries), in double then rounded once.
-void stage_twiddles(int N, float2* out) {
+// The stage table of length N (N - 1 entries) for a schedule variant, in
+// double then rounded once.
+void stage_twiddles(int N, int variant, float2* out) {
     int rad[ADMM_MAX_STAGES] = {};
-    const int nst = radices(N, rad, ADMM_MAX_STAGES);
+    const int nst = radices(N, rad, ADMM_MAX_STAGES, variant);
     int Ns = 1, off = 0;
     for (int s = 0; s < nst; ++s) {
         const int R = rad[s];
@@ -111,6 +128,7 @@ void stage_twiddles(int N, float2* out) {
 struct TileChoice {
     int tc = 0, b = 0;
     int bc[3] = {0, 0, 0};   // rows per row block by size class of the row length (0: use b)
+    int rsched = 0, csched = 0;   // radix schedule variants of the row and column transforms
 };
 
 constexpr int kPeriodsInFlight = 2;      // period graphs queued ahead of the host's stop test
@@ -179,6 +197,11 @@ extern "C" int32_t admm_fft_radices(int32_t n, int32_t* out, int32_t cap) {
     return radices(n, out, cap);
 }
 
+extern "C" int32_t admm_fft_schedule(int32_t n, int32_t variant, int32_t* out, int32_t cap) {
+    if (!out || cap <= 0) return -1;
+    return radices(n, out, cap, variant);
+}
+
 extern "C" admm_status admm_validate_problem(const admm_problem* prob) {
     if (!prob) return fail(ADMM_E_INVALID, "null problem");
     return validate(*prob);
@@ -224,6 +247,38 @@ extern "C" admm_status admm_deconv_plan(const admm_problem* probs, int32_t count
 // ext_arena (device memory of ext_cap bytes, not owned) replaces the plan's
 // own allocation; the plan then allocates nothing on the device or pinned in
 // host memory.
+extern "C" admm_status admm_deconv_plan_with(const admm_problem* probs, int32_t count, void* hip_stream,
+                                             const admm_tiles* tiles, admm_plan** out) {
+    if (!out) return fail(ADMM_E_INVALID, "null output pointer");
+    *out = nullptr;
+    if (!probs || count < 1) return fail(ADMM_E_INVALID, "need at least one problem");
+    if (!tiles) return fail(ADMM_E_INVALID, "null tile description");
+    if (tiles->cols_per_block < 0 || tiles->rows_per_block < 0 || tiles->row_schedule < 0 ||
+        tiles->row_schedule >= FFT_VARIANTS || tiles->col_schedule < 0 || tiles->col_schedule >= FFT_VARIANTS - 1)
+        return fail(ADMM_E_INVALID, "tile counts must be >= 0, row schedule 0..%d, column schedule 0..%d",
+                    FFT_VARIANTS - 1, FFT_VARIANTS - 2);
+    for (int i = 0; i < count; ++i) {
+        admm_status s = validate(probs[i]);
+        if (s != ADMM_OK) {
+            admm_host::prefix_error("problem " + std::to_string(i) + ": ");
+            return s;
+        }
+    }
+    TileChoice t;
+    t.tc = tiles->cols_per_block;
+    t.b = tiles->rows_per_block;
+    t.rsched = tiles->row_schedule;
+    t.csched = tiles->col_schedule;
+    admm_plan* P = new admm_plan();
+    admm_status s = build_plan(P, probs, count, hip_stream, t);
+    if (s != ADMM_OK) {
+        admm_plan_destroy(P);
+        return s;
+    }
+    *out = P;
+    return ADMM_OK;
+}
+
 static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t count, void* hip_stream,
                               TileChoice tile, void* ext_arena, size_t ext_cap) {
     auto bail = [](admm_status s) { return s; };
@@ -245,15 +300,21 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     P->probs.assign(probs, probs + count);
     P->hd.resize(count);
 
-    // distinct transform lengths -> table offsets
-    std::map<int, int> tab_off;
+    // distinct (transform length, schedule variant) pairs -> table offsets
+    std::map<std::pair<int, int>, int> tab_off;
     int tab_len = 0;
-    for (int i = 0; i < count; ++i)
-        for (int N : {probs[i].H, probs[i].W})
-            if (!tab_off.count(N)) {
-                tab_off[N] = tab_len;
-                tab_len += 2 * N;
-            }
+    auto slot = [&](int N, int v) {
+        const auto key = std::make_pair(N, v);
+        if (!tab_off.count(key)) {
+            tab_off[key] = tab_len;
+            tab_len += 2 * N;
+        }
+        return tab_off[key];
+    };
+    for (int i = 0; i < count; ++i) {
+        slot(probs[i].W, effective_variant(probs[i].W, tile.rsched, false));
+        slot(probs[i].H, effective_variant(probs[i].H, tile.csched, true));
+    }
 
     // about two blocks per compute unit per pass (measured best on 8 x 512^2: TC = 4,
     // B = 8; on one 512^2 problem: TC = 1, B = 2)
@@ -279,8 +340,9 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         d.tau = (float)(q.lambda / mu2);
         d.inv_hw = (float)(1.0 / ((double)q.H * q.W));
         d.inv1pmu1 = (float)(1.0 / (1.0 + mu1));
-        fill_plan(d.fr, q.W, tab_off[q.W]);
-        fill_plan(d.fc, q.H, tab_off[q.H]);
+        const int rv = effective_variant(q.W, tile.rsched, false), cv = effective_variant(q.H, tile.csched, true);
+        fill_plan(d.fr, q.W, slot(q.W, rv), rv);
+        fill_plan(d.fc, q.H, slot(q.H, cv), cv);
         const int per = std::max(1, (target_blocks + count - 1) / count);
         // column tile: one column per wave of the column-pass block, as many as LDS holds
         int tcmax = 0;
@@ -514,14 +576,14 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         std::vector<float2> tw(tab_len);
         std::vector<float> s2(tab_len);
         for (auto& kv : tab_off) {
-            const int N = kv.first, b = kv.second;
+            const int N = kv.first.first, v = kv.first.second, b = kv.second;
             for (int k = 0; k < N; ++k) {
                 const double ang = 2.0 * M_PI * (double)k / (double)N;
                 tw[b + k] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
                 const double sn = std::sin(M_PI * (double)k / (double)N);
                 s2[b + k] = (float)(4.0 * sn * sn);
             }
-            stage_twiddles(N, tw.data() + b + N);
+            stage_twiddles(N, v, tw.data() + b + N);
         }
         HIP_TRY(hipMemcpy(P->d_tw, tw.data(), sizeof(float2) * tab_len, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(P->d_s2, s2.data(), sizeof(float) * tab_len, hipMemcpyHostToDevice));
@@ -1199,6 +1261,8 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
             best.tc = it->second.tc;
             best.b = it->second.rows;
             for (int c = 0; c < 3; ++c) best.bc[c] = it->second.rows_c[c];
+            best.rsched = it->second.rsched;
+            best.csched = it->second.csched;
             have = true;
         }
     }
@@ -1246,6 +1310,8 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
                 for (const ProbDesc& d : P->hd) {
                     shape.push_back(d.TC);
                     shape.push_back(d.B);
+                    shape.push_back(d.fr.variant);
+                    shape.push_back(d.fc.variant);
                 }
                 auto it = timed.find(shape);
                 if (it != timed.end()) {
@@ -1297,6 +1363,26 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
                 }
             }
         }
+        // radix schedules (the tile shape fixed): each alternative of the column
+        // transforms, then of the row transforms, kept on a clear gain. A
+        // schedule changes the rounding of the transforms, not what they
+        // compute (every variant is checked against the oracle by the tests).
+        if (best.tc >= 1 && best.b >= 1) {
+            for (int pass = 0; pass < 2 && st == ADMM_OK; ++pass) {
+                const int nv = pass == 0 ? FFT_VARIANTS - 1 : FFT_VARIANTS;   // no radix 16 in columns
+                for (int v = 1; v < nv && st == ADMM_OK; ++v) {
+                    TileChoice t = best;
+                    (pass == 0 ? t.csched : t.rsched) = v;
+                    double us = 0.0;
+                    const admm_status s = trial(t, &us);
+                    if (s == ADMM_OK && us < 0.995 * best_t) {
+                        best_t = us;
+                        best = t;
+                    }
+                    if (s == ADMM_E_DEVICE || s == ADMM_E_NOMEM) st = s;
+                }
+            }
+        }
         double best_c = 0.0, best_r = 0.0;   // per-pass figures of the choice, for the record
         if (st == ADMM_OK && best.tc >= 1 && best.b >= 1) {
             admm_plan* P = new admm_plan();
@@ -1313,6 +1399,8 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
         rec.tc = best.tc;
         rec.rows = best.b;
         for (int c = 0; c < 3; ++c) rec.rows_c[c] = best.bc[c];
+        rec.rsched = best.rsched;
+        rec.csched = best.csched;
         rec.col_us = best_c;
         rec.row_us = best_r;
         if (cache_path) {
@@ -1335,6 +1423,14 @@ extern "C" admm_status admm_plan_tiles(const admm_plan* P, int32_t index, int32_
     if (!P || index < 0 || index >= P->count) return fail(ADMM_E_INVALID, "bad plan or index");
     if (tc) *tc = P->hd[index].TC;
     if (rows) *rows = P->hd[index].B;
+    return ADMM_OK;
+}
+
+extern "C" admm_status admm_plan_schedules(const admm_plan* P, int32_t index, int32_t* row_schedule,
+                                           int32_t* col_schedule) {
+    if (!P || index < 0 || index >= P->count) return fail(ADMM_E_INVALID, "bad plan or index");
+    if (row_schedule) *row_schedule = P->hd[index].fr.variant;
+    if (col_schedule) *col_schedule = P->hd[index].fc.variant;
     return ADMM_OK;
 }
 

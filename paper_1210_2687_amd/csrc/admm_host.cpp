@@ -111,8 +111,12 @@ bool parse_cache(const std::string& text, std::map<std::string, TuneEntry>& out)
                 // non-negative numbers: anything else makes the file malformed
                 // (and keeps the conversions below defined)
                 const bool count = f == "tc" || f == "rows" || f == "rows_512" || f == "rows_1024" || f == "rows_2048";
-                if (!std::isfinite(v) || v < 0.0 || (count && (v > kMaxTileCount || v != std::floor(v))))
+                const bool sched = f == "rsched" || f == "csched";
+                if (!std::isfinite(v) || v < 0.0 || (count && (v > kMaxTileCount || v != std::floor(v))) ||
+                    (sched && (v >= kScheduleVariants || v != std::floor(v))))
                     return false;
+                if (f == "rsched") e.rsched = (int)v;
+                else if (f == "csched") e.csched = (int)v;
                 if (f == "tc") e.tc = (int)v;
                 else if (f == "rows") e.rows = (int)v;
                 else if (f == "rows_512") e.rows_c[0] = (int)v;
@@ -146,11 +150,13 @@ std::string format_cache(const std::map<std::string, TuneEntry>& m) {
     std::string s = "{\n";
     size_t i = 0;
     for (const auto& kv : m) {
-        char buf[256];
+        char buf[512];
         std::string extra;
         static const char* names[3] = {"rows_512", "rows_1024", "rows_2048"};
         for (int c = 0; c < 3; ++c)
             if (kv.second.rows_c[c] > 0) extra += ", \"" + std::string(names[c]) + "\": " + std::to_string(kv.second.rows_c[c]);
+        if (kv.second.rsched > 0) extra += ", \"rsched\": " + std::to_string(kv.second.rsched);
+        if (kv.second.csched > 0) extra += ", \"csched\": " + std::to_string(kv.second.csched);
         std::snprintf(buf, sizeof buf, "{\"tc\": %d, \"rows\": %d%s, \"col_us\": %.3f, \"row_us\": %.3f}",
                       kv.second.tc, kv.second.rows, extra.c_str(), kv.second.col_us, kv.second.row_us);
         s += "  \"" + kv.first + "\": " + buf + (++i < m.size() ? ",\n" : "\n");

@@ -28,14 +28,17 @@ bool smooth7(int n);
 admm_status validate(const admm_problem& p);
 
 // One cache entry: columns per column block, rows per row block (and per
-// size class of the row length: 0 = use rows) and the per-launch timings of
-// the choice, for the record.
+// size class of the row length: 0 = use rows), the radix schedule variants
+// ("rsched", "csched"; written when not 0) and the per-launch timings of the
+// choice, for the record.
 constexpr double kMaxTileCount = 4096.0;
 struct TuneEntry {
     int tc = 0, rows = 0;
     int rows_c[3] = {0, 0, 0};   // "rows_512", "rows_1024", "rows_2048"
+    int rsched = 0, csched = 0;  // radix schedule variants of the row and column transforms
     double col_us = 0.0, row_us = 0.0;
 };
+constexpr int kScheduleVariants = 4;
 
 // Parse the cache text; false if it is not an object of objects of numbers
 // with valid values.

@@ -80,6 +80,55 @@ __host__ __device__ constexpr int fft_schedule(int n, int* out, int cap) {
     return nst;
 }
 
+// Alternative radix schedules (the autotuner's radix dimension). Variant 0 is
+// fft_schedule; the others reorder or regroup the same factorisation:
+//   1  powers of two as radix 4 (one radix 2 for an odd exponent), then 7, 5, 3;
+//   2  the odd radices first, then radix 8 with a 4 or 2 tail;
+//   3  powers of two as radix 16 with one 8, 4 or 2 for the rest, then 7, 5, 3
+//      (block-level row transforms only: a wave-level column stage does not
+//      hold 16 operands per butterfly).
+// Returns the number of stages written to out, or -1 (not 7-smooth, too many
+// stages, unknown variant).
+constexpr int FFT_VARIANTS = 4;
+__host__ __device__ constexpr int fft_schedule_variant(int n, int variant, int* out, int cap) {
+    if (variant == 0) return fft_schedule(n, out, cap);
+    if (n < 2 || variant < 0 || variant >= FFT_VARIANTS) return -1;
+    int a = 0;
+    while (n % 2 == 0) {
+        n /= 2;
+        ++a;
+    }
+    int odd[40] = {};
+    int no = 0;
+    for (int p = 7; p >= 3; p -= 2)
+        while (n % p == 0) {
+            n /= p;
+            odd[no++] = p;
+        }
+    if (n != 1) return -1;
+    int r[40] = {};
+    int m = 0;
+    if (variant == 1) {
+        for (int i = 0; i < a / 2; ++i) r[m++] = 4;
+        if (a % 2) r[m++] = 2;
+        for (int i = 0; i < no; ++i) r[m++] = odd[i];
+    } else if (variant == 2) {
+        for (int i = 0; i < no; ++i) r[m++] = odd[i];
+        for (int i = 0; i < a / 3; ++i) r[m++] = 8;
+        if (a % 3 == 1) r[m++] = 2;
+        else if (a % 3 == 2) r[m++] = 4;
+    } else {
+        for (int i = 0; i < a / 4; ++i) r[m++] = 16;
+        if (a % 4 == 1) r[m++] = 2;
+        else if (a % 4 == 2) r[m++] = 4;
+        else if (a % 4 == 3) r[m++] = 8;
+        for (int i = 0; i < no; ++i) r[m++] = odd[i];
+    }
+    if (m < 1 || m > cap) return -1;
+    for (int i = 0; i < m; ++i) out[i] = r[i];
+    return m;
+}
+
 // Per-stage constants of one transform length: for stage s of radix R after
 // Ns = product of the earlier radices, nbf = N / R butterflies, the exact
 // reciprocal multipliers of nbf and Ns (x / d == umulhi(x, ceil(2^32 / d)) for x, d <
@@ -91,6 +140,7 @@ struct FftPlanDev {
     int N;
     int nst;
     int ends8;                  // first and last stage are radix 8 (register-fused column pass)
+    int variant;                // schedule variant (0: fft_schedule, which the compile-time paths follow)
     int tw_off;                 // offset of this length's tables in the shared table arrays
     int rad[ADMM_MAX_STAGES];
     int ns[ADMM_MAX_STAGES];

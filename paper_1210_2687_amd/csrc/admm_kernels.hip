@@ -165,7 +165,7 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
     constexpr int NST = CSched<NF>::nst();
     static_assert(CSched<NF>::rad(0) == 8 && CSched<NF>::rad(NST - 1) == 8 && CSt<NF, 0>::NB == NB8,
                   "fixed column length must start and end with radix 8");
-    const bool fixed = H == NF;
+    const bool fixed = H == NF && p.fc.variant == 0;
 
     if (fused) {
         // forward: stage 0 (radix 8, no twiddles) from registers

@@ -4,7 +4,8 @@
 // (eqs. (19), (25), (33)); this header provides the 1-D transforms from which
 // the row and column passes are built.
 //
-// Algorithm: Stockham auto-sort, mixed radix {2,3,4,5,7,8}. At a stage of
+// Algorithm: Stockham auto-sort, mixed radix {2,3,4,5,7,8,16} (16 in the
+// block-level transforms only). At a stage of
 // radix R with Ns = product of the radices already applied, butterfly j of a
 // length-N transform reads x[j + r N/R] (r < R), multiplies input r by the
 // twiddle w_N^{r (j mod Ns) N/(Ns R)}, takes an R-point DFT and writes output r
@@ -217,10 +218,39 @@ template <int R, bool INV, typename E> __device__ __forceinline__ void dft_odd(E
     v[0] = sum;
 }
 
+// 16 points as two 8-point DFTs of the even and odd inputs, the odd ones
+// rotated by w16^k = exp(s 2 pi i k / 16), then 8 sums and 8 differences
+template <bool INV, typename E> __device__ __forceinline__ void dft16(E* v) {
+    constexpr float C1 = 0.92387953251128676f, S1 = 0.38268343236508977f, H = 0.70710678118654752f;
+    E e[8], o[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        e[m] = v[2 * m];
+        o[m] = v[2 * m + 1];
+    }
+    dft8<INV>(e);
+    dft8<INV>(o);
+    constexpr float sg = INV ? 1.0f : -1.0f;
+    o[1] = cmul(o[1], make_float2(C1, sg * S1));
+    o[2] = cmul(o[2], make_float2(H, sg * H));
+    o[3] = cmul(o[3], make_float2(S1, sg * C1));
+    o[4] = cmuli<INV>(o[4]);
+    o[5] = cmul(o[5], make_float2(-S1, sg * C1));
+    o[6] = cmul(o[6], make_float2(-H, sg * H));
+    o[7] = cmul(o[7], make_float2(-C1, sg * S1));
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        E a = e[k], b = o[k];
+        v[k] = cadd(a, b);
+        v[k + 8] = csub(a, b);
+    }
+}
+
 template <int R, bool INV, typename E> __device__ __forceinline__ void dft(E* v) {
     if constexpr (R == 2) dft2<INV>(v);
     else if constexpr (R == 4) dft4<INV>(v);
     else if constexpr (R == 8) dft8<INV>(v);
+    else if constexpr (R == 16) dft16<INV>(v);
     else dft_odd<R, INV>(v);
 }
 
@@ -301,6 +331,7 @@ __device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const floa
         const unsigned mnbf = f.mnbf[s], mns = f.mns[s];
         const ADMM_LDS float2* t = stw + f.tso[s];
         switch (R) {
+            case 16: stockham_stage<16, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
             case 8: stockham_stage<8, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
             case 4: stockham_stage<4, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
             case 2: stockham_stage<2, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
@@ -509,7 +540,7 @@ __device__ __forceinline__ void c_stages(ADMM_LDS E* buf, const ADMM_LDS float2*
 // when N == NF, else the general stages.
 template <int NF, int EPL, bool INV, typename E>
 __device__ __forceinline__ void wave_fft(ADMM_LDS E* buf, const ADMM_LDS float2* stw, const FftPlanDev& f, int lane) {
-    if (f.N == NF)
+    if (f.N == NF && f.variant == 0)
         c_stages<NF, 0, CSched<NF>::nst(), INV>(buf, stw, lane);
     else
         wave_stages<EPL, INV>(buf, stw, f, 0, f.nst, lane);
@@ -589,7 +620,7 @@ __device__ __forceinline__ void b_stages(ADMM_LDS E* buf, int pitch, const ADMM_
 template <int NF, int NTHR, int MAXT, int MAXE, bool INV, typename E>
 __device__ __forceinline__ void rows_fft(E* gbuf, int pitch, const FftPlanDev& f, const float2* gstw, int ntrans,
                                          int tid) {
-    if (f.N == NF)
+    if (f.N == NF && f.variant == 0)
         b_stages<NF, 0, CSched<NF>::nst(), NTHR, MAXT, INV>((ADMM_LDS E*)gbuf, pitch, (const ADMM_LDS float2*)gstw,
                                                             ntrans, tid);
     else

@@ -35,7 +35,8 @@ int main(int argc, char** argv) {
                          "{\"a\":{\"tc\":1e999}}", "{\"a\":{\"tc\":-3}}", "{\"a\":{\"rows\":nan}}",
                          "{\"a\":{\"rows\":1e300}}", "{\"a\":{\"tc\":2.5}}", "{\"a\":{\"col_us\":-1}}",
                          "{\"a\":{\"col_us\":inf}}", "{\"a\\\"\":{}}", "{\"a\":{\"tc\":1}", "[1,2]",
-                         "{\"a\":{\"tc\":2147483648}}", "{\"a\":{\"tc\":-2147483649}}", "{\"\":{\"\":0}} x"};
+                         "{\"a\":{\"tc\":2147483648}}", "{\"a\":{\"tc\":-2147483649}}", "{\"\":{\"\":0}} x",
+                         "{\"a\":{\"rsched\":4}}", "{\"a\":{\"csched\":1.5}}"};
     for (const char* t : bad) {
         std::map<std::string, TuneEntry> m;
         CHECK(!parse_cache(t, m));
@@ -47,6 +48,8 @@ int main(int argc, char** argv) {
         e.tc = 1 + (int)(g() % 4);
         e.rows = 1 + (int)(g() % 16);
         e.rows_c[g() % 3] = (int)(g() % 17);
+        e.rsched = (int)(g() % 4);
+        e.csched = (int)(g() % 3);
         e.col_us = (double)(g() % 100000) / 1000.0;
         e.row_us = (double)(g() % 100000) / 1000.0;
         ref["gfx950|tv" + std::to_string(i) + "x" + std::to_string(g() % 2048) + "*8"] = e;
@@ -59,7 +62,8 @@ int main(int argc, char** argv) {
         const auto it = back.find(kv.first);
         CHECK(it != back.end() && it->second.tc == kv.second.tc && it->second.rows == kv.second.rows &&
               it->second.rows_c[0] == kv.second.rows_c[0] && it->second.rows_c[1] == kv.second.rows_c[1] &&
-              it->second.rows_c[2] == kv.second.rows_c[2]);
+              it->second.rows_c[2] == kv.second.rows_c[2] && it->second.rsched == kv.second.rsched &&
+              it->second.csched == kv.second.csched);
     }
     const char alphabet[] = "{}[]\":,. -+0123456789eEinfatcrowsu_x\\\n\t";
     long parsed = 0;
@@ -82,6 +86,7 @@ int main(int argc, char** argv) {
                 CHECK(kv.second.tc >= 0 && kv.second.tc <= (int)kMaxTileCount);
                 CHECK(kv.second.rows >= 0 && kv.second.rows <= (int)kMaxTileCount);
                 CHECK(std::isfinite(kv.second.col_us) && kv.second.col_us >= 0.0);
+                CHECK(kv.second.rsched >= 0 && kv.second.rsched < kScheduleVariants);
             }
         }
     }

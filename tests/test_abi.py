@@ -116,3 +116,26 @@ def test_product_path_has_no_oracle_dependency():
         if fn.endswith(".py"):
             src = open(os.path.join(pkg, fn)).read()
             assert "import oracle" not in src and "from oracle" not in src, fn
+
+
+@pytest.mark.parametrize("n", [8, 12, 64, 96, 160, 448, 512, 1000, 1024, 1960, 2048])
+def test_schedule_variants_factor_n(n):
+    default = A.admm_fft_radices(n)
+    assert A.admm_fft_schedule(n, 0) == default
+    a = 0
+    m = n
+    while m % 2 == 0:
+        m //= 2
+        a += 1
+    for v in (1, 2, 3):
+        r = A.admm_fft_schedule(n, v)
+        assert r is not None and int(np.prod(r)) == n, (n, v, r)
+        assert all(x in (2, 3, 4, 5, 7, 8, 16) for x in r)
+        assert sorted(x for x in r if x % 2) == sorted(x for x in default if x % 2)   # same odd factors
+        if v == 1:
+            assert all(x in (2, 3, 4, 5, 7) for x in r)
+        if v == 2 and any(x % 2 for x in r):
+            assert r[0] % 2 == 1                         # odd radices first
+        if v == 3:
+            assert r.count(16) == a // 4
+    assert A.admm_fft_schedule(n, 4) is None and A.admm_fft_schedule(n, -1) is None

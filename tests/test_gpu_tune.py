@@ -87,3 +87,58 @@ def test_pass_timing_entry_point():
         again = _run(plan2, probs)
     for a, b in zip(ref, again):
         assert np.array_equal(a, b)
+
+
+# ------------------------------------------- radix schedules (the tuner's radix dimension)
+def _oracle_z(p, K):
+    import oracle as O
+    if p.reg == "frame":
+        return O.fa_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, p.levels, iters=K)["z"]
+    return O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=K)["z"]
+
+
+def _sched_batch():
+    # lengths with each kind of factorisation: powers of two (512, 256, 64),
+    # mixed (96 = 2^5 3, 160 = 2^5 5, 448 = 2^6 7, 120 = 2^3 15, 1000 = 2^3 5^3)
+    from gpu_util import full_problem
+    return [full_problem(601, 96, 160, 7), full_problem(602, 512, 448, 9, "motion"),
+            full_problem(603, 120, 1000, 5, "uniform"), full_problem(604, 256, 64, 7),
+            full_problem(605, 64, 96, 5, reg="frame", levels=2)]
+
+
+@pytest.mark.parametrize("rsched,csched", [(0, 0), (1, 0), (2, 0), (3, 0), (0, 1), (0, 2), (3, 2), (1, 1)])
+def test_every_radix_schedule_matches_the_oracle(rsched, csched):
+    # a schedule changes the rounding of the transforms only: each variant is
+    # held to the per-iterate bar against the FP64 oracle (not bitwise)
+    from gpu_util import check_iterate
+    import torch
+    probs = _sched_batch()
+    K = 12
+    with A.Plan(probs, tiles={"row_schedule": rsched, "col_schedule": csched}) as plan:
+        used = [plan.schedules(i) for i in range(len(probs))]
+        ys = [dev(p.y) for p in probs]
+        xs = [torch.zeros_like(y) for y in ys]
+        plan.batch(ys, xs, max_iters=K)
+        got = [host(x) for x in xs]
+    announce(f"schedules requested ({rsched}, {csched}), used {used}")
+    for p, (rv, cv) in zip(probs, used):
+        H, W = p.shape
+        # the variant is used unless it gives the length the default schedule
+        same_r = A.admm_fft_schedule(W, rsched) == A.admm_fft_schedule(W, 0)
+        same_c = A.admm_fft_schedule(H, csched) == A.admm_fft_schedule(H, 0)
+        assert rv == (0 if same_r else rsched) and cv == (0 if same_c else csched)
+    for p, z in zip(probs, got):
+        check_iterate(z, _oracle_z(p, K), what=f"{p.shape} schedules ({rsched}, {csched})")
+
+
+def test_tuner_records_and_reuses_radix_schedules(tmp_path):
+    probs = _sched_batch()[:3]
+    path = str(tmp_path / "tune.json")
+    with A.Plan(probs, tune=True, cache_path=path) as plan:
+        chosen = [plan.schedules(i) for i in range(len(probs))]
+    entry = json.load(open(path))[A.admm_tune_key(_cprobs(probs), _arch())]
+    announce(f"tuned entry {entry}, schedules {chosen}")
+    assert 0 <= entry.get("rsched", 0) <= 3 and 0 <= entry.get("csched", 0) <= 2
+    # planning again from the cache reproduces the schedules without measuring
+    with A.Plan(probs, tune=True, cache_path=path) as plan:
+        assert [plan.schedules(i) for i in range(len(probs))] == chosen
