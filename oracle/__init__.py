@@ -12,6 +12,9 @@ Unknown Boundaries Using the Alternating Direction Method of Multipliers":
 * TV-MD: Alg. 3 (ADMM-TV) with the data-term update of eq. (49)  (Sec. IV-D)
 * FA-MD: Alg. 2 (ADMM-2) with H1 = A, H2 = P, the z-step of eqs. (24)-(25)
   and the proximity operators of eqs. (40) and (16)                (Sec. IV-C)
+* TV-CG / FA-CG: the Reeves-Sorel variants with H1 = M A, the z-step by the
+  Sherman-Morrison-Woodbury split and one warm-started conjugate-gradient
+  iteration on the boundary system                         (Sec. IV-B..IV-D)
 
 Design rules: the convolution A and its adjoint are direct spatial sums over
 kernel taps, the z-step uses a naive dense-matrix DFT (never ``np.fft``), all
@@ -32,6 +35,9 @@ from .admm import (
     tv_objective, fa_objective, tv_residuals, fa_residuals,
     warm_start_state, zsolve_tv, zsolve_fa, default_mu,
 )
+from .cg import (
+    TVCGState, FACGState, tv_cg_step, tv_cg_run, fa_cg_step, fa_cg_run, boundary_cg, cg_zsolve,
+)
 from .cnn import conv3x3_fwd, conv3x3_dgrad, conv3x3_wgrad, relu, adam_step
 
 __all__ = [
@@ -42,5 +48,6 @@ __all__ = [
     "TVState", "FAState", "tv_md_step", "tv_md_run", "fa_md_step", "fa_md_run",
     "tv_objective", "fa_objective", "tv_residuals", "fa_residuals",
     "warm_start_state", "zsolve_tv", "zsolve_fa", "default_mu",
+    "TVCGState", "FACGState", "tv_cg_step", "tv_cg_run", "fa_cg_step", "fa_cg_run", "boundary_cg", "cg_zsolve",
     "conv3x3_fwd", "conv3x3_dgrad", "conv3x3_wgrad", "relu", "adam_step",
 ]

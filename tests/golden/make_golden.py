@@ -35,6 +35,13 @@ At every recorded iteration k >= 2 the files also hold the primal and dual
 residuals of the stopping rule (definitions in ``residuals``), from the same
 exact state: u_k, u_{k-1}, d_k and G z_k.
 
+The CG fixtures (method cg) run the Reeves-Sorel variants on the same tiny
+problems: H1 = M A, the z-step through C = (A^T A + gamma R^T R)^{-1} (a dense
+solve) and the boundary system S v = v - B C B^T v with B the rows of A at the
+unobserved pixels, one conjugate-gradient (steepest-descent) step per
+iteration from the previous v (Sec. IV-B..IV-D). The data block of their
+residuals is M A z - u1.
+
 Run ``python tests/golden/make_golden.py`` to rewrite the ``.txt`` files.
 """
 
@@ -125,7 +132,17 @@ def _fa_problem_8x8():
                 lam=Q(1, 64), mu1=Q(1, 2), mu2=Q(1, 8), iters=8, record=[1, 2, 3, 5, 8])
 
 
-PROBLEMS = (_tv_problem, _fa_problem, _tv_problem_8x10, _fa_problem_8x8)
+def _tv_cg_problem():
+    # TV-CG (Sec. IV-D, Reeves-Sorel) on the 5 x 6 TV-MD problem
+    return dict(_tv_problem(), name="tv_cg_5x6", method="cg")
+
+
+def _fa_cg_problem():
+    # FA-CG (Sec. IV-C, Reeves-Sorel) on the 4 x 6 FA-MD problem
+    return dict(_fa_problem(), name="fa_cg_4x6_J2", method="cg")
+
+
+PROBLEMS = (_tv_problem, _fa_problem, _tv_problem_8x10, _fa_problem_8x8, _tv_cg_problem, _fa_cg_problem)
 
 
 # ----------------------------------------------------------------- dense algebra
@@ -338,6 +355,31 @@ def run(pb):
         N = [add(row, scale(mu2, brow)) for row, brow in zip(N, BtB)]
 
     fac = lu_factor(N)
+    cg = pb.get("method", "md") == "cg"
+    if cg:
+        # Reeves-Sorel variants: H1 = M A. C^{-1} = A^T A + gamma R^T R (dense),
+        # B = the rows of A at the unobserved pixels, boundary system
+        # S v = v - B C B^T v, one CG step per iteration from the previous v
+        gamma = mu2 / mu1
+        NC = matmul(At, A)
+        for B_, Bt_ in zip(R, Rt):
+            BtB = matmul(Bt_, B_)
+            NC = [add(row, scale(gamma, brow)) for row, brow in zip(NC, BtB)]
+        facC = lu_factor(NC)
+        unobs = [i for i in range(n) if m[i] == 0]
+        Brows = [A[i] for i in unobs]
+
+        def Bt_of(v):   # B^T v as an n-vector
+            out = [zero] * n
+            for vj, row in zip(v, Brows):
+                out = [o + vj * a for o, a in zip(out, row)]
+            return out
+
+        def S_of(v):
+            w = lu_solve(facC, Bt_of(v))
+            return [vj - sum((a * b for a, b in zip(row, w)), zero) for vj, row in zip(v, Brows)]
+
+        vcg = [zero] * len(unobs)
     u1, d1 = [zero] * n, [zero] * n
     ur = [[zero] * n for _ in R]
     dr = [[zero] * n for _ in R]
@@ -346,14 +388,37 @@ def run(pb):
     z = None
     for k in range(1, pb["iters"] + 1):
         u1_prev, ur_prev = u1, ur
-        rhs = scale(mu1, matvec(At, add(u1, d1)))
-        for Bt, ub, db in zip(Rt, ur, dr):
-            rhs = add(rhs, scale(mu2, matvec(Bt, add(ub, db))))
-        z = lu_solve(fac, rhs)
-        Az = matvec(A, z)
-        v1 = [a - d for a, d in zip(Az, d1)]
-        u1 = [(mi * yi + mu1 * vi) / (mi + mu1) for mi, yi, vi in zip(m, y, v1)]
-        d1 = [d - (a - u) for d, a, u in zip(d1, Az, u1)]
+        if not cg:
+            rhs = scale(mu1, matvec(At, add(u1, d1)))
+            for Bt, ub, db in zip(Rt, ur, dr):
+                rhs = add(rhs, scale(mu2, matvec(Bt, add(ub, db))))
+            z = lu_solve(fac, rhs)
+            Az = matvec(A, z)
+            v1 = [a - d for a, d in zip(Az, d1)]
+            u1 = [(mi * yi + mu1 * vi) / (mi + mu1) for mi, yi, vi in zip(m, y, v1)]
+            d1 = [d - (a - u) for d, a, u in zip(d1, Az, u1)]
+        else:
+            # r = mu1 A^T M^T zeta1 + mu2 R^T zeta_R (TV); A^T M^T zeta1 + gamma R^T zeta_R (FA)
+            w1 = mu1 if reg == "tv" else one
+            w2 = mu2 if reg == "tv" else gamma
+            rhs = scale(w1, matvec(At, [mi * a for mi, a in zip(m, add(u1, d1))]))
+            for Bt, ub, db in zip(Rt, ur, dr):
+                rhs = add(rhs, scale(w2, matvec(Bt, add(ub, db))))
+            t = lu_solve(facC, rhs)
+            b = [sum((a * c for a, c in zip(row, t)), zero) for row in Brows]
+            cres = [bi - si for bi, si in zip(b, S_of(vcg))]
+            rr = sum((a * a for a in cres), zero)
+            if rr != 0:
+                q = S_of(cres)
+                pq = sum((a * c for a, c in zip(cres, q)), zero)
+                if pq > 0:
+                    al = rr / pq
+                    vcg = [vj + al * rj for vj, rj in zip(vcg, cres)]
+            wz = add(t, lu_solve(facC, Bt_of(vcg)))
+            z = [a / w1 for a in wz]
+            Az = [mi * a for mi, a in zip(m, matvec(A, z))]      # M A z (zero off the mask)
+            u1 = [mi * (yi + mu1 * (a - d)) / (1 + mu1) for mi, yi, a, d in zip(m, y, Az, d1)]
+            d1 = [d - (a - u) for d, a, u in zip(d1, Az, u1)]
         Rz = [matvec(B, z) for B in R]
         vr = [[a - d for a, d in zip(Rb, db)] for Rb, db in zip(Rz, dr)]
         if reg == "tv":
@@ -401,15 +466,23 @@ def _dec(v):
 
 def write(pb, zs, obj, res):
     path = os.path.join(HERE, pb["name"] + ".txt")
-    cite = ("TV-MD: Alg. 3 with the z-step of eq. (33) and the data step of eq. (49), Sec. IV-D"
-            if pb["reg"] == "tv" else
-            "FA-MD: Alg. 2 with the z-step of eqs. (24)-(25), data step eq. (40), soft threshold eq. (16), Sec. IV-C")
+    if pb.get("method", "md") == "cg":
+        cite = ("TV-CG: Alg. 3 with A replaced by M A, the z-step of eq. (51) with one warm-started CG step, "
+                "Sec. IV-D" if pb["reg"] == "tv" else
+                "FA-CG: Alg. 2 with H1 = M A (eq. (45)), the z-step of eq. (47) with one warm-started CG step, "
+                "Sec. IV-C")
+    else:
+        cite = ("TV-MD: Alg. 3 with the z-step of eq. (33) and the data step of eq. (49), Sec. IV-D"
+                if pb["reg"] == "tv" else
+                "FA-MD: Alg. 2 with the z-step of eqs. (24)-(25), data step eq. (40), soft threshold eq. (16), "
+                "Sec. IV-C")
     arith = "60-digit decimal" if pb["reg"] == "tv" else "exact rational"
     lines = [
         f"# {cite}.",
         f"# Cold start, dense explicit operators, {arith} arithmetic; written by tests/golden/make_golden.py.",
         "# Values are row-major; inputs are exact fractions; z values carry 26 significant digits.",
         f"reg {pb['reg']}",
+        f"method {pb.get('method', 'md')}",
         f"levels {pb.get('J', 0)}",
         f"shape {pb['H']} {pb['W']}",
         "kernel " + " ".join(str(v) for row in pb["kernel"] for v in row),

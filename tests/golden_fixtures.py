@@ -7,6 +7,7 @@ import numpy as np
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 NAMES = ("tv_md_5x6", "fa_md_4x6_J2", "tv_md_8x10", "fa_md_8x8_J3")
+CG_NAMES = ("tv_cg_5x6", "fa_cg_4x6_J2")
 
 
 def load(name):
@@ -25,7 +26,7 @@ def load(name):
                 out["residuals"][int(vals[0])] = (float(vals[1]), float(vals[2]))
             elif key == "objective":
                 out["objective"] = (int(vals[0]), float(vals[1]))
-            elif key in ("reg",):
+            elif key in ("reg", "method"):
                 out[key] = vals[0]
             elif key in ("levels", "iters"):
                 out[key] = int(vals[0])
