@@ -12,6 +12,12 @@
  *                   Haar Parseval frame, J levels, 3J+1 bands), z-step
  *                   eqs. (24)-(25), prox eqs. (40) and (16), objective eq. (44).
  *
+ * With method ADMM_METHOD_CG the same objectives are minimised by the
+ * Reeves-Sorel variants TV-CG / FA-CG the paper compares against (Sec. IV-B
+ * to IV-D): H1 = M A, the z-step split by eqs. (43), (47), (51) into circulant
+ * solves and one conjugate-gradient iteration on the boundary system, warm
+ * started from the previous outer iteration.
+ *
  * Conventions shared by every entry point:
  *  - Images are row-major float32 planes of H*W elements (pitch W).
  *  - "DEVICE" pointers are HIP device allocations on the current device;
@@ -46,6 +52,11 @@ typedef enum {
 
 typedef enum { ADMM_REG_TV = 0, ADMM_REG_FRAME = 1 } admm_reg;
 
+/* Splitting of the data term: mask decoupling (the paper's method, the
+ * default) or the Reeves-Sorel boundary system with one CG iteration per
+ * outer iteration (TV-CG, FA-CG). */
+typedef enum { ADMM_METHOD_MD = 0, ADMM_METHOD_CG = 1 } admm_method;
+
 /* One problem of a plan. */
 typedef struct {
     int32_t H, W;            /* unknown-domain size; each side 7-smooth, 8..2048       */
@@ -58,6 +69,8 @@ typedef struct {
     double lambda;           /* regularisation weight, >= 0                            */
     double mu1, mu2;         /* ADMM penalties; a value <= 0 selects the rule of Sec. V:
                                 mu2 = 10 lambda, mu1 = min(1, 5000 mu2)                */
+    int32_t method;          /* admm_method; every problem of a plan has the same one.
+                                ADMM_METHOD_CG solves start cold (st must be NULL)      */
 } admm_problem;
 
 /* Solve options. */
@@ -122,7 +135,8 @@ admm_status admm_deconv_plan(const admm_problem* probs, int32_t count, void* hip
 /* Solve the single problem of a plan with count == 1.
  * y:    DEVICE H*W observation; entries where mask == 0 are ignored.
  * x:    DEVICE H*W output, the last iterate z_k.
- * st:   NULL for a cold start (u0 = d0 = 0), else initial state in / final out.
+ * st:   NULL for a cold start (u0 = d0 = 0), else initial state in / final out
+ *       (method MD only: a CG plan returns ADMM_E_UNSUPPORTED for a non-NULL st).
  * info: HOST, receives the result.                                            */
 admm_status admm_deconv_solve(admm_plan* plan, const float* y, float* x, admm_state* st,
                               const admm_opts* opts, admm_info* info);
@@ -140,7 +154,8 @@ admm_status admm_deconv_solve(admm_plan* plan, const float* y, float* x, admm_st
  * that pair of calls.
  * Limit: the problem's workspace (spectra, kernel spectrum, duals, scratch
  * planes, tables; about 60 B per pixel for TV and (30 + 12 (3J+1)) B per pixel
- * for the frame) must fit the static workspace, else ADMM_E_UNSUPPORTED
+ * for the frame, 32 B per pixel more with method CG) must fit the static
+ * workspace, else ADMM_E_UNSUPPORTED
  * before any device work. Every call on a device reuses that device's
  * workspace: calls that overlap on one device (two threads or two streams)
  * race and must be serialised by the caller.                                  */

@@ -15,7 +15,8 @@ import numpy as np
 
 __all__ = [
     "ADMM_OK", "ADMM_E_INVALID", "ADMM_E_UNSUPPORTED", "ADMM_E_SINGULAR", "ADMM_E_NOMEM",
-    "ADMM_E_DEVICE", "ADMM_E_DIVERGED", "ADMM_REG_TV", "ADMM_REG_FRAME", "ADMM_FLAG_GRAPH",
+    "ADMM_E_DEVICE", "ADMM_E_DIVERGED", "ADMM_REG_TV", "ADMM_REG_FRAME", "ADMM_METHOD_MD", "ADMM_METHOD_CG",
+    "ADMM_FLAG_GRAPH",
     "ADMM_FLAG_PROFILE", "admm_plan_kernel_times",
     "AdmmError", "lib", "lib_path", "exported_symbols",
     "admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
@@ -26,6 +27,7 @@ __all__ = [
 
 ADMM_OK, ADMM_E_INVALID, ADMM_E_UNSUPPORTED, ADMM_E_SINGULAR, ADMM_E_NOMEM, ADMM_E_DEVICE, ADMM_E_DIVERGED = range(7)
 ADMM_REG_TV, ADMM_REG_FRAME = 0, 1
+ADMM_METHOD_MD, ADMM_METHOD_CG = 0, 1
 ADMM_FLAG_GRAPH = 1
 ADMM_FLAG_PROFILE = 2
 
@@ -42,7 +44,7 @@ class admm_problem(ctypes.Structure):
     _fields_ = [("H", c_int32), ("W", c_int32), ("ksize", c_int32),
                 ("kernel", POINTER(c_float)), ("mask", POINTER(c_uint8)),
                 ("reg", c_int32), ("levels", c_int32),
-                ("lam", c_double), ("mu1", c_double), ("mu2", c_double)]
+                ("lam", c_double), ("mu1", c_double), ("mu2", c_double), ("method", c_int32)]
 
 
 class admm_opts(ctypes.Structure):
@@ -173,8 +175,10 @@ def admm_fft_radices(n):
     return None if k < 0 else list(buf[:k])
 
 
-def make_problem(kernel, mask, lam, mu1=-1.0, mu2=-1.0, reg=ADMM_REG_TV, levels=0):
-    """Host-side problem description; keeps the host arrays alive with it."""
+def make_problem(kernel, mask, lam, mu1=-1.0, mu2=-1.0, reg=ADMM_REG_TV, levels=0, method=None):
+    """Host-side problem description; keeps the host arrays alive with it.
+    method: ADMM_METHOD_MD (default, mask decoupling) or ADMM_METHOD_CG (the
+    Reeves-Sorel variants TV-CG / FA-CG)."""
     kernel = np.ascontiguousarray(kernel, dtype=np.float32)
     mask = np.ascontiguousarray(mask, dtype=np.uint8)
     p = admm_problem()
@@ -185,6 +189,7 @@ def make_problem(kernel, mask, lam, mu1=-1.0, mu2=-1.0, reg=ADMM_REG_TV, levels=
     p.reg = reg
     p.levels = levels
     p.lam, p.mu1, p.mu2 = float(lam), float(mu1), float(mu2)
+    p.method = ADMM_METHOD_MD if method is None else int(method)
     p._keep = (kernel, mask)
     return p
 
@@ -427,12 +432,13 @@ def alloc_state(H, W, nreg=2, device="cuda"):
 class Plan:
     """Convenience owner of a plan handle built from ``workloads.Problem``-like objects."""
 
-    def __init__(self, problems, stream=None, tune=False, cache_path=None, tiles=None):
+    def __init__(self, problems, stream=None, tune=False, cache_path=None, tiles=None, method=ADMM_METHOD_MD):
         self.problems = list(problems)
         self._cprobs = []
         for p in self.problems:
             reg = ADMM_REG_FRAME if getattr(p, "reg", "tv") == "frame" else ADMM_REG_TV
-            self._cprobs.append(make_problem(p.kernel, p.mask, p.lam, p.mu1, p.mu2, reg, getattr(p, "levels", 0)))
+            self._cprobs.append(make_problem(p.kernel, p.mask, p.lam, p.mu1, p.mu2, reg, getattr(p, "levels", 0),
+                                             method))
         self.nregs = [3 * p.levels + 1 if getattr(p, "reg", "tv") == "frame" else 2 for p in self.problems]
         if tiles is not None:
             self.handle = admm_deconv_plan_with(self._cprobs, stream=stream, **tiles)

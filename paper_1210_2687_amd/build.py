@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadmmdeconv.so")
-SOURCES = ["admm_api.hip", "admm_kernels.hip", "admm_frame.hip", "conv_bf16.hip"]
+SOURCES = ["admm_api.hip", "admm_kernels.hip", "admm_frame.hip", "admm_cg.hip", "conv_bf16.hip"]
 HOST_SOURCES = ["admm_host.cpp"]   # plain C++ (no device code)
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

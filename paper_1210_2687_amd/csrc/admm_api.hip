@@ -133,11 +133,13 @@ struct TileChoice {
 
 constexpr int kPeriodsInFlight = 2;      // period graphs queued ahead of the host's stop test
 constexpr int kPeriodIters = 40;         // iterations per period graph (whole check periods)
+constexpr int kProfClasses = 7;          // kernel classes of the profiling totals
 
 struct admm_plan {
     hipStream_t stream = nullptr;
     TileChoice tile;                      // what the plan was built with
     int count = 0;
+    int method = METHOD_MD;               // shared by every problem of the plan
     std::vector<admm_problem> probs;      // copies (host pointers cleared)
     std::vector<ProbDesc> hd;             // host copy of the descriptors
     std::vector<int> col_beg, col_end, row_beg, row_end, frm_beg, frm_end;   // item ranges per problem
@@ -171,11 +173,11 @@ struct admm_plan {
     int* h_active_dev = nullptr;
     hipEvent_t pev[kPeriodsInFlight] = {};
     // profiling: per-class totals of the last profiled run
-    double prof_ms[6] = {0, 0, 0, 0, 0, 0};
-    int prof_n[6] = {0, 0, 0, 0, 0, 0};
+    double prof_ms[kProfClasses] = {};
+    int prof_n[kProfClasses] = {};
 };
 
-static const char* const kProfNames[6] = {"col", "row_tv", "row_inv", "frame", "row_fwd", "reduce"};
+static const char* const kProfNames[kProfClasses] = {"col", "row_tv", "row_inv", "frame", "row_fwd", "reduce", "cg"};
 
 namespace {
 
@@ -295,6 +297,15 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         else
             (void)hipGetLastError();
     }
+    for (int i = 1; i < count; ++i)
+        if (probs[i].method != probs[0].method)
+            return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: every problem of a plan needs the same method", i));
+    P->method = probs[0].method == ADMM_METHOD_CG ? METHOD_CG : METHOD_MD;
+    const bool cg = P->method == METHOD_CG;
+    if (cg && lds_cap > 65536 && cap > 65536 && allow_dynamic_lds_cg(lds_cap) != hipSuccess) {
+        (void)hipGetLastError();
+        cap = 65536;
+    }
     P->stream = (hipStream_t)hip_stream;
     P->count = count;
     P->probs.assign(probs, probs + count);
@@ -340,6 +351,8 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         d.tau = (float)(q.lambda / mu2);
         d.inv_hw = (float)(1.0 / ((double)q.H * q.W));
         d.inv1pmu1 = (float)(1.0 / (1.0 + mu1));
+        d.method = P->method;
+        d.mut = q.reg == ADMM_REG_TV ? (float)mu1 : 1.0f;
         const int rv = effective_variant(q.W, tile.rsched, false), cv = effective_variant(q.H, tile.csched, true);
         fill_plan(d.fr, q.W, slot(q.W, rv), rv);
         fill_plan(d.fc, q.H, slot(q.H, cv), cv);
@@ -356,7 +369,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         int bmax = 0;
         if (q.reg == ADMM_REG_TV) {
             while (bmax + 1 <= std::min(q.H, row_tv_max_rows(q.W)) && fits(bmax + 3, d.fr, row_maxe()) &&
-                   lds_rowtv_bytes(q.W, bmax + 1) <= cap)
+                   lds_rowtv_bytes(q.W, bmax + 1) <= cap && (!cg || lds_cgtv_bytes(q.W, bmax + 1) <= cap))
                 ++bmax;
         } else {
             while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) && fits(bmax + 1, d.fr, row_maxe()) &&
@@ -485,6 +498,8 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     const size_t o_info = take(sizeof(InfoDev) * count);
     const size_t o_kbase = take(sizeof(int));
     const size_t o_part = take(sizeof(double) * ADMM_NSUM * std::max(part, 1));
+    const size_t o_cgpart = cg ? take(sizeof(double) * 2 * std::max(part, 1)) : 0;
+    const size_t o_cgalpha = cg ? take(sizeof(float) * count) : 0;
     const size_t o_tw = take(sizeof(float2) * tab_len);
     const size_t o_s2 = take(sizeof(float) * tab_len);
     // row sums of the kernel spectrum (host-computed, consumed at plan time):
@@ -495,6 +510,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     const size_t o_T = ext_arena ? take(t_bytes) : 0;
     struct Offs {
         size_t spec0, spec1, lam, d1, dreg0, dreg1, u1p, uregp, tmpA, tmpB, zpl, mask;
+        size_t cg[7];   // v, e, A e, O1, A O1, O2, A O2 (method CG)
     };
     std::vector<Offs> po(count);
     for (int i = 0; i < count; ++i) {
@@ -511,8 +527,9 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         o.uregp = take(n * d.nb * sizeof(float));
         o.tmpA = take(n * sizeof(float));
         o.tmpB = take(n * sizeof(float));
-        o.zpl = d.reg == REG_FRAME ? take(n * sizeof(float)) : o.tmpA;
+        o.zpl = d.reg == REG_FRAME || cg ? take(n * sizeof(float)) : o.tmpA;
         o.mask = take(n);
+        for (int j = 0; j < 7; ++j) o.cg[j] = cg ? take(n * sizeof(float)) : 0;
     }
     P->arena_bytes = off;
     if (ext_arena) {
@@ -569,6 +586,11 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         d.tmpB = (float*)(A + o.tmpB);
         d.zpl = (float*)(A + o.zpl);
         d.mask = (const uint8_t*)(A + o.mask);
+        if (cg) {
+            float** planes[7] = {&d.cgv, &d.cge, &d.cgae, &d.cgo1, &d.cgao1, &d.cgo2, &d.cgao2};
+            for (int j = 0; j < 7; ++j) *planes[j] = (float*)(A + o.cg[j]);
+            d.cgalpha = (float*)(A + o_cgalpha) + i;
+        }
     }
 
     // twiddle and |Delta|^2 tables, in double then rounded once
@@ -609,6 +631,12 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     base_ctx.partials = P->d_partials;
     base_ctx.tw = P->d_tw;
     base_ctx.s2 = P->d_s2;
+    if (cg) {
+        base_ctx.cgpart = (double*)(A + o_cgpart);
+        for (int i = 0; i < count; ++i)
+            if (P->hd[i].reg == REG_TV)
+                base_ctx.lds_cgtv = std::max(base_ctx.lds_cgtv, lds_cgtv_bytes(P->hd[i].W, P->hd[i].B));
+    }
     for (int c = 0; c < ADMM_COL_CLASSES; ++c) {
         base_ctx.col_beg[c] = col_cb[c];
         base_ctx.col_cnt[c] = col_cc[c];
@@ -687,6 +715,8 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
     if (!o || !infos || !y || !x) return fail(ADMM_E_INVALID, "null argument");
     if (o->max_iters < 1 || o->check_every < 1) return fail(ADMM_E_INVALID, "max_iters and check_every must be >= 1");
     const int count = P->count;
+    const bool cg = P->method == METHOD_CG;
+    if (cg && st) return fail(ADMM_E_UNSUPPORTED, "method CG solves start cold: pass no state");
     for (int i = 0; i < count; ++i) {
         if (!y[i] || !x[i]) return fail(ADMM_E_INVALID, "null y/x for problem %d", i);
         if (st && (!st[i].u1 || !st[i].d1 || !st[i].ureg || !st[i].dreg))
@@ -720,7 +750,11 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
             HIP_TRY(hipMemsetAsync(d.dreg0, 0, n * d.nb * sizeof(float), sm));
             HIP_TRY(hipMemsetAsync(d.u1p, 0, n * sizeof(float), sm));
             HIP_TRY(hipMemsetAsync(d.uregp, 0, n * d.nb * sizeof(float), sm));
-        } else {
+        }
+        if (cg) {
+            // the first right-hand side (u = d = 0), the boundary estimate v and its images
+            for (float* q : {d.tmpA, d.tmpB, d.cgv, d.cge, d.cgae}) HIP_TRY(launch_zero(sm, q, n));
+        } else if (st) {
             HIP_TRY(hipMemcpyAsync(d.u1p, st[i].u1, n * sizeof(float), hipMemcpyDeviceToDevice, sm));
             HIP_TRY(hipMemcpyAsync(d.uregp, st[i].ureg, n * d.nb * sizeof(float), hipMemcpyDeviceToDevice, sm));
             if (d.reg == REG_TV) {
@@ -774,8 +808,32 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
         ev.clear();
     };
     // one iteration on contexts cA (all), cT (TV rows), cF (FA rows/frame)
+    // method CG (see admm_cg.hip): both circulant solves run forward rows,
+    // columns and inverse rows in place on spec0; the CG and data steps run
+    // per row block, then the TV step or the frame step
+    auto cg_iteration = [&](const LaunchCtx& cA, const LaunchCtx& cT, const LaunchCtx& cF, int par,
+                            int flags) -> hipError_t {
+        hipError_t e = hipSuccess;
+        const LaunchCtx* rows[2] = {&cT, &cF};
+        auto each = [&](int cls, auto&& fn) {
+            for (const LaunchCtx* r : rows)
+                if (e == hipSuccess && r->nrow) e = timed(cls, [&] { return fn(*r); });
+        };
+        for (int solve = 0; solve < 2 && e == hipSuccess; ++solve) {
+            each(4, [&](const LaunchCtx& r) { return launch_row_fwd(r, 0, 0, true); });
+            if (e == hipSuccess) e = timed(0, [&] { return launch_col(cA, 0, COL_SOLVE); });
+            each(2, [&](const LaunchCtx& r) { return launch_row_inv(r, 0, 2 + solve, 0, true); });
+            each(6, [&](const LaunchCtx& r) { return solve == 0 ? launch_cg_dir(r) : launch_cg_dot(r); });
+        }
+        if (e == hipSuccess) e = timed(6, [&] { return launch_cg_alpha(cA, count); });
+        each(6, [&](const LaunchCtx& r) { return launch_cg_update(r, flags); });
+        if (e == hipSuccess && cT.nrow) e = timed(6, [&] { return launch_cg_tv(cT, par, flags); });
+        if (e == hipSuccess && cF.nrow) e = timed(3, [&] { return launch_frame(cF, par, flags, 0, true); });
+        return e;
+    };
     auto iteration = [&](const LaunchCtx& cA, const LaunchCtx& cT, const LaunchCtx& cF, int par, int flags,
                          bool last) -> hipError_t {
+        if (cg) return cg_iteration(cA, cT, cF, par, flags);
         hipError_t e = timed(0, [&] { return launch_col(cA, par, COL_SOLVE); });
         if (e == hipSuccess && P->nrowtv) e = timed(1, [&] { return launch_row_tv(cT, par, flags); });
         if (e == hipSuccess && P->nrowfa) {
@@ -932,7 +990,7 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
     }
     if (profile) {
         HIP_TRY(hipStreamSynchronize(sm));
-        for (int i = 0; i < 6; ++i) {
+        for (int i = 0; i < kProfClasses; ++i) {
             P->prof_ms[i] = 0;
             P->prof_n[i] = 0;
         }
@@ -1098,13 +1156,13 @@ extern "C" admm_status admm_warmstart_dual(admm_plan* P, int32_t index, const fl
 
 extern "C" int32_t admm_plan_kernel_times(const admm_plan* P, admm_kernel_time* out, int32_t cap) {
     if (!P) return 0;
-    for (int i = 0; i < 6 && out && i < cap; ++i) {
+    for (int i = 0; i < kProfClasses && out && i < cap; ++i) {
         std::memset(&out[i], 0, sizeof out[i]);
         std::snprintf(out[i].name, sizeof out[i].name, "%s", kProfNames[i]);
         out[i].launches = P->prof_n[i];
         out[i].total_ms = P->prof_ms[i];
     }
-    return 6;
+    return kProfClasses;
 }
 
 // ------------------------------------------------------------ FFT autotuner
@@ -1139,8 +1197,8 @@ admm_status time_plan(admm_plan* P, const float* const* y, float* const* x, doub
         if (rep == 0) continue;   // the first run warms caches and code
         const double c = P->prof_n[0] ? P->prof_ms[0] / P->prof_n[0] * 1e3 : 0.0;
         double r = 0.0;
-        for (int k = 1; k <= 4; ++k)
-            if (P->prof_n[k]) r += P->prof_ms[k] / P->prof_n[k] * 1e3;
+        for (int k = 1; k < kProfClasses; ++k)   // everything but the columns and the reduction
+            if (k != 5 && P->prof_n[k]) r += P->prof_ms[k] / P->prof_n[k] * 1e3;
         best_c = std::min(best_c, c);
         best_r = std::min(best_r, r);
     }

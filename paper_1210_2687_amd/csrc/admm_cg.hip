@@ -1,0 +1,334 @@
+// admm_cg.hip — gfx950 kernels of the Reeves-Sorel variants TV-CG and FA-CG
+// (Sec. IV-B..IV-D): H1 = M A, the z-step by the Sherman-Morrison-Woodbury
+// split z = (C r + C B^T v) / mu_t, C the circulant inverse, B the rows of A at
+// the unobserved pixels, v from one conjugate-gradient iteration on the
+// boundary system (I - B C B^T) v = B C r started at the previous v.
+//
+// One iteration, with the circulant solves done by the FFT passes (row DFT,
+// column DFT + solve + inverse, inverse row DFT into a pair of planes):
+//   solve 1   (M (u1 + d1), s)   -> O1 = C r / mu_t, AO1 = A O1
+//   k_cg_dir  p = res = B (C r + C B^T v) - v on the unobserved pixels, with
+//             C B^T v and A C B^T v held as the images e, Ae; sum p^2
+//   solve 2   (p, 0)             -> O2 = C B^T p, AO2 = A O2
+//   k_cg_dot  sum p (I - B C B^T) p = sum p (p - (1 - m) AO2)
+//   k_cg_alpha  a = sum p^2 / sum p S p (0 unless both are positive)
+//   k_cg_update v += a p, e += a O2, Ae += a AO2 (linearity of C B^T and A),
+//             z = O1 + e / mu_t, A z = AO1 + Ae / mu_t, data step on the
+//             observed pixels u1 = (y + mu1 (A z - d1)) / (1 + mu1),
+//             d1 <- d1 - (A z - u1), next M (u1 + d1)
+//   k_cg_tv   (TV) vector soft threshold, TV duals, next s = mu2 D^T (u + d);
+//             the frame variant runs the FA frame step on z instead.
+// Every kernel takes the rows of one row item of a problem (the work items of
+// the row passes) and skips finished problems.
+#include "admm_internal.h"
+#include "admm_launch.h"
+#include "fft_lds.h"
+
+namespace admm {
+
+constexpr int NTG = 512;
+
+namespace {
+
+__device__ __forceinline__ double cg_wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sum K per-thread values over the block into out[0..K) (thread 0 writes).
+template <int K>
+__device__ void cg_block_sums(const double* v, double* out) {
+    __shared__ double sm[NTG / 64][K];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const double s = cg_wave_sum(v[i]);
+        if (lane == 0) sm[wave][i] = s;
+    }
+    __syncthreads();
+    if (tid < K) {
+        double s = 0.0;
+        for (int w = 0; w < NTG / 64; ++w) s += sm[w][tid];
+        out[tid] = s;
+    }
+}
+
+// The block's residual sums into its slot: every entry (odd == false; the data
+// step, whose regulariser entries are zero) or the odd entries only (the TV
+// step, which runs after the data step on the same row block).
+__device__ void cg_write_sums(const double* acc, double* slot, bool odd) {
+    __shared__ double out[ADMM_NSUM];
+    cg_block_sums<ADMM_NSUM>(acc, out);
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < ADMM_NSUM && (!odd || (t & 1))) slot[t] = out[t];
+}
+
+}  // namespace
+
+// p = res on the unobserved pixels (0 on the observed), into tmpA, with tmpB = 0:
+// the input pair of the second solve.
+__global__ __launch_bounds__(NTG) void k_cg_dir(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                               const InfoDev* __restrict__ info, double* __restrict__ cgpart) {
+    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    if (!info[it.prob].active) return;
+    const ProbDesc& p = pd[it.prob];
+    const int W = p.W, nr = min(p.B, p.H - it.start);
+    const unsigned base = (unsigned)(it.start * W), cnt = (unsigned)(nr * W);
+    const float mut = p.mut;
+    const uint8_t* const MK = p.mask;
+    const float* const AO1 = p.cgao1;
+    const float* const AE = p.cgae;
+    const float* const V = p.cgv;
+    float* const TA = p.tmpA;
+    float* const TB = p.tmpB;
+    double acc[1] = {0.0};
+    for (unsigned i = threadIdx.x; i < cnt; i += NTG) {
+        const unsigned g = base + i;
+        const bool obs = gld(MK, g) != 0;
+        const float r = fmaf(mut, gld(AO1, g), gld(AE, g)) - gld(V, g);
+        const float pv = obs ? 0.0f : r;
+        gst(TA, g, pv);
+        gst(TB, g, 0.0f);
+        acc[0] += (double)pv * (double)pv;
+    }
+    __shared__ double res[1];
+    cg_block_sums<1>(acc, res);
+    __syncthreads();
+    if (threadIdx.x == 0) cgpart[(size_t)(p.part_base + it.blk) * 2] = res[0];
+}
+
+// sum p (I - B C B^T) p over the block's rows: p (p - (1 - m) AO2)
+__global__ __launch_bounds__(NTG) void k_cg_dot(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                               const InfoDev* __restrict__ info, double* __restrict__ cgpart) {
+    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    if (!info[it.prob].active) return;
+    const ProbDesc& p = pd[it.prob];
+    const int W = p.W, nr = min(p.B, p.H - it.start);
+    const unsigned base = (unsigned)(it.start * W), cnt = (unsigned)(nr * W);
+    const uint8_t* const MK = p.mask;
+    const float* const TA = p.tmpA;
+    const float* const AO2 = p.cgao2;
+    double acc[1] = {0.0};
+    for (unsigned i = threadIdx.x; i < cnt; i += NTG) {
+        const unsigned g = base + i;
+        const bool obs = gld(MK, g) != 0;
+        const float pv = gld(TA, g);
+        const float q = obs ? 0.0f : pv - gld(AO2, g);
+        acc[0] += (double)pv * (double)q;
+    }
+    __shared__ double res[1];
+    cg_block_sums<1>(acc, res);
+    __syncthreads();
+    if (threadIdx.x == 0) cgpart[(size_t)(p.part_base + it.blk) * 2 + 1] = res[0];
+}
+
+// a = sum p^2 / sum p S p per problem, summed over its row blocks in a fixed
+// order; 0 when the direction vanishes or the quotient is not a positive number.
+__global__ void k_cg_alpha(const ProbDesc* __restrict__ pd, const InfoDev* __restrict__ info,
+                           const double* __restrict__ cgpart, int count) {
+    const int prob = blockIdx.x * blockDim.x + threadIdx.x;
+    if (prob >= count || !info[prob].active) return;
+    const ProbDesc& p = pd[prob];
+    double rr = 0.0, pq = 0.0;
+    for (int b = 0; b < p.nrowblk; ++b) {
+        rr += cgpart[(size_t)(p.part_base + b) * 2];
+        pq += cgpart[(size_t)(p.part_base + b) * 2 + 1];
+    }
+    const double a = (rr > 0.0 && pq > 0.0) ? rr / pq : 0.0;
+    p.cgalpha[0] = isfinite(a) ? (float)a : 0.0f;
+}
+
+// CG update, z, A z and the data step (observed pixels), the data block's
+// residual sums on check iterations (the regulariser entries written as zero).
+template <bool CHK>
+__global__ __launch_bounds__(NTG) void k_cg_update(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                                  const InfoDev* __restrict__ info, int flags,
+                                                  double* __restrict__ partials) {
+    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    if (!info[it.prob].active) return;
+    const ProbDesc& p = pd[it.prob];
+    const int W = p.W, nr = min(p.B, p.H - it.start);
+    const unsigned base = (unsigned)(it.start * W), cnt = (unsigned)(nr * W);
+    const float a = p.cgalpha[0], inv_mut = 1.0f / p.mut, mu1 = p.mu1, c1 = p.inv1pmu1;
+    const uint8_t* const MK = p.mask;
+    const float* const YV = p.y;
+    const float* const TA = p.tmpA;   // p of this iteration
+    const float* const O1 = p.cgo1;
+    const float* const AO1 = p.cgao1;
+    const float* const O2 = p.cgo2;
+    const float* const AO2 = p.cgao2;
+    float* const V = p.cgv;
+    float* const E = p.cge;
+    float* const AE = p.cgae;
+    float* const D1 = p.d1;
+    float* const ZP = p.zpl;
+    float* const XO = p.x;
+    float* const U1P = p.u1p;
+    float* const ZETA = p.tmpA;       // next M (u1 + d1), written after p is read
+    double acc[ADMM_NSUM];
+#pragma unroll
+    for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
+    for (unsigned i = threadIdx.x; i < cnt; i += NTG) {
+        const unsigned g = base + i;
+        const bool obs = gld(MK, g) != 0;
+        const float pv = gld(TA, g);
+        const float e = fmaf(a, gld(O2, g), gld(E, g));
+        const float ae = fmaf(a, gld(AO2, g), gld(AE, g));
+        gst(V, g, fmaf(a, pv, gld(V, g)));
+        gst(E, g, e);
+        gst(AE, g, ae);
+        const float z = fmaf(e, inv_mut, gld(O1, g));
+        const float Az = fmaf(ae, inv_mut, gld(AO1, g));
+        const float MAz = obs ? Az : 0.0f;
+        const float d1o = gld(D1, g);
+        const float yv = obs ? gld(YV, g) : 0.0f;
+        const float v1 = MAz - d1o;
+        const float u1 = obs ? fmaf(yv - v1, c1, v1) : 0.0f;   // (y + mu1 v) / (1 + mu1) on the observed pixels
+        const float d1n = d1o - (MAz - u1);
+        gst(D1, g, d1n);
+        gst(ZP, g, z);
+        gst(ZETA, g, u1 + d1n);
+        if (flags & F_WRITE_X) gst(XO, g, z);
+        if (CHK) {
+            const float e0 = MAz - u1, f6 = u1 - gld(U1P, g), ry = obs ? yv - Az : 0.0f;
+            acc[0] += (double)(e0 * e0);
+            acc[2] += (double)(MAz * MAz);
+            acc[4] += (double)(u1 * u1);
+            acc[6] += (double)(f6 * f6);
+            acc[8] += (double)(d1n * d1n);
+            acc[10] += (double)(ry * ry);
+        }
+        if (flags & F_WRITE_UPREV) gst(U1P, g, u1);
+    }
+    if (CHK) cg_write_sums(acc, partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM, false);
+}
+
+// TV step of TV-CG on z (the plane k_cg_update wrote): vector soft threshold
+// and TV duals for the block's rows and the row above (whose u + d enters the
+// adjoint difference), then s = mu2 D^T (u + d) for the block's rows; the TV
+// block's residual sums on check iterations (odd entries). LDS: (nr + 1) x W of
+// each component of u + d.
+template <bool CHK>
+__global__ __launch_bounds__(NTG) void k_cg_tv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                              const InfoDev* __restrict__ info, int par, int flags,
+                                              double* __restrict__ partials) {
+    extern __shared__ float ud[];
+    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    if (!info[it.prob].active) return;
+    const ProbDesc& p = pd[it.prob];
+    const int H = p.H, W = p.W, r0 = it.start, nr = min(p.B, H - r0);
+    const unsigned n = (unsigned)(H * W);
+    const float tau = p.tau, mu2 = p.mu2;
+    const float* const Z = p.zpl;
+    const float* const dh_in = par ? p.dreg1 : p.dreg0;
+    const float* const dv_in = dh_in + n;
+    float* const dh_out = par ? p.dreg0 : p.dreg1;
+    float* const dv_out = dh_out + n;
+    float* const UREGP = p.uregp;
+    float* const TB = p.tmpB;
+    float* udh = ud;
+    float* udv = ud + (size_t)(nr + 1) * W;
+    double acc[ADMM_NSUM];
+#pragma unroll
+    for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
+    const int tot = (nr + 1) * W;
+    for (int i = threadIdx.x; i < tot; i += NTG) {
+        const int rr = i / W, c = i - rr * W;
+        const int r = rr == 0 ? (r0 == 0 ? H - 1 : r0 - 1) : r0 + rr - 1;   // row r0 - 1 + rr (wrapped)
+        const int rn = r + 1 == H ? 0 : r + 1, cn = c + 1 == W ? 0 : c + 1;
+        const unsigned g = (unsigned)(r * W + c);
+        const float zc = gld(Z, g);
+        const float zh = gld(Z, (unsigned)(r * W + cn)) - zc;
+        const float zv = gld(Z, (unsigned)(rn * W + c)) - zc;
+        const float dh = gld(dh_in, g), dv = gld(dv_in, g);
+        const float vh = zh - dh, vv = zv - dv;
+        const float rho = __builtin_amdgcn_sqrtf(fmaf(vh, vh, vv * vv));
+        const float sc = rho > tau ? (rho - tau) * __builtin_amdgcn_rcpf(rho) : 0.0f;
+        const float uh = vh * sc, uv = vv * sc;
+        const float dhn = uh - vh, dvn = uv - vv;   // d - (D z - u)
+        udh[i] = uh + dhn;
+        udv[i] = uv + dvn;
+        if (rr > 0) {
+            gst(dh_out, g, dhn);
+            gst(dv_out, g, dvn);
+            if (flags & F_WRITE_UPREV) {
+                gst(UREGP, g, uh);
+                gst(UREGP, n + g, uv);
+            }
+            if (CHK) {
+                const float e1h = zh - uh, e1v = zv - uv;
+                const float f7h = uh - gld(UREGP, g), f7v = uv - gld(UREGP, n + g);
+                acc[1] += (double)fmaf(e1h, e1h, e1v * e1v);
+                acc[3] += (double)fmaf(zh, zh, zv * zv);
+                acc[5] += (double)fmaf(uh, uh, uv * uv);
+                acc[7] += (double)fmaf(f7h, f7h, f7v * f7v);
+                acc[9] += (double)fmaf(dhn, dhn, dvn * dvn);
+                acc[11] += (double)sqrtf(fmaf(zh, zh, zv * zv));
+            }
+        }
+    }
+    __syncthreads();
+    const int own = nr * W;
+    for (int i = threadIdx.x; i < own; i += NTG) {
+        const int rr = i / W + 1, c = i - (rr - 1) * W;
+        const int k = rr * W + c, kl = rr * W + (c == 0 ? W - 1 : c - 1), ku = k - W;
+        const float s = mu2 * ((udh[kl] - udh[k]) + (udv[ku] - udv[k]));
+        gst(TB, (unsigned)((r0 + rr - 1) * W + c), s);
+    }
+    if (CHK) cg_write_sums(acc, partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM, true);
+}
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_cg_dir(const LaunchCtx& L) {
+    if (!L.nrow) return hipSuccess;
+    hipLaunchKernelGGL(k_cg_dir, dim3(L.nrow), dim3(NTG), 0, L.stream, L.desc, L.row_items, L.info, L.cgpart);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_dot(const LaunchCtx& L) {
+    if (!L.nrow) return hipSuccess;
+    hipLaunchKernelGGL(k_cg_dot, dim3(L.nrow), dim3(NTG), 0, L.stream, L.desc, L.row_items, L.info, L.cgpart);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_alpha(const LaunchCtx& L, int count) {
+    hipLaunchKernelGGL(k_cg_alpha, dim3((count + 63) / 64), dim3(64), 0, L.stream, L.desc, L.info, L.cgpart, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const LaunchCtx& L, int flags) {
+    if (!L.nrow) return hipSuccess;
+    if (flags & F_CHECK)
+        hipLaunchKernelGGL(k_cg_update<true>, dim3(L.nrow), dim3(NTG), 0, L.stream, L.desc, L.row_items, L.info, flags,
+                           L.partials);
+    else
+        hipLaunchKernelGGL(k_cg_update<false>, dim3(L.nrow), dim3(NTG), 0, L.stream, L.desc, L.row_items, L.info,
+                           flags, L.partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_tv(const LaunchCtx& L, int par, int flags) {
+    if (!L.nrow) return hipSuccess;
+    if (flags & F_CHECK)
+        hipLaunchKernelGGL(k_cg_tv<true>, dim3(L.nrow), dim3(NTG), L.lds_cgtv, L.stream, L.desc, L.row_items, L.info,
+                           par, flags, L.partials);
+    else
+        hipLaunchKernelGGL(k_cg_tv<false>, dim3(L.nrow), dim3(NTG), L.lds_cgtv, L.stream, L.desc, L.row_items, L.info,
+                           par, flags, L.partials);
+    return hipGetLastError();
+}
+
+size_t lds_cgtv_bytes(int W, int B) { return (size_t)2 * (B + 1) * W * sizeof(float); }
+
+hipError_t allow_dynamic_lds_cg(int bytes) {
+    const void* fns[] = {reinterpret_cast<const void*>(&k_cg_tv<false>), reinterpret_cast<const void*>(&k_cg_tv<true>)};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace admm

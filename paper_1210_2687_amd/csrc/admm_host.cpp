@@ -45,6 +45,7 @@ admm_status validate(const admm_problem& p) {
     if (p.ksize < 1 || p.ksize % 2 == 0 || p.ksize > std::min(p.H, p.W))
         return fail(ADMM_E_UNSUPPORTED, "kernel side %d must be odd and <= min(H, W)", p.ksize);
     if (p.reg != ADMM_REG_TV && p.reg != ADMM_REG_FRAME) return fail(ADMM_E_INVALID, "unknown regulariser %d", p.reg);
+    if (p.method != ADMM_METHOD_MD && p.method != ADMM_METHOD_CG) return fail(ADMM_E_INVALID, "unknown method %d", p.method);
     if (p.reg == ADMM_REG_FRAME && (p.levels < 1 || p.levels > 4))
         return fail(ADMM_E_UNSUPPORTED, "frame levels %d outside 1..4", p.levels);
     if (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)) return fail(ADMM_E_INVALID, "lambda must be finite and >= 0");

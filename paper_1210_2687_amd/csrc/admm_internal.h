@@ -188,7 +188,23 @@ struct ProbDesc {
     float* st_d1;
     float* st_ureg;
     float* st_dreg;
+    // Reeves-Sorel variants (method CG): the boundary-system estimate v, the
+    // images C B^T v and A C B^T v, the outputs (z part, A z part) of the two
+    // circulant solves of an iteration, the step length, and mu_t (mu1 for TV,
+    // where the solve returns t / mu1; 1 for the frame)
+    int method;
+    float mut;
+    float* cgv;
+    float* cge;
+    float* cgae;
+    float* cgo1;
+    float* cgao1;
+    float* cgo2;
+    float* cgao2;
+    float* cgalpha;
 };
+
+enum { METHOD_MD = 0, METHOD_CG = 1 };
 
 struct WorkItem {
     int prob;

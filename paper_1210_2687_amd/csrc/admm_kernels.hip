@@ -634,6 +634,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
 // Inverse row DFT of (z^ + i A z^) for rows [r0, r0 + nr).
 //   mode 0 (blur): write z (the real part) to tmpB.
 //   mode 1 (FA data step): z -> zpl, mask prox and data dual (eq. (40)), zeta1 -> tmpA.
+//   mode 2, 3 (method CG): the two parts to (cgo1, cgao1), (cgo2, cgao2).
 // Rows padded as in k_row_fwd.
 template <int CPT, int RB>
 __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
@@ -664,6 +665,22 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
             for (int j = 0; j < CPT; ++j) {
                 const int c = tid + j * NT;
                 if (c < W) gst(TB, off + (unsigned)(rr * W + c), X[rr * pitch + pidx(c)].x);
+            }
+        }
+        return;
+    }
+    if (mode >= 2) {
+        float* const O = mode == 2 ? p.cgo1 : p.cgo2;
+        float* const AO = mode == 2 ? p.cgao1 : p.cgao2;
+        for (int rr = 0; rr < nr; ++rr) {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int c = tid + j * NT;
+                if (c >= W) continue;
+                const float2 xv = X[rr * pitch + pidx(c)];
+                const unsigned g = off + (unsigned)(rr * W + c);
+                gst(O, g, xv.x);
+                gst(AO, g, xv.y);
             }
         }
         return;
