@@ -147,7 +147,7 @@ def host_data(args):
 
 
 # ------------------------------------------------------------------ GPU workloads
-def timed_batch(probs, iters, steps, warmup, tune, graph=True):
+def timed_batch(probs, iters, steps, warmup, tune, graph=True, method=0):
     """Plan (autotuned tiles unless tune is False), warm up, time `steps` cold-start
     batched solves of `iters` iterations. Returns (plan, ys, xs, result dict)."""
     import torch
@@ -155,7 +155,7 @@ def timed_batch(probs, iters, steps, warmup, tune, graph=True):
     ys = [torch.tensor(p.y, dtype=torch.float32, device="cuda") for p in probs]
     xs = [torch.zeros_like(y) for y in ys]
     t0 = time.perf_counter()
-    plan = A.Plan(probs, tune=tune, cache_path=os.environ.get("ADMM_TUNE_CACHE"))
+    plan = A.Plan(probs, tune=tune, cache_path=os.environ.get("ADMM_TUNE_CACHE"), method=method)
     t_plan = time.perf_counter() - t0
     run = lambda: plan.batch(ys, xs, max_iters=iters, tol=0.0, graph=graph)
     for _ in range(warmup):
@@ -193,17 +193,108 @@ def dominant_roofline(plan, probs, kt, reps=50):
             "alg_bytes_per_launch": int(alg[dom]), "timing": f"{reps} back-to-back launches between one HIP event pair"}
 
 
-def run_throughput(name, probs, iters, steps, warmup, tune, desc):
+def run_throughput(name, probs, iters, steps, warmup, tune, desc, method=0):
     log(f"{name}: {desc}")
-    plan, ys, xs, r = timed_batch(probs, iters, steps, warmup, tune)
+    plan, ys, xs, r = timed_batch(probs, iters, steps, warmup, tune, method=method)
     kt = kernel_breakdown(plan, ys, xs, min(iters, 100))
     out = {"workload": desc, "value": round(r["value"], 1), "unit": "Mpx*iter/s", "ms_per_step": round(r["ms_per_step"], 3),
            "steps": steps, "problems": len(probs), "pixels": r["pixels"], "iters": iters, "tiles": r["tiles"],
-           "plan_s": r["plan_s"], "roofline_iteration": iteration_roofline(probs, r["us_per_iter"]),
-           "roofline_dominant": dominant_roofline(plan, probs, kt), "kernel_us_event_per_launch": kt}
+           "plan_s": r["plan_s"], "us_per_iter": round(r["us_per_iter"], 3), "kernel_us_event_per_launch": kt}
+    if method == 0:   # the rooflines price the MD schedule's launches
+        out["roofline_iteration"] = iteration_roofline(probs, r["us_per_iter"])
+        out["roofline_dominant"] = dominant_roofline(plan, probs, kt)
+        log(f"{name}: {out['value']:.1f} Mpx*iter/s, iteration at {out['roofline_iteration']['frac']:.3f} of HBM peak")
+    else:
+        log(f"{name}: {out['value']:.1f} Mpx*iter/s, {r['us_per_iter']:.2f} us per iteration")
     plan.close()
-    log(f"{name}: {out['value']:.1f} Mpx*iter/s, iteration at {out['roofline_iteration']['frac']:.3f} of HBM peak")
     return out
+
+
+def _solve_ms(plan, y, x, reps=3, **kw):
+    """Median wall time (ms) of `reps` solves on the plan's stream, and the last info."""
+    import torch
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = plan.solve(y, x, graph=True, **kw)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(times)), info
+
+
+def _us_per_iter(plan, y, x, K=400):
+    """Microseconds per iteration: solves of K and 3K iterations, the difference
+    over 2K (the per-solve work cancels)."""
+    a, _ = _solve_ms(plan, y, x, max_iters=K, check_every=K)
+    b, _ = _solve_ms(plan, y, x, max_iters=3 * K, check_every=3 * K)
+    return (b - a) * 1e3 / (2 * K)
+
+
+def run_md_vs_cg(obj_tol=1e-4, c=10, max_iters=20000):
+    """The paper's MD-vs-CG comparison (Sec. V, Tables 3 and 4) on synthetic
+    256 x 256 images with its four 19 x 19 blurs at 40 dB BSNR: each MD solve
+    runs to the paper's stopping rule (relative change of the objective from
+    one iteration to the next <= obj_tol), then the CG variant runs until its
+    objective reaches the MD solve's final objective (the smallest multiple of
+    c found by doubling and bisection over cold-start solves); both solves
+    timed whole. Also the time per iteration of the four solvers (Table 4)."""
+    import torch
+    from paper_1210_2687_amd import admm as A
+    from paper_1210_2687_amd import workloads as WL
+    log("md_vs_cg: TV/FA MD vs CG on the four 19x19 blurs, 256^2, 40 dB")
+    rows, per_iter = [], {}
+    for reg in ("tv", "frame"):
+        name = "TV" if reg == "tv" else "FA"
+        for i, blur in enumerate(WL.COMPARISON_BLURS):
+            p = WL.comparison_problem(i, reg)
+            y = torch.tensor(p.y, dtype=torch.float32, device="cuda")
+            x = torch.zeros_like(y)
+            with A.Plan([p]) as md, A.Plan([p], method=A.ADMM_METHOD_CG) as cg:
+                md.solve(y, x, max_iters=max_iters, obj_tol=obj_tol, check_every=1, graph=True)   # graphs captured
+                t_md, info_md = _solve_ms(md, y, x, max_iters=max_iters, obj_tol=obj_tol, check_every=1)
+                f_md = info_md["objective"]
+
+                def f_cg(K):
+                    return cg.solve(y, x, max_iters=K, check_every=K, graph=True)["objective"]
+
+                K = c
+                while K <= max_iters and f_cg(K) > f_md:
+                    K *= 2
+                k_cg, t_cg = None, None
+                if K <= max_iters:
+                    lo, hi = (K // 2 if K > c else 0), K
+                    while hi - lo > c:
+                        mid = (lo + hi) // 2 // c * c
+                        if mid <= lo:
+                            break
+                        if f_cg(mid) <= f_md:
+                            hi = mid
+                        else:
+                            lo = mid
+                    k_cg = hi
+                    t_cg, info_cg = _solve_ms(cg, y, x, max_iters=k_cg, check_every=k_cg)
+                if i == 0:
+                    per_iter[f"{name}-MD"] = round(_us_per_iter(md, y, x), 2)
+                    per_iter[f"{name}-CG"] = round(_us_per_iter(cg, y, x), 2)
+            rows.append({"solver": name, "blur": blur, "md_iters": info_md["iters"], "md_converged": info_md["converged"],
+                         "md_ms": round(t_md, 3), "md_objective": f_md, "cg_iters": k_cg,
+                         "cg_ms": None if t_cg is None else round(t_cg, 3),
+                         "cg_over_md_time": None if t_cg is None else round(t_cg / t_md, 3)})
+            log(f"md_vs_cg: {name} {blur}: MD {info_md['iters']} it {t_md:.2f} ms, CG {k_cg} it "
+                f"{t_cg if t_cg is None else round(t_cg, 2)} ms")
+    ratios = {}
+    for name in ("TV", "FA"):
+        r = [q["cg_over_md_time"] for q in rows if q["solver"] == name and q["cg_over_md_time"] is not None]
+        ratios[name] = round(float(np.mean(r)), 3) if r else None
+    return {"workload": "TV and FA (J = 3) MD vs CG: 256x256 synthetic images, 19x19 out-of-focus / motion / "
+                        "uniform / Gaussian blurs, valid region only, 40 dB BSNR, lambda 2e-4, mu by the rule of "
+                        "Sec. V; MD until the objective changes by <= 1e-4 (relative) in an iteration, CG until "
+                        "its objective reaches the MD one",
+            "rows": rows, "mean_cg_over_md_time": ratios, "us_per_iter": per_iter,
+            "cg_over_md_per_iter": {n: round(per_iter[f"{n}-CG"] / per_iter[f"{n}-MD"], 3) for n in ("TV", "FA")},
+            "paper_context": "Table 4 (MATLAB, Core i5 2.39 GHz): 0.033 / 0.058 / 0.059 / 0.096 s per iteration "
+                             "(TV-MD, TV-CG, FA-MD, FA-CG); Table 3: CG 1.5-2x the MD time"}
 
 
 def run_c1(p, steps=5):
@@ -374,7 +465,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="tv8x512", choices=["tv8x512", "tv64x512", "fa1024", "ragged256"],
+    ap.add_argument("--workload", default="tv8x512",
+                    choices=["tv8x512", "tv64x512", "fa1024", "ragged256", "md_vs_cg", "tv8x512_cg"],
                     help="the headline is tv8x512; with --quick, the others run alone (profiling)")
     ap.add_argument("--quick", action="store_true", help="only the chosen workload, no other configs")
     ap.add_argument("--iters", type=int, default=500, help="ADMM iterations per headline step")
@@ -425,6 +517,12 @@ def main():
         # one other workload alone, for profiling
         if args.workload == "fa1024":
             configs["c3"] = run_c3(data["c3"])
+        elif args.workload == "md_vs_cg":
+            configs["md_vs_cg"] = run_md_vs_cg()
+        elif args.workload == "tv8x512_cg":
+            configs["headline_cg"] = run_throughput("headline_cg", data["c2"], args.iters, args.steps, args.warmup,
+                                                    tune, f"TV-CG on the headline batch, {args.iters} iterations",
+                                                    method=A.ADMM_METHOD_CG)
         elif args.workload == "ragged256":
             configs["c4"] = run_throughput("c4", data["c4"], 200, args.steps, args.warmup, tune,
                                            "TV-MD ragged batch of 256 problems, sides 128..1024 (7-smooth), "
@@ -456,6 +554,11 @@ def main():
         configs["beyond_cache"] = run_throughput("beyond_cache", data["c64"], 500, 3, 1, tune,
                                                  "TV-MD batch of 64 x 512x512 (the 8 headline images repeated), "
                                                  "500 iterations")
+        configs["headline_cg"] = run_throughput("headline_cg", probs, args.iters, 3, 1, tune,
+                                                f"TV-CG (Reeves-Sorel, one CG step) on the headline batch of "
+                                                f"{args.batch} x {args.size}^2, {args.iters} iterations",
+                                                method=A.ADMM_METHOD_CG)
+        configs["md_vs_cg"] = run_md_vs_cg()
         configs["c4"] = run_throughput("c4", data["c4"], 200, 2, 1, tune,
                                        "TV-MD ragged batch of 256 problems, sides 128..1024 (7-smooth), kernels "
                                        "Gaussian/uniform/motion 5..31, lambda log-uniform 1e-5..1e-3, 200 iterations")

@@ -81,12 +81,16 @@ typedef struct {
     int32_t check_every;     /* residual check period c (>= 1); the last iteration is
                                 always checked so info is filled                       */
     uint32_t flags;          /* ADMM_FLAG_* below                                      */
+    double obj_tol;          /* the paper's rule (Sec. V): also stop at a check iteration
+                                where |F_k - F_prev| <= obj_tol |F_prev|, F_prev the
+                                objective at the previous check (with check_every = 1:
+                                the previous iteration); <= 0: off                      */
 } admm_opts;
 
 /* ADMM_FLAG_GRAPH: iterations are replayed from hipGraphs captured once per
  * plan (captured on an internal stream, launched on the plan's stream). With
- * tol > 0 and an even check period, whole check periods, residual checks
- * included, are replayed and the stopping test is read from host-mapped
+ * a stopping rule (tol > 0 or obj_tol > 0) and an even check period or a
+ * period of 1, whole check periods, checks included, are replayed and the stopping test is read from host-mapped
  * memory with at most two graphs queued; iterations queued past a problem's
  * stop leave it unchanged. Iterates, states and infos are identical to eager
  * launches.

@@ -48,7 +48,8 @@ class admm_problem(ctypes.Structure):
 
 
 class admm_opts(ctypes.Structure):
-    _fields_ = [("max_iters", c_int32), ("tol", c_double), ("check_every", c_int32), ("flags", c_uint32)]
+    _fields_ = [("max_iters", c_int32), ("tol", c_double), ("check_every", c_int32), ("flags", c_uint32),
+                ("obj_tol", c_double)]
 
 
 class admm_info(ctypes.Structure):
@@ -303,26 +304,27 @@ def _state(st, n, R):
     return s
 
 
-def _opts(max_iters, tol, check_every, graph, profile=False):
+def _opts(max_iters, tol, check_every, graph, profile=False, obj_tol=0.0):
     o = admm_opts()
     o.max_iters, o.tol, o.check_every = int(max_iters), float(tol), int(check_every)
+    o.obj_tol = float(obj_tol)
     o.flags = (ADMM_FLAG_GRAPH if graph else 0) | (ADMM_FLAG_PROFILE if profile else 0)
     return o
 
 
 def admm_deconv_solve(plan, y, x, state=None, max_iters=100, tol=0.0, check_every=10, graph=False,
-                      profile=False, nreg=2):
+                      profile=False, nreg=2, obj_tol=0.0):
     n = y.numel()
     info = admm_info()
     st = _state(state, n, nreg)
     _check(lib().admm_deconv_solve(plan, _dev(y), _dev(x, n), ctypes.byref(st) if st else None,
-                                   ctypes.byref(_opts(max_iters, tol, check_every, graph, profile)),
+                                   ctypes.byref(_opts(max_iters, tol, check_every, graph, profile, obj_tol)),
                                    ctypes.byref(info)))
     return info.as_dict()
 
 
 def admm_deconv_solve_static(problem, y, x, state=None, max_iters=100, tol=0.0, check_every=10, nreg=2,
-                             stream=None):
+                             stream=None, obj_tol=0.0):
     """Plan and solve one problem (``make_problem``) in the library's static
     device workspace, allocating nothing."""
     n = y.numel()
@@ -330,13 +332,13 @@ def admm_deconv_solve_static(problem, y, x, state=None, max_iters=100, tol=0.0, 
     st = _state(state, n, nreg)
     _check(lib().admm_deconv_solve_static(ctypes.byref(problem), _dev(y), _dev(x, n),
                                           ctypes.byref(st) if st else None,
-                                          ctypes.byref(_opts(max_iters, tol, check_every, False)),
+                                          ctypes.byref(_opts(max_iters, tol, check_every, False, False, obj_tol)),
                                           ctypes.byref(info), _stream_ptr(stream)))
     return info.as_dict()
 
 
 def admm_deconv_batch(plan, ys, xs, states=None, max_iters=100, tol=0.0, check_every=10, graph=False,
-                      profile=False, nregs=None, raise_on_diverged=True):
+                      profile=False, nregs=None, raise_on_diverged=True, obj_tol=0.0):
     cnt = len(ys)
     yp = (c_void_p * cnt)(*[_dev(t) for t in ys])
     xp = (c_void_p * cnt)(*[_dev(t, ys[i].numel()) for i, t in enumerate(xs)])
@@ -346,7 +348,8 @@ def admm_deconv_batch(plan, ys, xs, states=None, max_iters=100, tol=0.0, check_e
         sts = (admm_state * cnt)(*[_state(s, ys[i].numel(), nregs[i]) for i, s in enumerate(states)])
     infos = (admm_info * cnt)()
     status = lib().admm_deconv_batch(plan, yp, xp, sts,
-                                     ctypes.byref(_opts(max_iters, tol, check_every, graph, profile)), infos)
+                                     ctypes.byref(_opts(max_iters, tol, check_every, graph, profile, obj_tol)),
+                                     infos)
     if status != ADMM_OK and not (status == ADMM_E_DIVERGED and not raise_on_diverged):
         _check(status)
     return [i.as_dict() for i in infos]

@@ -164,10 +164,10 @@ struct admm_plan {
     hipStream_t cap_stream = nullptr;
     std::map<int, hipGraphExec_t> graphs;
     // graph replay of whole check periods (tolerance solves): executable per
-    // (period, periods per graph, state export, tolerance bits); the iteration
+    // (period, periods per graph, state export, tolerance bits of both rules); the iteration
     // counter they advance; active flags mirrored into host-mapped memory; one
     // event per graph in flight
-    std::map<std::tuple<int, int, int, uint64_t>, hipGraphExec_t> pgraphs;
+    std::map<std::tuple<int, int, int, uint64_t, uint64_t>, hipGraphExec_t> pgraphs;
     int* d_kbase = nullptr;
     int* h_active = nullptr;
     int* h_active_dev = nullptr;
@@ -782,10 +782,11 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
         HIP_TRY(hipMemcpyAsync(P->d_info, P->h_info, sizeof(InfoDev) * count, hipMemcpyHostToDevice, sm));
     }
     const int K = o->max_iters, c = o->check_every;
-    const double tol = o->tol;
+    const double tol = o->tol, obj_tol = o->obj_tol > 0.0 ? o->obj_tol : 0.0;
+    const bool stopping = tol > 0 || obj_tol > 0;   // a stopping rule is checked every c iterations
     const bool profile = (o->flags & ADMM_FLAG_PROFILE) != 0 && !P->no_alloc;
     const bool use_graph = (o->flags & ADMM_FLAG_GRAPH) && !profile && !P->no_alloc;
-    auto is_check = [&](int k) { return k == K || (tol > 0 && k % c == 0); };
+    auto is_check = [&](int k) { return k == K || (stopping && k % c == 0); };
     auto is_plain = [&](int k) { return k < K && !is_check(k) && !is_check(k + 1); };
 
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
@@ -882,7 +883,9 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
     auto get_period_graph = [&](int g, hipGraphExec_t* exec) -> admm_status {
         uint64_t tb = 0;
         std::memcpy(&tb, &tol, sizeof tb);
-        const auto key = std::make_tuple(c, g, st ? 1 : 0, tb);
+        uint64_t ob = 0;
+        std::memcpy(&ob, &obj_tol, sizeof ob);
+        const auto key = std::make_tuple(c, g, st ? 1 : 0, tb, ob);
         auto it = P->pgraphs.find(key);
         if (it != P->pgraphs.end()) {
             *exec = it->second;
@@ -895,11 +898,12 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
         hipError_t e = hipSuccess;
         for (int q = 1; q <= g && e == hipSuccess; ++q) {
             for (int j = 1; j <= c && e == hipSuccess; ++j) {
-                int flags = F_FORWARD | (j == c - 1 ? F_WRITE_UPREV : 0);
+                // u_k is kept on the iteration before each check (every one for period 1)
+                int flags = F_FORWARD | (j == c - 1 || c == 1 ? F_WRITE_UPREV : 0);
                 if (j == c) flags |= F_CHECK | F_WRITE_X | (st ? F_EXPORT : 0);
-                e = iteration(cA, cT, cF, (j - 1) & 1, flags, false);
+                e = iteration(cA, cT, cF, ((q - 1) * c + j - 1) & 1, flags, false);
             }
-            if (e == hipSuccess) e = launch_reduce(cA, count, tol, q * c, 0, P->d_kbase, P->h_active_dev);
+            if (e == hipSuccess) e = launch_reduce(cA, count, tol, obj_tol, q * c, 0, P->d_kbase, P->h_active_dev);
         }
         if (e == hipSuccess) e = launch_tick(cA, P->d_kbase, g * c, false);
         hipGraph_t gr = nullptr;
@@ -920,14 +924,18 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
     int par = 0;
     int k = 1;
     bool all_done = false;
-    if (use_graph && tol > 0 && c >= 2 && c % 2 == 0 && c < K) {
+    // an even number of iterations per graph keeps the ping-pong parity: an even
+    // period, or period 1 with an even number of periods
+    if (use_graph && stopping && (c % 2 == 0 || c == 1) && c < K) {
         for (hipEvent_t& e : P->pev)
             if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         for (int i = 0; i < count; ++i) P->h_active[i] = 1;
         HIP_TRY(launch_tick(P->all, P->d_kbase, 0, true));
         const int gmax = std::max(1, kPeriodIters / c);
         for (int n = 0; k + c - 1 < K; ++n) {
-            const int g = std::min(gmax, (K - k) / c);   // whole periods that end before K
+            int g = std::min(gmax, (K - k) / c);   // whole periods that end before K
+            if (c % 2) g &= ~1;
+            if (g < 1) break;
             hipEvent_t& ev_n = P->pev[n % kPeriodsInFlight];
             if (n >= kPeriodsInFlight) {
                 HIP_TRY(hipEventSynchronize(ev_n));   // graph n - kPeriodsInFlight has finished
@@ -972,12 +980,12 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
             }
         }
         if (check) {
-            hipError_t e = timed(5, [&] { return launch_reduce(P->all, count, tol, k, last ? 1 : 0); });
+            hipError_t e = timed(5, [&] { return launch_reduce(P->all, count, tol, obj_tol, k, last ? 1 : 0); });
             if (e != hipSuccess) {
                 release_events();
                 return fail(ADMM_E_DEVICE, "reduction launch failed: %s", hipGetErrorString(e));
             }
-            if (!last && tol > 0) {
+            if (!last && stopping) {
                 HIP_TRY(hipMemcpyAsync(P->h_info, P->d_info, sizeof(InfoDev) * count, hipMemcpyDeviceToHost, sm));
                 HIP_TRY(hipStreamSynchronize(sm));
                 bool any = false;

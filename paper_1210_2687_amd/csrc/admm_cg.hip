@@ -253,11 +253,7 @@ __global__ __launch_bounds__(NTG) void k_cg_tv(const ProbDesc* __restrict__ pd, 
         if (rr > 0) {
             gst(dh_out, g, dhn);
             gst(dv_out, g, dvn);
-            if (flags & F_WRITE_UPREV) {
-                gst(UREGP, g, uh);
-                gst(UREGP, n + g, uv);
-            }
-            if (CHK) {
+            if (CHK) {   // reads u_{k-1} before a check iteration that also keeps u_k (period 1) overwrites it
                 const float e1h = zh - uh, e1v = zv - uv;
                 const float f7h = uh - gld(UREGP, g), f7v = uv - gld(UREGP, n + g);
                 acc[1] += (double)fmaf(e1h, e1h, e1v * e1v);
@@ -266,6 +262,10 @@ __global__ __launch_bounds__(NTG) void k_cg_tv(const ProbDesc* __restrict__ pd, 
                 acc[7] += (double)fmaf(f7h, f7h, f7v * f7v);
                 acc[9] += (double)fmaf(dhn, dhn, dvn * dvn);
                 acc[11] += (double)sqrtf(fmaf(zh, zh, zv * zv));
+            }
+            if (flags & F_WRITE_UPREV) {
+                gst(UREGP, g, uh);
+                gst(UREGP, n + g, uv);
             }
         }
     }

@@ -192,10 +192,12 @@ std::string make_key(const admm_problem* probs, int count, const char* arch) {
     std::vector<std::string> sh;
     for (int i = 0; i < count; ++i) {
         char b[48];
+        // method CG plans run other kernels: their own entries ("tvcg...", "facg...")
+        const char* cg = probs[i].method == ADMM_METHOD_CG ? "cg" : "";
         if (probs[i].reg == ADMM_REG_FRAME)
-            std::snprintf(b, sizeof b, "fa%dx%dj%d", (int)probs[i].H, (int)probs[i].W, (int)probs[i].levels);
+            std::snprintf(b, sizeof b, "fa%s%dx%dj%d", cg, (int)probs[i].H, (int)probs[i].W, (int)probs[i].levels);
         else
-            std::snprintf(b, sizeof b, "tv%dx%d", (int)probs[i].H, (int)probs[i].W);
+            std::snprintf(b, sizeof b, "tv%s%dx%d", cg, (int)probs[i].H, (int)probs[i].W);
         sh.push_back(b);
     }
     std::sort(sh.begin(), sh.end());

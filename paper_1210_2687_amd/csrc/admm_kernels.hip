@@ -791,8 +791,9 @@ __global__ void k_import_tv(const ProbDesc* __restrict__ pd, int prob) {
 // receives each problem's active flag so that the host can see the end of a
 // solve without synchronising.
 __global__ __launch_bounds__(NT) void k_reduce(const ProbDesc* __restrict__ pd, const double* __restrict__ partials,
-                                               InfoDev* __restrict__ info, double tol, int iter, int final_iter,
-                                               const int* __restrict__ iter_dev, int* __restrict__ host_active) {
+                                               InfoDev* __restrict__ info, double tol, double obj_tol, int iter,
+                                               int final_iter, const int* __restrict__ iter_dev,
+                                               int* __restrict__ host_active) {
     __shared__ double sm[NT / 64][ADMM_NSUM];
     const int prob = blockIdx.x;
     if (!info[prob].active) return;
@@ -826,6 +827,8 @@ __global__ __launch_bounds__(NT) void k_reduce(const ProbDesc* __restrict__ pd, 
         const double dual = sqrt(mu1 * mu1 * s[6] + mu2 * mu2 * s[7]);
         const double dden = fmax(sqrt(mu1 * mu1 * s[8] + mu2 * mu2 * s[9]), 1e-30);
         InfoDev f = info[prob];
+        const bool had_check = f.iters > 0;   // a previous check iteration left its objective
+        const double f_prev = f.objective;
         f.iters = iter_dev ? iter_dev[0] + iter : iter;
         f.r_pri = pri / den;
         f.r_dual = dual / dden;
@@ -835,7 +838,8 @@ __global__ __launch_bounds__(NT) void k_reduce(const ProbDesc* __restrict__ pd, 
         if (!finite) {
             f.diverged = 1;
             f.active = 0;
-        } else if (tol > 0.0 && f.r_pri <= tol && f.r_dual <= tol) {
+        } else if ((tol > 0.0 && f.r_pri <= tol && f.r_dual <= tol) ||
+                   (obj_tol > 0.0 && had_check && fabs(f.objective - f_prev) <= obj_tol * fabs(f_prev))) {
             f.converged = 1;
             f.active = 0;
         }
@@ -1038,9 +1042,9 @@ hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool
 
 int row_max_rows(int w) { return ROW_RB[size_class(w)]; }
 
-hipError_t launch_reduce(const LaunchCtx& L, int count, double tol, int iter, int final_iter, const int* iter_dev,
-                         int* host_active) {
-    hipLaunchKernelGGL(k_reduce, dim3(count), dim3(NT), 0, L.stream, L.desc, L.partials, L.info, tol, iter,
+hipError_t launch_reduce(const LaunchCtx& L, int count, double tol, double obj_tol, int iter, int final_iter,
+                         const int* iter_dev, int* host_active) {
+    hipLaunchKernelGGL(k_reduce, dim3(count), dim3(NT), 0, L.stream, L.desc, L.partials, L.info, tol, obj_tol, iter,
                        final_iter, iter_dev, host_active);
     return hipGetLastError();
 }

@@ -50,7 +50,7 @@ hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags);
 hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated);
 hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool gated);
 hipError_t launch_frame(const LaunchCtx& L, int par, int flags, int import_mode, bool gated);
-hipError_t launch_reduce(const LaunchCtx& L, int count, double tol, int iter, int final_iter,
+hipError_t launch_reduce(const LaunchCtx& L, int count, double tol, double obj_tol, int iter, int final_iter,
                          const int* iter_dev = nullptr, int* host_active = nullptr);
 hipError_t launch_tick(const LaunchCtx& L, int* counter, int c, bool set);   // counter = set ? c : counter + c
 hipError_t launch_zero(hipStream_t stream, float* p, size_t n);

@@ -37,7 +37,8 @@ from scipy import ndimage
 __all__ = [
     "Problem", "rng", "synth_image", "kernel_uniform", "kernel_gaussian",
     "kernel_motion", "kernel_disk", "valid_mask", "observe", "next_smooth7",
-    "is_smooth7", "config1", "config2", "config3", "config4", "config5_problem",
+    "is_smooth7", "config1", "config2", "config3", "config4", "config5_problem", "comparison_problem",
+    "COMPARISON_BLURS",
 ]
 
 
@@ -389,3 +390,37 @@ def boundary_pair(index, observed=480, k=25, family="uniform", sigma=1e-3, lam=2
     bc = Problem(y=y_obs, mask=ones, kernel=h, lam=lam, mu1=mu, mu2=mu, reg=reg, levels=J)
     et = Problem(y=edge_taper(y_obs, h), mask=ones, kernel=h, lam=lam, mu1=mu, mu2=mu, reg=reg, levels=J)
     return md, bc, et, x[l:H - l, l:W - l].copy(), y_obs
+
+
+COMPARISON_BLURS = ("out-of-focus", "linear motion", "uniform", "Gaussian")
+
+
+def comparison_problem(index, reg="tv", bsnr=40.0, size=256, levels=3):
+    """The MD-vs-CG comparison setting of Sec. V: a size x size unknown image
+    (the paper's cameraman is 256 x 256), one of four 19 x 19 blurs
+    (COMPARISON_BLURS[index]: disk of radius 9, 19-px motion at a random angle,
+    uniform, Gaussian sigma 3), observed on the valid region only (the
+    (size - 18)^2 pixels free of the boundary), white noise at the given BSNR
+    (variance of the valid blurred image over sigma^2, in dB), lambda 2e-4,
+    penalties by the rule of Sec. V (mu2 = 10 lambda, mu1 = min(1, 5000 mu2)).
+    reg: "tv" or "frame" (undecimated Haar, ``levels`` levels)."""
+    g = rng(1000 * 7 + 10 * index + int(bsnr))
+    H = W = size
+    x = synth_image(g, H, W, grf_scale=16.0)
+    k = 19
+    if index == 0:
+        h = kernel_disk(9.0, k)
+    elif index == 1:
+        h = kernel_motion(k, 19.0, g.uniform(0, math.pi))
+    elif index == 2:
+        h = kernel_uniform(k)
+    else:
+        h = kernel_gaussian(k, 3.0)
+    m = valid_mask(H, W, k // 2)
+    blurred = _blur_periodic(x, h)
+    sigma = math.sqrt(float(np.var(blurred[m > 0])) / 10.0 ** (bsnr / 10.0))
+    y = np.where(m > 0, blurred + sigma * g.standard_normal((H, W)), 0.0)
+    lam = 2e-4
+    mu2 = 10.0 * lam
+    return Problem(y=y, mask=m, kernel=h, lam=lam, mu1=min(1.0, 5000.0 * mu2), mu2=mu2, x_true=x,
+                   reg=reg, levels=levels if reg == "frame" else 0)

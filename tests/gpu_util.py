@@ -52,11 +52,11 @@ def full_problem(seed, H, W, k, family="gaussian", missing=0.3, lam=2e-4, mu=0.0
     return WL.Problem(y=y, mask=m, kernel=h, lam=lam, mu1=mu, mu2=mu, x_true=x, reg=reg, levels=levels)
 
 
-def gpu_solve(plan, prob, iters, state=None, tol=0.0, check_every=10, graph=False):
+def gpu_solve(plan, prob, iters, state=None, tol=0.0, check_every=10, graph=False, obj_tol=0.0):
     import torch
     y = dev(prob.y)
     x = torch.zeros_like(y)
-    info = plan.solve(y, x, state, max_iters=iters, tol=tol, check_every=check_every, graph=graph)
+    info = plan.solve(y, x, state, max_iters=iters, tol=tol, check_every=check_every, graph=graph, obj_tol=obj_tol)
     return host(x), info
 
 

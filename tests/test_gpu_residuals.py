@@ -82,3 +82,61 @@ def test_stop_iteration_follows_the_oracle_residuals(graph):
         assert all(max(hist[k]) > tol * (1 - 2e-3) for k in hist if k < kg)
         rp, rd = hist[kg]
         assert abs(info["r_pri"] - rp) <= RES_TOL * rp and abs(info["r_dual"] - rd) <= RES_TOL * rd
+
+
+def _objective_trace(p, K):
+    """F(z_k) for k = 1..K of the oracle's run (the paper's stopping quantity)."""
+    y, m, h = np.asarray(p.y, np.float64), p.mask.astype(np.float64), p.kernel
+    if p.reg == "frame":
+        F = lambda z: O.fa_objective(z, p.y, p.mask, p.kernel, p.lam, p.levels)
+        zs = O.fa_md_run(y, m, h, p.lam, p.mu1, p.mu2, p.levels, iters=K, record=range(1, K + 1))["zs"]
+    else:
+        F = lambda z: O.tv_objective(z, p.y, p.mask, p.kernel, p.lam)
+        zs = O.tv_md_run(y, m, h, p.lam, p.mu1, p.mu2, iters=K, record=range(1, K + 1))["zs"]
+    return {k: F(z) for k, z in zs.items()}
+
+
+@pytest.mark.parametrize("case", ["tv", "frame"])
+def test_objective_change_stop_follows_the_oracle(case):
+    # the paper's rule (Sec. V): stop at the first k with |F_k - F_{k-1}| <= 1e-4 F_{k-1};
+    # checked every iteration, eager and graph-replayed; the GPU stop must be an
+    # iteration where the oracle's relative change is <= 1e-4 up to FP32 noise,
+    # and no earlier iteration may clearly pass
+    obj_tol = 1e-4
+    if case == "tv":
+        p = full_problem(411, 64, 80, 7, mu=0.05)
+    else:
+        p = full_problem(412, 64, 64, 5, reg="frame", levels=2, mu=0.05)
+    ref = (O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=3000, obj_tol=obj_tol) if case == "tv" else
+           O.fa_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, p.levels, iters=3000, obj_tol=obj_tol))
+    assert ref["converged"]
+    ko = ref["iters"]
+    Fs = _objective_trace(p, ko + 5)
+    change = {k: abs(Fs[k] - Fs[k - 1]) / Fs[k - 1] for k in range(2, ko + 6)}
+    with A.Plan([p]) as plan:
+        runs = [gpu_solve(plan, p, 3000, check_every=1, graph=g, obj_tol=obj_tol) for g in (False, True)]
+    (z0, i0), (z1, i1) = runs
+    announce(f"  {case}: gpu stops at {i0['iters']} (graph {i1['iters']}), oracle at {ko}")
+    assert i0["iters"] == i1["iters"] and np.array_equal(z0, z1)
+    kg = i0["iters"]
+    assert i0["converged"] == 1
+    assert change[kg] <= obj_tol * (1 + 2e-2)
+    assert all(change[k] > obj_tol * (1 - 2e-2) for k in change if k < kg)
+    assert abs(i0["objective"] - Fs[kg]) <= 1e-4 * Fs[kg]
+
+
+def test_objective_change_stop_of_the_cg_variant_is_consistent():
+    # TV-CG with the paper's rule: the stop iteration k satisfies the rule on the
+    # device's own objective sequence (solves of k - 2, k - 1 and k iterations)
+    # and k - 1 does not
+    obj_tol = 1e-4
+    p = full_problem(413, 64, 80, 7, mu=0.05)
+    with A.Plan([p], method=A.ADMM_METHOD_CG) as plan:
+        z, info = gpu_solve(plan, p, 3000, check_every=1, graph=True, obj_tol=obj_tol)
+        k = info["iters"]
+        assert info["converged"] == 1 and k > 3
+        F = {j: gpu_solve(plan, p, j, check_every=j)[1]["objective"] for j in (k - 2, k - 1, k)}
+    announce(f"  cg stops at {k}")
+    assert F[k] == info["objective"]
+    assert abs(F[k] - F[k - 1]) <= obj_tol * abs(F[k - 1])
+    assert abs(F[k - 1] - F[k - 2]) > obj_tol * abs(F[k - 2])
