@@ -15,6 +15,8 @@ Unknown Boundaries Using the Alternating Direction Method of Multipliers":
 * TV-CG / FA-CG: the Reeves-Sorel variants with H1 = M A, the z-step by the
   Sherman-Morrison-Woodbury split and one warm-started conjugate-gradient
   iteration on the boundary system                         (Sec. IV-B..IV-D)
+* FS-MD: frame synthesis, Alg. 2 with H1 = A W, H2 = I, the z-step of
+  eq. (17) by eqs. (18) and (20)                                  (Sec. IV-C)
 
 Design rules: the convolution A and its adjoint are direct spatial sums over
 kernel taps, the z-step uses a naive dense-matrix DFT (never ``np.fft``), all
@@ -38,6 +40,7 @@ from .admm import (
 from .cg import (
     TVCGState, FACGState, tv_cg_step, tv_cg_run, fa_cg_step, fa_cg_run, boundary_cg, cg_zsolve,
 )
+from .fs import FSState, fs_zsolve, fs_md_step, fs_md_run, fs_objective, fs_residuals
 from .cnn import conv3x3_fwd, conv3x3_dgrad, conv3x3_wgrad, relu, adam_step
 
 __all__ = [
@@ -49,5 +52,6 @@ __all__ = [
     "tv_objective", "fa_objective", "tv_residuals", "fa_residuals",
     "warm_start_state", "zsolve_tv", "zsolve_fa", "default_mu",
     "TVCGState", "FACGState", "tv_cg_step", "tv_cg_run", "fa_cg_step", "fa_cg_run", "boundary_cg", "cg_zsolve",
+    "FSState", "fs_zsolve", "fs_md_step", "fs_md_run", "fs_objective", "fs_residuals",
     "conv3x3_fwd", "conv3x3_dgrad", "conv3x3_wgrad", "relu", "adam_step",
 ]

@@ -35,6 +35,14 @@ At every recorded iteration k >= 2 the files also hold the primal and dual
 residuals of the stopping rule (definitions in ``residuals``), from the same
 exact state: u_k, u_{k-1}, d_k and G z_k.
 
+The FS fixture (method fs) runs FS-MD, the frame-synthesis formulation of
+eq. (35): unknowns are the 3J+1 coefficient bands z of the image x = W z with
+W = P^T, H1 = A W, H2 = I, the z-step as the dense solve of its normal
+equations (mu1 W^T A^T A W + mu2 I) z = mu1 W^T A^T zeta1 + mu2 zeta2 (no
+use of eq. (18)), the data prox of eq. (40) on A W z and the soft threshold of
+eq. (16) on z. Its "z" lines hold the image x_k = W z_k; its residuals take
+the blocks A W z - u1 and z - u2, and its objective is eq. (35).
+
 The CG fixtures (method cg) run the Reeves-Sorel variants on the same tiny
 problems: H1 = M A, the z-step through C = (A^T A + gamma R^T R)^{-1} (a dense
 solve) and the boundary system S v = v - B C B^T v with B the rows of A at the
@@ -142,7 +150,13 @@ def _fa_cg_problem():
     return dict(_fa_problem(), name="fa_cg_4x6_J2", method="cg")
 
 
-PROBLEMS = (_tv_problem, _fa_problem, _tv_problem_8x10, _fa_problem_8x8, _tv_cg_problem, _fa_cg_problem)
+def _fs_problem():
+    # FS-MD (Sec. IV-C, frame synthesis) on the 4 x 6 FA-MD problem's data
+    return dict(_fa_problem(), name="fs_md_4x6_J2", method="fs")
+
+
+PROBLEMS = (_tv_problem, _fa_problem, _tv_problem_8x10, _fa_problem_8x8, _tv_cg_problem, _fa_cg_problem,
+            _fs_problem)
 
 
 # ----------------------------------------------------------------- dense algebra
@@ -328,7 +342,53 @@ def residuals(Az, Rz, u1, ur, d1, dr, u1_prev, ur_prev, mu1, mu2):
     return pri / den, dual / dden
 
 
+def run_fs(pb):
+    """FS-MD in exact rational arithmetic (see the module header)."""
+    one = Q(1)
+    H, W_, J = pb["H"], pb["W"], pb["J"]
+    n = H * W_
+    zero = one * 0
+    h = pb["kernel"]
+    m = [one * v for v in pb["mask"]]
+    y = list(pb["y"])
+    lam, mu1, mu2 = pb["lam"], pb["mu1"], pb["mu2"]
+    tau = lam / mu2
+    A = conv_matrix(h, H, W_, one)
+    P = [row for band in haar_bands(H, W_, J, one) for row in band]      # d x n analysis
+    Wm = transpose(P)                                                   # n x d synthesis W = P^T
+    AW = matmul(A, Wm)
+    AWt = transpose(AW)
+    d = len(P)
+    N = [scale(mu1, row) for row in matmul(AWt, AW)]
+    for i in range(d):
+        N[i][i] += mu2
+    fac = lu_factor(N)
+    u1, d1 = [zero] * n, [zero] * n
+    u2, d2 = [zero] * d, [zero] * d
+    out, res, z = {}, {}, None
+    for k in range(1, pb["iters"] + 1):
+        u1_prev, u2_prev = u1, u2
+        rhs = add(scale(mu1, matvec(AWt, add(u1, d1))), scale(mu2, add(u2, d2)))
+        z = lu_solve(fac, rhs)
+        AWz = matvec(AW, z)
+        v1 = [a - b for a, b in zip(AWz, d1)]
+        u1 = [(mi * yi + mu1 * vi) / (mi + mu1) for mi, yi, vi in zip(m, y, v1)]
+        d1 = [b - (a - u) for b, a, u in zip(d1, AWz, u1)]
+        v2 = [a - b for a, b in zip(z, d2)]
+        u2 = [(abs(a) - tau) * (1 if a > 0 else -1) if abs(a) > tau else zero for a in v2]
+        d2 = [b - (a - u) for b, a, u in zip(d2, z, u2)]
+        if k in pb["record"]:
+            out[k] = matvec(Wm, z)
+            if k >= 2:
+                res[k] = residuals(AWz, [z], u1, [u2], d1, [d2], u1_prev, [u2_prev], mu1, mu2)
+    AWz = matvec(AW, z)
+    fit = sum(((mi * (yi - a)) ** 2 for mi, yi, a in zip(m, y, AWz)), zero) / 2
+    return out, fit + lam * sum((abs(a) for a in z), zero), res
+
+
 def run(pb):
+    if pb.get("method") == "fs":
+        return run_fs(pb)
     reg = pb["reg"]
     one = Q(1) if reg == "fa" else Decimal(1)
     cv = (lambda q: q) if reg == "fa" else (lambda q: Decimal(q.numerator) / Decimal(q.denominator))
@@ -466,7 +526,10 @@ def _dec(v):
 
 def write(pb, zs, obj, res):
     path = os.path.join(HERE, pb["name"] + ".txt")
-    if pb.get("method", "md") == "cg":
+    if pb.get("method") == "fs":
+        cite = ("FS-MD: Alg. 2 with H1 = A W, H2 = I (eqs. (13), (14)), the z-step of eq. (17), data step eq. (40), "
+                "soft threshold eq. (16) on the coefficients, objective eq. (35), Sec. IV-C")
+    elif pb.get("method", "md") == "cg":
         cite = ("TV-CG: Alg. 3 with A replaced by M A, the z-step of eq. (51) with one warm-started CG step, "
                 "Sec. IV-D" if pb["reg"] == "tv" else
                 "FA-CG: Alg. 2 with H1 = M A (eq. (45)), the z-step of eq. (47) with one warm-started CG step, "

@@ -8,6 +8,7 @@ import numpy as np
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 NAMES = ("tv_md_5x6", "fa_md_4x6_J2", "tv_md_8x10", "fa_md_8x8_J3")
 CG_NAMES = ("tv_cg_5x6", "fa_cg_4x6_J2")
+FS_NAMES = ("fs_md_4x6_J2",)
 
 
 def load(name):
