@@ -11,6 +11,13 @@
  *   ADMM_REG_FRAME  FA-MD (Sec. IV-C): Alg. 2 with H1 = A, H2 = P (undecimated
  *                   Haar Parseval frame, J levels, 3J+1 bands), z-step
  *                   eqs. (24)-(25), prox eqs. (40) and (16), objective eq. (44).
+ *   ADMM_REG_FRAME_SYNTHESIS
+ *                   FS-MD (Sec. IV-C): the synthesis formulation of eq. (35),
+ *                   unknowns the 3J+1 coefficient bands z of the image
+ *                   x = W z (W = P^T, the same frame), Alg. 2 with H1 = A W,
+ *                   H2 = I, z-step eq. (17) (by eqs. (18) and (20)), prox
+ *                   eqs. (40) and (16). The output is the image x = W z; the
+ *                   state's ureg / dreg hold u2 / d2 of the coefficients.
  *
  * With method ADMM_METHOD_CG the same objectives are minimised by the
  * Reeves-Sorel variants TV-CG / FA-CG the paper compares against (Sec. IV-B
@@ -50,7 +57,7 @@ typedef enum {
     ADMM_E_DIVERGED = 6      /* non-finite iterate (info.diverged = 1)                  */
 } admm_status;
 
-typedef enum { ADMM_REG_TV = 0, ADMM_REG_FRAME = 1 } admm_reg;
+typedef enum { ADMM_REG_TV = 0, ADMM_REG_FRAME = 1, ADMM_REG_FRAME_SYNTHESIS = 2 } admm_reg;
 
 /* Splitting of the data term: mask decoupling (the paper's method, the
  * default) or the Reeves-Sorel boundary system with one CG iteration per
@@ -65,12 +72,14 @@ typedef struct {
     const uint8_t* mask;     /* HOST, H*W, 1 = observed (row of M), 0 = unobserved;
                                 copied at plan time                                    */
     int32_t reg;             /* admm_reg                                               */
-    int32_t levels;          /* frame levels J (1..4) for ADMM_REG_FRAME, else ignored */
+    int32_t levels;          /* frame levels J (1..4) for the two frame regularisers,
+                                else ignored                                           */
     double lambda;           /* regularisation weight, >= 0                            */
     double mu1, mu2;         /* ADMM penalties; a value <= 0 selects the rule of Sec. V:
                                 mu2 = 10 lambda, mu1 = min(1, 5000 mu2)                */
     int32_t method;          /* admm_method; every problem of a plan has the same one.
-                                ADMM_METHOD_CG solves start cold (st must be NULL)      */
+                                ADMM_METHOD_CG solves start cold (st must be NULL) and
+                                take ADMM_REG_TV or ADMM_REG_FRAME                     */
 } admm_problem;
 
 /* Solve options. */

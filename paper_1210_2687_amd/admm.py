@@ -15,7 +15,8 @@ import numpy as np
 
 __all__ = [
     "ADMM_OK", "ADMM_E_INVALID", "ADMM_E_UNSUPPORTED", "ADMM_E_SINGULAR", "ADMM_E_NOMEM",
-    "ADMM_E_DEVICE", "ADMM_E_DIVERGED", "ADMM_REG_TV", "ADMM_REG_FRAME", "ADMM_METHOD_MD", "ADMM_METHOD_CG",
+    "ADMM_E_DEVICE", "ADMM_E_DIVERGED", "ADMM_REG_TV", "ADMM_REG_FRAME", "ADMM_REG_FRAME_SYNTHESIS",
+    "ADMM_METHOD_MD", "ADMM_METHOD_CG",
     "ADMM_FLAG_GRAPH",
     "ADMM_FLAG_PROFILE", "admm_plan_kernel_times",
     "AdmmError", "lib", "lib_path", "exported_symbols",
@@ -26,7 +27,8 @@ __all__ = [
 ]
 
 ADMM_OK, ADMM_E_INVALID, ADMM_E_UNSUPPORTED, ADMM_E_SINGULAR, ADMM_E_NOMEM, ADMM_E_DEVICE, ADMM_E_DIVERGED = range(7)
-ADMM_REG_TV, ADMM_REG_FRAME = 0, 1
+ADMM_REG_TV, ADMM_REG_FRAME, ADMM_REG_FRAME_SYNTHESIS = 0, 1, 2
+_REGS = {"tv": ADMM_REG_TV, "frame": ADMM_REG_FRAME, "synthesis": ADMM_REG_FRAME_SYNTHESIS}
 ADMM_METHOD_MD, ADMM_METHOD_CG = 0, 1
 ADMM_FLAG_GRAPH = 1
 ADMM_FLAG_PROFILE = 2
@@ -439,10 +441,10 @@ class Plan:
         self.problems = list(problems)
         self._cprobs = []
         for p in self.problems:
-            reg = ADMM_REG_FRAME if getattr(p, "reg", "tv") == "frame" else ADMM_REG_TV
+            reg = _REGS[getattr(p, "reg", "tv")]
             self._cprobs.append(make_problem(p.kernel, p.mask, p.lam, p.mu1, p.mu2, reg, getattr(p, "levels", 0),
                                              method))
-        self.nregs = [3 * p.levels + 1 if getattr(p, "reg", "tv") == "frame" else 2 for p in self.problems]
+        self.nregs = [2 if getattr(p, "reg", "tv") == "tv" else 3 * p.levels + 1 for p in self.problems]
         if tiles is not None:
             self.handle = admm_deconv_plan_with(self._cprobs, stream=stream, **tiles)
         elif tune:

@@ -341,8 +341,11 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         d.W = q.W;
         d.P = q.W / 2 + 1;
         d.reg = q.reg;
-        d.J = q.reg == ADMM_REG_FRAME ? q.levels : 0;
-        d.nb = q.reg == ADMM_REG_FRAME ? 3 * q.levels + 1 : 2;
+        // both frame formulations plan as frame problems; fs selects the synthesis steps
+        d.fs = q.reg == ADMM_REG_FRAME_SYNTHESIS;
+        if (d.fs) d.reg = REG_FRAME;
+        d.J = d.reg == REG_FRAME ? q.levels : 0;
+        d.nb = d.reg == REG_FRAME ? 3 * q.levels + 1 : 2;
         double mu1, mu2;
         penalties(q, &mu1, &mu2);
         d.mu1 = (float)mu1;
@@ -384,7 +387,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         if (const char* e = std::getenv("ADMM_ROWS")) d.B = std::max(1, std::min(bmax, std::atoi(e)));
         d.nrowblk = (q.H + d.B - 1) / d.B;
         d.ncolblk = (d.P + d.TC - 1) / d.TC;
-        if (q.reg == ADMM_REG_FRAME) {
+        if (d.reg == REG_FRAME) {
             d.frm_tile = frame_tile(q.levels);
             d.nfrmblk = ((q.H + d.frm_tile - 1) / d.frm_tile) * ((q.W + d.frm_tile - 1) / d.frm_tile);
         }
@@ -451,7 +454,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         lds_frm_c[c] = 0;
         for (int i : order) {
             const ProbDesc& d = P->hd[i];
-            if (d.reg != REG_FRAME || frame_class(d.H, d.W, d.J) != c) continue;
+            if (d.reg != REG_FRAME || frame_class(d.H, d.W, d.J, d.fs) != c) continue;
             P->frm_beg[i] = (int)frm.size();
             for (int b = 0; b < d.nfrmblk; ++b) frm.push_back({i, b, b, 0});
             P->frm_end[i] = (int)frm.size();
@@ -754,9 +757,15 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
         if (cg) {
             // the first right-hand side (u = d = 0), the boundary estimate v and its images
             for (float* q : {d.tmpA, d.tmpB, d.cgv, d.cge, d.cgae}) HIP_TRY(launch_zero(sm, q, n));
+        } else if (d.fs && !st) {
+            // synthesis: the first data step reads W zeta2 = s / mu2 (zero at a cold start)
+            HIP_TRY(launch_zero(sm, d.tmpB, n));
         } else if (st) {
             HIP_TRY(hipMemcpyAsync(d.u1p, st[i].u1, n * sizeof(float), hipMemcpyDeviceToDevice, sm));
-            HIP_TRY(hipMemcpyAsync(d.uregp, st[i].ureg, n * d.nb * sizeof(float), hipMemcpyDeviceToDevice, sm));
+            // analysis: u_reg of the previous iteration (dual residual); synthesis: the
+            // coefficient dual d2 (its primal residual takes z = v + d2_{k-1}, and u2 is the state)
+            HIP_TRY(hipMemcpyAsync(d.uregp, d.fs ? st[i].dreg : st[i].ureg, n * d.nb * sizeof(float),
+                                   hipMemcpyDeviceToDevice, sm));
             if (d.reg == REG_TV) {
                 HIP_TRY(launch_import_tv(P->all, i, n));
             } else {

@@ -1,4 +1,4 @@
-// admm_frame.hip — frame-analysis step of FA-MD (Sec. IV-C) on gfx950.
+// admm_frame.hip — frame step of FA-MD and FS-MD (Sec. IV-C) on gfx950.
 //
 // For each FT x FT tile of the image this kernel computes, from z (written by
 // the row pass) and the frame duals d2:
@@ -17,6 +17,22 @@
 //   omega bands of level j on [-(2^j - 1), FT)^2, synthesised level by level
 //   from j = J down to 1 into a'_{j-1} on [-(2^(j-1) - 1), FT)^2; q = mu2 a'_0.
 // The duals are ping-pong buffers: halo reads see only the previous iteration.
+//
+// FS-MD (template FS): the unknowns are the coefficients z of x = W z, W = P^T.
+// With W W^T = I the z-step of eq. (17) (its matrix inverted by eq. (18))
+// has the closed form
+//   x = W z = (mu1 A^T A + mu2 I)^{-1} (mu1 A^T zeta1 + mu2 W zeta2),
+//   z = zeta2 + P (x - W zeta2),
+// (substitute z = zeta2 + W^T q into eq. (17): q = x - W zeta2 solves it, and
+// the solution is unique), so the spectral pass solves for x as FA-MD does,
+// with s = mu2 W zeta2, and the row pass hands this kernel e = x - s / mu2.
+// With zeta2 = u2 + d2 the thresholded argument is v = z - d2 = u2 + P e, and
+//   u2' = soft(v, lambda / mu2),  d2' = u2' - v,  zeta2' = u2' + d2',
+//   s'  = mu2 P^T zeta2'.
+// The working state is u2 (ping-pong); z = v + d2 is needed only for the
+// residual sums, so d2 is kept (in the u_prev planes) on the iteration before
+// a check, while the dual residual reads u2 of the previous iteration from the
+// state itself.
 #include "admm_internal.h"
 #include "admm_launch.h"
 #include "fft_lds.h"
@@ -60,7 +76,7 @@ __host__ __device__ constexpr int fr_cdiv(int a, int b) { return (a + b - 1) / b
 // initialised from it; used to start or resume a solve.
 enum { FR_PLAIN = 0, FR_CHECK = 1, FR_IMPORT = 2 };
 
-template <int J, bool SMALL, int MODE>
+template <int J, bool SMALL, int MODE, bool FS>
 __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                int nitems, int par, int flags, const InfoDev* __restrict__ info,
                                                double* __restrict__ partials) {
@@ -186,6 +202,30 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
     // prox, dual update and omega = u2 + d2'. Only the owner of a coefficient
     // (its tile) writes it back and counts it in the residual sums.
     auto coef = [&](float Pz, float dl, float uprev, unsigned g, bool own) -> float {
+        if (FS) {
+            // Pz = P e, dl = u2 of the previous iteration, uprev = d2_{k-1} (check iterations)
+            const float v = dl + Pz;
+            const float u = softf(v, tau);
+            const float dn = u - v;              // d2' = d2 - (z - u2')
+            if (own) {
+                gst(dout, g, u);
+                if (chk) {
+                    const float z = v + uprev, e = z - u, f = u - dl;
+                    acc[1] += (double)(e * e);
+                    acc[3] += (double)(z * z);
+                    acc[5] += (double)(u * u);
+                    acc[7] += (double)(f * f);
+                    acc[9] += (double)(dn * dn);
+                    acc[11] += (double)fabsf(z);
+                }
+                if (flags & F_WRITE_UPREV) gst(UREGP, g, dn);
+                if (flags & F_EXPORT) {
+                    gst(SUREG, g, u);
+                    gst(SDREG, g, dn);
+                }
+            }
+            return u + dn;
+        }
         const float v = Pz - dl;
         const float u = softf(v, tau);
         const float dn = u - v;                  // d2 - (P z - u2)
@@ -210,7 +250,7 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
     };
     auto coef_import = [&](unsigned g, bool own) -> float {
         const float d = gld(SDREG, g), u = gld(SUREG, g);
-        if (own) gst(dout, g, d);
+        if (own) gst(dout, g, FS ? u : d);   // the working state: d2 (analysis) or u2 (synthesis)
         return u + d;
     };
     auto owns = [&](int i, int k) { return (unsigned)i < hlim && (unsigned)k < wlim; };
@@ -314,9 +354,9 @@ __global__ void k_import_fa(const ProbDesc* __restrict__ pd, int prob) {
     gst(p.d1, g, gld(p.st_d1, g));
 }
 
-int frame_class(int H, int W, int J) {
+int frame_class(int H, int W, int J, bool fs) {
     const int w = frame_tile(J) + 2 * ((1 << J) - 1);
-    return 2 * (J - 1) + ((H < w || W < w) ? 1 : 0);
+    return (fs ? 8 : 0) + 2 * (J - 1) + ((H < w || W < w) ? 1 : 0);
 }
 
 size_t lds_frame_bytes(int J) {
@@ -327,20 +367,34 @@ size_t lds_frame_bytes(int J) {
 }
 
 namespace {
-template <int J, bool SMALL>
+template <int J, bool SMALL, bool FS>
 void launch_frame_class(const LaunchCtx& L, int c, int par, int flags, int import_mode, bool gated) {
     const WorkItem* it = L.frm_items + L.frm_beg[c];
     const int n = L.frm_cnt[c];
     const InfoDev* info = gated ? L.info : nullptr;
     if (import_mode)
-        hipLaunchKernelGGL((k_frame<J, SMALL, FR_IMPORT>), dim3(n), dim3(NTF), L.lds_frm_c[c], L.stream, L.desc, it, n,
-                           par, flags, info, L.partials);
+        hipLaunchKernelGGL((k_frame<J, SMALL, FR_IMPORT, FS>), dim3(n), dim3(NTF), L.lds_frm_c[c], L.stream, L.desc,
+                           it, n, par, flags, info, L.partials);
     else if (flags & F_CHECK)
-        hipLaunchKernelGGL((k_frame<J, SMALL, FR_CHECK>), dim3(n), dim3(NTF), L.lds_frm_c[c], L.stream, L.desc, it, n,
-                           par, flags, info, L.partials);
+        hipLaunchKernelGGL((k_frame<J, SMALL, FR_CHECK, FS>), dim3(n), dim3(NTF), L.lds_frm_c[c], L.stream, L.desc,
+                           it, n, par, flags, info, L.partials);
     else
-        hipLaunchKernelGGL((k_frame<J, SMALL, FR_PLAIN>), dim3(n), dim3(NTF), L.lds_frm_c[c], L.stream, L.desc, it, n,
-                           par, flags, info, L.partials);
+        hipLaunchKernelGGL((k_frame<J, SMALL, FR_PLAIN, FS>), dim3(n), dim3(NTF), L.lds_frm_c[c], L.stream, L.desc,
+                           it, n, par, flags, info, L.partials);
+}
+
+template <bool FS>
+void launch_frame_kind(const LaunchCtx& L, int c, int par, int flags, int import_mode, bool gated) {
+    switch (c & 7) {
+        case 0: launch_frame_class<1, false, FS>(L, c, par, flags, import_mode, gated); break;
+        case 1: launch_frame_class<1, true, FS>(L, c, par, flags, import_mode, gated); break;
+        case 2: launch_frame_class<2, false, FS>(L, c, par, flags, import_mode, gated); break;
+        case 3: launch_frame_class<2, true, FS>(L, c, par, flags, import_mode, gated); break;
+        case 4: launch_frame_class<3, false, FS>(L, c, par, flags, import_mode, gated); break;
+        case 5: launch_frame_class<3, true, FS>(L, c, par, flags, import_mode, gated); break;
+        case 6: launch_frame_class<4, false, FS>(L, c, par, flags, import_mode, gated); break;
+        default: launch_frame_class<4, true, FS>(L, c, par, flags, import_mode, gated); break;
+    }
 }
 }  // namespace
 
@@ -348,16 +402,10 @@ void launch_frame_class(const LaunchCtx& L, int c, int par, int flags, int impor
 hipError_t launch_frame(const LaunchCtx& L, int par, int flags, int import_mode, bool gated) {
     for (int c = 0; c < ADMM_FRAME_CLASSES; ++c) {
         if (!L.frm_items || L.frm_cnt[c] == 0) continue;
-        switch (c) {
-            case 0: launch_frame_class<1, false>(L, c, par, flags, import_mode, gated); break;
-            case 1: launch_frame_class<1, true>(L, c, par, flags, import_mode, gated); break;
-            case 2: launch_frame_class<2, false>(L, c, par, flags, import_mode, gated); break;
-            case 3: launch_frame_class<2, true>(L, c, par, flags, import_mode, gated); break;
-            case 4: launch_frame_class<3, false>(L, c, par, flags, import_mode, gated); break;
-            case 5: launch_frame_class<3, true>(L, c, par, flags, import_mode, gated); break;
-            case 6: launch_frame_class<4, false>(L, c, par, flags, import_mode, gated); break;
-            default: launch_frame_class<4, true>(L, c, par, flags, import_mode, gated); break;
-        }
+        if (c < 8)
+            launch_frame_kind<false>(L, c, par, flags, import_mode, gated);
+        else
+            launch_frame_kind<true>(L, c, par, flags, import_mode, gated);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -44,9 +44,12 @@ admm_status validate(const admm_problem& p) {
     if (!p.kernel || !p.mask) return fail(ADMM_E_INVALID, "null kernel or mask pointer");
     if (p.ksize < 1 || p.ksize % 2 == 0 || p.ksize > std::min(p.H, p.W))
         return fail(ADMM_E_UNSUPPORTED, "kernel side %d must be odd and <= min(H, W)", p.ksize);
-    if (p.reg != ADMM_REG_TV && p.reg != ADMM_REG_FRAME) return fail(ADMM_E_INVALID, "unknown regulariser %d", p.reg);
+    if (p.reg != ADMM_REG_TV && p.reg != ADMM_REG_FRAME && p.reg != ADMM_REG_FRAME_SYNTHESIS)
+        return fail(ADMM_E_INVALID, "unknown regulariser %d", p.reg);
     if (p.method != ADMM_METHOD_MD && p.method != ADMM_METHOD_CG) return fail(ADMM_E_INVALID, "unknown method %d", p.method);
-    if (p.reg == ADMM_REG_FRAME && (p.levels < 1 || p.levels > 4))
+    if (p.method == ADMM_METHOD_CG && p.reg == ADMM_REG_FRAME_SYNTHESIS)
+        return fail(ADMM_E_UNSUPPORTED, "the synthesis formulation runs with mask decoupling only");
+    if (p.reg != ADMM_REG_TV && (p.levels < 1 || p.levels > 4))
         return fail(ADMM_E_UNSUPPORTED, "frame levels %d outside 1..4", p.levels);
     if (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)) return fail(ADMM_E_INVALID, "lambda must be finite and >= 0");
     if (!std::isfinite(p.mu1) || !std::isfinite(p.mu2)) return fail(ADMM_E_INVALID, "mu must be finite");
@@ -194,8 +197,9 @@ std::string make_key(const admm_problem* probs, int count, const char* arch) {
         char b[48];
         // method CG plans run other kernels: their own entries ("tvcg...", "facg...")
         const char* cg = probs[i].method == ADMM_METHOD_CG ? "cg" : "";
-        if (probs[i].reg == ADMM_REG_FRAME)
-            std::snprintf(b, sizeof b, "fa%s%dx%dj%d", cg, (int)probs[i].H, (int)probs[i].W, (int)probs[i].levels);
+        if (probs[i].reg != ADMM_REG_TV)
+            std::snprintf(b, sizeof b, "%s%s%dx%dj%d", probs[i].reg == ADMM_REG_FRAME ? "fa" : "fs", cg,
+                          (int)probs[i].H, (int)probs[i].W, (int)probs[i].levels);
         else
             std::snprintf(b, sizeof b, "tv%s%dx%d", cg, (int)probs[i].H, (int)probs[i].W);
         sh.push_back(b);

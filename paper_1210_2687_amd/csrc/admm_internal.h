@@ -193,6 +193,7 @@ struct ProbDesc {
     // circulant solves of an iteration, the step length, and mu_t (mu1 for TV,
     // where the solve returns t / mu1; 1 for the frame)
     int method;
+    int fs;                     // frame synthesis (FS-MD): the frame pass works on coefficients
     float mut;
     float* cgv;
     float* cge;

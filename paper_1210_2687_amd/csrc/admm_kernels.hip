@@ -633,7 +633,9 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
 // ------------------------------------------------------------ spectrum rows -> planes
 // Inverse row DFT of (z^ + i A z^) for rows [r0, r0 + nr).
 //   mode 0 (blur): write z (the real part) to tmpB.
-//   mode 1 (FA data step): z -> zpl, mask prox and data dual (eq. (40)), zeta1 -> tmpA.
+//   mode 1 (FA data step): z -> zpl, mask prox and data dual (eq. (40)), zeta1 -> tmpA;
+//          for a synthesis problem (FS-MD) zpl receives x - s / mu2 = x - W zeta2 instead
+//          (tmpB holds s = mu2 W zeta2 of the previous frame step).
 //   mode 2, 3 (method CG): the two parts to (cgo1, cgao1), (cgo2, cgao2).
 // Rows padded as in k_row_fwd.
 template <int CPT, int RB>
@@ -687,6 +689,8 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     }
     const float c1 = p.inv1pmu1;
     const bool chk = flags & F_CHECK;
+    const bool fs = p.fs != 0;
+    const float inv_mu2 = 1.0f / p.mu2;
     // descriptor fields read once (the row loop's global stores would make the
     // compiler reload each of them, and wait for it, on every row)
     float* const D1 = p.d1;
@@ -698,6 +702,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     float* const SD1 = p.st_d1;
     const uint8_t* const MK = p.mask;
     const float* const YV = p.y;
+    const float* const SB = p.tmpB;
     double acc[ADMM_NSUM];
 #pragma unroll
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
@@ -735,7 +740,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
                 const float d1n = u1 - v1;
                 gst(D1, g, d1n);
                 gst(TA, g, u1 + d1n);
-                gst(ZP, g, z);
+                gst(ZP, g, fs ? fmaf(-inv_mu2, gld(SB, g), z) : z);
                 if (flags & F_WRITE_X) gst(XO, g, z);
                 if (chk) {
                     const float e0 = Az - u1, f6 = u1 - gld(U1P, g), ry = yv - Az;

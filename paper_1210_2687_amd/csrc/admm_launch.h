@@ -5,7 +5,7 @@
 
 namespace admm {
 
-constexpr int ADMM_FRAME_CLASSES = 8;
+constexpr int ADMM_FRAME_CLASSES = 16;   // (analysis, synthesis) x levels 1..4 x (small image)
 // column classes: 2 x (size class of the column length) + 1 for a general
 // schedule (first or last stage not radix 8: the column cannot stay in
 // registers around the solve), each launched with its own instantiation
@@ -75,7 +75,7 @@ size_t lds_col_bytes(int H, int TC);
 size_t lds_rowtv_bytes(int W, int B);
 size_t lds_row_bytes(int W, int B);
 size_t lds_frame_bytes(int J);
-int frame_class(int H, int W, int J);       // 2 (J - 1) + (image smaller than a window)
+int frame_class(int H, int W, int J, bool fs);   // 8 fs + 2 (J - 1) + (image smaller than a window)
 int col_max_tiles();                       // columns per column-pass block (one per wave)
 int row_tv_max_rows(int w);                  // rows per block of the TV row pass for width w
 int row_max_rows(int w);                     // rows per block of the plain row passes for width w

@@ -56,7 +56,7 @@ class Problem:
     mu1: float
     mu2: float
     x_true: np.ndarray = field(repr=False, default=None)
-    reg: str = "tv"        # "tv" or "frame"
+    reg: str = "tv"        # "tv", "frame" (analysis, FA) or "synthesis" (FS)
     levels: int = 0        # frame levels J for reg == "frame"
 
     @property

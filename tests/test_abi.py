@@ -48,12 +48,24 @@ def _prob(**kw):
     kern = kw.pop("kernel", WL.kernel_uniform(k))
     mask = kw.pop("mask", WL.valid_mask(H, W, k // 2))
     return A.make_problem(kern, mask, kw.pop("lam", 1e-3), reg=kw.pop("reg", A.ADMM_REG_TV),
-                          levels=kw.pop("levels", 0))
+                          levels=kw.pop("levels", 0), method=kw.pop("method", None))
 
 
 def test_validation_accepts_good_problem():
     assert A.admm_validate_problem(_prob()) == A.ADMM_OK
     assert A.admm_validate_problem(_prob(reg=A.ADMM_REG_FRAME, levels=3)) == A.ADMM_OK
+    assert A.admm_validate_problem(_prob(reg=A.ADMM_REG_FRAME_SYNTHESIS, levels=2)) == A.ADMM_OK
+    for reg, J in ((A.ADMM_REG_TV, 0), (A.ADMM_REG_FRAME, 2)):
+        assert A.admm_validate_problem(_prob(reg=reg, levels=J, method=A.ADMM_METHOD_CG)) == A.ADMM_OK
+
+
+def test_validation_of_methods_and_the_synthesis_formulation():
+    # FS-MD needs frame levels; the synthesis formulation has no CG variant here; unknown methods are invalid
+    assert A.admm_validate_problem(_prob(reg=A.ADMM_REG_FRAME_SYNTHESIS, levels=0)) == A.ADMM_E_UNSUPPORTED
+    assert A.admm_validate_problem(_prob(reg=A.ADMM_REG_FRAME_SYNTHESIS, levels=1,
+                                         method=A.ADMM_METHOD_CG)) == A.ADMM_E_UNSUPPORTED
+    assert A.admm_validate_problem(_prob(method=7)) == A.ADMM_E_INVALID
+    assert A.admm_validate_problem(_prob(reg=3)) == A.ADMM_E_INVALID
 
 
 @pytest.mark.parametrize("case,status", [
