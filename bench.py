@@ -13,6 +13,12 @@ The same JSON line also carries, under "configs", the other workloads:
               oracle's wall time is in cpu_baseline)
   c3          FA-MD 1024^2, J = 3, 13x13 disk, 20% missing 8x8 blocks, time to
               residual tolerance 1e-4
+  c3_fs       FS-MD (frame synthesis) on the c3 data, 400 iterations
+  headline_cg TV-CG (Reeves-Sorel, one CG step per iteration) on the
+              headline batch
+  md_vs_cg    the paper's MD-vs-CG comparison (Tables 3 and 4): 256^2,
+              four 19x19 blurs, TV and FA, MD to the paper's stopping rule,
+              CG to the MD objective
   c4          ragged batch of 256 TV-MD problems (sides 128..1024, kernels
               5..31), 200 iterations
   beyond_cache  64 x 512^2 TV-MD, 500 iterations (working set ~0.9 GB, far
@@ -27,6 +33,7 @@ launch duration as well. ``--quick`` runs the headline alone.
 """
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -69,9 +76,11 @@ def alg_bytes_per_launch(problems):
              y (4 B / px) and the mask (1 B / px); write d1, d^h, d^v
              (12 B / px) and the next half spectra (16 B / entry).
     row_inv: read the half spectra (16 B / entry), d1, y, mask (9 B / px);
-             write d1, zeta1, z (12 B / px).
+             write d1, zeta1, z (12 B / px); the synthesis formulation also
+             reads s (4 B / px).
     frame:   read z (4 B / px) and the 3J+1 frame duals, write the duals and
-             q (4 B / px): 8 + 8 (3J+1) B / px.
+             q (4 B / px): 8 + 8 (3J+1) B / px (the synthesis formulation:
+             x - W zeta2 and the coefficients u2, the same count).
     row_fwd: read zeta1 and q (8 B / px), write the half spectra (16 B / entry).
     Halo re-reads are not counted (they are overhead, not algorithmic).
     """
@@ -81,8 +90,9 @@ def alg_bytes_per_launch(problems):
         hp = H * (W // 2 + 1)
         n = H * W
         out["col"] += 40 * hp
-        if getattr(p, "reg", "tv") == "frame":
-            out["row_inv"] += 16 * hp + 21 * n
+        reg = getattr(p, "reg", "tv")
+        if reg in ("frame", "synthesis"):
+            out["row_inv"] += 16 * hp + (25 if reg == "synthesis" else 21) * n
             out["frame"] += (8 + 8 * (3 * p.levels + 1)) * n
             out["row_fwd"] += 8 * n + 16 * hp
         else:
@@ -129,8 +139,9 @@ def host_data(args):
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=workers) as ex:
         data["c2"] = list(ex.map(partial(_c2_member, size=args.size), range(args.batch)))
-        if args.workload == "fa1024" or not args.quick:
+        if args.workload in ("fa1024", "fs1024") or not args.quick:
             data["c3"] = WL.config3(size=1024, levels=3)
+            data["c3_fs"] = dataclasses.replace(data["c3"], reg="synthesis")
         if args.workload == "ragged256" or not args.quick:
             data["c4"] = list(ex.map(WL.config4, range(256), chunksize=4))
         if args.workload == "tv64x512" or not args.quick:
@@ -466,7 +477,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tv8x512",
-                    choices=["tv8x512", "tv64x512", "fa1024", "ragged256", "md_vs_cg", "tv8x512_cg"],
+                    choices=["tv8x512", "tv64x512", "fa1024", "fs1024", "ragged256", "md_vs_cg", "tv8x512_cg"],
                     help="the headline is tv8x512; with --quick, the others run alone (profiling)")
     ap.add_argument("--quick", action="store_true", help="only the chosen workload, no other configs")
     ap.add_argument("--iters", type=int, default=500, help="ADMM iterations per headline step")
@@ -478,6 +489,8 @@ def main():
     ap.add_argument("--ws-steps", type=int, default=8000, help="warm-start Adam steps of 8")
     ap.add_argument("--ws-eval", type=int, default=512, help="warm-start evaluation problems (512x512)")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--c3-max-iters", type=int, default=5000,
+                    help="iteration cap of the FA 1024^2 time-to-tolerance solves (a small cap shortens profiled runs)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the planner's heuristic tile shapes instead of the autotuner (which runs at plan time, "
                          "outside the timed region; ADMM_TUNE_CACHE names an optional JSON cache)")
@@ -516,7 +529,10 @@ def main():
     if args.quick and args.workload != "tv8x512":
         # one other workload alone, for profiling
         if args.workload == "fa1024":
-            configs["c3"] = run_c3(data["c3"])
+            configs["c3"] = run_c3(data["c3"], max_iters=args.c3_max_iters)
+        elif args.workload == "fs1024":
+            configs["c3_fs"] = run_throughput("c3_fs", [data["c3_fs"]], 400, args.steps, args.warmup, tune,
+                                              "FS-MD on the FA 1024x1024 J = 3 data, 400 iterations")
         elif args.workload == "md_vs_cg":
             configs["md_vs_cg"] = run_md_vs_cg()
         elif args.workload == "tv8x512_cg":
@@ -554,6 +570,9 @@ def main():
         configs["beyond_cache"] = run_throughput("beyond_cache", data["c64"], 500, 3, 1, tune,
                                                  "TV-MD batch of 64 x 512x512 (the 8 headline images repeated), "
                                                  "500 iterations")
+        configs["c3_fs"] = run_throughput("c3_fs", [data["c3_fs"]], 400, 3, 1, tune,
+                                          "FS-MD (frame synthesis, eq. (35)) on the FA 1024x1024 J = 3 data, "
+                                          "400 iterations")
         configs["headline_cg"] = run_throughput("headline_cg", probs, args.iters, 3, 1, tune,
                                                 f"TV-CG (Reeves-Sorel, one CG step) on the headline batch of "
                                                 f"{args.batch} x {args.size}^2, {args.iters} iterations",

@@ -502,7 +502,6 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     const size_t o_kbase = take(sizeof(int));
     const size_t o_part = take(sizeof(double) * ADMM_NSUM * std::max(part, 1));
     const size_t o_cgpart = cg ? take(sizeof(double) * 2 * std::max(part, 1)) : 0;
-    const size_t o_cgalpha = cg ? take(sizeof(float) * count) : 0;
     const size_t o_tw = take(sizeof(float2) * tab_len);
     const size_t o_s2 = take(sizeof(float) * tab_len);
     // row sums of the kernel spectrum (host-computed, consumed at plan time):
@@ -592,7 +591,6 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         if (cg) {
             float** planes[7] = {&d.cgv, &d.cge, &d.cgae, &d.cgo1, &d.cgao1, &d.cgo2, &d.cgao2};
             for (int j = 0; j < 7; ++j) *planes[j] = (float*)(A + o.cg[j]);
-            d.cgalpha = (float*)(A + o_cgalpha) + i;
         }
     }
 
@@ -819,8 +817,10 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
     };
     // one iteration on contexts cA (all), cT (TV rows), cF (FA rows/frame)
     // method CG (see admm_cg.hip): both circulant solves run forward rows,
-    // columns and inverse rows in place on spec0; the CG and data steps run
-    // per row block, then the TV step or the frame step
+    // columns and inverse rows in place on spec0 (the first solve's inverse
+    // rows also form the boundary-system direction and transform it for the
+    // second); the CG and data steps run per row block, then the TV step or
+    // the frame step
     auto cg_iteration = [&](const LaunchCtx& cA, const LaunchCtx& cT, const LaunchCtx& cF, int par,
                             int flags) -> hipError_t {
         hipError_t e = hipSuccess;
@@ -829,13 +829,12 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
             for (const LaunchCtx* r : rows)
                 if (e == hipSuccess && r->nrow) e = timed(cls, [&] { return fn(*r); });
         };
+        // the inverse rows of the first solve end with the forward rows of the second
+        each(4, [&](const LaunchCtx& r) { return launch_row_fwd(r, 0, 0, true); });
         for (int solve = 0; solve < 2 && e == hipSuccess; ++solve) {
-            each(4, [&](const LaunchCtx& r) { return launch_row_fwd(r, 0, 0, true); });
             if (e == hipSuccess) e = timed(0, [&] { return launch_col(cA, 0, COL_SOLVE); });
             each(2, [&](const LaunchCtx& r) { return launch_row_inv(r, 0, 2 + solve, 0, true); });
-            each(6, [&](const LaunchCtx& r) { return solve == 0 ? launch_cg_dir(r) : launch_cg_dot(r); });
         }
-        if (e == hipSuccess) e = timed(6, [&] { return launch_cg_alpha(cA, count); });
         each(6, [&](const LaunchCtx& r) { return launch_cg_update(r, flags); });
         if (e == hipSuccess && cT.nrow) e = timed(6, [&] { return launch_cg_tv(cT, par, flags); });
         if (e == hipSuccess && cF.nrow) e = timed(3, [&] { return launch_frame(cF, par, flags, 0, true); });

@@ -6,16 +6,19 @@
 //
 // One iteration, with the circulant solves done by the FFT passes (row DFT,
 // column DFT + solve + inverse, inverse row DFT into a pair of planes):
-//   solve 1   (M (u1 + d1), s)   -> O1 = C r / mu_t, AO1 = A O1
-//   k_cg_dir  p = res = B (C r + C B^T v) - v on the unobserved pixels, with
-//             C B^T v and A C B^T v held as the images e, Ae; sum p^2
-//   solve 2   (p, 0)             -> O2 = C B^T p, AO2 = A O2
-//   k_cg_dot  sum p (I - B C B^T) p = sum p (p - (1 - m) AO2)
-//   k_cg_alpha  a = sum p^2 / sum p S p (0 unless both are positive)
-//   k_cg_update v += a p, e += a O2, Ae += a AO2 (linearity of C B^T and A),
-//             z = O1 + e / mu_t, A z = AO1 + Ae / mu_t, data step on the
-//             observed pixels u1 = (y + mu1 (A z - d1)) / (1 + mu1),
-//             d1 <- d1 - (A z - u1), next M (u1 + d1)
+//   solve 1   (M (u1 + d1), s)   -> O1 = C r / mu_t, AO1 = A O1; the inverse
+//             row pass also forms p = res = B (C r + C B^T v) - v on the
+//             unobserved pixels (C B^T v and A C B^T v held as the images e,
+//             Ae), the row block's sum p^T p and the forward row DFT of
+//             (mu1 p, 0), which starts the second solve
+//   solve 2   (p, 0)             -> O2 = C B^T p, AO2 = A O2, and the row
+//             block's p^T (I - B C B^T) p = p^T (p - (1 - m) AO2)
+//   k_cg_update  a = sum p^T p / sum p^T S p over the problem's row blocks (0
+//             unless both are positive), v += a p, e += a O2, Ae += a AO2
+//             (linearity of C B^T and A), z = O1 + e / mu_t,
+//             A z = AO1 + Ae / mu_t, data step on the observed pixels
+//             u1 = (y + mu1 (A z - d1)) / (1 + mu1), d1 <- d1 - (A z - u1),
+//             next M (u1 + d1)
 //   k_cg_tv   (TV) vector soft threshold, TV duals, next s = mu2 D^T (u + d);
 //             the frame variant runs the FA frame step on z instead.
 // Every kernel takes the rows of one row item of a problem (the work items of
@@ -67,91 +70,36 @@ __device__ void cg_write_sums(const double* acc, double* slot, bool odd) {
 
 }  // namespace
 
-// p = res on the unobserved pixels (0 on the observed), into tmpA, with tmpB = 0:
-// the input pair of the second solve.
-__global__ __launch_bounds__(NTG) void k_cg_dir(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
-                                               const InfoDev* __restrict__ info, double* __restrict__ cgpart) {
-    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    if (!info[it.prob].active) return;
-    const ProbDesc& p = pd[it.prob];
-    const int W = p.W, nr = min(p.B, p.H - it.start);
-    const unsigned base = (unsigned)(it.start * W), cnt = (unsigned)(nr * W);
-    const float mut = p.mut;
-    const uint8_t* const MK = p.mask;
-    const float* const AO1 = p.cgao1;
-    const float* const AE = p.cgae;
-    const float* const V = p.cgv;
-    float* const TA = p.tmpA;
-    float* const TB = p.tmpB;
-    double acc[1] = {0.0};
-    for (unsigned i = threadIdx.x; i < cnt; i += NTG) {
-        const unsigned g = base + i;
-        const bool obs = gld(MK, g) != 0;
-        const float r = fmaf(mut, gld(AO1, g), gld(AE, g)) - gld(V, g);
-        const float pv = obs ? 0.0f : r;
-        gst(TA, g, pv);
-        gst(TB, g, 0.0f);
-        acc[0] += (double)pv * (double)pv;
-    }
-    __shared__ double res[1];
-    cg_block_sums<1>(acc, res);
-    __syncthreads();
-    if (threadIdx.x == 0) cgpart[(size_t)(p.part_base + it.blk) * 2] = res[0];
-}
-
-// sum p (I - B C B^T) p over the block's rows: p (p - (1 - m) AO2)
-__global__ __launch_bounds__(NTG) void k_cg_dot(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
-                                               const InfoDev* __restrict__ info, double* __restrict__ cgpart) {
-    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    if (!info[it.prob].active) return;
-    const ProbDesc& p = pd[it.prob];
-    const int W = p.W, nr = min(p.B, p.H - it.start);
-    const unsigned base = (unsigned)(it.start * W), cnt = (unsigned)(nr * W);
-    const uint8_t* const MK = p.mask;
-    const float* const TA = p.tmpA;
-    const float* const AO2 = p.cgao2;
-    double acc[1] = {0.0};
-    for (unsigned i = threadIdx.x; i < cnt; i += NTG) {
-        const unsigned g = base + i;
-        const bool obs = gld(MK, g) != 0;
-        const float pv = gld(TA, g);
-        const float q = obs ? 0.0f : pv - gld(AO2, g);
-        acc[0] += (double)pv * (double)q;
-    }
-    __shared__ double res[1];
-    cg_block_sums<1>(acc, res);
-    __syncthreads();
-    if (threadIdx.x == 0) cgpart[(size_t)(p.part_base + it.blk) * 2 + 1] = res[0];
-}
-
-// a = sum p^2 / sum p S p per problem, summed over its row blocks in a fixed
-// order; 0 when the direction vanishes or the quotient is not a positive number.
-__global__ void k_cg_alpha(const ProbDesc* __restrict__ pd, const InfoDev* __restrict__ info,
-                           const double* __restrict__ cgpart, int count) {
-    const int prob = blockIdx.x * blockDim.x + threadIdx.x;
-    if (prob >= count || !info[prob].active) return;
-    const ProbDesc& p = pd[prob];
-    double rr = 0.0, pq = 0.0;
-    for (int b = 0; b < p.nrowblk; ++b) {
-        rr += cgpart[(size_t)(p.part_base + b) * 2];
-        pq += cgpart[(size_t)(p.part_base + b) * 2 + 1];
-    }
-    const double a = (rr > 0.0 && pq > 0.0) ? rr / pq : 0.0;
-    p.cgalpha[0] = isfinite(a) ? (float)a : 0.0f;
-}
-
 // CG update, z, A z and the data step (observed pixels), the data block's
 // residual sums on check iterations (the regulariser entries written as zero).
 template <bool CHK>
 __global__ __launch_bounds__(NTG) void k_cg_update(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                   const InfoDev* __restrict__ info, int flags,
-                                                  double* __restrict__ partials) {
+                                                  const double* __restrict__ cgpart, double* __restrict__ partials) {
     const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     if (!info[it.prob].active) return;
     const ProbDesc& p = pd[it.prob];
     const int W = p.W, nr = min(p.B, p.H - it.start);
     const unsigned base = (unsigned)(it.start * W), cnt = (unsigned)(nr * W);
-    const float a = p.cgalpha[0], inv_mut = 1.0f / p.mut, mu1 = p.mu1, c1 = p.inv1pmu1;
+    // the step length from the row blocks' sums; every block of the problem
+    // adds them in the same order, so all of them use the same a
+    __shared__ float a_sh;
+    {
+        double two[2] = {0.0, 0.0};
+        for (int b = threadIdx.x; b < p.nrowblk; b += NTG) {
+            two[0] += cgpart[(size_t)(p.part_base + b) * 2];
+            two[1] += cgpart[(size_t)(p.part_base + b) * 2 + 1];
+        }
+        __shared__ double sums[2];
+        cg_block_sums<2>(two, sums);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double q = (sums[0] > 0.0 && sums[1] > 0.0) ? sums[0] / sums[1] : 0.0;
+            a_sh = isfinite(q) ? (float)q : 0.0f;
+        }
+        __syncthreads();
+    }
+    const float a = a_sh, inv_mut = 1.0f / p.mut, mu1 = p.mu1, c1 = p.inv1pmu1;
     const uint8_t* const MK = p.mask;
     const float* const YV = p.y;
     const float* const TA = p.tmpA;   // p of this iteration
@@ -281,31 +229,14 @@ __global__ __launch_bounds__(NTG) void k_cg_tv(const ProbDesc* __restrict__ pd, 
 }
 
 // ------------------------------------------------------------ launchers
-hipError_t launch_cg_dir(const LaunchCtx& L) {
-    if (!L.nrow) return hipSuccess;
-    hipLaunchKernelGGL(k_cg_dir, dim3(L.nrow), dim3(NTG), 0, L.stream, L.desc, L.row_items, L.info, L.cgpart);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_dot(const LaunchCtx& L) {
-    if (!L.nrow) return hipSuccess;
-    hipLaunchKernelGGL(k_cg_dot, dim3(L.nrow), dim3(NTG), 0, L.stream, L.desc, L.row_items, L.info, L.cgpart);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_alpha(const LaunchCtx& L, int count) {
-    hipLaunchKernelGGL(k_cg_alpha, dim3((count + 63) / 64), dim3(64), 0, L.stream, L.desc, L.info, L.cgpart, count);
-    return hipGetLastError();
-}
-
 hipError_t launch_cg_update(const LaunchCtx& L, int flags) {
     if (!L.nrow) return hipSuccess;
     if (flags & F_CHECK)
         hipLaunchKernelGGL(k_cg_update<true>, dim3(L.nrow), dim3(NTG), 0, L.stream, L.desc, L.row_items, L.info, flags,
-                           L.partials);
+                           L.cgpart, L.partials);
     else
         hipLaunchKernelGGL(k_cg_update<false>, dim3(L.nrow), dim3(NTG), 0, L.stream, L.desc, L.row_items, L.info,
-                           flags, L.partials);
+                           flags, L.cgpart, L.partials);
     return hipGetLastError();
 }
 

@@ -190,8 +190,8 @@ struct ProbDesc {
     float* st_dreg;
     // Reeves-Sorel variants (method CG): the boundary-system estimate v, the
     // images C B^T v and A C B^T v, the outputs (z part, A z part) of the two
-    // circulant solves of an iteration, the step length, and mu_t (mu1 for TV,
-    // where the solve returns t / mu1; 1 for the frame)
+    // circulant solves of an iteration, and mu_t (mu1 for TV, where the solve
+    // returns t / mu1; 1 for the frame)
     int method;
     int fs;                     // frame synthesis (FS-MD): the frame pass works on coefficients
     float mut;
@@ -202,7 +202,6 @@ struct ProbDesc {
     float* cgao1;
     float* cgo2;
     float* cgao2;
-    float* cgalpha;
 };
 
 enum { METHOD_MD = 0, METHOD_CG = 1 };

@@ -636,7 +636,8 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
 //   mode 1 (FA data step): z -> zpl, mask prox and data dual (eq. (40)), zeta1 -> tmpA;
 //          for a synthesis problem (FS-MD) zpl receives x - s / mu2 = x - W zeta2 instead
 //          (tmpB holds s = mu2 W zeta2 of the previous frame step).
-//   mode 2, 3 (method CG): the two parts to (cgo1, cgao1), (cgo2, cgao2).
+//   mode 2, 3 (method CG): the two parts to (cgo1, cgao1), (cgo2, cgao2), and the
+//          boundary-system direction and its sums (below).
 // Rows padded as in k_row_fwd.
 template <int CPT, int RB>
 __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
@@ -672,8 +673,23 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
         return;
     }
     if (mode >= 2) {
-        float* const O = mode == 2 ? p.cgo1 : p.cgo2;
-        float* const AO = mode == 2 ? p.cgao1 : p.cgao2;
+        // method CG: the two parts of the solve to (O, A O), and the boundary-system
+        // step on the unobserved pixels. Mode 2 (first solve, O1 = C r / mu_t):
+        // the direction p = B (C r + C B^T v) - v = mu_t A O1 + A e - v into
+        // tmpA, p^T p, and the forward row DFT of (mu1 p, 0) into spec0, the
+        // input of the second solve (as the forward row pass would compute it
+        // from tmpA and a zero plane); mode 3 (second solve, O2 = C B^T p):
+        // p^T (I - B C B^T) p = p^T (p - A O2). The block's sum goes to slot 0
+        // or 1 of its pair in `partials` (the launcher passes the CG sums there).
+        const bool first = mode == 2;
+        float* const O = first ? p.cgo1 : p.cgo2;
+        float* const AO = first ? p.cgao1 : p.cgao2;
+        float* const TA = p.tmpA;
+        const float* const AE = p.cgae;
+        const float* const V = p.cgv;
+        const uint8_t* const MK = p.mask;
+        const float mut = p.mut, mu1 = p.mu1;
+        double acc = 0.0;
         for (int rr = 0; rr < nr; ++rr) {
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
@@ -683,7 +699,34 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
                 const unsigned g = off + (unsigned)(rr * W + c);
                 gst(O, g, xv.x);
                 gst(AO, g, xv.y);
+                const bool obs = gld(MK, g) != 0;
+                if (first) {
+                    const float r = fmaf(mut, xv.y, gld(AE, g)) - gld(V, g);
+                    const float pv = obs ? 0.0f : r;
+                    gst(TA, g, pv);
+                    X[rr * pitch + pidx(c)] = make_float2(mu1 * pv, 0.0f);   // the entry this thread read
+                    acc += (double)pv * (double)pv;
+                } else {
+                    const float pv = gld(TA, g);
+                    const float q = obs ? 0.0f : pv - xv.y;
+                    acc += (double)pv * (double)q;
+                }
             }
+        }
+        if (first) {
+            __syncthreads();
+            rows_fft<NT * CPT, NT, RB, MAXE_ROW, false>(X, pitch, p.fr, twl, nr, tid);
+            store_rows_split<true>(X, pitch, p.spec0, H, W, P, r0, nr, tid);
+        }
+        __syncthreads();   // X becomes the reduction scratch
+        double* const red = reinterpret_cast<double*>(X);
+        const double sw = wave_sum(acc);
+        if ((tid & 63) == 0) red[tid >> 6] = sw;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < NT / 64; ++w) sum += red[w];
+            partials[(size_t)(p.part_base + it.blk) * 2 + (first ? 0 : 1)] = sum;
         }
         return;
     }
@@ -1026,19 +1069,20 @@ hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
 
 hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool gated) {
     const InfoDev* info = gated ? L.info : nullptr;
+    double* const part = mode >= 2 ? L.cgpart : L.partials;   // modes 2, 3: the CG sums
     for (int c = 0; c < 3; ++c) {
         const int n = L.rrow_cnt[c];
         if (!n) continue;
         const WorkItem* it = L.row_items + L.rrow_beg[c];
         if (c == 0)
             hipLaunchKernelGGL((k_row_inv<1, ROW_RB[0]>), dim3(n), dim3(NT), L.lds_rrow_c[0], L.stream, L.desc, it, n,
-                               par, mode, flags, info, L.tw, L.partials);
+                               par, mode, flags, info, L.tw, part);
         else if (c == 1)
             hipLaunchKernelGGL((k_row_inv<2, ROW_RB[1]>), dim3(n), dim3(NT), L.lds_rrow_c[1], L.stream, L.desc, it, n,
-                               par, mode, flags, info, L.tw, L.partials);
+                               par, mode, flags, info, L.tw, part);
         else
             hipLaunchKernelGGL((k_row_inv<4, ROW_RB[2]>), dim3(n), dim3(NT), L.lds_rrow_c[2], L.stream, L.desc, it, n,
-                               par, mode, flags, info, L.tw, L.partials);
+                               par, mode, flags, info, L.tw, part);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

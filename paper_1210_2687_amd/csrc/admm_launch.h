@@ -40,7 +40,8 @@ struct LaunchCtx {
     // class c are [frm_beg[c], frm_beg[c] + frm_cnt[c]) of frm_items
     int frm_beg[ADMM_FRAME_CLASSES] = {}, frm_cnt[ADMM_FRAME_CLASSES] = {};
     size_t lds_frm_c[ADMM_FRAME_CLASSES] = {};
-    // method CG: two sums per row block (p^T p, p^T S p) and the TV step's LDS
+    // method CG: two sums per row block (p^T p, p^T S p; written by the inverse
+    // row pass, modes 2 and 3) and the TV step's LDS
     double* cgpart = nullptr;
     size_t lds_cgtv = 0;
 };
@@ -62,9 +63,6 @@ hipError_t launch_warmstart(const LaunchCtx& L, int prob, size_t n, const float*
                             const float* y, float* u1, float* d1, float* ureg, float* dreg);
 
 // Reeves-Sorel variants (method CG), over the row items of the context
-hipError_t launch_cg_dir(const LaunchCtx& L);
-hipError_t launch_cg_dot(const LaunchCtx& L);
-hipError_t launch_cg_alpha(const LaunchCtx& L, int count);
 hipError_t launch_cg_update(const LaunchCtx& L, int flags);
 hipError_t launch_cg_tv(const LaunchCtx& L, int par, int flags);
 size_t lds_cgtv_bytes(int W, int B);
