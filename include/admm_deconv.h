@@ -318,6 +318,30 @@ int32_t admm_fft_schedule(int32_t n, int32_t variant, int32_t* out, int32_t cap)
 /* admm_validate_problem: the plan-time checks for one problem, no allocation. */
 admm_status admm_validate_problem(const admm_problem* prob);
 
+/* ---- Observations of any size (host only, no device work) ----
+ * An observation of obs_h x obs_w pixels blurred by a k x k kernel depends on
+ * an unknown domain of (obs_h + k - 1) x (obs_w + k - 1) pixels (Sec. IV-A,
+ * eq. (34)); the transforms need 7-smooth sides of at most 2048. The helpers
+ * embed the observation in the smallest 7-smooth domain that holds that
+ * unknown domain: the rows and columns added at the bottom and right are
+ * unknowns that no observed pixel depends on, so only the regulariser sets
+ * them (on a 67 x 73 domain padded to 70 x 75 the estimate on the observed
+ * region moves by about 1e-3 relative).
+ *
+ * admm_embed_size: H, W (HOST outputs) = the smallest 7-smooth sides
+ *   >= obs_h + ksize - 1 and >= obs_w + ksize - 1. ADMM_E_INVALID for
+ *   non-positive sizes or null outputs, ADMM_E_UNSUPPORTED for an even
+ *   ksize or a side above 2048.
+ * admm_embed_observation: y_obs (HOST, obs_h*obs_w row-major) goes to rows
+ *   l .. l + obs_h - 1 and columns l .. l + obs_w - 1 (l = ksize / 2) of the
+ *   HOST H*W plane y (zero elsewhere); mask (HOST, H*W) is 1 there and 0
+ *   elsewhere, or obs_mask's value there when obs_mask (HOST, obs_h*obs_w,
+ *   0 = missing pixel) is not NULL. H and W must hold the unknown domain
+ *   (>= obs + ksize - 1; any sides the plan accepts), else ADMM_E_INVALID.  */
+admm_status admm_embed_size(int32_t obs_h, int32_t obs_w, int32_t ksize, int32_t* H, int32_t* W);
+admm_status admm_embed_observation(const float* y_obs, const uint8_t* obs_mask, int32_t obs_h, int32_t obs_w,
+                                   int32_t ksize, int32_t H, int32_t W, float* y, uint8_t* mask);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,6 +23,7 @@ __all__ = [
     "admm_deconv_plan", "admm_deconv_solve", "admm_deconv_batch", "admm_deconv_blur",
     "admm_deconv_solve_static", "admm_warmstart_map", "admm_plan_destroy", "admm_last_error", "admm_fft_radices",
     "admm_validate_problem", "admm_fft_schedule", "admm_deconv_plan_with", "admm_plan_schedules",
+    "admm_embed_size", "admm_embed_observation",
     "Plan", "make_problem", "alloc_state",
 ]
 
@@ -113,6 +114,9 @@ def lib():
         L.admm_last_error.restype = c_char_p
         L.admm_fft_radices.argtypes = [c_int32, POINTER(c_int32), c_int32]
         L.admm_validate_problem.argtypes = [POINTER(admm_problem)]
+        L.admm_embed_size.argtypes = [c_int32, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32)]
+        L.admm_embed_observation.argtypes = [POINTER(c_float), POINTER(c_uint8), c_int32, c_int32, c_int32, c_int32,
+                                             c_int32, POINTER(c_float), POINTER(c_uint8)]
         L.admm_plan_kernel_times.argtypes = [c_void_p, POINTER(admm_kernel_time), c_int32]
         L.admm_plan_kernel_times.restype = c_int32
         L.admm_deconv_plan_tuned.argtypes = [POINTER(admm_problem), c_int32, c_void_p, c_char_p, POINTER(c_void_p)]
@@ -159,6 +163,7 @@ def exported_symbols():
             "admm_validate_problem", "admm_plan_kernel_times", "admm_deconv_plan_tuned", "admm_tune_key",
             "admm_tune_cache_lookup", "admm_tune_cache_store", "admm_plan_tiles", "admm_plan_time_pass",
             "admm_deconv_plan_with", "admm_plan_schedules", "admm_fft_schedule",
+            "admm_embed_size", "admm_embed_observation",
             "admm_conv3x3_pack_weights", "admm_conv3x3_bf16_fwd", "admm_conv3x3_bf16_wgrad_workspace",
             "admm_conv3x3_bf16_wgrad", "admm_adam_step", "admm_ws_input", "admm_ws_loss", "admm_ws_output"]
 
@@ -205,6 +210,30 @@ def admm_fft_schedule(n, variant):
 
 def admm_validate_problem(prob):
     return lib().admm_validate_problem(ctypes.byref(prob))
+
+
+def admm_embed_size(obs_h, obs_w, ksize):
+    """(H, W): the smallest 7-smooth unknown domain holding an obs_h x obs_w
+    observation blurred by a ksize x ksize kernel."""
+    H, W = c_int32(), c_int32()
+    _check(lib().admm_embed_size(int(obs_h), int(obs_w), int(ksize), ctypes.byref(H), ctypes.byref(W)))
+    return H.value, W.value
+
+
+def admm_embed_observation(y_obs, ksize, obs_mask=None, shape=None):
+    """(y, mask) on the unknown domain ``shape`` (default: admm_embed_size) with
+    the observation at rows / columns ksize // 2 onwards."""
+    y_obs = np.ascontiguousarray(y_obs, dtype=np.float32)
+    oh, ow = y_obs.shape
+    H, W = shape if shape is not None else admm_embed_size(oh, ow, ksize)
+    y = np.empty((H, W), np.float32)
+    m = np.empty((H, W), np.uint8)
+    om = None if obs_mask is None else np.ascontiguousarray(obs_mask, dtype=np.uint8)
+    _check(lib().admm_embed_observation(y_obs.ctypes.data_as(POINTER(c_float)),
+                                        None if om is None else om.ctypes.data_as(POINTER(c_uint8)),
+                                        oh, ow, int(ksize), H, W, y.ctypes.data_as(POINTER(c_float)),
+                                        m.ctypes.data_as(POINTER(c_uint8))))
+    return y, m
 
 
 def _stream_ptr(stream):

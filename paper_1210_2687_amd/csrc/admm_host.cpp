@@ -224,3 +224,50 @@ std::string make_key(const admm_problem* probs, int count, const char* arch) {
 }
 
 }  // namespace admm_host
+
+namespace {
+
+int next_smooth7(int n) {
+    while (!admm_host::smooth7(n)) ++n;
+    return n;
+}
+
+}  // namespace
+
+extern "C" admm_status admm_embed_size(int32_t obs_h, int32_t obs_w, int32_t ksize, int32_t* H, int32_t* W) {
+    using admm_host::fail;
+    if (!H || !W) return fail(ADMM_E_INVALID, "null output pointer");
+    if (obs_h < 1 || obs_w < 1 || ksize < 1) return fail(ADMM_E_INVALID, "sizes must be positive");
+    if (ksize % 2 == 0) return fail(ADMM_E_UNSUPPORTED, "kernel side %d must be odd", ksize);
+    const long long need_h = (long long)obs_h + ksize - 1, need_w = (long long)obs_w + ksize - 1;
+    if (need_h > ADMM_MAX_SIDE || need_w > ADMM_MAX_SIDE)
+        return fail(ADMM_E_UNSUPPORTED, "unknown domain %lldx%lld above %d", need_h, need_w, ADMM_MAX_SIDE);
+    const int h = next_smooth7(std::max<int>(8, (int)need_h)), w = next_smooth7(std::max<int>(8, (int)need_w));
+    if (h > ADMM_MAX_SIDE || w > ADMM_MAX_SIDE)
+        return fail(ADMM_E_UNSUPPORTED, "no 7-smooth side <= %d holds %lldx%lld", ADMM_MAX_SIDE, need_h, need_w);
+    *H = h;
+    *W = w;
+    return ADMM_OK;
+}
+
+extern "C" admm_status admm_embed_observation(const float* y_obs, const uint8_t* obs_mask, int32_t obs_h,
+                                              int32_t obs_w, int32_t ksize, int32_t H, int32_t W, float* y,
+                                              uint8_t* mask) {
+    using admm_host::fail;
+    if (!y_obs || !y || !mask) return fail(ADMM_E_INVALID, "null pointer");
+    if (obs_h < 1 || obs_w < 1 || ksize < 1 || ksize % 2 == 0) return fail(ADMM_E_INVALID, "bad sizes");
+    if ((long long)H < (long long)obs_h + ksize - 1 || (long long)W < (long long)obs_w + ksize - 1)
+        return fail(ADMM_E_INVALID, "%dx%d does not hold the unknown domain of a %dx%d observation and a %d kernel", H, W,
+                    obs_h, obs_w, ksize);
+    const int l = ksize / 2;
+    std::fill(y, y + (size_t)H * W, 0.0f);
+    std::fill(mask, mask + (size_t)H * W, (uint8_t)0);
+    for (int r = 0; r < obs_h; ++r)
+        for (int c = 0; c < obs_w; ++c) {
+            const size_t s = (size_t)r * obs_w + c, d = (size_t)(r + l) * W + (c + l);
+            const uint8_t m = obs_mask ? (obs_mask[s] != 0) : 1;
+            mask[d] = m;
+            y[d] = m ? y_obs[s] : 0.0f;
+        }
+    return ADMM_OK;
+}

@@ -1,0 +1,67 @@
+"""Observations of any size: the library's embedding helpers (host only) and
+the reading they rest on (Sec. IV-A, eq. (34)): the unknown domain of an
+obs_h x obs_w observation and a k x k kernel is (obs_h + k - 1) x
+(obs_w + k - 1); rows and columns added beyond it are unknowns that no
+observed pixel depends on. The oracle, whose DFT is a dense matrix product and
+takes any length, solves the exact domain and the embedded one: their
+estimates on the observed region agree to about 1e-3."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1210_2687_amd import admm as A
+from paper_1210_2687_amd import workloads as WL
+
+
+@pytest.mark.parametrize("oh,ow,k,H,W", [(113, 127, 9, 125, 135), (61, 67, 7, 70, 75), (1, 1, 1, 8, 8),
+                                         (2030, 2041, 7, 2048, 2048), (500, 500, 13, 512, 512)])
+def test_embed_size_is_the_smallest_7_smooth_domain(oh, ow, k, H, W):
+    assert A.admm_embed_size(oh, ow, k) == (H, W)
+    for n, need in ((H, oh + k - 1), (W, ow + k - 1)):
+        assert n >= max(8, need) and WL.is_smooth7(n)
+        assert not any(WL.is_smooth7(m) for m in range(max(8, need), n))
+
+
+@pytest.mark.parametrize("args,status", [((2043, 10, 7), A.ADMM_E_UNSUPPORTED), ((10, 10, 4), A.ADMM_E_UNSUPPORTED),
+                                         ((0, 10, 3), A.ADMM_E_INVALID), ((10, -1, 3), A.ADMM_E_INVALID)])
+def test_embed_size_errors(args, status):
+    with pytest.raises(A.AdmmError) as e:
+        A.admm_embed_size(*args)
+    assert e.value.status == status
+
+
+def test_embedded_observation_places_data_and_mask():
+    g = np.random.default_rng(3)
+    y_obs = g.standard_normal((13, 17)).astype(np.float32)
+    miss = (g.uniform(size=(13, 17)) > 0.25).astype(np.uint8)
+    y, m = A.admm_embed_observation(y_obs, 5, obs_mask=miss)
+    assert y.shape == m.shape == A.admm_embed_size(13, 17, 5) == (18, 21)
+    assert np.array_equal(m[2:15, 2:19], miss) and m.sum() == miss.sum()
+    assert np.array_equal(y[2:15, 2:19], np.where(miss > 0, y_obs, 0))
+    assert np.all(y[m == 0] == 0)
+    y2, m2 = A.admm_embed_observation(y_obs, 5, shape=(20, 24))
+    assert m2.sum() == 13 * 17 and np.array_equal(y2[2:15, 2:19], y_obs)
+    with pytest.raises(A.AdmmError):
+        A.admm_embed_observation(y_obs, 5, shape=(16, 21))       # smaller than the unknown domain
+
+
+def test_embedding_barely_moves_the_estimate_on_the_observed_region():
+    g = WL.rng(5)
+    ho, wo, k = 61, 67, 7
+    l = k // 2
+    H0, W0 = ho + 2 * l, wo + 2 * l                     # the exact unknown domain, 67 x 73 (not 7-smooth)
+    x = WL.synth_image(g, H0, W0, grf_scale=16.0)
+    h = WL.kernel_gaussian(k, k / 4.5)
+    m0 = WL.valid_mask(H0, W0, l)
+    y0 = WL.observe(g, x, h, m0, 2e-3)
+    y1, m1 = A.admm_embed_observation(y0[l:l + ho, l:l + wo], k)
+    assert y1.shape == (70, 75)
+    lam, mu, K = 2e-4, 0.05, 1500
+    z0 = O.tv_md_run(y0, m0, h, lam, mu, mu, iters=K)["z"][l:l + ho, l:l + wo]
+    z1 = O.tv_md_run(y1.astype(np.float64), m1, h, lam, mu, mu, iters=K)["z"][l:l + ho, l:l + wo]
+    rel = np.linalg.norm(z1 - z0) / np.linalg.norm(z0)
+    xt = x[l:l + ho, l:l + wo]
+    isnr = lambda z: 10 * np.log10(np.sum((y0[l:l + ho, l:l + wo] - xt) ** 2) / np.sum((z - xt) ** 2))
+    assert rel <= 5e-3, rel
+    assert abs(isnr(z1) - isnr(z0)) <= 0.1

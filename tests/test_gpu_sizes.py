@@ -103,3 +103,20 @@ def test_tv_config2_member_at_its_iteration_count():
     announce("TV config-2 member 4 (512^2 motion), k = 100, 500")
     p = WL.config2(4)
     _single(p, [100, 500])
+
+
+def test_observation_of_a_non_7_smooth_size_through_the_embedding():
+    # a 113 x 127 observation (9 x 9 kernel: exact unknown domain 121 x 135, 121
+    # not 7-smooth) embedded by the library's helper in 125 x 135, 30% missing
+    announce("embedded 113 x 127 observation")
+    g = WL.rng(91)
+    k = 9
+    x = WL.synth_image(g, 121, 135, grf_scale=16.0)
+    h = WL.kernel_motion(k, 9.0, 0.7)
+    full = WL.valid_mask(121, 135, k // 2)
+    y_exact = WL.observe(g, x, h, full, 2e-3)
+    miss = (g.uniform(size=(113, 127)) >= 0.3).astype(np.uint8)
+    y, m = A.admm_embed_observation(y_exact[4:117, 4:131], k, obs_mask=miss)
+    assert y.shape == (125, 135)
+    p = WL.Problem(y=y.astype(np.float64), mask=m, kernel=h, lam=2e-4, mu1=0.01, mu2=0.01)
+    _single(p, [2, 20])

@@ -299,8 +299,9 @@ def test_largest_kernel_on_small_images(reg):
 
 def test_batch_of_smallest_and_largest_problems():
     # one plan holding an 8 x 8 problem, a 2000 x 1960 one (tiled, general
-    # schedules) and a 2048 x 2048 one (tiled, radix-8 schedules): every size
-    # class of both passes in the same launches
+    # schedules) and a 2048 x 2048 one (tiled, radix-8 schedules): the smallest
+    # and largest size classes of both passes in the same launches (the middle
+    # class, lengths 513..1024, runs in tests/test_gpu_sizes.py)
     import torch
     announce("batch: 8 x 8, 2000 x 1960, 2048 x 2048")
     small = fast_tv_problem(76, 8, 8, 3)
