@@ -127,7 +127,7 @@ void stage_twiddles(int N, int variant, float2* out) {
 // columns per column-pass block and rows per row-pass block.
 struct TileChoice {
     int tc = 0, b = 0;
-    int bc[3] = {0, 0, 0};   // rows per row block by size class of the row length (0: use b)
+    int bc[ADMM_ROW_CLASSES] = {};   // rows per row block by size class of the row length (0: use b)
     int rsched = 0, csched = 0;   // radix schedule variants of the row and column transforms
 };
 
@@ -144,6 +144,7 @@ struct admm_plan {
     std::vector<ProbDesc> hd;             // host copy of the descriptors
     std::vector<int> col_beg, col_end, row_beg, row_end, frm_beg, frm_end;   // item ranges per problem
     int ncol = 0, nrowtv = 0, nrowfa = 0, nfrm = 0;
+    int nrowtvs = 0;                      // TV row items of rows longer than 2048 (three-pass schedule)
     int ntv = 0, nfa = 0;
     char* arena = nullptr;
     size_t arena_bytes = 0;
@@ -160,6 +161,7 @@ struct admm_plan {
     float2* d_tw = nullptr;
     float* d_s2 = nullptr;
     LaunchCtx all, tv, fa;
+    LaunchCtx tvs;                        // TV rows longer than 2048 (three-pass schedule)
     // graph replay of plain iterations: executable per chunk length (even)
     hipStream_t cap_stream = nullptr;
     std::map<int, hipGraphExec_t> graphs;
@@ -302,9 +304,15 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
             return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: every problem of a plan needs the same method", i));
     P->method = probs[0].method == ADMM_METHOD_CG ? METHOD_CG : METHOD_MD;
     const bool cg = P->method == METHOD_CG;
-    if (cg && lds_cap > 65536 && cap > 65536 && allow_dynamic_lds_cg(lds_cap) != hipSuccess) {
-        (void)hipGetLastError();
-        cap = 65536;
+    // the TV step (method CG, and TV rows longer than 2048) holds a little static
+    // LDS (its block sums) beside the dynamic part: its own limit
+    constexpr size_t kTvStepStatic = 1024;
+    size_t tv_cap = 65536 - kTvStepStatic;
+    if (lds_cap > 65536 && cap > 65536) {
+        if (allow_dynamic_lds_cg((int)((size_t)lds_cap - kTvStepStatic)) == hipSuccess)
+            tv_cap = (size_t)lds_cap - kTvStepStatic;
+        else
+            (void)hipGetLastError();
     }
     P->stream = (hipStream_t)hip_stream;
     P->count = count;
@@ -368,11 +376,22 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         d.TC = std::min(std::min(tcmax, tc_batch), d.P);
         if (tile.tc > 0) d.TC = std::min(d.TC, tile.tc);
         if (const char* e = std::getenv("ADMM_TC")) d.TC = std::max(1, std::min(d.TC, std::atoi(e)));
+        if (q.H > 2048) {   // the block-level column pass: one column per block, 16 operands per thread
+            d.TC = 1;
+            if (!fits(1, d.fc, 16))
+                return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: column schedule of length %d does not fit a block", i,
+                                 q.H));
+        }
         // rows per row-pass block
         int bmax = 0;
-        if (q.reg == ADMM_REG_TV) {
+        const bool tv_split = q.reg == ADMM_REG_TV && q.W > 2048;   // three-pass TV schedule
+        if (q.reg == ADMM_REG_TV && !tv_split) {
             while (bmax + 1 <= std::min(q.H, row_tv_max_rows(q.W)) && fits(bmax + 3, d.fr, row_maxe()) &&
-                   lds_rowtv_bytes(q.W, bmax + 1) <= cap && (!cg || lds_cgtv_bytes(q.W, bmax + 1) <= cap))
+                   lds_rowtv_bytes(q.W, bmax + 1) <= cap && (!cg || lds_tvstep_bytes(q.W, bmax + 1) <= tv_cap))
+                ++bmax;
+        } else if (tv_split) {
+            while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) && fits(bmax + 1, d.fr, row_maxe()) &&
+                   lds_row_bytes(q.W, bmax + 1) <= cap && lds_tvstep_bytes(q.W, bmax + 1) <= tv_cap)
                 ++bmax;
         } else {
             while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) && fits(bmax + 1, d.fr, row_maxe()) &&
@@ -380,7 +399,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
                 ++bmax;
         }
         if (bmax < 1) return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: row length %d does not fit a block", i, q.W));
-        const int bmin = q.reg == ADMM_REG_TV ? std::min(bmax, 2) : 1;   // TV: halo rows cost (B + 2) / B
+        const int bmin = q.reg == ADMM_REG_TV && !tv_split ? std::min(bmax, 2) : 1;   // fused TV: halo rows cost (B + 2) / B
         d.B = std::max(bmin, std::min(bmax, (q.H + per - 1) / per));
         const int breq = tile.bc[size_class(q.W)] > 0 ? tile.bc[size_class(q.W)] : tile.b;
         if (breq > 0) d.B = std::min(bmax, breq);
@@ -409,8 +428,8 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     // column items grouped by column class and TV row items by size class (each
     // class is one launch of its own instantiation), largest problems first
     // within a class
-    int col_cb[ADMM_COL_CLASSES], col_cc[ADMM_COL_CLASSES], rtv_cb[3], rtv_cc[3];
-    size_t lds_col_c[ADMM_COL_CLASSES] = {}, lds_rtv_c[3] = {0, 0, 0};
+    int col_cb[ADMM_COL_CLASSES], col_cc[ADMM_COL_CLASSES], rtv_cb[ADMM_ROW_CLASSES], rtv_cc[ADMM_ROW_CLASSES];
+    size_t lds_col_c[ADMM_COL_CLASSES] = {}, lds_rtv_c[ADMM_ROW_CLASSES] = {};
     for (int c = 0; c < ADMM_COL_CLASSES; ++c) {
         col_cb[c] = (int)col.size();
         for (int i : order) {
@@ -423,7 +442,8 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         }
         col_cc[c] = (int)col.size() - col_cb[c];
     }
-    for (int c = 0; c < 3; ++c) {
+    // (class 3, rows longer than 2048, takes the three-pass TV schedule: no fused pass)
+    for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
         rtv_cb[c] = (int)rowtv.size();
         for (int i : order) {
             ProbDesc& d = P->hd[i];
@@ -431,7 +451,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
                 P->row_beg[i] = (int)rowtv.size();
                 for (int b = 0; b < d.nrowblk; ++b) rowtv.push_back({i, b * d.B, b, 0});
                 P->row_end[i] = (int)rowtv.size();
-                lds_rtv_c[c] = std::max(lds_rtv_c[c], lds_rowtv_bytes(d.W, d.B));
+                if (c < 3) lds_rtv_c[c] = std::max(lds_rtv_c[c], lds_rowtv_bytes(d.W, d.B));
             }
         }
         rtv_cc[c] = (int)rowtv.size() - rtv_cb[c];
@@ -464,9 +484,9 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     }
     // FA row items grouped by size class of the row length, like the TV rows; the
     // plain row passes of each context use the classes of its own row items
-    int rfa_cb[3], rfa_cc[3];
-    size_t lds_rfa_c[3] = {0, 0, 0}, lds_rtvp_c[3] = {0, 0, 0};
-    for (int c = 0; c < 3; ++c) {
+    int rfa_cb[ADMM_ROW_CLASSES], rfa_cc[ADMM_ROW_CLASSES];
+    size_t lds_rfa_c[ADMM_ROW_CLASSES] = {}, lds_rtvp_c[ADMM_ROW_CLASSES] = {};
+    for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
         rfa_cb[c] = (int)rowfa.size();
         for (int i : order) {
             const ProbDesc& d = P->hd[i];
@@ -484,6 +504,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     }
     P->ncol = (int)col.size();
     P->nrowtv = (int)rowtv.size();
+    P->nrowtvs = rtv_cc[3];
     P->nrowfa = (int)rowfa.size();
     P->nfrm = (int)frm.size();
 
@@ -520,7 +541,8 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         const size_t n = (size_t)d.H * d.W, hp = (size_t)d.H * d.P;
         Offs& o = po[i];
         o.spec0 = take(hp * sizeof(float4));
-        o.spec1 = d.reg == REG_TV ? take(hp * sizeof(float4)) : o.spec0;
+        const bool split = d.reg == REG_TV && d.W > 2048;   // three-pass TV: one spectrum, a z plane
+        o.spec1 = d.reg == REG_TV && !split ? take(hp * sizeof(float4)) : o.spec0;
         o.lam = take(hp * sizeof(float2));
         o.d1 = take(n * sizeof(float));
         o.dreg0 = take(n * d.nb * sizeof(float));
@@ -529,7 +551,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         o.uregp = take(n * d.nb * sizeof(float));
         o.tmpA = take(n * sizeof(float));
         o.tmpB = take(n * sizeof(float));
-        o.zpl = d.reg == REG_FRAME || cg ? take(n * sizeof(float)) : o.tmpA;
+        o.zpl = d.reg == REG_FRAME || cg || split ? take(n * sizeof(float)) : o.tmpA;
         o.mask = take(n);
         for (int j = 0; j < 7; ++j) o.cg[j] = cg ? take(n * sizeof(float)) : 0;
     }
@@ -632,18 +654,16 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     base_ctx.partials = P->d_partials;
     base_ctx.tw = P->d_tw;
     base_ctx.s2 = P->d_s2;
-    if (cg) {
-        base_ctx.cgpart = (double*)(A + o_cgpart);
-        for (int i = 0; i < count; ++i)
-            if (P->hd[i].reg == REG_TV)
-                base_ctx.lds_cgtv = std::max(base_ctx.lds_cgtv, lds_cgtv_bytes(P->hd[i].W, P->hd[i].B));
-    }
+    if (cg) base_ctx.cgpart = (double*)(A + o_cgpart);
+    for (int i = 0; i < count; ++i)   // the TV step: every TV problem of a CG plan, long TV rows of an MD plan
+        if (P->hd[i].reg == REG_TV && (cg || P->hd[i].W > 2048))
+            base_ctx.lds_tvstep = std::max(base_ctx.lds_tvstep, lds_tvstep_bytes(P->hd[i].W, P->hd[i].B));
     for (int c = 0; c < ADMM_COL_CLASSES; ++c) {
         base_ctx.col_beg[c] = col_cb[c];
         base_ctx.col_cnt[c] = col_cc[c];
         base_ctx.lds_col_c[c] = lds_col_c[c];
     }
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c) {   // the fused TV row pass: classes 0..2
         base_ctx.rtv_beg[c] = rtv_cb[c];
         base_ctx.rtv_cnt[c] = rtv_cc[c];
         base_ctx.lds_rtv_c[c] = lds_rtv_c[c];
@@ -662,7 +682,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     P->fa = base_ctx;
     P->fa.row_items = P->d_items + col.size() + rowtv.size();
     P->fa.nrow = P->nrowfa;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
         P->tv.rrow_beg[c] = rtv_cb[c];
         P->tv.rrow_cnt[c] = rtv_cc[c];
         P->tv.lds_rrow_c[c] = lds_rtvp_c[c];
@@ -672,6 +692,15 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     }
     P->fa.frm_items = P->d_items + col.size() + rowtv.size() + rowfa.size();
     P->fa.nfrm = P->nfrm;
+    // the TV problems with rows longer than 2048 alone (their row items are the
+    // last class of the TV list): plain row passes and the TV step
+    P->tvs = base_ctx;
+    P->tvs.row_items = P->d_items + col.size() + rtv_cb[3];
+    P->tvs.nrow = P->nrowtvs;
+    for (int c = 0; c < 3; ++c) P->tvs.rtv_cnt[c] = 0;
+    P->tvs.rrow_beg[3] = 0;
+    P->tvs.rrow_cnt[3] = rtv_cc[3];
+    P->tvs.lds_rrow_c[3] = lds_rtvp_c[3];
 
     // kernel spectra Lambda (eq. (19)): host computes the row sums T[a][k2] in double
     for (int i = 0; i < count; ++i) {
@@ -836,15 +865,22 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
             each(2, [&](const LaunchCtx& r) { return launch_row_inv(r, 0, 2 + solve, 0, true); });
         }
         each(6, [&](const LaunchCtx& r) { return launch_cg_update(r, flags); });
-        if (e == hipSuccess && cT.nrow) e = timed(6, [&] { return launch_cg_tv(cT, par, flags); });
+        if (e == hipSuccess && cT.nrow) e = timed(6, [&] { return launch_tv_step(cT, par, flags); });
         if (e == hipSuccess && cF.nrow) e = timed(3, [&] { return launch_frame(cF, par, flags, 0, true); });
         return e;
     };
-    auto iteration = [&](const LaunchCtx& cA, const LaunchCtx& cT, const LaunchCtx& cF, int par, int flags,
-                         bool last) -> hipError_t {
+    // cS: the TV problems with rows longer than 2048, which run inverse rows with
+    // the data step (z to the z plane), the TV step and forward rows
+    auto iteration = [&](const LaunchCtx& cA, const LaunchCtx& cT, const LaunchCtx& cF, const LaunchCtx& cS, int par,
+                         int flags, bool last) -> hipError_t {
         if (cg) return cg_iteration(cA, cT, cF, par, flags);
         hipError_t e = timed(0, [&] { return launch_col(cA, par, COL_SOLVE); });
         if (e == hipSuccess && P->nrowtv) e = timed(1, [&] { return launch_row_tv(cT, par, flags); });
+        if (e == hipSuccess && P->nrowtvs) {
+            e = timed(2, [&] { return launch_row_inv(cS, 0, 1, flags, true); });
+            if (e == hipSuccess) e = timed(1, [&] { return launch_tv_step(cS, par, flags); });
+            if (e == hipSuccess && !last) e = timed(4, [&] { return launch_row_fwd(cS, 0, 0, true); });
+        }
         if (e == hipSuccess && P->nrowfa) {
             e = timed(2, [&] { return launch_row_inv(cF, 0, 1, flags, true); });
             if (e == hipSuccess) e = timed(3, [&] { return launch_frame(cF, par, flags, 0, true); });
@@ -859,11 +895,11 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
             return ADMM_OK;
         }
         if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
-        LaunchCtx cA = P->all, cT = P->tv, cF = P->fa;
-        cA.stream = cT.stream = cF.stream = P->cap_stream;
+        LaunchCtx cA = P->all, cT = P->tv, cF = P->fa, cS = P->tvs;
+        cA.stream = cT.stream = cF.stream = cS.stream = P->cap_stream;
         HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
-        for (int i = 0; i < G && e == hipSuccess; ++i) e = iteration(cA, cT, cF, i & 1, F_FORWARD, false);
+        for (int i = 0; i < G && e == hipSuccess; ++i) e = iteration(cA, cT, cF, cS, i & 1, F_FORWARD, false);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(P->cap_stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -900,8 +936,8 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
             return ADMM_OK;
         }
         if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
-        LaunchCtx cA = P->all, cT = P->tv, cF = P->fa;
-        cA.stream = cT.stream = cF.stream = P->cap_stream;
+        LaunchCtx cA = P->all, cT = P->tv, cF = P->fa, cS = P->tvs;
+        cA.stream = cT.stream = cF.stream = cS.stream = P->cap_stream;
         HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         for (int q = 1; q <= g && e == hipSuccess; ++q) {
@@ -909,7 +945,7 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
                 // u_k is kept on the iteration before each check (every one for period 1)
                 int flags = F_FORWARD | (j == c - 1 || c == 1 ? F_WRITE_UPREV : 0);
                 if (j == c) flags |= F_CHECK | F_WRITE_X | (st ? F_EXPORT : 0);
-                e = iteration(cA, cT, cF, ((q - 1) * c + j - 1) & 1, flags, false);
+                e = iteration(cA, cT, cF, cS, ((q - 1) * c + j - 1) & 1, flags, false);
             }
             if (e == hipSuccess) e = launch_reduce(cA, count, tol, obj_tol, q * c, 0, P->d_kbase, P->h_active_dev);
         }
@@ -981,7 +1017,7 @@ admm_status run(admm_plan* P, const float* const* y, float* const* x, admm_state
         int flags = (last ? 0 : F_FORWARD) | (next_check ? F_WRITE_UPREV : 0);
         if (check) flags |= F_CHECK | F_WRITE_X | (st ? F_EXPORT : 0);
         {
-            hipError_t e = iteration(P->all, P->tv, P->fa, par, flags, last);
+            hipError_t e = iteration(P->all, P->tv, P->fa, P->tvs, par, flags, last);
             if (e != hipSuccess) {
                 release_events();
                 return fail(ADMM_E_DEVICE, "iteration %d launch failed: %s", k, hipGetErrorString(e));
@@ -1110,7 +1146,7 @@ LaunchCtx single(const admm_plan* P, int i) {
     c.frm_items = nullptr;
     c.nfrm = 0;
     for (int k = 0; k < ADMM_COL_CLASSES; ++k) c.col_beg[k] = c.col_cnt[k] = 0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < ADMM_ROW_CLASSES; ++k) {
         c.rtv_beg[k] = c.rrow_beg[k] = 0;
         c.rtv_cnt[k] = c.rrow_cnt[k] = 0;
     }
@@ -1334,7 +1370,7 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
         if (it != cache.end() && it->second.tc > 0 && it->second.rows > 0) {
             best.tc = it->second.tc;
             best.b = it->second.rows;
-            for (int c = 0; c < 3; ++c) best.bc[c] = it->second.rows_c[c];
+            for (int c = 0; c < ADMM_ROW_CLASSES; ++c) best.bc[c] = it->second.rows_c[c];
             best.rsched = it->second.rsched;
             best.csched = it->second.csched;
             have = true;
@@ -1418,10 +1454,12 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
             }
             if (s == ADMM_E_DEVICE || s == ADMM_E_NOMEM) st = s;
         }
-        bool cls[3] = {false, false, false};
+        bool cls[ADMM_ROW_CLASSES] = {};
+        int ncls = 0;
         for (int i = 0; i < count; ++i) cls[size_class(probs[i].W)] = true;
-        if (cls[0] + cls[1] + cls[2] > 1 && best.tc >= 1 && best.b >= 1) {
-            for (int c = 0; c < 3 && st == ADMM_OK; ++c) {
+        for (int c = 0; c < ADMM_ROW_CLASSES; ++c) ncls += cls[c];
+        if (ncls > 1 && best.tc >= 1 && best.b >= 1) {
+            for (int c = 0; c < ADMM_ROW_CLASSES && st == ADMM_OK; ++c) {
                 if (!cls[c]) continue;
                 for (int k = 0; k < nb && st == ADMM_OK; ++k) {
                     if (bs[k] == best.b) continue;   // the common count is the incumbent
@@ -1472,7 +1510,7 @@ extern "C" admm_status admm_deconv_plan_tuned(const admm_problem* probs, int32_t
         if (best.tc < 1 || best.b < 1) return fail(ADMM_E_UNSUPPORTED, "autotuner: no tile shape could be planned");
         rec.tc = best.tc;
         rec.rows = best.b;
-        for (int c = 0; c < 3; ++c) rec.rows_c[c] = best.bc[c];
+        for (int c = 0; c < ADMM_ROW_CLASSES; ++c) rec.rows_c[c] = best.bc[c];
         rec.rsched = best.rsched;
         rec.csched = best.csched;
         rec.col_us = best_c;

@@ -19,8 +19,11 @@
 //             A z = AO1 + Ae / mu_t, data step on the observed pixels
 //             u1 = (y + mu1 (A z - d1)) / (1 + mu1), d1 <- d1 - (A z - u1),
 //             next M (u1 + d1)
-//   k_cg_tv   (TV) vector soft threshold, TV duals, next s = mu2 D^T (u + d);
+//   k_tv_step (TV) vector soft threshold, TV duals, next s = mu2 D^T (u + d);
 //             the frame variant runs the FA frame step on z instead.
+// k_tv_step is also the TV step of TV-MD for rows longer than 2048, which run
+// the three-pass schedule (inverse rows with the data step into z, this step,
+// forward rows) instead of the fused TV row pass.
 // Every kernel takes the rows of one row item of a problem (the work items of
 // the row passes) and skips finished problems.
 #include "admm_internal.h"
@@ -153,13 +156,13 @@ __global__ __launch_bounds__(NTG) void k_cg_update(const ProbDesc* __restrict__ 
     if (CHK) cg_write_sums(acc, partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM, false);
 }
 
-// TV step of TV-CG on z (the plane k_cg_update wrote): vector soft threshold
-// and TV duals for the block's rows and the row above (whose u + d enters the
-// adjoint difference), then s = mu2 D^T (u + d) for the block's rows; the TV
-// block's residual sums on check iterations (odd entries). LDS: (nr + 1) x W of
-// each component of u + d.
+// TV step on z (the plane k_cg_update or the inverse row pass wrote): vector
+// soft threshold and TV duals for the block's rows and the row above (whose
+// u + d enters the adjoint difference), then s = mu2 D^T (u + d) for the
+// block's rows; the TV block's residual sums on check iterations (odd
+// entries). LDS: (nr + 1) x W of each component of u + d.
 template <bool CHK>
-__global__ __launch_bounds__(NTG) void k_cg_tv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+__global__ __launch_bounds__(NTG) void k_tv_step(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                               const InfoDev* __restrict__ info, int par, int flags,
                                               double* __restrict__ partials) {
     extern __shared__ float ud[];
@@ -175,6 +178,8 @@ __global__ __launch_bounds__(NTG) void k_cg_tv(const ProbDesc* __restrict__ pd, 
     float* const dh_out = par ? p.dreg0 : p.dreg1;
     float* const dv_out = dh_out + n;
     float* const UREGP = p.uregp;
+    float* const SUREG = p.st_ureg;
+    float* const SDREG = p.st_dreg;
     float* const TB = p.tmpB;
     float* udh = ud;
     float* udv = ud + (size_t)(nr + 1) * W;
@@ -215,6 +220,12 @@ __global__ __launch_bounds__(NTG) void k_cg_tv(const ProbDesc* __restrict__ pd, 
                 gst(UREGP, g, uh);
                 gst(UREGP, n + g, uv);
             }
+            if (flags & F_EXPORT) {
+                gst(SUREG, g, uh);
+                gst(SUREG, n + g, uv);
+                gst(SDREG, g, dhn);
+                gst(SDREG, n + g, dvn);
+            }
         }
     }
     __syncthreads();
@@ -240,21 +251,22 @@ hipError_t launch_cg_update(const LaunchCtx& L, int flags) {
     return hipGetLastError();
 }
 
-hipError_t launch_cg_tv(const LaunchCtx& L, int par, int flags) {
+hipError_t launch_tv_step(const LaunchCtx& L, int par, int flags) {
     if (!L.nrow) return hipSuccess;
     if (flags & F_CHECK)
-        hipLaunchKernelGGL(k_cg_tv<true>, dim3(L.nrow), dim3(NTG), L.lds_cgtv, L.stream, L.desc, L.row_items, L.info,
-                           par, flags, L.partials);
+        hipLaunchKernelGGL(k_tv_step<true>, dim3(L.nrow), dim3(NTG), L.lds_tvstep, L.stream, L.desc, L.row_items,
+                           L.info, par, flags, L.partials);
     else
-        hipLaunchKernelGGL(k_cg_tv<false>, dim3(L.nrow), dim3(NTG), L.lds_cgtv, L.stream, L.desc, L.row_items, L.info,
-                           par, flags, L.partials);
+        hipLaunchKernelGGL(k_tv_step<false>, dim3(L.nrow), dim3(NTG), L.lds_tvstep, L.stream, L.desc, L.row_items,
+                           L.info, par, flags, L.partials);
     return hipGetLastError();
 }
 
-size_t lds_cgtv_bytes(int W, int B) { return (size_t)2 * (B + 1) * W * sizeof(float); }
+size_t lds_tvstep_bytes(int W, int B) { return (size_t)2 * (B + 1) * W * sizeof(float); }
 
 hipError_t allow_dynamic_lds_cg(int bytes) {
-    const void* fns[] = {reinterpret_cast<const void*>(&k_cg_tv<false>), reinterpret_cast<const void*>(&k_cg_tv<true>)};
+    const void* fns[] = {reinterpret_cast<const void*>(&k_tv_step<false>),
+                         reinterpret_cast<const void*>(&k_tv_step<true>)};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;

@@ -9,7 +9,7 @@
 #include "../../include/admm_deconv.h"
 
 #ifndef ADMM_MAX_SIDE
-#define ADMM_MAX_SIDE 2048
+#define ADMM_MAX_SIDE 4096
 #endif
 
 namespace admm_host {
@@ -34,7 +34,7 @@ admm_status validate(const admm_problem& p);
 constexpr double kMaxTileCount = 4096.0;
 struct TuneEntry {
     int tc = 0, rows = 0;
-    int rows_c[3] = {0, 0, 0};   // "rows_512", "rows_1024", "rows_2048"
+    int rows_c[4] = {0, 0, 0, 0};   // "rows_512", "rows_1024", "rows_2048", "rows_4096"
     int rsched = 0, csched = 0;  // radix schedule variants of the row and column transforms
     double col_us = 0.0, row_us = 0.0;
 };

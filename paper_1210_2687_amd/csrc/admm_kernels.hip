@@ -32,8 +32,8 @@ constexpr int ROW_BURST = 8;       // plane elements per thread fetched together
 // transforms, per size class (as many as keep the kernel at 128 VGPRs or fewer,
 // two blocks per compute unit)
 constexpr int RTV_EARLY[3] = {5, 3, 1};
-// most rows per block of the plain row passes, per size class (W <= 512, 1024, 2048)
-constexpr int ROW_RB[3] = {16, 8, 4};
+// most rows per block of the plain row passes, per size class (W <= 512, 1024, 2048, 4096)
+constexpr int ROW_RB[ADMM_ROW_CLASSES] = {16, 8, 4, 2};
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -304,6 +304,46 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
     for (int e = lane; e < H; e += 64) gst(S, e, lds_ld(buf + pidx(e)));
 }
 
+// Column pass for columns longer than 2048 (up to 4096): one block of NTB
+// threads per column. The column (H float4 entries: the two packed complex
+// sequences) and the stage table sit in LDS and every stage runs block-wide
+// (fft_lds over float4 elements, any schedule of the plan); the solve between
+// the transforms is the one of k_col, entry by entry.
+constexpr int NTB = 512;
+constexpr int MAXE_BIG = 16;   // float4 operands per thread in a stage (radix 2..8, length <= 4096)
+__global__ __launch_bounds__(NTB) void k_col_big(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                                 int nitems, int par, int mode, const InfoDev* __restrict__ info,
+                                                 const float2* __restrict__ tw, const float* __restrict__ s2tab) {
+    extern __shared__ float4 cl[];
+    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    if (info && !info[it.prob].active) return;
+    const ProbDesc& p = pd[it.prob];
+    const int H = p.H, col = it.start;   // one column per work item
+    const int tid = threadIdx.x;
+    float4* S = ((p.reg == REG_TV && par) ? p.spec1 : p.spec0) + (size_t)col * H;
+    const float2* L = p.lamhat + (size_t)col * H;
+    const float* s2H = s2tab + p.fc.tw_off;
+    const float mu1 = p.mu1, mu2 = p.mu2, ihw = p.inv_hw;
+    const float w2 = p.reg == REG_TV ? s2tab[p.fr.tw_off + col] : 0.0f;
+    float2* twg = reinterpret_cast<float2*>(cl);                  // stage table: H - 1 entries
+    float4* buf = cl + (H + 1) / 2;                                // the column, padded (pidx)
+    ADMM_LDS float2* const tl = (ADMM_LDS float2*)twg;
+    ADMM_LDS float4* const bl = (ADMM_LDS float4*)buf;
+    const float2* tws = tw + p.fc.tw_off + H;
+    for (int e = tid; e < H - 1; e += NTB) lds_st(tl + e, gld(tws, (unsigned)e));
+    for (int e = tid; e < H; e += NTB) lds_st(bl + pidx(e), gld(S, (unsigned)e));
+    __syncthreads();
+    fft_lds<MAXE_BIG, false, true>(buf, p.fc, twg, 1, 0, tid, NTB);
+    for (int e = tid; e < H; e += NTB) {
+        const float2 lm = gld(L, (unsigned)e);
+        const float w = p.reg == REG_TV ? s2H[e] + w2 : 1.0f;
+        lds_st(bl + pidx(e), col_solve(lds_ld(bl + pidx(e)), lm, w, mu1, mu2, ihw, mode));
+    }
+    __syncthreads();
+    fft_lds<MAXE_BIG, true, true>(buf, p.fc, twg, 1, 0, tid, NTB);
+    for (int e = tid; e < H; e += NTB) gst(S, (unsigned)e, lds_ld(bl + pidx(e)));
+}
+
 // ------------------------------------------------------------ row helpers
 // Load transposed half-spectrum rows [rbeg, rbeg + nrows) (wrapping mod H) as
 // full complex rows Y = z^ + i A z^ (Hermitian completion of both halves), row
@@ -393,7 +433,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     __builtin_assume(nr >= 1);
     const int nrh = nr + 2;
     const int tid = threadIdx.x;
-    const unsigned n = (unsigned)(H * W);   // planes hold at most 2048^2 values: 32-bit offsets
+    const unsigned n = (unsigned)(H * W);   // planes hold at most 4096^2 values: 32-bit offsets
     const int pitch = row_pitch(W);                                        // padded rows (pidx)
     float* dl = reinterpret_cast<float*>(X + (size_t)(p.B + 2) * pitch);   // 2 x W: delta^h of the row (ping-pong)
     float2* twl = reinterpret_cast<float2*>(dl + 2 * W);                 // row twiddles
@@ -968,6 +1008,7 @@ __global__ void k_scale2(const float* __restrict__ d, float* __restrict__ p, siz
 
 // ------------------------------------------------------------ host launchers
 static size_t col_lds(int H, int TC) {
+    if (H > 2048) TC = 1;   // the block-level column pass: one column per block
     return (size_t)((H + 1) / 2) * sizeof(float4) + (size_t)TC * pidx_len(H) * sizeof(float4);
 }
 static size_t rowtv_lds(int W, int B) {
@@ -982,9 +1023,9 @@ static size_t row_lds(int W, int B) {
     return b > scratch ? b : scratch;
 }
 
-int size_class(int n) { return n <= 512 ? 0 : (n <= 1024 ? 1 : 2); }
+int size_class(int n) { return n <= 512 ? 0 : (n <= 1024 ? 1 : (n <= 2048 ? 2 : 3)); }
 
-int col_class(const ProbDesc& d) { return 2 * size_class(d.H) + (d.fc.ends8 ? 0 : 1); }
+int col_class(const ProbDesc& d) { return d.H > 2048 ? 6 : 2 * size_class(d.H) + (d.fc.ends8 ? 0 : 1); }
 
 namespace {
 template <int EPL, bool GEN>
@@ -1005,7 +1046,11 @@ hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
             case 2: launch_col_class<16, false>(L, c, par, mode, info); break;
             case 3: launch_col_class<16, true>(L, c, par, mode, info); break;
             case 4: launch_col_class<32, false>(L, c, par, mode, info); break;
-            default: launch_col_class<32, true>(L, c, par, mode, info); break;
+            case 5: launch_col_class<32, true>(L, c, par, mode, info); break;
+            default:
+                hipLaunchKernelGGL(k_col_big, dim3(L.col_cnt[c]), dim3(NTB), L.lds_col_c[c], L.stream, L.desc,
+                                   L.col_items + L.col_beg[c], L.col_cnt[c], par, mode, info, L.tw, L.s2);
+                break;
         }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1028,7 +1073,7 @@ void launch_row_tv_class(const LaunchCtx& L, int c, int par, int flags) {
 }  // namespace
 
 hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags) {
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c) {   // rows longer than 2048 take the three-pass schedule (no fused class)
         if (!L.rtv_cnt[c]) continue;
         if (c == 0)
             launch_row_tv_class<1, 8, RTV_EARLY[0]>(L, c, par, flags);
@@ -1048,7 +1093,7 @@ int row_tv_max_rows(int w) { return w <= NT ? 8 : (w <= 2 * NT ? 6 : 2); }
 // length: CPT columns per thread, at most ROW_RB[c] rows per block.
 hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
     const InfoDev* info = gated ? L.info : nullptr;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
         const int n = L.rrow_cnt[c];
         if (!n) continue;
         const WorkItem* it = L.row_items + L.rrow_beg[c];
@@ -1058,8 +1103,11 @@ hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
         else if (c == 1)
             hipLaunchKernelGGL((k_row_fwd<2, ROW_RB[1]>), dim3(n), dim3(NT), L.lds_rrow_c[1], L.stream, L.desc, it, n,
                                par, src, info, L.tw);
-        else
+        else if (c == 2)
             hipLaunchKernelGGL((k_row_fwd<4, ROW_RB[2]>), dim3(n), dim3(NT), L.lds_rrow_c[2], L.stream, L.desc, it, n,
+                               par, src, info, L.tw);
+        else
+            hipLaunchKernelGGL((k_row_fwd<8, ROW_RB[3]>), dim3(n), dim3(NT), L.lds_rrow_c[3], L.stream, L.desc, it, n,
                                par, src, info, L.tw);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1070,7 +1118,7 @@ hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
 hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool gated) {
     const InfoDev* info = gated ? L.info : nullptr;
     double* const part = mode >= 2 ? L.cgpart : L.partials;   // modes 2, 3: the CG sums
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
         const int n = L.rrow_cnt[c];
         if (!n) continue;
         const WorkItem* it = L.row_items + L.rrow_beg[c];
@@ -1080,8 +1128,11 @@ hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool
         else if (c == 1)
             hipLaunchKernelGGL((k_row_inv<2, ROW_RB[1]>), dim3(n), dim3(NT), L.lds_rrow_c[1], L.stream, L.desc, it, n,
                                par, mode, flags, info, L.tw, part);
-        else
+        else if (c == 2)
             hipLaunchKernelGGL((k_row_inv<4, ROW_RB[2]>), dim3(n), dim3(NT), L.lds_rrow_c[2], L.stream, L.desc, it, n,
+                               par, mode, flags, info, L.tw, part);
+        else
+            hipLaunchKernelGGL((k_row_inv<8, ROW_RB[3]>), dim3(n), dim3(NT), L.lds_rrow_c[3], L.stream, L.desc, it, n,
                                par, mode, flags, info, L.tw, part);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1151,6 +1202,9 @@ hipError_t allow_dynamic_lds(int bytes) {
         reinterpret_cast<const void*>(&k_row_fwd<1, ROW_RB[0]>),
         reinterpret_cast<const void*>(&k_row_fwd<2, ROW_RB[1]>),
         reinterpret_cast<const void*>(&k_row_fwd<4, ROW_RB[2]>),
+        reinterpret_cast<const void*>(&k_row_fwd<8, ROW_RB[3]>),
+        reinterpret_cast<const void*>(&k_row_inv<8, ROW_RB[3]>),
+        reinterpret_cast<const void*>(&k_col_big),
         reinterpret_cast<const void*>(&k_row_inv<1, ROW_RB[0]>),
         reinterpret_cast<const void*>(&k_row_inv<2, ROW_RB[1]>),
         reinterpret_cast<const void*>(&k_row_inv<4, ROW_RB[2]>)};

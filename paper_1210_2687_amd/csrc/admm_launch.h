@@ -8,8 +8,14 @@ namespace admm {
 constexpr int ADMM_FRAME_CLASSES = 16;   // (analysis, synthesis) x levels 1..4 x (small image)
 // column classes: 2 x (size class of the column length) + 1 for a general
 // schedule (first or last stage not radix 8: the column cannot stay in
-// registers around the solve), each launched with its own instantiation
-constexpr int ADMM_COL_CLASSES = 6;
+// registers around the solve), each launched with its own instantiation, and
+// class 6 for columns longer than 2048 (block-level transforms, any schedule)
+constexpr int ADMM_COL_CLASSES = 7;
+// size classes of the row length: <= 512, <= 1024, <= 2048, <= 4096 (rows
+// longer than 2048 run the plain row passes only; a TV problem with such rows
+// takes the three-pass schedule: inverse rows with the data step, the TV step,
+// forward rows)
+constexpr int ADMM_ROW_CLASSES = 4;
 
 // Everything a launch needs; item lists are device arrays, counts are the grid sizes.
 struct LaunchCtx {
@@ -31,19 +37,20 @@ struct LaunchCtx {
     // col_items / row_items
     int col_beg[ADMM_COL_CLASSES] = {}, col_cnt[ADMM_COL_CLASSES] = {};
     size_t lds_col_c[ADMM_COL_CLASSES] = {};
-    int rtv_beg[3] = {0, 0, 0}, rtv_cnt[3] = {0, 0, 0};
-    size_t lds_rtv_c[3] = {0, 0, 0};
+    int rtv_beg[ADMM_ROW_CLASSES] = {}, rtv_cnt[ADMM_ROW_CLASSES] = {};
+    size_t lds_rtv_c[ADMM_ROW_CLASSES] = {};
     // size classes of the plain row passes (FA rows, blur, state import) over row_items
-    int rrow_beg[3] = {0, 0, 0}, rrow_cnt[3] = {0, 0, 0};
-    size_t lds_rrow_c[3] = {0, 0, 0};
+    int rrow_beg[ADMM_ROW_CLASSES] = {}, rrow_cnt[ADMM_ROW_CLASSES] = {};
+    size_t lds_rrow_c[ADMM_ROW_CLASSES] = {};
     // frame classes (levels 1..4, image smaller than a window or not): items of
     // class c are [frm_beg[c], frm_beg[c] + frm_cnt[c]) of frm_items
     int frm_beg[ADMM_FRAME_CLASSES] = {}, frm_cnt[ADMM_FRAME_CLASSES] = {};
     size_t lds_frm_c[ADMM_FRAME_CLASSES] = {};
     // method CG: two sums per row block (p^T p, p^T S p; written by the inverse
-    // row pass, modes 2 and 3) and the TV step's LDS
+    // row pass, modes 2 and 3); the TV step's LDS (method CG, and TV-MD rows
+    // longer than 2048)
     double* cgpart = nullptr;
-    size_t lds_cgtv = 0;
+    size_t lds_tvstep = 0;
 };
 
 hipError_t launch_col(const LaunchCtx& L, int par, int mode);
@@ -64,8 +71,9 @@ hipError_t launch_warmstart(const LaunchCtx& L, int prob, size_t n, const float*
 
 // Reeves-Sorel variants (method CG), over the row items of the context
 hipError_t launch_cg_update(const LaunchCtx& L, int flags);
-hipError_t launch_cg_tv(const LaunchCtx& L, int par, int flags);
-size_t lds_cgtv_bytes(int W, int B);
+// the TV step over a z plane (TV-CG; TV-MD rows longer than 2048)
+hipError_t launch_tv_step(const LaunchCtx& L, int par, int flags);
+size_t lds_tvstep_bytes(int W, int B);
 hipError_t allow_dynamic_lds_cg(int bytes);
 
 hipError_t allow_dynamic_lds(int bytes);
@@ -77,8 +85,8 @@ int frame_class(int H, int W, int J, bool fs);   // 8 fs + 2 (J - 1) + (image sm
 int col_max_tiles();                       // columns per column-pass block (one per wave)
 int row_tv_max_rows(int w);                  // rows per block of the TV row pass for width w
 int row_max_rows(int w);                     // rows per block of the plain row passes for width w
-int size_class(int n);                      // 0: n <= 512, 1: n <= 1024, 2: larger
-int col_class(const ProbDesc& d);           // 2 size_class(H) + (general column schedule)
+int size_class(int n);                      // 0: n <= 512, 1: n <= 1024, 2: n <= 2048, 3: larger
+int col_class(const ProbDesc& d);           // 2 size_class(H) + (general column schedule); 6 above 2048
 int row_maxe();
 int block_threads();
 

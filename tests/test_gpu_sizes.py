@@ -120,3 +120,43 @@ def test_observation_of_a_non_7_smooth_size_through_the_embedding():
     assert y.shape == (125, 135)
     p = WL.Problem(y=y.astype(np.float64), mask=m, kernel=h, lam=2e-4, mu1=0.01, mu2=0.01)
     _single(p, [2, 20])
+
+
+@pytest.mark.parametrize("shape,k", [((4096, 64), 7), ((64, 4096), 9)])
+def test_tv_sides_above_2048(shape, k):
+    # columns of 4096: the block-level column pass; rows of 4096: the
+    # three-pass TV schedule (inverse rows with the data step, TV step, forward rows)
+    announce(f"tv {shape} k={k}")
+    _single(full_problem(95, *shape, k, missing=0.3), [2, 4])
+
+
+def test_frame_rows_above_2048_with_a_general_schedule():
+    announce("fa 48 x 3072 J=2")
+    _single(full_problem(96, 48, 3072, 5, reg="frame", levels=2, mu=0.02), [2, 4])
+
+
+def test_long_tv_rows_resume_bitwise_and_cg_parity():
+    # the three-pass TV schedule exports and imports its state bit for bit, and
+    # TV-CG runs on the same long rows (plain row passes of the longest class)
+    import torch
+    announce("64 x 2560 TV: resume and CG")
+    p = full_problem(97, 64, 2560, 7, missing=0.3)
+    H, W = p.shape
+    with A.Plan([p]) as plan:
+        s1 = A.alloc_state(H, W)
+        x12, _ = gpu_solve(plan, p, 12, state=s1)
+        s2 = A.alloc_state(H, W)
+        gpu_solve(plan, p, 5, state=s2)
+        x12b, _ = gpu_solve(plan, p, 7, state=s2)
+    assert np.array_equal(x12, x12b)
+    for key in ("u1", "d1", "ureg", "dreg"):
+        assert torch.equal(s1[key], s2[key]), key
+    K = 4
+    st = O.TVCGState.zeros(H, W)
+    spectra = (O.kernel_spectrum(p.kernel, H, W), *O.diff_spectra(H, W))
+    m = p.mask.astype(np.float64)
+    for _ in range(K):
+        st, z, _ = O.tv_cg_step(st, np.asarray(p.y, np.float64), m, p.kernel, p.lam, p.mu1, p.mu2, spectra)
+    with A.Plan([p], method=A.ADMM_METHOD_CG) as plan:
+        zc, _ = gpu_solve(plan, p, K, check_every=K)
+    check_iterate(zc, z, what="tv-cg k=4")

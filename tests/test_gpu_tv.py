@@ -10,7 +10,7 @@ import pytest
 import oracle as O
 from paper_1210_2687_amd import admm as A
 from paper_1210_2687_amd import workloads as WL
-from gpu_util import dev, host, rel, gpu_solve, announce, fast_tv_problem
+from gpu_util import dev, host, rel, gpu_solve, announce, fast_tv_problem, check_iterate
 
 pytestmark = pytest.mark.gpu
 
@@ -228,6 +228,21 @@ def test_largest_sizes_by_tiling(reps):
     e = rel(z, np.tile(ref, reps))
     announce(f"  {big.shape}: rel err {e:.2e}")
     assert e <= ITER_TOL
+
+
+@pytest.mark.parametrize("reps", [(64, 64), (40, 40), (64, 8)])
+def test_sides_above_2048_by_tiling(reps):
+    # 4096 x 4096, 2560 x 2560 (general schedules) and 4096 x 512 TV problems: the
+    # block-level column pass and (4096, 2560 wide) the three-pass TV schedule,
+    # against the oracle on one 64 x 64 tile, with the element-wise bound
+    announce(f"tiled TV {reps}")
+    base = fast_tv_problem(72, 64, 64, 7)
+    big = _tiled(base, reps)
+    K = 20
+    ref = O.tv_md_run(base.y, base.mask, base.kernel, base.lam, base.mu1, base.mu2, iters=K)["z"]
+    with A.Plan([big]) as plan:
+        z, _ = gpu_solve(plan, big, K, graph=True)
+    check_iterate(z, np.tile(ref, reps), ITER_TOL, f"{big.shape}")
 
 
 def test_frame_largest_size_by_tiling():
