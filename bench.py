@@ -19,6 +19,8 @@ The same JSON line also carries, under "configs", the other workloads:
   md_vs_cg    the paper's MD-vs-CG comparison (Tables 3 and 4): 256^2,
               four 19x19 blurs, TV and FA, MD to the paper's stopping rule,
               CG to the MD objective
+  tv4096      TV-MD 4096^2, 100 iterations (sides above 2048: the block-level
+              column pass and the three-pass TV row schedule)
   c4          ragged batch of 256 TV-MD problems (sides 128..1024, kernels
               5..31), 200 iterations
   beyond_cache  64 x 512^2 TV-MD, 500 iterations (working set ~0.9 GB, far
@@ -82,6 +84,9 @@ def alg_bytes_per_launch(problems):
              q (4 B / px): 8 + 8 (3J+1) B / px (the synthesis formulation:
              x - W zeta2 and the coefficients u2, the same count).
     row_fwd: read zeta1 and q (8 B / px), write the half spectra (16 B / entry).
+    TV rows longer than 2048 run the three-pass schedule: row_inv and row_fwd
+    as for the frame, and the TV step (counted under row_tv): read z and the
+    two duals, write the duals and s, 24 B / px.
     Halo re-reads are not counted (they are overhead, not algorithmic).
     """
     out = {"col": 0, "row_tv": 0, "row_inv": 0, "frame": 0, "row_fwd": 0}
@@ -94,6 +99,10 @@ def alg_bytes_per_launch(problems):
         if reg in ("frame", "synthesis"):
             out["row_inv"] += 16 * hp + (25 if reg == "synthesis" else 21) * n
             out["frame"] += (8 + 8 * (3 * p.levels + 1)) * n
+            out["row_fwd"] += 8 * n + 16 * hp
+        elif W > 2048:
+            out["row_inv"] += 16 * hp + 21 * n
+            out["row_tv"] += 24 * n
             out["row_fwd"] += 8 * n + 16 * hp
         else:
             out["row_tv"] += 32 * hp + 29 * n
@@ -138,6 +147,8 @@ def host_data(args):
     workers = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=workers) as ex:
+        # the 4096^2 image (about 16 s of host work) is drawn beside the others
+        big = ex.submit(_c2_member, 0, 4096) if (args.workload == "tv4096" or not args.quick) else None
         data["c2"] = list(ex.map(partial(_c2_member, size=args.size), range(args.batch)))
         if args.workload in ("fa1024", "fs1024") or not args.quick:
             data["c3"] = WL.config3(size=1024, levels=3)
@@ -146,6 +157,8 @@ def host_data(args):
             data["c4"] = list(ex.map(WL.config4, range(256), chunksize=4))
         if args.workload == "tv64x512" or not args.quick:
             data["c64"] = [data["c2"][i % len(data["c2"])] for i in range(64)]
+        if args.workload == "tv4096" or not args.quick:
+            data["c_big"] = [big.result()]
         if not args.quick:
             data["c1"] = WL.config1()
             if args.ws_train:
@@ -477,7 +490,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tv8x512",
-                    choices=["tv8x512", "tv64x512", "fa1024", "fs1024", "ragged256", "md_vs_cg", "tv8x512_cg"],
+                    choices=["tv8x512", "tv64x512", "tv4096", "fa1024", "fs1024", "ragged256", "md_vs_cg",
+                             "tv8x512_cg"],
                     help="the headline is tv8x512; with --quick, the others run alone (profiling)")
     ap.add_argument("--quick", action="store_true", help="only the chosen workload, no other configs")
     ap.add_argument("--iters", type=int, default=500, help="ADMM iterations per headline step")
@@ -533,6 +547,9 @@ def main():
         elif args.workload == "fs1024":
             configs["c3_fs"] = run_throughput("c3_fs", [data["c3_fs"]], 400, args.steps, args.warmup, tune,
                                               "FS-MD on the FA 1024x1024 J = 3 data, 400 iterations")
+        elif args.workload == "tv4096":
+            configs["tv4096"] = run_throughput("tv4096", data["c_big"], 100, args.steps, args.warmup, tune,
+                                               "TV-MD 4096x4096, 100 iterations")
         elif args.workload == "md_vs_cg":
             configs["md_vs_cg"] = run_md_vs_cg()
         elif args.workload == "tv8x512_cg":
@@ -578,6 +595,9 @@ def main():
                                                 f"{args.batch} x {args.size}^2, {args.iters} iterations",
                                                 method=A.ADMM_METHOD_CG)
         configs["md_vs_cg"] = run_md_vs_cg()
+        configs["tv4096"] = run_throughput("tv4096", data["c_big"], 100, 3, 1, tune,
+                                           "TV-MD 4096x4096 (the headline image family: 19x19 Gaussian sigma 3, 40% "
+                                           "missing), 100 iterations: block-level column pass and three-pass TV rows")
         configs["c4"] = run_throughput("c4", data["c4"], 200, 2, 1, tune,
                                        "TV-MD ragged batch of 256 problems, sides 128..1024 (7-smooth), kernels "
                                        "Gaussian/uniform/motion 5..31, lambda log-uniform 1e-5..1e-3, 200 iterations")

@@ -1551,7 +1551,10 @@ extern "C" admm_status admm_plan_time_pass(admm_plan* P, const char* kernel, int
     const std::string k = kernel;
     const bool fa = k == "frame" || k == "row_inv" || k == "row_fwd";
     if (k != "col" && k != "row_tv" && !fa) return fail(ADMM_E_INVALID, "unknown pass kernel %s", kernel);
-    if ((k == "row_tv" && !P->nrowtv) || (fa && !P->nfa))
+    // "row_tv": the fused TV row pass and the TV step of long TV rows; "row_inv",
+    // "row_fwd": the plain row passes of the frame problems and of long TV rows
+    if ((k == "row_tv" && !P->nrowtv) || (k == "frame" && !P->nfa) ||
+        ((k == "row_inv" || k == "row_fwd") && !P->nrowfa && !P->nrowtvs))
         return fail(ADMM_E_INVALID, "the plan has no %s launches", kernel);
     // every problem active, as in a running solve (a finished solve leaves them inactive)
     for (int i = 0; i < P->count; ++i) {
@@ -1561,10 +1564,18 @@ extern "C" admm_status admm_plan_time_pass(admm_plan* P, const char* kernel, int
     HIP_TRY(hipMemcpyAsync(P->d_info, P->h_info, sizeof(InfoDev) * P->count, hipMemcpyHostToDevice, P->stream));
     auto launch = [&]() -> hipError_t {
         if (k == "col") return launch_col(P->all, 0, COL_SOLVE);
-        if (k == "row_tv") return launch_row_tv(P->tv, 0, F_FORWARD);
         if (k == "frame") return launch_frame(P->fa, 0, 0, 0, true);
-        if (k == "row_inv") return launch_row_inv(P->fa, 0, 1, 0, true);
-        return launch_row_fwd(P->fa, 0, 0, true);
+        hipError_t e = hipSuccess;
+        if (k == "row_tv") {
+            e = launch_row_tv(P->tv, 0, F_FORWARD);
+            if (e == hipSuccess && P->nrowtvs) e = launch_tv_step(P->tvs, 0, 0);
+            return e;
+        }
+        const bool inv = k == "row_inv";
+        for (const LaunchCtx* c : {&P->fa, &P->tvs})
+            if (e == hipSuccess && c->nrow)
+                e = inv ? launch_row_inv(*c, 0, 1, 0, true) : launch_row_fwd(*c, 0, 0, true);
+        return e;
     };
     HIP_TRY(launch());   // warm
     hipEvent_t e0 = nullptr, e1 = nullptr;
