@@ -386,15 +386,15 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         int bmax = 0;
         const bool tv_split = q.reg == ADMM_REG_TV && q.W > 2048;   // three-pass TV schedule
         if (q.reg == ADMM_REG_TV && !tv_split) {
-            while (bmax + 1 <= std::min(q.H, row_tv_max_rows(q.W)) && fits(bmax + 3, d.fr, row_maxe()) &&
+            while (bmax + 1 <= std::min(q.H, row_tv_max_rows(q.W)) && fits(bmax + 3, d.fr, row_maxe(q.W)) &&
                    lds_rowtv_bytes(q.W, bmax + 1) <= cap && (!cg || lds_tvstep_bytes(q.W, bmax + 1) <= tv_cap))
                 ++bmax;
         } else if (tv_split) {
-            while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) && fits(bmax + 1, d.fr, row_maxe()) &&
+            while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) && fits(bmax + 1, d.fr, row_maxe(q.W)) &&
                    lds_row_bytes(q.W, bmax + 1) <= cap && lds_tvstep_bytes(q.W, bmax + 1) <= tv_cap)
                 ++bmax;
         } else {
-            while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) && fits(bmax + 1, d.fr, row_maxe()) &&
+            while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) && fits(bmax + 1, d.fr, row_maxe(q.W)) &&
                    lds_row_bytes(q.W, bmax + 1) <= cap)
                 ++bmax;
         }

@@ -33,6 +33,7 @@
 namespace admm {
 
 constexpr int NTG = 512;
+constexpr int TVS_BAND_MAX_W = 2048;   // longer rows take the row-walking TV step
 
 namespace {
 
@@ -160,16 +161,62 @@ __global__ __launch_bounds__(NTG) void k_cg_update(const ProbDesc* __restrict__ 
 // soft threshold and TV duals for the block's rows and the row above (whose
 // u + d enters the adjoint difference), then s = mu2 D^T (u + d) for the
 // block's rows; the TV block's residual sums on check iterations (odd
-// entries). LDS: (nr + 1) x W of each component of u + d.
+// entries). One element of a row at (r, c):
+//   v = D z - d, u = vector soft threshold of v at tau, d' = u - v (= d - (D z - u)),
+// with D z the periodic forward differences (z(r, c + 1) - z, z(r + 1, c) - z).
+struct TvElem {
+    float zh, zv, uh, uv, dhn, dvn;
+};
+__device__ __forceinline__ TvElem tv_elem(float zc, float zr, float zd, float dh, float dv, float tau) {
+    TvElem t;
+    t.zh = zr - zc;
+    t.zv = zd - zc;
+    const float vh = t.zh - dh, vv = t.zv - dv;
+    const float rho = __builtin_amdgcn_sqrtf(fmaf(vh, vh, vv * vv));
+    const float sc = rho > tau ? (rho - tau) * __builtin_amdgcn_rcpf(rho) : 0.0f;
+    t.uh = vh * sc;
+    t.uv = vv * sc;
+    t.dhn = t.uh - vh;
+    t.dvn = t.uv - vv;
+    return t;
+}
+
+// Outputs of one element of the block's own rows: the new duals, the check
+// sums, u of this iteration (for the next check) and the exported state.
 template <bool CHK>
-__global__ __launch_bounds__(NTG) void k_tv_step(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
-                                              const InfoDev* __restrict__ info, int par, int flags,
-                                              double* __restrict__ partials) {
-    extern __shared__ float ud[];
-    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    if (!info[it.prob].active) return;
-    const ProbDesc& p = pd[it.prob];
-    const int H = p.H, W = p.W, r0 = it.start, nr = min(p.B, H - r0);
+__device__ __forceinline__ void tv_elem_out(const TvElem& t, unsigned g, unsigned n, float uph, float upv, int flags,
+                                            float* dh_out, float* dv_out, float* UREGP, float* SUREG, float* SDREG,
+                                            double* acc) {
+    gst(dh_out, g, t.dhn);
+    gst(dv_out, g, t.dvn);
+    if (CHK) {   // u_{k-1} was read before a check iteration that also keeps u_k (period 1) overwrites it
+        const float e1h = t.zh - t.uh, e1v = t.zv - t.uv;
+        const float f7h = t.uh - uph, f7v = t.uv - upv;
+        acc[1] += (double)fmaf(e1h, e1h, e1v * e1v);
+        acc[3] += (double)fmaf(t.zh, t.zh, t.zv * t.zv);
+        acc[5] += (double)fmaf(t.uh, t.uh, t.uv * t.uv);
+        acc[7] += (double)fmaf(f7h, f7h, f7v * f7v);
+        acc[9] += (double)fmaf(t.dhn, t.dhn, t.dvn * t.dvn);
+        acc[11] += (double)sqrtf(fmaf(t.zh, t.zh, t.zv * t.zv));
+    }
+    if (flags & F_WRITE_UPREV) {
+        gst(UREGP, g, t.uh);
+        gst(UREGP, n + g, t.uv);
+    }
+    if (flags & F_EXPORT) {
+        gst(SUREG, g, t.uh);
+        gst(SUREG, n + g, t.uv);
+        gst(SDREG, g, t.dhn);
+        gst(SDREG, n + g, t.dvn);
+    }
+}
+
+// Rows of up to 2048: the block's (nr + 1) x W elements are spread over all
+// threads; u + d of every row (both components) goes to LDS, then s.
+// LDS: (nr + 1) x W of each component of u + d.
+template <bool CHK>
+__device__ void tv_step_band(const ProbDesc& p, int r0, int nr, int par, int flags, float* ud, double* acc) {
+    const int H = p.H, W = p.W;
     const unsigned n = (unsigned)(H * W);
     const float tau = p.tau, mu2 = p.mu2;
     const float* const Z = p.zpl;
@@ -183,49 +230,19 @@ __global__ __launch_bounds__(NTG) void k_tv_step(const ProbDesc* __restrict__ pd
     float* const TB = p.tmpB;
     float* udh = ud;
     float* udv = ud + (size_t)(nr + 1) * W;
-    double acc[ADMM_NSUM];
-#pragma unroll
-    for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
     const int tot = (nr + 1) * W;
     for (int i = threadIdx.x; i < tot; i += NTG) {
         const int rr = i / W, c = i - rr * W;
         const int r = rr == 0 ? (r0 == 0 ? H - 1 : r0 - 1) : r0 + rr - 1;   // row r0 - 1 + rr (wrapped)
         const int rn = r + 1 == H ? 0 : r + 1, cn = c + 1 == W ? 0 : c + 1;
         const unsigned g = (unsigned)(r * W + c);
-        const float zc = gld(Z, g);
-        const float zh = gld(Z, (unsigned)(r * W + cn)) - zc;
-        const float zv = gld(Z, (unsigned)(rn * W + c)) - zc;
-        const float dh = gld(dh_in, g), dv = gld(dv_in, g);
-        const float vh = zh - dh, vv = zv - dv;
-        const float rho = __builtin_amdgcn_sqrtf(fmaf(vh, vh, vv * vv));
-        const float sc = rho > tau ? (rho - tau) * __builtin_amdgcn_rcpf(rho) : 0.0f;
-        const float uh = vh * sc, uv = vv * sc;
-        const float dhn = uh - vh, dvn = uv - vv;   // d - (D z - u)
-        udh[i] = uh + dhn;
-        udv[i] = uv + dvn;
+        const TvElem t = tv_elem(gld(Z, g), gld(Z, (unsigned)(r * W + cn)), gld(Z, (unsigned)(rn * W + c)),
+                                 gld(dh_in, g), gld(dv_in, g), tau);
+        udh[i] = t.uh + t.dhn;
+        udv[i] = t.uv + t.dvn;
         if (rr > 0) {
-            gst(dh_out, g, dhn);
-            gst(dv_out, g, dvn);
-            if (CHK) {   // reads u_{k-1} before a check iteration that also keeps u_k (period 1) overwrites it
-                const float e1h = zh - uh, e1v = zv - uv;
-                const float f7h = uh - gld(UREGP, g), f7v = uv - gld(UREGP, n + g);
-                acc[1] += (double)fmaf(e1h, e1h, e1v * e1v);
-                acc[3] += (double)fmaf(zh, zh, zv * zv);
-                acc[5] += (double)fmaf(uh, uh, uv * uv);
-                acc[7] += (double)fmaf(f7h, f7h, f7v * f7v);
-                acc[9] += (double)fmaf(dhn, dhn, dvn * dvn);
-                acc[11] += (double)sqrtf(fmaf(zh, zh, zv * zv));
-            }
-            if (flags & F_WRITE_UPREV) {
-                gst(UREGP, g, uh);
-                gst(UREGP, n + g, uv);
-            }
-            if (flags & F_EXPORT) {
-                gst(SUREG, g, uh);
-                gst(SUREG, n + g, uv);
-                gst(SDREG, g, dhn);
-                gst(SDREG, n + g, dvn);
-            }
+            const float uph = CHK ? gld(UREGP, g) : 0.0f, upv = CHK ? gld(UREGP, n + g) : 0.0f;
+            tv_elem_out<CHK>(t, g, n, uph, upv, flags, dh_out, dv_out, UREGP, SUREG, SDREG, acc);
         }
     }
     __syncthreads();
@@ -236,6 +253,95 @@ __global__ __launch_bounds__(NTG) void k_tv_step(const ProbDesc* __restrict__ pd
         const float s = mu2 * ((udh[kl] - udh[k]) + (udv[ku] - udv[k]));
         gst(TB, (unsigned)((r0 + rr - 1) * W + c), s);
     }
+}
+
+// Rows of 2049..4096: thread t owns columns t, t + NTG, ... (TVW_CPT of them,
+// clamped to the row) and walks the rows from the one above the block's first
+// row down. Each row's inputs are fetched in one burst of unconditional loads;
+// the vertical component of u + d of the row above stays in registers, the
+// horizontal one of the current row goes through LDS (two row buffers, so one
+// barrier per row). LDS: 2 x W floats.
+constexpr int TVW_CPT = 8;   // W <= TVW_CPT * NTG
+template <bool CHK>
+__device__ void tv_step_walk(const ProbDesc& p, int r0, int nr, int par, int flags, float* ud, double* acc) {
+    const int H = p.H, W = p.W, tid = threadIdx.x;
+    const unsigned n = (unsigned)(H * W);
+    const float tau = p.tau, mu2 = p.mu2;
+    const float* const Z = p.zpl;
+    const float* const dh_in = par ? p.dreg1 : p.dreg0;
+    const float* const dv_in = dh_in + n;
+    float* const dh_out = par ? p.dreg0 : p.dreg1;
+    float* const dv_out = dh_out + n;
+    float* const UREGP = p.uregp;
+    float* const SUREG = p.st_ureg;
+    float* const SDREG = p.st_dreg;
+    float* const TB = p.tmpB;
+    float udv_up[TVW_CPT];
+#pragma unroll
+    for (int j = 0; j < TVW_CPT; ++j) udv_up[j] = 0.0f;
+    for (int rr = 0; rr <= nr; ++rr) {
+        const int r = rr == 0 ? (r0 == 0 ? H - 1 : r0 - 1) : r0 + rr - 1;   // row r0 - 1 + rr (wrapped)
+        const int rn = r + 1 == H ? 0 : r + 1;
+        const bool own = rr > 0;
+        float zc[TVW_CPT], zr[TVW_CPT], zd[TVW_CPT], dh[TVW_CPT], dv[TVW_CPT], uph[TVW_CPT], upv[TVW_CPT];
+#pragma unroll
+        for (int j = 0; j < TVW_CPT; ++j) {
+            const int c = min(tid + j * NTG, W - 1), cn = c + 1 == W ? 0 : c + 1;
+            const unsigned g = (unsigned)(r * W + c);
+            zc[j] = gld(Z, g);
+            zr[j] = gld(Z, (unsigned)(r * W + cn));
+            zd[j] = gld(Z, (unsigned)(rn * W + c));
+            dh[j] = gld(dh_in, g);
+            dv[j] = gld(dv_in, g);
+            uph[j] = CHK ? gld(UREGP, g) : 0.0f;
+            upv[j] = CHK ? gld(UREGP, n + g) : 0.0f;
+        }
+        float* const ub = ud + (rr & 1) * W;
+        float udv[TVW_CPT];
+#pragma unroll
+        for (int j = 0; j < TVW_CPT; ++j) {
+            const int c = tid + j * NTG;
+            const TvElem t = tv_elem(zc[j], zr[j], zd[j], dh[j], dv[j], tau);
+            udv[j] = t.uv + t.dvn;
+            if (c < W) {
+                ub[c] = t.uh + t.dhn;
+                if (own)
+                    tv_elem_out<CHK>(t, (unsigned)(r * W + c), n, uph[j], upv[j], flags, dh_out, dv_out, UREGP, SUREG,
+                                     SDREG, acc);
+            }
+        }
+        __syncthreads();
+        if (own) {
+#pragma unroll
+            for (int j = 0; j < TVW_CPT; ++j) {
+                const int c = tid + j * NTG;
+                if (c < W) {
+                    const float s = mu2 * ((ub[c == 0 ? W - 1 : c - 1] - ub[c]) + (udv_up[j] - udv[j]));
+                    gst(TB, (unsigned)(r * W + c), s);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < TVW_CPT; ++j) udv_up[j] = udv[j];
+    }
+}
+
+template <bool CHK>
+__global__ __launch_bounds__(NTG) void k_tv_step(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                              const InfoDev* __restrict__ info, int par, int flags,
+                                              double* __restrict__ partials) {
+    extern __shared__ float ud[];
+    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    if (!info[it.prob].active) return;
+    const ProbDesc& p = pd[it.prob];
+    const int r0 = it.start, nr = min(p.B, p.H - r0);
+    double acc[ADMM_NSUM];
+#pragma unroll
+    for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
+    if (p.W > TVS_BAND_MAX_W)
+        tv_step_walk<CHK>(p, r0, nr, par, flags, ud, acc);
+    else
+        tv_step_band<CHK>(p, r0, nr, par, flags, ud, acc);
     if (CHK) cg_write_sums(acc, partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM, true);
 }
 
@@ -262,7 +368,9 @@ hipError_t launch_tv_step(const LaunchCtx& L, int par, int flags) {
     return hipGetLastError();
 }
 
-size_t lds_tvstep_bytes(int W, int B) { return (size_t)2 * (B + 1) * W * sizeof(float); }
+size_t lds_tvstep_bytes(int W, int B) {
+    return W > TVS_BAND_MAX_W ? (size_t)2 * W * sizeof(float) : (size_t)2 * (B + 1) * W * sizeof(float);
+}
 
 hipError_t allow_dynamic_lds_cg(int bytes) {
     const void* fns[] = {reinterpret_cast<const void*>(&k_tv_step<false>),

@@ -33,7 +33,14 @@ constexpr int ROW_BURST = 8;       // plane elements per thread fetched together
 // two blocks per compute unit)
 constexpr int RTV_EARLY[3] = {5, 3, 1};
 // most rows per block of the plain row passes, per size class (W <= 512, 1024, 2048, 4096)
-constexpr int ROW_RB[ADMM_ROW_CLASSES] = {16, 8, 4, 2};
+constexpr int ROW_RB[ADMM_ROW_CLASSES] = {16, 8, 4, 4};
+// Rows longer than 2048 (CPT = 8): the plain row passes read the stage table
+// from global memory through the caches, so that four padded rows fit the LDS
+// (two rows would write 32-byte pieces of the transposed spectrum, which the
+// caches do not merge at this size: measured at 2.4x the spectrum's bytes), and
+// take up to 32 operands per thread in a stage.
+template <int CPT> constexpr bool row_twg() { return CPT * NT > 2048; }
+template <int CPT> constexpr int row_maxe_c() { return row_twg<CPT>() ? 32 : MAXE_ROW; }
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -306,11 +313,14 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
 
 // Column pass for columns longer than 2048 (up to 4096): one block of NTB
 // threads per column. The column (H float4 entries: the two packed complex
-// sequences) and the stage table sit in LDS and every stage runs block-wide
-// (fft_lds over float4 elements, any schedule of the plan); the solve between
-// the transforms is the one of k_col, entry by entry.
+// sequences) sits in LDS and every stage runs block-wide (fft_lds over float4
+// elements, any schedule of the plan); the stage table is read from global
+// memory through the caches (it is shared by every column of the length), so
+// that two blocks fit a compute unit. The solve between the transforms is the
+// one of k_col, entry by entry.
 constexpr int NTB = 512;
 constexpr int MAXE_BIG = 16;   // float4 operands per thread in a stage (radix 2..8, length <= 4096)
+constexpr int NLB = (ADMM_MAX_SIDE + NTB - 1) / NTB;   // column entries per thread
 __global__ __launch_bounds__(NTB) void k_col_big(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                  int nitems, int par, int mode, const InfoDev* __restrict__ info,
                                                  const float2* __restrict__ tw, const float* __restrict__ s2tab) {
@@ -325,22 +335,42 @@ __global__ __launch_bounds__(NTB) void k_col_big(const ProbDesc* __restrict__ pd
     const float* s2H = s2tab + p.fc.tw_off;
     const float mu1 = p.mu1, mu2 = p.mu2, ihw = p.inv_hw;
     const float w2 = p.reg == REG_TV ? s2tab[p.fr.tw_off + col] : 0.0f;
-    float2* twg = reinterpret_cast<float2*>(cl);                  // stage table: H - 1 entries
-    float4* buf = cl + (H + 1) / 2;                                // the column, padded (pidx)
-    ADMM_LDS float2* const tl = (ADMM_LDS float2*)twg;
+    float4* buf = cl;                                              // the column, padded (pidx)
     ADMM_LDS float4* const bl = (ADMM_LDS float4*)buf;
-    const float2* tws = tw + p.fc.tw_off + H;
-    for (int e = tid; e < H - 1; e += NTB) lds_st(tl + e, gld(tws, (unsigned)e));
-    for (int e = tid; e < H; e += NTB) lds_st(bl + pidx(e), gld(S, (unsigned)e));
-    __syncthreads();
-    fft_lds<MAXE_BIG, false, true>(buf, p.fc, twg, 1, 0, tid, NTB);
-    for (int e = tid; e < H; e += NTB) {
-        const float2 lm = gld(L, (unsigned)e);
-        const float w = p.reg == REG_TV ? s2H[e] + w2 : 1.0f;
-        lds_st(bl + pidx(e), col_solve(lds_ld(bl + pidx(e)), lm, w, mu1, mu2, ihw, mode));
+    const float2* tws = tw + p.fc.tw_off + H;                      // stage table: H - 1 entries
+    // the column, then the solve's coefficients, each in one burst of
+    // unconditional loads (indices clamped), so that the block waits for one
+    // memory latency instead of one per element
+    {
+        float4 v[NLB];
+#pragma unroll
+        for (int u = 0; u < NLB; ++u) v[u] = gld(S, (unsigned)min(tid + u * NTB, H - 1));
+#pragma unroll
+        for (int u = 0; u < NLB; ++u) {
+            const int e = tid + u * NTB;
+            if (e < H) lds_st(bl + pidx(e), v[u]);
+        }
     }
     __syncthreads();
-    fft_lds<MAXE_BIG, true, true>(buf, p.fc, twg, 1, 0, tid, NTB);
+    fft_lds<MAXE_BIG, false, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
+    // (fetched after the transform: held across it, they would cost the
+    // registers that let two blocks share a compute unit)
+    float2 lm[NLB];
+    float wq[NLB];
+#pragma unroll
+    for (int u = 0; u < NLB; ++u) {
+        const int e = min(tid + u * NTB, H - 1);
+        lm[u] = gld(L, (unsigned)e);
+        wq[u] = p.reg == REG_TV ? gld(s2H, (unsigned)e) + w2 : 1.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < NLB; ++u) {   // computed on clamped entries too, so that the loads above stay in their burst
+        const int e = tid + u * NTB;
+        const float4 z = col_solve(lds_ld(bl + pidx(min(e, H - 1))), lm[u], wq[u], mu1, mu2, ihw, mode);
+        if (e < H) lds_st(bl + pidx(e), z);
+    }
+    __syncthreads();
+    fft_lds<MAXE_BIG, true, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
     for (int e = tid; e < H; e += NTB) gst(S, (unsigned)e, lds_ld(bl + pidx(e)));
 }
 
@@ -629,14 +659,17 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
     const float* a = p.tmpA + (size_t)r0 * W;
     const float* b = p.tmpB + (size_t)r0 * W;
     const float mu1 = p.mu1;
+    constexpr bool TWG = row_twg<CPT>();
     // the stage table, then bursts of RCH rows of both planes per thread
     // (unconditional loads, rows and columns clamped; the second plane is read
     // but not used for src 1), so that each burst costs one memory latency
     constexpr int RCH = CPT >= ROW_BURST ? 1 : ROW_BURST / CPT;
     const float2* tws = tw + p.fr.tw_off + W;
     float2 tv[CPT];
+    if constexpr (!TWG) {
 #pragma unroll
-    for (int u = 0; u < CPT; ++u) tv[u] = gld(tws, (unsigned)min(tid + u * NT, W - 1));
+        for (int u = 0; u < CPT; ++u) tv[u] = gld(tws, (unsigned)min(tid + u * NT, W - 1));
+    }
     for (int rb = 0; rb < nr; rb += RCH) {
         float va[RCH][CPT], vb[RCH][CPT];
 #pragma unroll
@@ -649,7 +682,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
                 vb[k][j] = gld(b, g);
             }
         }
-        if (rb == 0) {
+        if (!TWG && rb == 0) {
 #pragma unroll
             for (int u = 0; u < CPT; ++u)
                 if (tid + u * NT < W) twl[tid + u * NT] = tv[u];
@@ -666,7 +699,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
         }
     }
     __syncthreads();
-    rows_fft<NT * CPT, NT, RB, MAXE_ROW, false>(X, pitch, p.fr, twl, nr, tid);
+    rows_fft<NT * CPT, NT, RB, row_maxe_c<CPT>(), false, TWG>(X, pitch, p.fr, TWG ? tws : twl, nr, tid);
     store_rows_split<true>(X, pitch, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
 }
 
@@ -693,13 +726,15 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     const int nr = min(p.B, H - r0);
     const int tid = threadIdx.x;
     const int pitch = row_pitch(W);
-    float2* twl = X + (size_t)p.B * pitch;
+    constexpr bool TWG = row_twg<CPT>();
+    const float2* const tws = tw + p.fr.tw_off + W;
+    float2* const twl = TWG ? nullptr : X + (size_t)p.B * pitch;
+    const float2* const stab = TWG ? tws : twl;
     // spectrum rows r0 .. r0 + nr - 1 (P <= NT CPT / 2 + 1 entries each), then the stage table
     constexpr int NLD = ((NT * CPT / 2 + 1) * RB + NT - 1) / NT;
-    load_rows_hermitian<true, NLD, CPT>(X, pitch, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid, twl,
-                                        tw + p.fr.tw_off + W, W);
+    load_rows_hermitian<true, NLD, CPT>(X, pitch, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid, twl, tws, W);
     __syncthreads();
-    rows_fft<NT * CPT, NT, RB, MAXE_ROW, true>(X, pitch, p.fr, twl, nr, tid);
+    rows_fft<NT * CPT, NT, RB, row_maxe_c<CPT>(), true, TWG>(X, pitch, p.fr, stab, nr, tid);
     const unsigned off = (unsigned)(r0 * W);
     if (mode == 0) {
         float* const TB = p.tmpB;   // read once: the stores below would make the compiler reload it
@@ -755,7 +790,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
         }
         if (first) {
             __syncthreads();
-            rows_fft<NT * CPT, NT, RB, MAXE_ROW, false>(X, pitch, p.fr, twl, nr, tid);
+            rows_fft<NT * CPT, NT, RB, row_maxe_c<CPT>(), false, TWG>(X, pitch, p.fr, stab, nr, tid);
             store_rows_split<true>(X, pitch, p.spec0, H, W, P, r0, nr, tid);
         }
         __syncthreads();   // X becomes the reduction scratch
@@ -1008,7 +1043,7 @@ __global__ void k_scale2(const float* __restrict__ d, float* __restrict__ p, siz
 
 // ------------------------------------------------------------ host launchers
 static size_t col_lds(int H, int TC) {
-    if (H > 2048) TC = 1;   // the block-level column pass: one column per block
+    if (H > 2048) return (size_t)pidx_len(H) * sizeof(float4);   // the block-level column pass: the column alone
     return (size_t)((H + 1) / 2) * sizeof(float4) + (size_t)TC * pidx_len(H) * sizeof(float4);
 }
 static size_t rowtv_lds(int W, int B) {
@@ -1018,7 +1053,8 @@ static size_t rowtv_lds(int W, int B) {
     return b > scratch ? b : scratch;
 }
 static size_t row_lds(int W, int B) {
-    const size_t b = ((size_t)B * row_pitch(W) + W) * sizeof(float2);   // padded rows + twiddles
+    // padded rows + the stage table (in global memory for rows longer than 2048)
+    const size_t b = ((size_t)B * row_pitch(W) + (W > 2048 ? 0 : W)) * sizeof(float2);
     const size_t scratch = NT / 64 * ADMM_NSUM * sizeof(double);    // block sums reuse the rows
     return b > scratch ? b : scratch;
 }
@@ -1219,7 +1255,7 @@ size_t lds_col_bytes(int H, int TC) { return col_lds(H, TC); }
 size_t lds_rowtv_bytes(int W, int B) { return rowtv_lds(W, B); }
 size_t lds_row_bytes(int W, int B) { return row_lds(W, B); }
 int col_max_tiles() { return NTC / 64; }
-int row_maxe() { return MAXE_ROW; }
+int row_maxe(int w) { return w > 2048 ? row_maxe_c<8>() : MAXE_ROW; }
 int block_threads() { return NT; }
 
 }  // namespace admm

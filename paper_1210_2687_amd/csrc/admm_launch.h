@@ -87,7 +87,7 @@ int row_tv_max_rows(int w);                  // rows per block of the TV row pas
 int row_max_rows(int w);                     // rows per block of the plain row passes for width w
 int size_class(int n);                      // 0: n <= 512, 1: n <= 1024, 2: n <= 2048, 3: larger
 int col_class(const ProbDesc& d);           // 2 size_class(H) + (general column schedule); 6 above 2048
-int row_maxe();
+int row_maxe(int w);                        // operands per thread in a stage of the row passes for width w
 int block_threads();
 
 }  // namespace admm

@@ -63,6 +63,10 @@ __device__ __forceinline__ uint8_t gld(const uint8_t* p) { return *(const ADMM_G
 __device__ __forceinline__ void gst(float4* p, float4 a) { *(ADMM_GLOBAL vf4*)p = vf4{a.x, a.y, a.z, a.w}; }
 __device__ __forceinline__ void gst(float2* p, float2 a) { *(ADMM_GLOBAL vf2*)p = vf2{a.x, a.y}; }
 __device__ __forceinline__ void gst(float* p, float a) { *(ADMM_GLOBAL float*)p = a; }
+// A twiddle of a stage table that sits in LDS, or in global memory (read
+// through the caches) when a block's data leaves no room for it.
+__device__ __forceinline__ float2 tw_ld(const ADMM_LDS float2* p) { return lds_ld(p); }
+__device__ __forceinline__ float2 tw_ld(const float2* p) { return gld(p); }
 // base[i] with a 32-bit byte offset (every plane and spectrum is far below
 // 4 GiB), so the access takes a scalar base plus one 32-bit vector offset
 // instead of a 64-bit vector address per element
@@ -271,8 +275,8 @@ __host__ __device__ constexpr int row_pitch(int n) { return pidx_len(n) + ((36 -
 // synchronises between the loads and the stores of a stage. Requirement
 // (checked on the host): ntrans * N / R <= (MAXE / R) * nthr. stw: the stage's
 // twiddle block (entries [k][r - 1]).
-template <int R, int MAXE, bool INV, bool PAD, typename E>
-__device__ __forceinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS float2* stw, int ntrans, int tstride,
+template <int R, int MAXE, bool INV, bool PAD, typename E, typename TWP>
+__device__ __forceinline__ void stockham_stage(ADMM_LDS E* buf, TWP stw, int ntrans, int tstride,
                                             int Ns, int nbf, unsigned mnbf, unsigned mns, int tid, int nthr) {
     constexpr int NB = MAXE / R;
     const int total = ntrans * nbf;
@@ -292,10 +296,10 @@ __device__ __forceinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS f
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = lds_ld(b + (PAD ? pidx(j + r * nbf) : j + r * nbf));
             if (Ns > 1) {
-                const ADMM_LDS float2* tk = stw + k * (R - 1);
+                const TWP tk = stw + k * (R - 1);
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    float2 w = lds_ld(tk + r - 1);
+                    float2 w = tw_ld(tk + r - 1);
                     if (INV) w.y = -w.y;
                     v[i][r] = cmul(v[i][r], w);
                 }
@@ -319,19 +323,21 @@ __device__ __forceinline__ void stockham_stage(ADMM_LDS E* buf, const ADMM_LDS f
 
 // Full transform of `ntrans` length-N sequences in LDS at stride `tstride`
 // (natural order in and out, unnormalised); PAD: each sequence in the padded
-// layout (pidx); stw: the length's stage table in LDS.
-template <int MAXE, bool INV, bool PAD, typename E>
-__device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const float2* gstw, int ntrans, int tstride,
-                                        int tid, int nthr) {
-    ADMM_LDS E* buf = (ADMM_LDS E*)gbuf;
-    const ADMM_LDS float2* stw = (const ADMM_LDS float2*)gstw;
+// layout (pidx); stw: the length's stage table, in LDS (or, with TWG, in
+// global memory). R16: whether radix-16 stages are compiled (the column
+// schedules have none, and their code would set the kernel's register count).
+template <int MAXE, bool INV, bool PAD, bool R16, typename E, typename TWP>
+__device__ __forceinline__ void fft_lds_stages(ADMM_LDS E* buf, const FftPlanDev& f, TWP stw, int ntrans, int tstride,
+                                               int tid, int nthr) {
     const int nst = f.nst;
     for (int s = 0; s < nst; ++s) {
         const int R = f.rad[s], Ns = f.ns[s], nbf = f.nbf[s];
         const unsigned mnbf = f.mnbf[s], mns = f.mns[s];
-        const ADMM_LDS float2* t = stw + f.tso[s];
+        const TWP t = stw + f.tso[s];
         switch (R) {
-            case 16: stockham_stage<16, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
+            case 16:
+                if constexpr (R16) stockham_stage<16, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr);
+                break;
             case 8: stockham_stage<8, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
             case 4: stockham_stage<4, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
             case 2: stockham_stage<2, MAXE, INV, PAD>(buf, t, ntrans, tstride, Ns, nbf, mnbf, mns, tid, nthr); break;
@@ -341,6 +347,15 @@ __device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const floa
             default: break;
         }
     }
+}
+template <int MAXE, bool INV, bool PAD, bool TWG = false, bool R16 = true, typename E>
+__device__ __forceinline__ void fft_lds(E* gbuf, const FftPlanDev& f, const float2* gstw, int ntrans, int tstride,
+                                        int tid, int nthr) {
+    if constexpr (TWG)
+        fft_lds_stages<MAXE, INV, PAD, R16>((ADMM_LDS E*)gbuf, f, gstw, ntrans, tstride, tid, nthr);
+    else
+        fft_lds_stages<MAXE, INV, PAD, R16>((ADMM_LDS E*)gbuf, f, (const ADMM_LDS float2*)gstw, ntrans, tstride, tid,
+                                            nthr);
 }
 
 // ----------------------------------------------------------- wave-level transforms
@@ -550,8 +565,8 @@ __device__ __forceinline__ void wave_fft(ADMM_LDS E* buf, const ADMM_LDS float2*
 // rows at `pitch` in LDS share the stages; butterfly q = tid + i NTHR of a
 // stage belongs to row q / nbf and is butterfly q mod nbf of that row, and
 // with the length fixed every such division is a shift or a constant multiply.
-template <int N, int S, int NTHR, int MAXT, bool INV, typename E>
-__device__ __forceinline__ void b_stage(ADMM_LDS E* buf, int pitch, const ADMM_LDS float2* stw, int ntrans, int tid) {
+template <int N, int S, int NTHR, int MAXT, bool INV, typename E, typename TWP>
+__device__ __forceinline__ void b_stage(ADMM_LDS E* buf, int pitch, TWP stw, int ntrans, int tid) {
     using T = CSt<N, S>;
     constexpr int NBT = (MAXT * T::nbf + NTHR - 1) / NTHR;
     E v[NBT][T::R];
@@ -571,10 +586,10 @@ __device__ __forceinline__ void b_stage(ADMM_LDS E* buf, int pitch, const ADMM_L
                 for (int r = 0; r < T::R; ++r) v[i][r] = lds_ld(b + pidx(j + r * T::nbf));
             }
             if constexpr (T::Ns > 1) {
-                const ADMM_LDS float2* tk = stw + T::TSO + (j % T::Ns) * (T::R - 1);
+                const TWP tk = stw + T::TSO + (j % T::Ns) * (T::R - 1);
 #pragma unroll
                 for (int r = 1; r < T::R; ++r) {
-                    float2 w = lds_ld(tk + r - 1);
+                    float2 w = tw_ld(tk + r - 1);
                     if (INV) w.y = -w.y;
                     v[i][r] = cmul(v[i][r], w);
                 }
@@ -607,8 +622,8 @@ __device__ __forceinline__ void b_stage(ADMM_LDS E* buf, int pitch, const ADMM_L
     __syncthreads();
 }
 
-template <int N, int S0, int S1, int NTHR, int MAXT, bool INV, typename E>
-__device__ __forceinline__ void b_stages(ADMM_LDS E* buf, int pitch, const ADMM_LDS float2* stw, int ntrans, int tid) {
+template <int N, int S0, int S1, int NTHR, int MAXT, bool INV, typename E, typename TWP>
+__device__ __forceinline__ void b_stages(ADMM_LDS E* buf, int pitch, TWP stw, int ntrans, int tid) {
     if constexpr (S0 < S1) {
         b_stage<N, S0, NTHR, MAXT, INV>(buf, pitch, stw, ntrans, tid);
         b_stages<N, S0 + 1, S1, NTHR, MAXT, INV>(buf, pitch, stw, ntrans, tid);
@@ -616,15 +631,20 @@ __device__ __forceinline__ void b_stages(ADMM_LDS E* buf, int pitch, const ADMM_
 }
 
 // Transform `ntrans` <= MAXT padded rows at `pitch`: the fixed-length code when
-// the length is NF, else the run-time schedule (same layout).
-template <int NF, int NTHR, int MAXT, int MAXE, bool INV, typename E>
+// the length is NF, else the run-time schedule (same layout). TWG: the stage
+// table gstw is in global memory (else in LDS).
+template <int NF, int NTHR, int MAXT, int MAXE, bool INV, bool TWG = false, typename E>
 __device__ __forceinline__ void rows_fft(E* gbuf, int pitch, const FftPlanDev& f, const float2* gstw, int ntrans,
                                          int tid) {
-    if (f.N == NF && f.variant == 0)
-        b_stages<NF, 0, CSched<NF>::nst(), NTHR, MAXT, INV>((ADMM_LDS E*)gbuf, pitch, (const ADMM_LDS float2*)gstw,
-                                                            ntrans, tid);
-    else
-        fft_lds<MAXE, INV, true>(gbuf, f, gstw, ntrans, pitch, tid, NTHR);
+    if (f.N == NF && f.variant == 0) {
+        if constexpr (TWG)
+            b_stages<NF, 0, CSched<NF>::nst(), NTHR, MAXT, INV>((ADMM_LDS E*)gbuf, pitch, gstw, ntrans, tid);
+        else
+            b_stages<NF, 0, CSched<NF>::nst(), NTHR, MAXT, INV>((ADMM_LDS E*)gbuf, pitch,
+                                                                (const ADMM_LDS float2*)gstw, ntrans, tid);
+    } else {
+        fft_lds<MAXE, INV, true, TWG>(gbuf, f, gstw, ntrans, pitch, tid, NTHR);
+    }
 }
 
 // The N entries of a stage table into LDS: the first NPT per thread in one
