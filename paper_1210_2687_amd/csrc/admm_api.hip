@@ -35,6 +35,7 @@ using admm_host::smooth7;
 using admm_host::TuneEntry;
 using admm_host::validate;
 using admm_host::write_cache;
+static_assert(admm_host::kRowClasses == ADMM_ROW_CLASSES, "tuning cache fields: one per row size class");
 
 namespace {
 
@@ -376,9 +377,9 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         d.TC = std::min(std::min(tcmax, tc_batch), d.P);
         if (tile.tc > 0) d.TC = std::min(d.TC, tile.tc);
         if (const char* e = std::getenv("ADMM_TC")) d.TC = std::max(1, std::min(d.TC, std::atoi(e)));
-        if (q.H > 2048) {   // the block-level column pass: one column per block, 16 operands per thread
+        if (q.H > 2048) {   // the block-level column pass: one column per block
             d.TC = 1;
-            if (!fits(1, d.fc, 16))
+            if (!fits(1, d.fc, col_big_maxe(q.H)))
                 return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: column schedule of length %d does not fit a block", i,
                                  q.H));
         }
@@ -442,7 +443,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         }
         col_cc[c] = (int)col.size() - col_cb[c];
     }
-    // (class 3, rows longer than 2048, takes the three-pass TV schedule: no fused pass)
+    // (classes 3 and 4, rows longer than 2048, take the three-pass TV schedule: no fused pass)
     for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
         rtv_cb[c] = (int)rowtv.size();
         for (int i : order) {
@@ -504,7 +505,8 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     }
     P->ncol = (int)col.size();
     P->nrowtv = (int)rowtv.size();
-    P->nrowtvs = rtv_cc[3];
+    P->nrowtvs = 0;
+    for (int c = 3; c < ADMM_ROW_CLASSES; ++c) P->nrowtvs += rtv_cc[c];
     P->nrowfa = (int)rowfa.size();
     P->nfrm = (int)frm.size();
 
@@ -658,6 +660,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     for (int i = 0; i < count; ++i)   // the TV step: every TV problem of a CG plan, long TV rows of an MD plan
         if (P->hd[i].reg == REG_TV && (cg || P->hd[i].W > 2048))
             base_ctx.lds_tvstep = std::max(base_ctx.lds_tvstep, lds_tvstep_bytes(P->hd[i].W, P->hd[i].B));
+    for (int i = 0; i < count; ++i) base_ctx.tv_wide |= P->hd[i].reg == REG_TV && P->hd[i].W > 4096;
     for (int c = 0; c < ADMM_COL_CLASSES; ++c) {
         base_ctx.col_beg[c] = col_cb[c];
         base_ctx.col_cnt[c] = col_cc[c];
@@ -693,14 +696,16 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     P->fa.frm_items = P->d_items + col.size() + rowtv.size() + rowfa.size();
     P->fa.nfrm = P->nfrm;
     // the TV problems with rows longer than 2048 alone (their row items are the
-    // last class of the TV list): plain row passes and the TV step
+    // last classes of the TV list): plain row passes and the TV step
     P->tvs = base_ctx;
     P->tvs.row_items = P->d_items + col.size() + rtv_cb[3];
     P->tvs.nrow = P->nrowtvs;
     for (int c = 0; c < 3; ++c) P->tvs.rtv_cnt[c] = 0;
-    P->tvs.rrow_beg[3] = 0;
-    P->tvs.rrow_cnt[3] = rtv_cc[3];
-    P->tvs.lds_rrow_c[3] = lds_rtvp_c[3];
+    for (int c = 3; c < ADMM_ROW_CLASSES; ++c) {
+        P->tvs.rrow_beg[c] = rtv_cb[c] - rtv_cb[3];
+        P->tvs.rrow_cnt[c] = rtv_cc[c];
+        P->tvs.lds_rrow_c[c] = lds_rtvp_c[c];
+    }
 
     // kernel spectra Lambda (eq. (19)): host computes the row sums T[a][k2] in double
     for (int i = 0; i < count; ++i) {

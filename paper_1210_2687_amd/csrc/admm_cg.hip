@@ -215,7 +215,8 @@ __device__ __forceinline__ void tv_elem_out(const TvElem& t, unsigned g, unsigne
 // threads; u + d of every row (both components) goes to LDS, then s.
 // LDS: (nr + 1) x W of each component of u + d.
 template <bool CHK>
-__device__ void tv_step_band(const ProbDesc& p, int r0, int nr, int par, int flags, float* ud, double* acc) {
+__device__ __forceinline__ void tv_step_band(const ProbDesc& p, int r0, int nr, int par, int flags, float* ud,
+                                             double* acc) {
     const int H = p.H, W = p.W;
     const unsigned n = (unsigned)(H * W);
     const float tau = p.tau, mu2 = p.mu2;
@@ -255,15 +256,17 @@ __device__ void tv_step_band(const ProbDesc& p, int r0, int nr, int par, int fla
     }
 }
 
-// Rows of 2049..4096: thread t owns columns t, t + NTG, ... (TVW_CPT of them,
-// clamped to the row) and walks the rows from the one above the block's first
-// row down. Each row's inputs are fetched in one burst of unconditional loads;
-// the vertical component of u + d of the row above stays in registers, the
-// horizontal one of the current row goes through LDS (two row buffers, so one
-// barrier per row). LDS: 2 x W floats.
-constexpr int TVW_CPT = 8;   // W <= TVW_CPT * NTG
-template <bool CHK>
-__device__ void tv_step_walk(const ProbDesc& p, int r0, int nr, int par, int flags, float* ud, double* acc) {
+// Rows of 2049..8192: thread t owns columns t, t + NTG, ... (CPT of them,
+// clamped to the row; 8 up to 4096, 16 above) and walks the rows from the one
+// above the block's first row down. A row's inputs are fetched in bursts of
+// unconditional loads of TVW_BURST columns each; the vertical component of
+// u + d of the row above stays in registers, the horizontal one of the current
+// row goes through LDS (two row buffers, so one barrier per row).
+// LDS: 2 x W floats.
+constexpr int TVW_BURST = 8;
+template <bool CHK, int CPT>
+__device__ __forceinline__ void tv_step_walk(const ProbDesc& p, int r0, int nr, int par, int flags, float* ud,
+                                             double* acc) {
     const int H = p.H, W = p.W, tid = threadIdx.x;
     const unsigned n = (unsigned)(H * W);
     const float tau = p.tau, mu2 = p.mu2;
@@ -276,44 +279,48 @@ __device__ void tv_step_walk(const ProbDesc& p, int r0, int nr, int par, int fla
     float* const SUREG = p.st_ureg;
     float* const SDREG = p.st_dreg;
     float* const TB = p.tmpB;
-    float udv_up[TVW_CPT];
+    float udv_up[CPT];
 #pragma unroll
-    for (int j = 0; j < TVW_CPT; ++j) udv_up[j] = 0.0f;
+    for (int j = 0; j < CPT; ++j) udv_up[j] = 0.0f;
     for (int rr = 0; rr <= nr; ++rr) {
         const int r = rr == 0 ? (r0 == 0 ? H - 1 : r0 - 1) : r0 + rr - 1;   // row r0 - 1 + rr (wrapped)
         const int rn = r + 1 == H ? 0 : r + 1;
         const bool own = rr > 0;
-        float zc[TVW_CPT], zr[TVW_CPT], zd[TVW_CPT], dh[TVW_CPT], dv[TVW_CPT], uph[TVW_CPT], upv[TVW_CPT];
-#pragma unroll
-        for (int j = 0; j < TVW_CPT; ++j) {
-            const int c = min(tid + j * NTG, W - 1), cn = c + 1 == W ? 0 : c + 1;
-            const unsigned g = (unsigned)(r * W + c);
-            zc[j] = gld(Z, g);
-            zr[j] = gld(Z, (unsigned)(r * W + cn));
-            zd[j] = gld(Z, (unsigned)(rn * W + c));
-            dh[j] = gld(dh_in, g);
-            dv[j] = gld(dv_in, g);
-            uph[j] = CHK ? gld(UREGP, g) : 0.0f;
-            upv[j] = CHK ? gld(UREGP, n + g) : 0.0f;
-        }
         float* const ub = ud + (rr & 1) * W;
-        float udv[TVW_CPT];
+        float udv[CPT];
 #pragma unroll
-        for (int j = 0; j < TVW_CPT; ++j) {
-            const int c = tid + j * NTG;
-            const TvElem t = tv_elem(zc[j], zr[j], zd[j], dh[j], dv[j], tau);
-            udv[j] = t.uv + t.dvn;
-            if (c < W) {
-                ub[c] = t.uh + t.dhn;
-                if (own)
-                    tv_elem_out<CHK>(t, (unsigned)(r * W + c), n, uph[j], upv[j], flags, dh_out, dv_out, UREGP, SUREG,
-                                     SDREG, acc);
+        for (int j0 = 0; j0 < CPT; j0 += TVW_BURST) {
+            float zc[TVW_BURST], zr[TVW_BURST], zd[TVW_BURST], dh[TVW_BURST], dv[TVW_BURST], uph[TVW_BURST],
+                upv[TVW_BURST];
+#pragma unroll
+            for (int j = 0; j < TVW_BURST; ++j) {
+                const int c = min(tid + (j0 + j) * NTG, W - 1), cn = c + 1 == W ? 0 : c + 1;
+                const unsigned g = (unsigned)(r * W + c);
+                zc[j] = gld(Z, g);
+                zr[j] = gld(Z, (unsigned)(r * W + cn));
+                zd[j] = gld(Z, (unsigned)(rn * W + c));
+                dh[j] = gld(dh_in, g);
+                dv[j] = gld(dv_in, g);
+                uph[j] = CHK ? gld(UREGP, g) : 0.0f;
+                upv[j] = CHK ? gld(UREGP, n + g) : 0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < TVW_BURST; ++j) {
+                const int c = tid + (j0 + j) * NTG;
+                const TvElem t = tv_elem(zc[j], zr[j], zd[j], dh[j], dv[j], tau);
+                udv[j0 + j] = t.uv + t.dvn;
+                if (c < W) {
+                    ub[c] = t.uh + t.dhn;
+                    if (own)
+                        tv_elem_out<CHK>(t, (unsigned)(r * W + c), n, uph[j], upv[j], flags, dh_out, dv_out, UREGP,
+                                         SUREG, SDREG, acc);
+                }
             }
         }
         __syncthreads();
         if (own) {
 #pragma unroll
-            for (int j = 0; j < TVW_CPT; ++j) {
+            for (int j = 0; j < CPT; ++j) {
                 const int c = tid + j * NTG;
                 if (c < W) {
                     const float s = mu2 * ((ub[c == 0 ? W - 1 : c - 1] - ub[c]) + (udv_up[j] - udv[j]));
@@ -322,11 +329,13 @@ __device__ void tv_step_walk(const ProbDesc& p, int r0, int nr, int par, int fla
             }
         }
 #pragma unroll
-        for (int j = 0; j < TVW_CPT; ++j) udv_up[j] = udv[j];
+        for (int j = 0; j < CPT; ++j) udv_up[j] = udv[j];
     }
 }
 
-template <bool CHK>
+// WIDE: the instantiation that also takes rows longer than 4096 (their walk
+// holds twice the registers, which would cost the narrower rows occupancy).
+template <bool CHK, bool WIDE>
 __global__ __launch_bounds__(NTG) void k_tv_step(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                               const InfoDev* __restrict__ info, int par, int flags,
                                               double* __restrict__ partials) {
@@ -338,8 +347,10 @@ __global__ __launch_bounds__(NTG) void k_tv_step(const ProbDesc* __restrict__ pd
     double acc[ADMM_NSUM];
 #pragma unroll
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
-    if (p.W > TVS_BAND_MAX_W)
-        tv_step_walk<CHK>(p, r0, nr, par, flags, ud, acc);
+    if (WIDE && p.W > 4096)
+        tv_step_walk<CHK, 16>(p, r0, nr, par, flags, ud, acc);
+    else if (p.W > TVS_BAND_MAX_W)
+        tv_step_walk<CHK, 8>(p, r0, nr, par, flags, ud, acc);
     else
         tv_step_band<CHK>(p, r0, nr, par, flags, ud, acc);
     if (CHK) cg_write_sums(acc, partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM, true);
@@ -357,14 +368,24 @@ hipError_t launch_cg_update(const LaunchCtx& L, int flags) {
     return hipGetLastError();
 }
 
+namespace {
+template <bool WIDE>
+void launch_tv_step_w(const LaunchCtx& L, int par, int flags) {
+    if (flags & F_CHECK)
+        hipLaunchKernelGGL((k_tv_step<true, WIDE>), dim3(L.nrow), dim3(NTG), L.lds_tvstep, L.stream, L.desc,
+                           L.row_items, L.info, par, flags, L.partials);
+    else
+        hipLaunchKernelGGL((k_tv_step<false, WIDE>), dim3(L.nrow), dim3(NTG), L.lds_tvstep, L.stream, L.desc,
+                           L.row_items, L.info, par, flags, L.partials);
+}
+}  // namespace
+
 hipError_t launch_tv_step(const LaunchCtx& L, int par, int flags) {
     if (!L.nrow) return hipSuccess;
-    if (flags & F_CHECK)
-        hipLaunchKernelGGL(k_tv_step<true>, dim3(L.nrow), dim3(NTG), L.lds_tvstep, L.stream, L.desc, L.row_items,
-                           L.info, par, flags, L.partials);
+    if (L.tv_wide)
+        launch_tv_step_w<true>(L, par, flags);
     else
-        hipLaunchKernelGGL(k_tv_step<false>, dim3(L.nrow), dim3(NTG), L.lds_tvstep, L.stream, L.desc, L.row_items,
-                           L.info, par, flags, L.partials);
+        launch_tv_step_w<false>(L, par, flags);
     return hipGetLastError();
 }
 
@@ -373,8 +394,10 @@ size_t lds_tvstep_bytes(int W, int B) {
 }
 
 hipError_t allow_dynamic_lds_cg(int bytes) {
-    const void* fns[] = {reinterpret_cast<const void*>(&k_tv_step<false>),
-                         reinterpret_cast<const void*>(&k_tv_step<true>)};
+    const void* fns[] = {reinterpret_cast<const void*>(&k_tv_step<false, false>),
+                         reinterpret_cast<const void*>(&k_tv_step<true, false>),
+                         reinterpret_cast<const void*>(&k_tv_step<false, true>),
+                         reinterpret_cast<const void*>(&k_tv_step<true, true>)};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;

@@ -115,7 +115,7 @@ bool parse_cache(const std::string& text, std::map<std::string, TuneEntry>& out)
                 // non-negative numbers: anything else makes the file malformed
                 // (and keeps the conversions below defined)
                 const bool count = f == "tc" || f == "rows" || f == "rows_512" || f == "rows_1024" || f == "rows_2048" ||
-                                   f == "rows_4096";
+                                   f == "rows_4096" || f == "rows_8192";
                 const bool sched = f == "rsched" || f == "csched";
                 if (!std::isfinite(v) || v < 0.0 || (count && (v > kMaxTileCount || v != std::floor(v))) ||
                     (sched && (v >= kScheduleVariants || v != std::floor(v))))
@@ -128,6 +128,7 @@ bool parse_cache(const std::string& text, std::map<std::string, TuneEntry>& out)
                 else if (f == "rows_1024") e.rows_c[1] = (int)v;
                 else if (f == "rows_2048") e.rows_c[2] = (int)v;
                 else if (f == "rows_4096") e.rows_c[3] = (int)v;
+                else if (f == "rows_8192") e.rows_c[4] = (int)v;
                 else if (f == "col_us") e.col_us = v;
                 else if (f == "row_us") e.row_us = v;
                 skip_ws(p);
@@ -158,8 +159,8 @@ std::string format_cache(const std::map<std::string, TuneEntry>& m) {
     for (const auto& kv : m) {
         char buf[512];
         std::string extra;
-        static const char* names[4] = {"rows_512", "rows_1024", "rows_2048", "rows_4096"};
-        for (int c = 0; c < 4; ++c)
+        static const char* names[kRowClasses] = {"rows_512", "rows_1024", "rows_2048", "rows_4096", "rows_8192"};
+        for (int c = 0; c < kRowClasses; ++c)
             if (kv.second.rows_c[c] > 0) extra += ", \"" + std::string(names[c]) + "\": " + std::to_string(kv.second.rows_c[c]);
         if (kv.second.rsched > 0) extra += ", \"rsched\": " + std::to_string(kv.second.rsched);
         if (kv.second.csched > 0) extra += ", \"csched\": " + std::to_string(kv.second.csched);

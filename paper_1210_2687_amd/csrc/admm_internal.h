@@ -15,7 +15,7 @@
 
 #define ADMM_MAX_STAGES 12
 #define ADMM_NSUM 12
-#define ADMM_MAX_SIDE 4096
+#define ADMM_MAX_SIDE 8192
 #define ADMM_MAX_BANDS 16
 
 namespace admm {

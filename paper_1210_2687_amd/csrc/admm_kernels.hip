@@ -32,9 +32,9 @@ constexpr int ROW_BURST = 8;       // plane elements per thread fetched together
 // transforms, per size class (as many as keep the kernel at 128 VGPRs or fewer,
 // two blocks per compute unit)
 constexpr int RTV_EARLY[3] = {5, 3, 1};
-// most rows per block of the plain row passes, per size class (W <= 512, 1024, 2048, 4096)
-constexpr int ROW_RB[ADMM_ROW_CLASSES] = {16, 8, 4, 4};
-// Rows longer than 2048 (CPT = 8): the plain row passes read the stage table
+// most rows per block of the plain row passes, per size class (W <= 512, 1024, 2048, 4096, 8192)
+constexpr int ROW_RB[ADMM_ROW_CLASSES] = {16, 8, 4, 4, 2};
+// Rows longer than 2048 (CPT >= 8): the plain row passes read the stage table
 // from global memory through the caches, so that four padded rows fit the LDS
 // (two rows would write 32-byte pieces of the transposed spectrum, which the
 // caches do not merge at this size: measured at 2.4x the spectrum's bytes), and
@@ -311,16 +311,19 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
     for (int e = lane; e < H; e += 64) gst(S, e, lds_ld(buf + pidx(e)));
 }
 
-// Column pass for columns longer than 2048 (up to 4096): one block of NTB
+// Column pass for columns longer than 2048 (up to 8192): one block of NTB
 // threads per column. The column (H float4 entries: the two packed complex
 // sequences) sits in LDS and every stage runs block-wide (fft_lds over float4
 // elements, any schedule of the plan); the stage table is read from global
 // memory through the caches (it is shared by every column of the length), so
 // that two blocks fit a compute unit. The solve between the transforms is the
 // one of k_col, entry by entry.
+// NLB: most column entries per thread (H <= NLB NTB); MAXE: most float4
+// operands per thread in a stage (16 up to 4096, where the registers allow two
+// blocks per compute unit; 24 above, where the column's LDS allows one).
 constexpr int NTB = 512;
-constexpr int MAXE_BIG = 16;   // float4 operands per thread in a stage (radix 2..8, length <= 4096)
-constexpr int NLB = (ADMM_MAX_SIDE + NTB - 1) / NTB;   // column entries per thread
+template <int NLB> constexpr int col_big_maxe_c() { return NLB <= 8 ? 16 : 24; }
+template <int NLB>
 __global__ __launch_bounds__(NTB) void k_col_big(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                  int nitems, int par, int mode, const InfoDev* __restrict__ info,
                                                  const float2* __restrict__ tw, const float* __restrict__ s2tab) {
@@ -352,7 +355,8 @@ __global__ __launch_bounds__(NTB) void k_col_big(const ProbDesc* __restrict__ pd
         }
     }
     __syncthreads();
-    fft_lds<MAXE_BIG, false, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
+    constexpr int MAXE = col_big_maxe_c<NLB>();
+    fft_lds<MAXE, false, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
     // (fetched after the transform: held across it, they would cost the
     // registers that let two blocks share a compute unit)
     float2 lm[NLB];
@@ -370,7 +374,7 @@ __global__ __launch_bounds__(NTB) void k_col_big(const ProbDesc* __restrict__ pd
         if (e < H) lds_st(bl + pidx(e), z);
     }
     __syncthreads();
-    fft_lds<MAXE_BIG, true, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
+    fft_lds<MAXE, true, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
     for (int e = tid; e < H; e += NTB) gst(S, (unsigned)e, lds_ld(bl + pidx(e)));
 }
 
@@ -1059,9 +1063,13 @@ static size_t row_lds(int W, int B) {
     return b > scratch ? b : scratch;
 }
 
-int size_class(int n) { return n <= 512 ? 0 : (n <= 1024 ? 1 : (n <= 2048 ? 2 : 3)); }
+int size_class(int n) { return n <= 512 ? 0 : (n <= 1024 ? 1 : (n <= 2048 ? 2 : (n <= 4096 ? 3 : 4))); }
 
-int col_class(const ProbDesc& d) { return d.H > 2048 ? 6 : 2 * size_class(d.H) + (d.fc.ends8 ? 0 : 1); }
+int col_class(const ProbDesc& d) {
+    return d.H > 4096 ? 7 : (d.H > 2048 ? 6 : 2 * size_class(d.H) + (d.fc.ends8 ? 0 : 1));
+}
+
+int col_big_maxe(int h) { return h > 4096 ? col_big_maxe_c<16>() : col_big_maxe_c<8>(); }
 
 namespace {
 template <int EPL, bool GEN>
@@ -1083,8 +1091,12 @@ hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
             case 3: launch_col_class<16, true>(L, c, par, mode, info); break;
             case 4: launch_col_class<32, false>(L, c, par, mode, info); break;
             case 5: launch_col_class<32, true>(L, c, par, mode, info); break;
+            case 6:
+                hipLaunchKernelGGL(k_col_big<8>, dim3(L.col_cnt[c]), dim3(NTB), L.lds_col_c[c], L.stream, L.desc,
+                                   L.col_items + L.col_beg[c], L.col_cnt[c], par, mode, info, L.tw, L.s2);
+                break;
             default:
-                hipLaunchKernelGGL(k_col_big, dim3(L.col_cnt[c]), dim3(NTB), L.lds_col_c[c], L.stream, L.desc,
+                hipLaunchKernelGGL(k_col_big<16>, dim3(L.col_cnt[c]), dim3(NTB), L.lds_col_c[c], L.stream, L.desc,
                                    L.col_items + L.col_beg[c], L.col_cnt[c], par, mode, info, L.tw, L.s2);
                 break;
         }
@@ -1142,8 +1154,11 @@ hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
         else if (c == 2)
             hipLaunchKernelGGL((k_row_fwd<4, ROW_RB[2]>), dim3(n), dim3(NT), L.lds_rrow_c[2], L.stream, L.desc, it, n,
                                par, src, info, L.tw);
-        else
+        else if (c == 3)
             hipLaunchKernelGGL((k_row_fwd<8, ROW_RB[3]>), dim3(n), dim3(NT), L.lds_rrow_c[3], L.stream, L.desc, it, n,
+                               par, src, info, L.tw);
+        else
+            hipLaunchKernelGGL((k_row_fwd<16, ROW_RB[4]>), dim3(n), dim3(NT), L.lds_rrow_c[4], L.stream, L.desc, it, n,
                                par, src, info, L.tw);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1167,8 +1182,11 @@ hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool
         else if (c == 2)
             hipLaunchKernelGGL((k_row_inv<4, ROW_RB[2]>), dim3(n), dim3(NT), L.lds_rrow_c[2], L.stream, L.desc, it, n,
                                par, mode, flags, info, L.tw, part);
-        else
+        else if (c == 3)
             hipLaunchKernelGGL((k_row_inv<8, ROW_RB[3]>), dim3(n), dim3(NT), L.lds_rrow_c[3], L.stream, L.desc, it, n,
+                               par, mode, flags, info, L.tw, part);
+        else
+            hipLaunchKernelGGL((k_row_inv<16, ROW_RB[4]>), dim3(n), dim3(NT), L.lds_rrow_c[4], L.stream, L.desc, it, n,
                                par, mode, flags, info, L.tw, part);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1240,7 +1258,10 @@ hipError_t allow_dynamic_lds(int bytes) {
         reinterpret_cast<const void*>(&k_row_fwd<4, ROW_RB[2]>),
         reinterpret_cast<const void*>(&k_row_fwd<8, ROW_RB[3]>),
         reinterpret_cast<const void*>(&k_row_inv<8, ROW_RB[3]>),
-        reinterpret_cast<const void*>(&k_col_big),
+        reinterpret_cast<const void*>(&k_row_fwd<16, ROW_RB[4]>),
+        reinterpret_cast<const void*>(&k_row_inv<16, ROW_RB[4]>),
+        reinterpret_cast<const void*>(&k_col_big<8>),
+        reinterpret_cast<const void*>(&k_col_big<16>),
         reinterpret_cast<const void*>(&k_row_inv<1, ROW_RB[0]>),
         reinterpret_cast<const void*>(&k_row_inv<2, ROW_RB[1]>),
         reinterpret_cast<const void*>(&k_row_inv<4, ROW_RB[2]>)};
@@ -1255,7 +1276,7 @@ size_t lds_col_bytes(int H, int TC) { return col_lds(H, TC); }
 size_t lds_rowtv_bytes(int W, int B) { return rowtv_lds(W, B); }
 size_t lds_row_bytes(int W, int B) { return row_lds(W, B); }
 int col_max_tiles() { return NTC / 64; }
-int row_maxe(int w) { return w > 2048 ? row_maxe_c<8>() : MAXE_ROW; }
+int row_maxe(int w) { return w > 2048 ? row_maxe_c<8>() : MAXE_ROW; }   // the same for CPT 16
 int block_threads() { return NT; }
 
 }  // namespace admm

@@ -47,7 +47,7 @@ int main(int argc, char** argv) {
         TuneEntry e;
         e.tc = 1 + (int)(g() % 4);
         e.rows = 1 + (int)(g() % 16);
-        e.rows_c[g() % 4] = (int)(g() % 17);
+        e.rows_c[g() % admm_host::kRowClasses] = (int)(g() % 17);
         e.rsched = (int)(g() % 4);
         e.csched = (int)(g() % 3);
         e.col_us = (double)(g() % 100000) / 1000.0;
@@ -63,6 +63,7 @@ int main(int argc, char** argv) {
         CHECK(it != back.end() && it->second.tc == kv.second.tc && it->second.rows == kv.second.rows &&
               it->second.rows_c[0] == kv.second.rows_c[0] && it->second.rows_c[1] == kv.second.rows_c[1] &&
               it->second.rows_c[2] == kv.second.rows_c[2] && it->second.rows_c[3] == kv.second.rows_c[3] &&
+              it->second.rows_c[4] == kv.second.rows_c[4] &&
               it->second.rsched == kv.second.rsched &&
               it->second.csched == kv.second.csched);
     }

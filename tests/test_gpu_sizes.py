@@ -7,8 +7,11 @@ names the kernel instantiations it runs:
 
 * column pass: one instantiation per size class of the column length
   (<= 512, <= 1024, <= 2048) and schedule (first and last stage radix 8:
-  fixed; otherwise general);
+  fixed; otherwise general), and the block-level pass for columns of
+  2049..4096 and 4097..8192;
 * TV row pass: one per size class of the row length (rows per block 8, 6, 2);
+  rows longer than 2048 (classes <= 4096 and <= 8192) take the three-pass
+  schedule (plain inverse rows with the data step, TV step, forward rows);
 * FA row passes and frame step: per size class of the row length and J.
 
 Bar (TV-MD Alg. 3 with the data step of eq. (49); FA-MD Sec. IV-C): relative
@@ -130,17 +133,29 @@ def test_tv_sides_above_2048(shape, k):
     _single(full_problem(95, *shape, k, missing=0.3), [2, 4])
 
 
-def test_frame_rows_above_2048_with_a_general_schedule():
-    announce("fa 48 x 3072 J=2")
-    _single(full_problem(96, 48, 3072, 5, reg="frame", levels=2, mu=0.02), [2, 4])
+@pytest.mark.parametrize("shape,k", [((8192, 48), 7), ((48, 8192), 9), ((7000, 40), 5), ((40, 6000), 7)])
+def test_tv_sides_above_4096(shape, k):
+    # columns of 8192 (radix 8 four times, then 2) and 7000 (radices 8, 5, 5, 5,
+    # 7: a general schedule): the block-level column pass with 16 entries per
+    # thread; rows of 8192 (compile-time schedule) and 6000 (general): the
+    # fifth row class, two rows per block, in the three-pass TV schedule
+    announce(f"tv {shape} k={k}")
+    _single(full_problem(98, *shape, k, missing=0.3), [2, 4])
 
 
-def test_long_tv_rows_resume_bitwise_and_cg_parity():
+@pytest.mark.parametrize("shape", [(48, 3072), (40, 6000)])
+def test_frame_rows_above_2048_with_a_general_schedule(shape):
+    announce(f"fa {shape} J=2")
+    _single(full_problem(96, *shape, 5, reg="frame", levels=2, mu=0.02), [2, 4])
+
+
+@pytest.mark.parametrize("shape", [(64, 2560), (40, 8192)])
+def test_long_tv_rows_resume_bitwise_and_cg_parity(shape):
     # the three-pass TV schedule exports and imports its state bit for bit, and
-    # TV-CG runs on the same long rows (plain row passes of the longest class)
+    # TV-CG runs on the same long rows (plain row passes of the longer classes)
     import torch
-    announce("64 x 2560 TV: resume and CG")
-    p = full_problem(97, 64, 2560, 7, missing=0.3)
+    announce(f"{shape} TV: resume and CG")
+    p = full_problem(97, *shape, 7, missing=0.3)
     H, W = p.shape
     with A.Plan([p]) as plan:
         s1 = A.alloc_state(H, W)

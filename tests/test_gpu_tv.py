@@ -230,13 +230,15 @@ def test_largest_sizes_by_tiling(reps):
     assert e <= ITER_TOL
 
 
-@pytest.mark.parametrize("reps", [(64, 64), (40, 40), (64, 8)])
-def test_sides_above_2048_by_tiling(reps):
-    # 4096 x 4096, 2560 x 2560 (general schedules) and 4096 x 512 TV problems: the
-    # block-level column pass and (4096, 2560 wide) the three-pass TV schedule,
-    # against the oracle on one 64 x 64 tile, with the element-wise bound
-    announce(f"tiled TV {reps}")
-    base = fast_tv_problem(72, 64, 64, 7)
+@pytest.mark.parametrize("base_shape,reps", [((64, 64), (64, 64)), ((64, 64), (40, 40)), ((64, 64), (64, 8)),
+                                             ((64, 64), (128, 128)), ((125, 125), (56, 48))])
+def test_sides_above_2048_by_tiling(base_shape, reps):
+    # 4096 x 4096, 2560 x 2560 (general schedules), 4096 x 512, 8192 x 8192 and
+    # 7000 x 6000 (general schedules) TV problems: the block-level column passes
+    # and (rows longer than 2048) the three-pass TV schedule, against the oracle
+    # on one tile, with the element-wise bound
+    announce(f"tiled TV {base_shape} x {reps}")
+    base = fast_tv_problem(72, *base_shape, 7)
     big = _tiled(base, reps)
     K = 20
     ref = O.tv_md_run(base.y, base.mask, base.kernel, base.lam, base.mu1, base.mu2, iters=K)["z"]

@@ -80,7 +80,7 @@ def test_store_rejects_bad_entries(tmp_path, key, tc, rows):
 
 def test_per_class_row_counts_survive_other_writes(tmp_path):
     # the autotuner may record row counts per size class of the row length
-    # ("rows_512", "rows_1024", "rows_2048", "rows_4096"); lookup reports the common
+    # ("rows_512", "rows_1024", ..., "rows_8192"); lookup reports the common
     # (tc, rows), and rewriting the file for another key keeps those fields
     path = tmp_path / "tune.json"
     path.write_text(json.dumps({"gfx950|h0123456789abcdef*256": {"tc": 4, "rows": 5, "rows_512": 8,
