@@ -71,8 +71,7 @@ int effective_variant(int n, int variant, bool column) {
 
 // Does a block of NT threads with MAXE registers per thread fit `ntrans`
 // length-N transforms for every radix of the schedule?
-bool fits(int ntrans, const FftPlanDev& f, int maxe) {
-    const int nt = block_threads();
+bool fits(int ntrans, const FftPlanDev& f, int maxe, int nt = block_threads()) {
     for (int s = 0; s < f.nst; ++s) {
         const int R = f.rad[s];
         const long long bf = (long long)ntrans * (f.N / R);
@@ -379,7 +378,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         if (const char* e = std::getenv("ADMM_TC")) d.TC = std::max(1, std::min(d.TC, std::atoi(e)));
         if (q.H > 2048) {   // the block-level column pass: one column per block
             d.TC = 1;
-            if (!fits(1, d.fc, col_big_maxe(q.H)))
+            if (!fits(1, d.fc, COL_BIG_MAXE, col_big_threads(q.H)))
                 return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: column schedule of length %d does not fit a block", i,
                                  q.H));
         }

@@ -45,7 +45,7 @@ __device__ __forceinline__ double cg_wave_sum(double v) {
 
 // Sum K per-thread values over the block into out[0..K) (thread 0 writes).
 template <int K>
-__device__ void cg_block_sums(const double* v, double* out) {
+__device__ __forceinline__ void cg_block_sums(const double* v, double* out) {
     __shared__ double sm[NTG / 64][K];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
@@ -64,7 +64,7 @@ __device__ void cg_block_sums(const double* v, double* out) {
 // The block's residual sums into its slot: every entry (odd == false; the data
 // step, whose regulariser entries are zero) or the odd entries only (the TV
 // step, which runs after the data step on the same row block).
-__device__ void cg_write_sums(const double* acc, double* slot, bool odd) {
+__device__ __forceinline__ void cg_write_sums(const double* acc, double* slot, bool odd) {
     __shared__ double out[ADMM_NSUM];
     cg_block_sums<ADMM_NSUM>(acc, out);
     __syncthreads();

@@ -63,7 +63,7 @@ __device__ __forceinline__ void wave_sums_to_lds(const double* v, double* wsum) 
 
 // Sum ADMM_NSUM per-thread values over the block and write them to out[0..NSUM).
 // scratch: >= (NT/64) * ADMM_NSUM doubles of LDS.
-__device__ void block_sums_write(const double* v, double* scratch, double* out) {
+__device__ __forceinline__ void block_sums_write(const double* v, double* scratch, double* out) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     __syncthreads();
 #pragma unroll
@@ -315,15 +315,15 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
 // threads per column. The column (H float4 entries: the two packed complex
 // sequences) sits in LDS and every stage runs block-wide (fft_lds over float4
 // elements, any schedule of the plan); the stage table is read from global
-// memory through the caches (it is shared by every column of the length), so
-// that two blocks fit a compute unit. The solve between the transforms is the
-// one of k_col, entry by entry.
-// NLB: most column entries per thread (H <= NLB NTB); MAXE: most float4
-// operands per thread in a stage (16 up to 4096, where the registers allow two
-// blocks per compute unit; 24 above, where the column's LDS allows one).
-constexpr int NTB = 512;
-template <int NLB> constexpr int col_big_maxe_c() { return NLB <= 8 ? 16 : 24; }
-template <int NLB>
+// memory through the caches (it is shared by every column of the length). The
+// solve between the transforms is the one of k_col, entry by entry.
+// Columns of up to 4096 take 512 threads (two blocks share a compute unit),
+// longer ones 1024 (the column's LDS allows one block per compute unit, and
+// 16 waves hide more latency than 8). Every thread holds up to 8 column
+// entries (H <= 8 NTB) and up to 16 float4 operands in a stage.
+constexpr int NLB = 8;
+constexpr int MAXE_BIG = 16;
+template <int NTB>
 __global__ __launch_bounds__(NTB) void k_col_big(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                  int nitems, int par, int mode, const InfoDev* __restrict__ info,
                                                  const float2* __restrict__ tw, const float* __restrict__ s2tab) {
@@ -355,8 +355,7 @@ __global__ __launch_bounds__(NTB) void k_col_big(const ProbDesc* __restrict__ pd
         }
     }
     __syncthreads();
-    constexpr int MAXE = col_big_maxe_c<NLB>();
-    fft_lds<MAXE, false, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
+    fft_lds<MAXE_BIG, false, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
     // (fetched after the transform: held across it, they would cost the
     // registers that let two blocks share a compute unit)
     float2 lm[NLB];
@@ -374,7 +373,7 @@ __global__ __launch_bounds__(NTB) void k_col_big(const ProbDesc* __restrict__ pd
         if (e < H) lds_st(bl + pidx(e), z);
     }
     __syncthreads();
-    fft_lds<MAXE, true, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
+    fft_lds<MAXE_BIG, true, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
     for (int e = tid; e < H; e += NTB) gst(S, (unsigned)e, lds_ld(bl + pidx(e)));
 }
 
@@ -1069,7 +1068,7 @@ int col_class(const ProbDesc& d) {
     return d.H > 4096 ? 7 : (d.H > 2048 ? 6 : 2 * size_class(d.H) + (d.fc.ends8 ? 0 : 1));
 }
 
-int col_big_maxe(int h) { return h > 4096 ? col_big_maxe_c<16>() : col_big_maxe_c<8>(); }
+int col_big_threads(int h) { return h > 4096 ? 1024 : 512; }
 
 namespace {
 template <int EPL, bool GEN>
@@ -1092,11 +1091,11 @@ hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
             case 4: launch_col_class<32, false>(L, c, par, mode, info); break;
             case 5: launch_col_class<32, true>(L, c, par, mode, info); break;
             case 6:
-                hipLaunchKernelGGL(k_col_big<8>, dim3(L.col_cnt[c]), dim3(NTB), L.lds_col_c[c], L.stream, L.desc,
+                hipLaunchKernelGGL(k_col_big<512>, dim3(L.col_cnt[c]), dim3(512), L.lds_col_c[c], L.stream, L.desc,
                                    L.col_items + L.col_beg[c], L.col_cnt[c], par, mode, info, L.tw, L.s2);
                 break;
             default:
-                hipLaunchKernelGGL(k_col_big<16>, dim3(L.col_cnt[c]), dim3(NTB), L.lds_col_c[c], L.stream, L.desc,
+                hipLaunchKernelGGL(k_col_big<1024>, dim3(L.col_cnt[c]), dim3(1024), L.lds_col_c[c], L.stream, L.desc,
                                    L.col_items + L.col_beg[c], L.col_cnt[c], par, mode, info, L.tw, L.s2);
                 break;
         }
@@ -1260,8 +1259,8 @@ hipError_t allow_dynamic_lds(int bytes) {
         reinterpret_cast<const void*>(&k_row_inv<8, ROW_RB[3]>),
         reinterpret_cast<const void*>(&k_row_fwd<16, ROW_RB[4]>),
         reinterpret_cast<const void*>(&k_row_inv<16, ROW_RB[4]>),
-        reinterpret_cast<const void*>(&k_col_big<8>),
-        reinterpret_cast<const void*>(&k_col_big<16>),
+        reinterpret_cast<const void*>(&k_col_big<512>),
+        reinterpret_cast<const void*>(&k_col_big<1024>),
         reinterpret_cast<const void*>(&k_row_inv<1, ROW_RB[0]>),
         reinterpret_cast<const void*>(&k_row_inv<2, ROW_RB[1]>),
         reinterpret_cast<const void*>(&k_row_inv<4, ROW_RB[2]>)};

@@ -89,7 +89,8 @@ int row_tv_max_rows(int w);                  // rows per block of the TV row pas
 int row_max_rows(int w);                     // rows per block of the plain row passes for width w
 int size_class(int n);                      // 0: n <= 512, 1: <= 1024, 2: <= 2048, 3: <= 4096, 4: larger
 int col_class(const ProbDesc& d);           // 2 size_class(H) + (general column schedule); 6, 7 above 2048
-int col_big_maxe(int h);                    // operands per thread in a stage of the block-level column pass
+int col_big_threads(int h);                 // threads per block of the block-level column pass
+constexpr int COL_BIG_MAXE = 16;            // its operands per thread in a stage
 int row_maxe(int w);                        // operands per thread in a stage of the row passes for width w
 int block_threads();
 
