@@ -50,7 +50,8 @@ extern "C" {
 typedef enum {
     ADMM_OK = 0,
     ADMM_E_INVALID = 1,      /* null pointer, bad size/count, negative lambda ...      */
-    ADMM_E_UNSUPPORTED = 2,  /* even or too large kernel, side not 7-smooth or > 8192 */
+    ADMM_E_UNSUPPORTED = 2,  /* even or too large kernel, side not 7-smooth or > 16384,
+                                frame coefficients (H W (3J+1) floats) above 4 GiB      */
     ADMM_E_SINGULAR = 3,     /* TV with sum(kernel) == 0: the z-step matrix is singular */
     ADMM_E_NOMEM = 4,        /* device allocation failed                                */
     ADMM_E_DEVICE = 5,       /* HIP runtime error (no device, launch failure ...)       */
@@ -66,7 +67,7 @@ typedef enum { ADMM_METHOD_MD = 0, ADMM_METHOD_CG = 1 } admm_method;
 
 /* One problem of a plan. */
 typedef struct {
-    int32_t H, W;            /* unknown-domain size; each side 7-smooth, 8..8192       */
+    int32_t H, W;            /* unknown-domain size; each side 7-smooth, 8..16384      */
     int32_t ksize;           /* odd kernel side k = 2l+1, 1 <= k <= min(H, W)          */
     const float* kernel;     /* HOST, k*k row-major, tap (l, l) is the centre; copied  */
     const uint8_t* mask;     /* HOST, H*W, 1 = observed (row of M), 0 = unobserved;
@@ -234,8 +235,8 @@ admm_status admm_plan_time_pass(admm_plan* plan, const char* kernel, int32_t rep
  * plans on the device (whole iterations replayed from graphs, zero data, on
  * hip_stream): first the column tiles at the default row count, then the row
  * counts at the best tile, then, for batches whose row lengths fall in several
- * size classes (<= 512, <= 1024, <= 2048, <= 4096, <= 8192), each class's row
- * count with the others held (kept on a gain above 0.5%). A trial's time per iteration is
+ * size classes (<= 512, <= 1024, <= 2048, <= 4096, <= 8192, <= 16384), each
+ * class's row count with the others held (kept on a gain above 0.5%). A trial's time per iteration is
  * the difference of runs of K and 3K iterations (K = 4 to 20 by batch size,
  * best of three runs of each after a warm-up) over 2K, free of the per-run
  * work.
@@ -284,7 +285,7 @@ int32_t admm_tune_key(const admm_problem* probs, int32_t count, const char* arch
  * `key` is present, 0 if absent (or no file), -1 if the file is malformed;
  * store inserts or replaces an entry (tc, rows >= 1; timings in microseconds).
  * Entries the autotuner writes may also hold per-class row counts
- * ("rows_512", ..., "rows_8192") and radix schedule variants
+ * ("rows_512", ..., "rows_16384") and radix schedule variants
  * ("rsched", "csched"), which lookup does not report and store does not
  * write.                                                        */
 int32_t admm_tune_cache_lookup(const char* path, const char* key, int32_t* tc, int32_t* rows);
@@ -321,7 +322,7 @@ admm_status admm_validate_problem(const admm_problem* prob);
 /* ---- Observations of any size (host only, no device work) ----
  * An observation of obs_h x obs_w pixels blurred by a k x k kernel depends on
  * an unknown domain of (obs_h + k - 1) x (obs_w + k - 1) pixels (Sec. IV-A,
- * eq. (34)); the transforms need 7-smooth sides of at most 8192. The helpers
+ * eq. (34)); the transforms need 7-smooth sides of at most 16384. The helpers
  * embed the observation in the smallest 7-smooth domain that holds that
  * unknown domain: the rows and columns added at the bottom and right are
  * unknowns that no observed pixel depends on, so only the regulariser sets
@@ -331,7 +332,7 @@ admm_status admm_validate_problem(const admm_problem* prob);
  * admm_embed_size: H, W (HOST outputs) = the smallest 7-smooth sides
  *   >= obs_h + ksize - 1 and >= obs_w + ksize - 1. ADMM_E_INVALID for
  *   non-positive sizes or null outputs, ADMM_E_UNSUPPORTED for an even
- *   ksize or a side above 8192.
+ *   ksize or a side above 16384.
  * admm_embed_observation: y_obs (HOST, obs_h*obs_w row-major) goes to rows
  *   l .. l + obs_h - 1 and columns l .. l + obs_w - 1 (l = ksize / 2) of the
  *   HOST H*W plane y (zero elsewhere); mask (HOST, H*W) is 1 there and 0

@@ -333,6 +333,8 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     for (int i = 0; i < count; ++i) {
         slot(probs[i].W, effective_variant(probs[i].W, tile.rsched, false));
         slot(probs[i].H, effective_variant(probs[i].H, tile.csched, true));
+        const int hs = probs[i].H / col_split_factor(probs[i].H);   // sub-transforms of split columns
+        if (hs != probs[i].H) slot(hs, effective_variant(hs, tile.csched, true));
     }
 
     // about two blocks per compute unit per pass (measured best on 8 x 512^2: TC = 4,
@@ -367,6 +369,11 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         const int rv = effective_variant(q.W, tile.rsched, false), cv = effective_variant(q.H, tile.csched, true);
         fill_plan(d.fr, q.W, slot(q.W, rv), rv);
         fill_plan(d.fc, q.H, slot(q.H, cv), cv);
+        d.csp = col_split_factor(q.H);
+        if (d.csp > 1) {
+            const int hs = q.H / d.csp, sv = effective_variant(hs, tile.csched, true);
+            fill_plan(d.fc2, hs, slot(hs, sv), sv);
+        }
         const int per = std::max(1, (target_blocks + count - 1) / count);
         // column tile: one column per wave of the column-pass block, as many as LDS holds
         int tcmax = 0;
@@ -376,9 +383,9 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         d.TC = std::min(std::min(tcmax, tc_batch), d.P);
         if (tile.tc > 0) d.TC = std::min(d.TC, tile.tc);
         if (const char* e = std::getenv("ADMM_TC")) d.TC = std::max(1, std::min(d.TC, std::atoi(e)));
-        if (q.H > 2048) {   // the block-level column pass: one column per block
+        if (q.H > 2048) {   // the block-level column pass: one column (or sub-transform) per block
             d.TC = 1;
-            if (!fits(1, d.fc, COL_BIG_MAXE, col_big_threads(q.H)))
+            if (!fits(1, d.csp > 1 ? d.fc2 : d.fc, COL_BIG_MAXE, col_big_threads(q.H)))
                 return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: column schedule of length %d does not fit a block", i,
                                  q.H));
         }
@@ -405,7 +412,7 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         if (breq > 0) d.B = std::min(bmax, breq);
         if (const char* e = std::getenv("ADMM_ROWS")) d.B = std::max(1, std::min(bmax, std::atoi(e)));
         d.nrowblk = (q.H + d.B - 1) / d.B;
-        d.ncolblk = (d.P + d.TC - 1) / d.TC;
+        d.ncolblk = d.csp > 1 ? d.P * d.csp : (d.P + d.TC - 1) / d.TC;
         if (d.reg == REG_FRAME) {
             d.frm_tile = frame_tile(q.levels);
             d.nfrmblk = ((q.H + d.frm_tile - 1) / d.frm_tile) * ((q.W + d.frm_tile - 1) / d.frm_tile);
@@ -436,7 +443,8 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
             ProbDesc& d = P->hd[i];
             if (col_class(d) != c) continue;
             P->col_beg[i] = (int)col.size();
-            for (int b = 0; b < d.ncolblk; ++b) col.push_back({i, b * d.TC, b, 0});
+            for (int b = 0; b < d.ncolblk; ++b)   // split columns: one item per (column, sub-transform)
+                col.push_back(d.csp > 1 ? WorkItem{i, b / d.csp, b, b % d.csp} : WorkItem{i, b * d.TC, b, 0});
             P->col_end[i] = (int)col.size();
             lds_col_c[c] = std::max(lds_col_c[c], lds_col_bytes(d.H, d.TC));
         }
@@ -659,7 +667,9 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     for (int i = 0; i < count; ++i)   // the TV step: every TV problem of a CG plan, long TV rows of an MD plan
         if (P->hd[i].reg == REG_TV && (cg || P->hd[i].W > 2048))
             base_ctx.lds_tvstep = std::max(base_ctx.lds_tvstep, lds_tvstep_bytes(P->hd[i].W, P->hd[i].B));
-    for (int i = 0; i < count; ++i) base_ctx.tv_wide |= P->hd[i].reg == REG_TV && P->hd[i].W > 4096;
+    for (int i = 0; i < count; ++i)
+        if (P->hd[i].reg == REG_TV)
+            base_ctx.tv_cpt = std::max(base_ctx.tv_cpt, P->hd[i].W > 8192 ? 32 : (P->hd[i].W > 4096 ? 16 : 8));
     for (int c = 0; c < ADMM_COL_CLASSES; ++c) {
         base_ctx.col_beg[c] = col_cb[c];
         base_ctx.col_cnt[c] = col_cc[c];

@@ -256,9 +256,9 @@ __device__ __forceinline__ void tv_step_band(const ProbDesc& p, int r0, int nr, 
     }
 }
 
-// Rows of 2049..8192: thread t owns columns t, t + NTG, ... (CPT of them,
-// clamped to the row; 8 up to 4096, 16 above) and walks the rows from the one
-// above the block's first row down. A row's inputs are fetched in bursts of
+// Rows of 2049..16384: thread t owns columns t, t + NTG, ... (CPT of them,
+// clamped to the row; 8 up to 4096, 16 up to 8192, 32 above) and walks the
+// rows from the one above the block's first row down. A row's inputs are fetched in bursts of
 // unconditional loads of TVW_BURST columns each; the vertical component of
 // u + d of the row above stays in registers, the horizontal one of the current
 // row goes through LDS (two row buffers, so one barrier per row).
@@ -333,9 +333,11 @@ __device__ __forceinline__ void tv_step_walk(const ProbDesc& p, int r0, int nr, 
     }
 }
 
-// WIDE: the instantiation that also takes rows longer than 4096 (their walk
-// holds twice the registers, which would cost the narrower rows occupancy).
-template <bool CHK, bool WIDE>
+// MCPT: the widest walk the instantiation takes (8, 16 or 32 columns per
+// thread: rows of up to 4096, 8192, 16384); a wider walk holds more registers,
+// which would cost the narrower rows occupancy, so a launch takes the
+// narrowest instantiation its batch allows.
+template <bool CHK, int MCPT>
 __global__ __launch_bounds__(NTG) void k_tv_step(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                               const InfoDev* __restrict__ info, int par, int flags,
                                               double* __restrict__ partials) {
@@ -347,7 +349,9 @@ __global__ __launch_bounds__(NTG) void k_tv_step(const ProbDesc* __restrict__ pd
     double acc[ADMM_NSUM];
 #pragma unroll
     for (int i = 0; i < ADMM_NSUM; ++i) acc[i] = 0.0;
-    if (WIDE && p.W > 4096)
+    if (MCPT >= 32 && p.W > 8192)
+        tv_step_walk<CHK, 32>(p, r0, nr, par, flags, ud, acc);
+    else if (MCPT >= 16 && p.W > 4096)
         tv_step_walk<CHK, 16>(p, r0, nr, par, flags, ud, acc);
     else if (p.W > TVS_BAND_MAX_W)
         tv_step_walk<CHK, 8>(p, r0, nr, par, flags, ud, acc);
@@ -369,23 +373,25 @@ hipError_t launch_cg_update(const LaunchCtx& L, int flags) {
 }
 
 namespace {
-template <bool WIDE>
+template <int MCPT>
 void launch_tv_step_w(const LaunchCtx& L, int par, int flags) {
     if (flags & F_CHECK)
-        hipLaunchKernelGGL((k_tv_step<true, WIDE>), dim3(L.nrow), dim3(NTG), L.lds_tvstep, L.stream, L.desc,
+        hipLaunchKernelGGL((k_tv_step<true, MCPT>), dim3(L.nrow), dim3(NTG), L.lds_tvstep, L.stream, L.desc,
                            L.row_items, L.info, par, flags, L.partials);
     else
-        hipLaunchKernelGGL((k_tv_step<false, WIDE>), dim3(L.nrow), dim3(NTG), L.lds_tvstep, L.stream, L.desc,
+        hipLaunchKernelGGL((k_tv_step<false, MCPT>), dim3(L.nrow), dim3(NTG), L.lds_tvstep, L.stream, L.desc,
                            L.row_items, L.info, par, flags, L.partials);
 }
 }  // namespace
 
 hipError_t launch_tv_step(const LaunchCtx& L, int par, int flags) {
     if (!L.nrow) return hipSuccess;
-    if (L.tv_wide)
-        launch_tv_step_w<true>(L, par, flags);
+    if (L.tv_cpt > 16)
+        launch_tv_step_w<32>(L, par, flags);
+    else if (L.tv_cpt > 8)
+        launch_tv_step_w<16>(L, par, flags);
     else
-        launch_tv_step_w<false>(L, par, flags);
+        launch_tv_step_w<8>(L, par, flags);
     return hipGetLastError();
 }
 
@@ -394,10 +400,12 @@ size_t lds_tvstep_bytes(int W, int B) {
 }
 
 hipError_t allow_dynamic_lds_cg(int bytes) {
-    const void* fns[] = {reinterpret_cast<const void*>(&k_tv_step<false, false>),
-                         reinterpret_cast<const void*>(&k_tv_step<true, false>),
-                         reinterpret_cast<const void*>(&k_tv_step<false, true>),
-                         reinterpret_cast<const void*>(&k_tv_step<true, true>)};
+    const void* fns[] = {reinterpret_cast<const void*>(&k_tv_step<false, 8>),
+                         reinterpret_cast<const void*>(&k_tv_step<true, 8>),
+                         reinterpret_cast<const void*>(&k_tv_step<false, 16>),
+                         reinterpret_cast<const void*>(&k_tv_step<true, 16>),
+                         reinterpret_cast<const void*>(&k_tv_step<false, 32>),
+                         reinterpret_cast<const void*>(&k_tv_step<true, 32>)};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;

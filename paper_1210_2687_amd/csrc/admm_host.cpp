@@ -51,6 +51,12 @@ admm_status validate(const admm_problem& p) {
         return fail(ADMM_E_UNSUPPORTED, "the synthesis formulation runs with mask decoupling only");
     if (p.reg != ADMM_REG_TV && (p.levels < 1 || p.levels > 4))
         return fail(ADMM_E_UNSUPPORTED, "frame levels %d outside 1..4", p.levels);
+    // the kernels address each array with 32-bit byte offsets: the frame's 3J+1
+    // coefficient planes (and the TV pair of dual planes) must stay below 4 GiB
+    const long long planes = p.reg == ADMM_REG_TV ? 2 : 3LL * p.levels + 1;
+    if ((long long)p.H * p.W * planes * (long long)sizeof(float) > 0xFFFFFFFFLL)
+        return fail(ADMM_E_UNSUPPORTED, "%dx%d with %lld coefficient planes exceeds 4 GiB per array", p.H, p.W,
+                    planes);
     if (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)) return fail(ADMM_E_INVALID, "lambda must be finite and >= 0");
     if (!std::isfinite(p.mu1) || !std::isfinite(p.mu2)) return fail(ADMM_E_INVALID, "mu must be finite");
     double sum = 0.0, asum = 0.0;
@@ -115,7 +121,7 @@ bool parse_cache(const std::string& text, std::map<std::string, TuneEntry>& out)
                 // non-negative numbers: anything else makes the file malformed
                 // (and keeps the conversions below defined)
                 const bool count = f == "tc" || f == "rows" || f == "rows_512" || f == "rows_1024" || f == "rows_2048" ||
-                                   f == "rows_4096" || f == "rows_8192";
+                                   f == "rows_4096" || f == "rows_8192" || f == "rows_16384";
                 const bool sched = f == "rsched" || f == "csched";
                 if (!std::isfinite(v) || v < 0.0 || (count && (v > kMaxTileCount || v != std::floor(v))) ||
                     (sched && (v >= kScheduleVariants || v != std::floor(v))))
@@ -129,6 +135,7 @@ bool parse_cache(const std::string& text, std::map<std::string, TuneEntry>& out)
                 else if (f == "rows_2048") e.rows_c[2] = (int)v;
                 else if (f == "rows_4096") e.rows_c[3] = (int)v;
                 else if (f == "rows_8192") e.rows_c[4] = (int)v;
+                else if (f == "rows_16384") e.rows_c[5] = (int)v;
                 else if (f == "col_us") e.col_us = v;
                 else if (f == "row_us") e.row_us = v;
                 skip_ws(p);
@@ -159,7 +166,8 @@ std::string format_cache(const std::map<std::string, TuneEntry>& m) {
     for (const auto& kv : m) {
         char buf[512];
         std::string extra;
-        static const char* names[kRowClasses] = {"rows_512", "rows_1024", "rows_2048", "rows_4096", "rows_8192"};
+        static const char* names[kRowClasses] = {"rows_512",  "rows_1024", "rows_2048",
+                                                 "rows_4096", "rows_8192", "rows_16384"};
         for (int c = 0; c < kRowClasses; ++c)
             if (kv.second.rows_c[c] > 0) extra += ", \"" + std::string(names[c]) + "\": " + std::to_string(kv.second.rows_c[c]);
         if (kv.second.rsched > 0) extra += ", \"rsched\": " + std::to_string(kv.second.rsched);

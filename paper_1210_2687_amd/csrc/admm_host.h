@@ -9,7 +9,7 @@
 #include "../../include/admm_deconv.h"
 
 #ifndef ADMM_MAX_SIDE
-#define ADMM_MAX_SIDE 8192
+#define ADMM_MAX_SIDE 16384
 #endif
 
 namespace admm_host {
@@ -32,10 +32,10 @@ admm_status validate(const admm_problem& p);
 // ("rsched", "csched"; written when not 0) and the per-launch timings of the
 // choice, for the record.
 constexpr double kMaxTileCount = 4096.0;
-constexpr int kRowClasses = 5;   // size classes of the row length: <= 512, 1024, 2048, 4096, 8192
+constexpr int kRowClasses = 6;   // size classes of the row length: <= 512, 1024, 2048, 4096, 8192, 16384
 struct TuneEntry {
     int tc = 0, rows = 0;
-    int rows_c[kRowClasses] = {};   // "rows_512", "rows_1024", "rows_2048", "rows_4096", "rows_8192"
+    int rows_c[kRowClasses] = {};   // "rows_512", "rows_1024", ..., "rows_16384"
     int rsched = 0, csched = 0;  // radix schedule variants of the row and column transforms
     double col_us = 0.0, row_us = 0.0;
 };

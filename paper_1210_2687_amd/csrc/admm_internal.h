@@ -15,7 +15,7 @@
 
 #define ADMM_MAX_STAGES 12
 #define ADMM_NSUM 12
-#define ADMM_MAX_SIDE 8192
+#define ADMM_MAX_SIDE 16384
 #define ADMM_MAX_BANDS 16
 
 namespace admm {
@@ -170,6 +170,11 @@ struct ProbDesc {
     int part_base;              // first partial-vector slot of this problem
     float mu1, mu2, tau, lam, inv_hw, inv1pmu1;
     FftPlanDev fr, fc;          // row (length W) and column (length H) transforms
+    // columns longer than 8192: the column transform splits into csp
+    // sub-transforms of length H / csp (plan fc2) around a radix-csp pass
+    // through HBM (csp = 1: no split)
+    int csp;
+    FftPlanDev fc2;
     float4* spec0;
     float4* spec1;
     float2* lamhat;
@@ -210,7 +215,7 @@ struct WorkItem {
     int prob;
     int start;                  // first row (row pass), first column (column pass) or tile index
     int blk;                    // block index within the problem (partial-sum slot)
-    int pad;
+    int sub;                    // split column transforms: the sub-transform (0 otherwise)
 };
 
 struct InfoDev {

@@ -32,8 +32,8 @@ constexpr int ROW_BURST = 8;       // plane elements per thread fetched together
 // transforms, per size class (as many as keep the kernel at 128 VGPRs or fewer,
 // two blocks per compute unit)
 constexpr int RTV_EARLY[3] = {5, 3, 1};
-// most rows per block of the plain row passes, per size class (W <= 512, 1024, 2048, 4096, 8192)
-constexpr int ROW_RB[ADMM_ROW_CLASSES] = {16, 8, 4, 4, 2};
+// most rows per block of the plain row passes, per size class (W <= 512, 1024, 2048, 4096, 8192, 16384)
+constexpr int ROW_RB[ADMM_ROW_CLASSES] = {16, 8, 4, 4, 2, 1};
 // Rows longer than 2048 (CPT >= 8): the plain row passes read the stage table
 // from global memory through the caches, so that four padded rows fit the LDS
 // (two rows would write 32-byte pieces of the transposed spectrum, which the
@@ -311,12 +311,16 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
     for (int e = lane; e < H; e += 64) gst(S, e, lds_ld(buf + pidx(e)));
 }
 
-// Column pass for columns longer than 2048 (up to 8192): one block of NTB
-// threads per column. The column (H float4 entries: the two packed complex
-// sequences) sits in LDS and every stage runs block-wide (fft_lds over float4
-// elements, any schedule of the plan); the stage table is read from global
-// memory through the caches (it is shared by every column of the length). The
-// solve between the transforms is the one of k_col, entry by entry.
+// Column pass for columns longer than 2048: one block of NTB threads per
+// column, or, for columns longer than 8192, per sub-transform of a split column
+// (work item sub = k1: the csp-th part of the column at k1 H / csp, whose
+// entry e holds the spectrum at frequency k1 + csp e after the forward
+// transform; k_col_split runs before and after). The column (float4 entries:
+// the two packed complex sequences) sits in LDS and every stage runs
+// block-wide (fft_lds over float4 elements, any schedule of the plan); the
+// stage table is read from global memory through the caches (it is shared by
+// every column of the length). The solve between the transforms is the one of
+// k_col, entry by entry.
 // Columns of up to 4096 take 512 threads (two blocks share a compute unit),
 // longer ones 1024 (the column's LDS allows one block per compute unit, and
 // 16 waves hide more latency than 8). Every thread holds up to 8 column
@@ -331,50 +335,108 @@ __global__ __launch_bounds__(NTB) void k_col_big(const ProbDesc* __restrict__ pd
     const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     if (info && !info[it.prob].active) return;
     const ProbDesc& p = pd[it.prob];
-    const int H = p.H, col = it.start;   // one column per work item
+    const int H = p.H, col = it.start;   // one column (or sub-transform) per work item
     const int tid = threadIdx.x;
-    float4* S = ((p.reg == REG_TV && par) ? p.spec1 : p.spec0) + (size_t)col * H;
-    const float2* L = p.lamhat + (size_t)col * H;
+    const int csp = p.csp > 1 ? p.csp : 1, k1 = it.sub;
+    const FftPlanDev& f = csp > 1 ? p.fc2 : p.fc;
+    const int Hs = H / csp;                                        // this transform's length
+    float4* S = ((p.reg == REG_TV && par) ? p.spec1 : p.spec0) + (size_t)col * H + (size_t)k1 * Hs;
+    const float2* L = p.lamhat + (size_t)col * H;                  // indexed by frequency k1 + csp e
     const float* s2H = s2tab + p.fc.tw_off;
     const float mu1 = p.mu1, mu2 = p.mu2, ihw = p.inv_hw;
     const float w2 = p.reg == REG_TV ? s2tab[p.fr.tw_off + col] : 0.0f;
     float4* buf = cl;                                              // the column, padded (pidx)
     ADMM_LDS float4* const bl = (ADMM_LDS float4*)buf;
-    const float2* tws = tw + p.fc.tw_off + H;                      // stage table: H - 1 entries
+    const float2* tws = tw + f.tw_off + Hs;                        // stage table: Hs - 1 entries
     // the column, then the solve's coefficients, each in one burst of
     // unconditional loads (indices clamped), so that the block waits for one
     // memory latency instead of one per element
     {
         float4 v[NLB];
 #pragma unroll
-        for (int u = 0; u < NLB; ++u) v[u] = gld(S, (unsigned)min(tid + u * NTB, H - 1));
+        for (int u = 0; u < NLB; ++u) v[u] = gld(S, (unsigned)min(tid + u * NTB, Hs - 1));
 #pragma unroll
         for (int u = 0; u < NLB; ++u) {
             const int e = tid + u * NTB;
-            if (e < H) lds_st(bl + pidx(e), v[u]);
+            if (e < Hs) lds_st(bl + pidx(e), v[u]);
         }
     }
     __syncthreads();
-    fft_lds<MAXE_BIG, false, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
+    fft_lds<MAXE_BIG, false, true, true, false>(buf, f, tws, 1, 0, tid, NTB);
     // (fetched after the transform: held across it, they would cost the
     // registers that let two blocks share a compute unit)
     float2 lm[NLB];
     float wq[NLB];
 #pragma unroll
     for (int u = 0; u < NLB; ++u) {
-        const int e = min(tid + u * NTB, H - 1);
-        lm[u] = gld(L, (unsigned)e);
-        wq[u] = p.reg == REG_TV ? gld(s2H, (unsigned)e) + w2 : 1.0f;
+        const unsigned k = (unsigned)(k1 + csp * min(tid + u * NTB, Hs - 1));
+        lm[u] = gld(L, k);
+        wq[u] = p.reg == REG_TV ? gld(s2H, k) + w2 : 1.0f;
     }
 #pragma unroll
     for (int u = 0; u < NLB; ++u) {   // computed on clamped entries too, so that the loads above stay in their burst
         const int e = tid + u * NTB;
-        const float4 z = col_solve(lds_ld(bl + pidx(min(e, H - 1))), lm[u], wq[u], mu1, mu2, ihw, mode);
-        if (e < H) lds_st(bl + pidx(e), z);
+        const float4 z = col_solve(lds_ld(bl + pidx(min(e, Hs - 1))), lm[u], wq[u], mu1, mu2, ihw, mode);
+        if (e < Hs) lds_st(bl + pidx(e), z);
     }
     __syncthreads();
-    fft_lds<MAXE_BIG, true, true, true, false>(buf, p.fc, tws, 1, 0, tid, NTB);
-    for (int e = tid; e < H; e += NTB) gst(S, (unsigned)e, lds_ld(bl + pidx(e)));
+    fft_lds<MAXE_BIG, true, true, true, false>(buf, f, tws, 1, 0, tid, NTB);
+    for (int e = tid; e < Hs; e += NTB) gst(S, (unsigned)e, lds_ld(bl + pidx(e)));
+}
+
+// The radix-csp pass of a split column transform (columns longer than 8192,
+// H = csp Hs): the column is taken as csp interleaved sequences. Forward
+// (decimation in frequency), for each n2 < Hs:
+//   y_k1[n2] = w_H^(n2 k1) sum_n1 x[n2 + Hs n1] w_csp^(n1 k1),   w_N = exp(-2 pi i / N),
+// stored at k1 Hs + n2, so that the length-Hs transform of y_k1 holds the
+// column's spectrum at the frequencies k1 + csp k2. Inverse: the same steps
+// undone in reverse order (conjugate twiddles, then the inverse csp-point DFT
+// back to n2 + Hs n1). Both are in place: the csp entries a thread reads are
+// the ones it writes. Work item (column, sub = s): the s-th of csp slices of
+// the n2 range of that column.
+constexpr int NTS = 256;
+template <int R, bool INV>
+__device__ __forceinline__ void col_split_one(float4* __restrict__ S, const float2* __restrict__ twH, int Hs, int n2) {
+    float4 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = gld(S, (unsigned)(n2 + Hs * r));
+    if (INV) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            float2 w = gld(twH, (unsigned)(n2 * r));
+            w.y = -w.y;
+            v[r] = cmul(v[r], w);
+        }
+        dft<R, true>(v);
+    } else {
+        dft<R, false>(v);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], gld(twH, (unsigned)(n2 * r)));
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) gst(S, (unsigned)(n2 + Hs * r), v[r]);
+}
+
+template <bool INV>
+__global__ __launch_bounds__(NTS) void k_col_split(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+                                                   int nitems, int par, const InfoDev* __restrict__ info,
+                                                   const float2* __restrict__ tw) {
+    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    if (info && !info[it.prob].active) return;
+    const ProbDesc& p = pd[it.prob];
+    const int H = p.H, csp = p.csp, Hs = H / csp;
+    float4* S = ((p.reg == REG_TV && par) ? p.spec1 : p.spec0) + (size_t)it.start * H;
+    const float2* twH = tw + p.fc.tw_off;   // w_H^k, k < H (n2 k1 < H)
+    const int per = (Hs + csp - 1) / csp;
+    const int n0 = it.sub * per, n1 = min(n0 + per, Hs);
+    for (int n2 = n0 + (int)threadIdx.x; n2 < n1; n2 += NTS) {
+        switch (csp) {
+            case 2: col_split_one<2, INV>(S, twH, Hs, n2); break;
+            case 3: col_split_one<3, INV>(S, twH, Hs, n2); break;
+            case 5: col_split_one<5, INV>(S, twH, Hs, n2); break;
+            default: col_split_one<7, INV>(S, twH, Hs, n2); break;
+        }
+    }
 }
 
 // ------------------------------------------------------------ row helpers
@@ -1046,7 +1108,8 @@ __global__ void k_scale2(const float* __restrict__ d, float* __restrict__ p, siz
 
 // ------------------------------------------------------------ host launchers
 static size_t col_lds(int H, int TC) {
-    if (H > 2048) return (size_t)pidx_len(H) * sizeof(float4);   // the block-level column pass: the column alone
+    // the block-level column pass: the column (or sub-transform) alone
+    if (H > 2048) return (size_t)pidx_len(H / col_split_factor(H)) * sizeof(float4);
     return (size_t)((H + 1) / 2) * sizeof(float4) + (size_t)TC * pidx_len(H) * sizeof(float4);
 }
 static size_t rowtv_lds(int W, int B) {
@@ -1062,10 +1125,22 @@ static size_t row_lds(int W, int B) {
     return b > scratch ? b : scratch;
 }
 
-int size_class(int n) { return n <= 512 ? 0 : (n <= 1024 ? 1 : (n <= 2048 ? 2 : (n <= 4096 ? 3 : 4))); }
+int size_class(int n) {
+    return n <= 512 ? 0 : (n <= 1024 ? 1 : (n <= 2048 ? 2 : (n <= 4096 ? 3 : (n <= 8192 ? 4 : 5))));
+}
 
 int col_class(const ProbDesc& d) {
+    if (d.H > 8192) return 8;
     return d.H > 4096 ? 7 : (d.H > 2048 ? 6 : 2 * size_class(d.H) + (d.fc.ends8 ? 0 : 1));
+}
+
+// The smallest prime factor of a 7-smooth length above 8192 (its HBM pass's
+// radix: the sub-transforms are then at most 8192 long up to 16384).
+int col_split_factor(int h) {
+    if (h <= 8192) return 1;
+    for (int p : {2, 3, 5, 7})
+        if (h % p == 0) return p;
+    return 1;
 }
 
 int col_big_threads(int h) { return h > 4096 ? 1024 : 512; }
@@ -1094,10 +1169,19 @@ hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
                 hipLaunchKernelGGL(k_col_big<512>, dim3(L.col_cnt[c]), dim3(512), L.lds_col_c[c], L.stream, L.desc,
                                    L.col_items + L.col_beg[c], L.col_cnt[c], par, mode, info, L.tw, L.s2);
                 break;
-            default:
+            case 7:
                 hipLaunchKernelGGL(k_col_big<1024>, dim3(L.col_cnt[c]), dim3(1024), L.lds_col_c[c], L.stream, L.desc,
                                    L.col_items + L.col_beg[c], L.col_cnt[c], par, mode, info, L.tw, L.s2);
                 break;
+            default: {   // split columns: radix pass, sub-transforms with the solve, inverse radix pass
+                const WorkItem* it = L.col_items + L.col_beg[c];
+                const int n = L.col_cnt[c];
+                hipLaunchKernelGGL(k_col_split<false>, dim3(n), dim3(NTS), 0, L.stream, L.desc, it, n, par, info, L.tw);
+                hipLaunchKernelGGL(k_col_big<1024>, dim3(n), dim3(1024), L.lds_col_c[c], L.stream, L.desc, it, n, par,
+                                   mode, info, L.tw, L.s2);
+                hipLaunchKernelGGL(k_col_split<true>, dim3(n), dim3(NTS), 0, L.stream, L.desc, it, n, par, info, L.tw);
+                break;
+            }
         }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1156,8 +1240,11 @@ hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
         else if (c == 3)
             hipLaunchKernelGGL((k_row_fwd<8, ROW_RB[3]>), dim3(n), dim3(NT), L.lds_rrow_c[3], L.stream, L.desc, it, n,
                                par, src, info, L.tw);
-        else
+        else if (c == 4)
             hipLaunchKernelGGL((k_row_fwd<16, ROW_RB[4]>), dim3(n), dim3(NT), L.lds_rrow_c[4], L.stream, L.desc, it, n,
+                               par, src, info, L.tw);
+        else
+            hipLaunchKernelGGL((k_row_fwd<32, ROW_RB[5]>), dim3(n), dim3(NT), L.lds_rrow_c[5], L.stream, L.desc, it, n,
                                par, src, info, L.tw);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1184,8 +1271,11 @@ hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool
         else if (c == 3)
             hipLaunchKernelGGL((k_row_inv<8, ROW_RB[3]>), dim3(n), dim3(NT), L.lds_rrow_c[3], L.stream, L.desc, it, n,
                                par, mode, flags, info, L.tw, part);
-        else
+        else if (c == 4)
             hipLaunchKernelGGL((k_row_inv<16, ROW_RB[4]>), dim3(n), dim3(NT), L.lds_rrow_c[4], L.stream, L.desc, it, n,
+                               par, mode, flags, info, L.tw, part);
+        else
+            hipLaunchKernelGGL((k_row_inv<32, ROW_RB[5]>), dim3(n), dim3(NT), L.lds_rrow_c[5], L.stream, L.desc, it, n,
                                par, mode, flags, info, L.tw, part);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1259,6 +1349,8 @@ hipError_t allow_dynamic_lds(int bytes) {
         reinterpret_cast<const void*>(&k_row_inv<8, ROW_RB[3]>),
         reinterpret_cast<const void*>(&k_row_fwd<16, ROW_RB[4]>),
         reinterpret_cast<const void*>(&k_row_inv<16, ROW_RB[4]>),
+        reinterpret_cast<const void*>(&k_row_fwd<32, ROW_RB[5]>),
+        reinterpret_cast<const void*>(&k_row_inv<32, ROW_RB[5]>),
         reinterpret_cast<const void*>(&k_col_big<512>),
         reinterpret_cast<const void*>(&k_col_big<1024>),
         reinterpret_cast<const void*>(&k_row_inv<1, ROW_RB[0]>),
@@ -1275,7 +1367,7 @@ size_t lds_col_bytes(int H, int TC) { return col_lds(H, TC); }
 size_t lds_rowtv_bytes(int W, int B) { return rowtv_lds(W, B); }
 size_t lds_row_bytes(int W, int B) { return row_lds(W, B); }
 int col_max_tiles() { return NTC / 64; }
-int row_maxe(int w) { return w > 2048 ? row_maxe_c<8>() : MAXE_ROW; }   // the same for CPT 16
+int row_maxe(int w) { return w > 2048 ? row_maxe_c<8>() : MAXE_ROW; }   // the same for CPT 16, 32
 int block_threads() { return NT; }
 
 }  // namespace admm

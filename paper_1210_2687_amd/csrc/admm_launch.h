@@ -8,15 +8,16 @@ namespace admm {
 constexpr int ADMM_FRAME_CLASSES = 16;   // (analysis, synthesis) x levels 1..4 x (small image)
 // column classes: 2 x (size class of the column length) + 1 for a general
 // schedule (first or last stage not radix 8: the column cannot stay in
-// registers around the solve), each launched with its own instantiation, and
+// registers around the solve), each launched with its own instantiation,
 // classes 6 and 7 for columns of 2049..4096 and 4097..8192 (block-level
-// transforms, any schedule)
-constexpr int ADMM_COL_CLASSES = 8;
-// size classes of the row length: <= 512, <= 1024, <= 2048, <= 4096, <= 8192
-// (rows longer than 2048 run the plain row passes only; a TV problem with such
-// rows takes the three-pass schedule: inverse rows with the data step, the TV
-// step, forward rows)
-constexpr int ADMM_ROW_CLASSES = 5;
+// transforms, any schedule), and class 8 for longer columns (split into
+// sub-transforms of at most 8192 around a radix pass through HBM)
+constexpr int ADMM_COL_CLASSES = 9;
+// size classes of the row length: <= 512, <= 1024, <= 2048, <= 4096, <= 8192,
+// <= 16384 (rows longer than 2048 run the plain row passes only; a TV problem
+// with such rows takes the three-pass schedule: inverse rows with the data
+// step, the TV step, forward rows)
+constexpr int ADMM_ROW_CLASSES = 6;
 
 // Everything a launch needs; item lists are device arrays, counts are the grid sizes.
 struct LaunchCtx {
@@ -52,7 +53,7 @@ struct LaunchCtx {
     // longer than 2048)
     double* cgpart = nullptr;
     size_t lds_tvstep = 0;
-    bool tv_wide = false;   // some TV problem has rows longer than 4096 (the TV step's wide instantiation)
+    int tv_cpt = 8;   // columns per thread the TV step's row walk needs (8: rows <= 4096, 16: <= 8192, 32)
 };
 
 hipError_t launch_col(const LaunchCtx& L, int par, int mode);
@@ -87,8 +88,9 @@ int frame_class(int H, int W, int J, bool fs);   // 8 fs + 2 (J - 1) + (image sm
 int col_max_tiles();                       // columns per column-pass block (one per wave)
 int row_tv_max_rows(int w);                  // rows per block of the TV row pass for width w
 int row_max_rows(int w);                     // rows per block of the plain row passes for width w
-int size_class(int n);                      // 0: n <= 512, 1: <= 1024, 2: <= 2048, 3: <= 4096, 4: larger
-int col_class(const ProbDesc& d);           // 2 size_class(H) + (general column schedule); 6, 7 above 2048
+int size_class(int n);                      // 0: n <= 512, 1: <= 1024, 2: <= 2048, 3: <= 4096, 4: <= 8192, 5: larger
+int col_class(const ProbDesc& d);           // 2 size_class(H) + (general column schedule); 6, 7, 8 above 2048
+int col_split_factor(int h);                // radix of the HBM pass of a split column transform (1: none)
 int col_big_threads(int h);                 // threads per block of the block-level column pass
 constexpr int COL_BIG_MAXE = 16;            // its operands per thread in a stage
 int row_maxe(int w);                        // operands per thread in a stage of the row passes for width w

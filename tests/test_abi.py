@@ -86,7 +86,7 @@ def test_validation_errors(case, status):
     elif case == "not_smooth":
         p = _prob(H=33, W=40)
     elif case == "too_large":
-        p = _prob(H=16384, W=16)
+        p = _prob(H=32768, W=16)
     elif case == "zero_sum_tv":
         k = np.zeros((3, 3))
         k[1, 0], k[1, 2] = 1.0, -1.0

@@ -17,7 +17,7 @@ from paper_1210_2687_amd import workloads as WL
 @pytest.mark.parametrize("oh,ow,k,H,W", [(113, 127, 9, 125, 135), (61, 67, 7, 70, 75), (1, 1, 1, 8, 8),
                                          (2030, 2041, 7, 2048, 2048), (2043, 4090, 7, 2058, 4096),
                                          (500, 500, 13, 512, 512), (4091, 10, 7, 4116, 16),
-                                         (8150, 100, 5, 8192, 105)])
+                                         (8150, 100, 5, 8192, 105), (8190, 100, 7, 8232, 108)])
 def test_embed_size_is_the_smallest_7_smooth_domain(oh, ow, k, H, W):
     assert A.admm_embed_size(oh, ow, k) == (H, W)
     for n, need in ((H, oh + k - 1), (W, ow + k - 1)):
@@ -25,7 +25,7 @@ def test_embed_size_is_the_smallest_7_smooth_domain(oh, ow, k, H, W):
         assert not any(WL.is_smooth7(m) for m in range(max(8, need), n))
 
 
-@pytest.mark.parametrize("args,status", [((8187, 10, 7), A.ADMM_E_UNSUPPORTED), ((10, 10, 4), A.ADMM_E_UNSUPPORTED),
+@pytest.mark.parametrize("args,status", [((16379, 10, 7), A.ADMM_E_UNSUPPORTED), ((10, 10, 4), A.ADMM_E_UNSUPPORTED),
                                          ((0, 10, 3), A.ADMM_E_INVALID), ((10, -1, 3), A.ADMM_E_INVALID)])
 def test_embed_size_errors(args, status):
     with pytest.raises(A.AdmmError) as e:

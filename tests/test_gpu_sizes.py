@@ -7,11 +7,13 @@ names the kernel instantiations it runs:
 
 * column pass: one instantiation per size class of the column length
   (<= 512, <= 1024, <= 2048) and schedule (first and last stage radix 8:
-  fixed; otherwise general), and the block-level pass for columns of
-  2049..4096 and 4097..8192;
+  fixed; otherwise general), the block-level pass for columns of
+  2049..4096 and 4097..8192, and split columns above 8192 (a radix-p pass
+  through HBM around block-level sub-transforms);
 * TV row pass: one per size class of the row length (rows per block 8, 6, 2);
-  rows longer than 2048 (classes <= 4096 and <= 8192) take the three-pass
-  schedule (plain inverse rows with the data step, TV step, forward rows);
+  rows longer than 2048 (classes <= 4096, <= 8192, <= 16384) take the
+  three-pass schedule (plain inverse rows with the data step, TV step,
+  forward rows);
 * FA row passes and frame step: per size class of the row length and J.
 
 Bar (TV-MD Alg. 3 with the data step of eq. (49); FA-MD Sec. IV-C): relative
@@ -143,13 +145,24 @@ def test_tv_sides_above_4096(shape, k):
     _single(full_problem(98, *shape, k, missing=0.3), [2, 4])
 
 
-@pytest.mark.parametrize("shape", [(48, 3072), (40, 6000)])
+@pytest.mark.parametrize("shape,k", [((16384, 24), 7), ((24, 16384), 9), ((10125, 24), 5), ((24, 12000), 7)])
+def test_tv_sides_above_8192(shape, k):
+    # columns of 16384: two sub-transforms of 8192 around a radix-2 pass through
+    # HBM; 10125 = 3^4 5^3: three sub-transforms of 3375 (general schedule)
+    # around a radix-3 pass; rows of 16384 (compile-time schedule) and 12000
+    # (general): the sixth row class, one row per block, in the three-pass TV
+    # schedule
+    announce(f"tv {shape} k={k}")
+    _single(full_problem(99, *shape, k, missing=0.3), [2, 4])
+
+
+@pytest.mark.parametrize("shape", [(48, 3072), (40, 6000), (24, 12000)])
 def test_frame_rows_above_2048_with_a_general_schedule(shape):
     announce(f"fa {shape} J=2")
     _single(full_problem(96, *shape, 5, reg="frame", levels=2, mu=0.02), [2, 4])
 
 
-@pytest.mark.parametrize("shape", [(64, 2560), (40, 8192)])
+@pytest.mark.parametrize("shape", [(64, 2560), (40, 8192), (24, 16384)])
 def test_long_tv_rows_resume_bitwise_and_cg_parity(shape):
     # the three-pass TV schedule exports and imports its state bit for bit, and
     # TV-CG runs on the same long rows (plain row passes of the longer classes)

@@ -231,12 +231,13 @@ def test_largest_sizes_by_tiling(reps):
 
 
 @pytest.mark.parametrize("base_shape,reps", [((64, 64), (64, 64)), ((64, 64), (40, 40)), ((64, 64), (64, 8)),
-                                             ((64, 64), (128, 128)), ((125, 125), (56, 48))])
+                                             ((64, 64), (128, 128)), ((125, 125), (56, 48)), ((64, 64), (256, 256))])
 def test_sides_above_2048_by_tiling(base_shape, reps):
-    # 4096 x 4096, 2560 x 2560 (general schedules), 4096 x 512, 8192 x 8192 and
-    # 7000 x 6000 (general schedules) TV problems: the block-level column passes
-    # and (rows longer than 2048) the three-pass TV schedule, against the oracle
-    # on one tile, with the element-wise bound
+    # 4096 x 4096, 2560 x 2560 (general schedules), 4096 x 512, 8192 x 8192,
+    # 7000 x 6000 (general schedules) and 16384 x 16384 TV problems: the
+    # block-level column passes (split columns at 16384) and (rows longer than
+    # 2048) the three-pass TV schedule, against the oracle on one tile, with the
+    # element-wise bound
     announce(f"tiled TV {base_shape} x {reps}")
     base = fast_tv_problem(72, *base_shape, 7)
     big = _tiled(base, reps)
