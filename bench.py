@@ -23,6 +23,9 @@ The same JSON line also carries, under "configs", the other workloads:
               column pass and the three-pass TV row schedule)
   tv8192      (only with --quick --workload tv8192: its input takes over a
               minute of host work) TV-MD 8192^2, 20 iterations
+  tv16384     (only with --quick --workload tv16384) TV-MD 16384^2, 10
+              iterations, on the 4096^2 image tiled 4 x 4 (throughput does not
+              depend on the data; the columns run the split transform)
   c4          ragged batch of 256 TV-MD problems (sides 128..1024, kernels
               5..31), 200 iterations
   beyond_cache  64 x 512^2 TV-MD, 500 iterations (working set ~0.9 GB, far
@@ -152,6 +155,8 @@ def host_data(args):
         # the 4096^2 image (about 16 s of host work) is drawn beside the others
         big = ex.submit(_c2_member, 0, 4096) if (args.workload == "tv4096" or not args.quick) else None
         huge = ex.submit(_c2_member, 0, 8192) if args.workload == "tv8192" else None
+        if args.workload == "tv16384" and big is None:
+            big = ex.submit(_c2_member, 0, 4096)
         data["c2"] = list(ex.map(partial(_c2_member, size=args.size), range(args.batch)))
         if args.workload in ("fa1024", "fs1024") or not args.quick:
             data["c3"] = WL.config3(size=1024, levels=3)
@@ -164,6 +169,10 @@ def host_data(args):
             data["c_big"] = [big.result()]
         if huge is not None:
             data["c_huge"] = [huge.result()]
+        if args.workload == "tv16384":
+            b = big.result()
+            data["c_16k"] = [dataclasses.replace(b, y=np.tile(b.y, (4, 4)), mask=np.tile(b.mask, (4, 4)),
+                                                 x_true=None)]
         if not args.quick:
             data["c1"] = WL.config1()
             if args.ws_train:
@@ -495,7 +504,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tv8x512",
-                    choices=["tv8x512", "tv64x512", "tv4096", "tv8192", "fa1024", "fs1024", "ragged256", "md_vs_cg",
+                    choices=["tv8x512", "tv64x512", "tv4096", "tv8192", "tv16384", "fa1024", "fs1024", "ragged256", "md_vs_cg",
                              "tv8x512_cg"],
                     help="the headline is tv8x512; with --quick, the others run alone (profiling)")
     ap.add_argument("--quick", action="store_true", help="only the chosen workload, no other configs")
@@ -555,6 +564,9 @@ def main():
         elif args.workload == "tv4096":
             configs["tv4096"] = run_throughput("tv4096", data["c_big"], 100, args.steps, args.warmup, tune,
                                                "TV-MD 4096x4096, 100 iterations")
+        elif args.workload == "tv16384":
+            configs["tv16384"] = run_throughput("tv16384", data["c_16k"], 10, args.steps, args.warmup, tune,
+                                                "TV-MD 16384x16384 (a 4096^2 image tiled 4 x 4), 10 iterations")
         elif args.workload == "tv8192":
             configs["tv8192"] = run_throughput("tv8192", data["c_huge"], 20, args.steps, args.warmup, tune,
                                                "TV-MD 8192x8192, 20 iterations")
