@@ -103,6 +103,16 @@ def test_validation_errors(case, status):
     assert len(A.admm_last_error()) > 0
 
 
+def test_frame_coefficient_planes_stay_below_4_gib():
+    # the kernels address each plane with 32-bit byte offsets: 16384 x 8192 holds
+    # 3J + 1 = 7 frame planes (3.8 GB) at J = 2, not 10 at J = 3; TV's pair of
+    # dual planes fits at 16384 x 16384
+    assert A.admm_validate_problem(_prob(H=16384, W=8192, reg=A.ADMM_REG_FRAME, levels=2)) == A.ADMM_OK
+    assert A.admm_validate_problem(_prob(H=16384, W=8192, reg=A.ADMM_REG_FRAME, levels=3)) == A.ADMM_E_UNSUPPORTED
+    assert "4 GiB" in A.admm_last_error()
+    assert A.admm_validate_problem(_prob(H=16384, W=16384)) == A.ADMM_OK
+
+
 def test_zero_sum_kernel_allowed_for_frame():
     k = np.zeros((3, 3))
     k[1, 0], k[1, 2] = 1.0, -1.0
