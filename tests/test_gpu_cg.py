@@ -101,6 +101,16 @@ def test_tv_cg_parity_large_ragged_rows():
     _check_run(p, [2, 8])
 
 
+@pytest.mark.parametrize("shape,reg", [((16384, 24), "tv"), ((24, 12000), "frame")])
+def test_cg_parity_long_sides(shape, reg):
+    # TV-CG with columns of 16384 (both circulant solves through the split
+    # column transform) and FA-CG with rows of 12000 (the sixth row class in
+    # both inverse row modes)
+    announce(f"{reg}-cg parity {shape}")
+    p = full_problem(512, *shape, 5, reg=reg, levels=2 if reg == "frame" else 0, missing=0.3, mu=0.02)
+    _check_run(p, [2, 4])
+
+
 def test_cg_tile_shapes_do_not_change_iterates():
     # the CG step length sums per row block in a fixed order: another tiling
     # changes the rounding of the sums, within the parity bar

@@ -73,6 +73,15 @@ def test_fs_parity_large():
     _check(_fs_problem(711, 600, 1000, 3, k=13, missing=0.4, mu=0.01), [2, 6])
 
 
+@pytest.mark.parametrize("shape", [(24, 6000), (10125, 24)])
+def test_fs_parity_long_sides(shape):
+    # rows of 6000 (the fifth row class, stage table read through the caches)
+    # and columns of 10125 (split into three sub-transforms of 3375 around a
+    # radix-3 pass through HBM)
+    announce(f"fs parity {shape} J=2")
+    _check(_fs_problem(712, *shape, 2, k=5, mu=0.02), [2, 5])
+
+
 def test_fs_state_export_and_bitwise_resume():
     import torch
     announce("fs state export / resume")
