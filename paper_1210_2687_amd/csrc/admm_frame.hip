@@ -99,7 +99,7 @@ __global__ __launch_bounds__(NTF) void k_frame(const ProbDesc* __restrict__ pd, 
     const int ty = it.start / ntx, tx = it.start - ty * ntx;
     const int r0 = ty * FT, c0 = tx * FT;
     const unsigned hlim = (unsigned)min(FT, H - r0), wlim = (unsigned)min(FT, W - c0);   // owned part of the tile
-    const unsigned n = (unsigned)(H * W);   // planes hold at most 4096^2 values (13 bands of them within 2^32): 32-bit offsets
+    const unsigned n = (unsigned)(H * W);   // 32-bit offsets: the plan keeps the 3J+1 bands within 4 GiB
     const int tid = threadIdx.x;
     auto wrap = [&](int i, int m) { return SMALL ? wrapm(i, m) : wrap1(i, m); };
     const float tau = p.tau, mu2 = p.mu2;

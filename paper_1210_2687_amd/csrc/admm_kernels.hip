@@ -17,6 +17,11 @@
 // FA-MD (Sec. IV-C) uses k_col with K = 1 / (mu1 |Lambda|^2 + mu2) (eq. (25)),
 // then k_row_inv (inverse rows + data step), k_frame (frame analysis, soft
 // threshold, frame duals and synthesis q = mu2 P^T (u2 + d2)) and k_row_fwd.
+//
+// Long sides: columns longer than 2048 take k_col_big (one block per column),
+// those longer than 8192 split into sub-transforms around k_col_split's radix
+// pass through HBM; TV rows longer than 2048 run k_row_inv (data step),
+// k_tv_step and k_row_fwd in place of k_row_tv.
 #include <algorithm>
 
 #include "admm_internal.h"
@@ -528,7 +533,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     __builtin_assume(nr >= 1);
     const int nrh = nr + 2;
     const int tid = threadIdx.x;
-    const unsigned n = (unsigned)(H * W);   // planes hold at most 4096^2 values: 32-bit offsets
+    const unsigned n = (unsigned)(H * W);   // planes hold at most 16384^2 values (1 GiB): 32-bit offsets
     const int pitch = row_pitch(W);                                        // padded rows (pidx)
     float* dl = reinterpret_cast<float*>(X + (size_t)(p.B + 2) * pitch);   // 2 x W: delta^h of the row (ping-pong)
     float2* twl = reinterpret_cast<float2*>(dl + 2 * W);                 // row twiddles
