@@ -156,6 +156,17 @@ def test_tv_sides_above_8192(shape, k):
     _single(full_problem(99, *shape, k, missing=0.3), [2, 4])
 
 
+def test_batch_mixing_long_and_short_sides():
+    # one plan, one launch per class: split columns (16384), the fifth and sixth
+    # row classes in the three-pass TV schedule (8192, 16384 wide), a fused-row
+    # TV problem and a frame problem beside them
+    announce("mixed batch of long and short sides")
+    probs = [full_problem(101, 16384, 24, 5, missing=0.3), full_problem(102, 24, 16384, 7, missing=0.3),
+             full_problem(103, 32, 8192, 5, missing=0.3), full_problem(104, 96, 160, 7, missing=0.3),
+             full_problem(105, 64, 80, 5, reg="frame", levels=2, mu=0.02)]
+    _batch(probs, [2, 3])
+
+
 @pytest.mark.parametrize("shape", [(48, 3072), (40, 6000), (24, 12000)])
 def test_frame_rows_above_2048_with_a_general_schedule(shape):
     announce(f"fa {shape} J=2")
