@@ -397,12 +397,13 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
                    lds_rowtv_bytes(q.W, bmax + 1) <= cap && (!cg || lds_tvstep_bytes(q.W, bmax + 1) <= tv_cap))
                 ++bmax;
         } else if (tv_split) {
-            while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) && fits(bmax + 1, d.fr, row_maxe(q.W)) &&
-                   lds_row_bytes(q.W, bmax + 1) <= cap && lds_tvstep_bytes(q.W, bmax + 1) <= tv_cap)
+            while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) &&
+                   fits(bmax + 1, d.fr, row_maxe(q.W), row_threads(q.W)) && lds_row_bytes(q.W, bmax + 1) <= cap &&
+                   lds_tvstep_bytes(q.W, bmax + 1) <= tv_cap)
                 ++bmax;
         } else {
-            while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) && fits(bmax + 1, d.fr, row_maxe(q.W)) &&
-                   lds_row_bytes(q.W, bmax + 1) <= cap)
+            while (bmax + 1 <= std::min(q.H, row_max_rows(q.W)) &&
+                   fits(bmax + 1, d.fr, row_maxe(q.W), row_threads(q.W)) && lds_row_bytes(q.W, bmax + 1) <= cap)
                 ++bmax;
         }
         if (bmax < 1) return bail(fail(ADMM_E_UNSUPPORTED, "problem %d: row length %d does not fit a block", i, q.W));

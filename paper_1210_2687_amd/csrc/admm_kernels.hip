@@ -39,13 +39,17 @@ constexpr int ROW_BURST = 8;       // plane elements per thread fetched together
 constexpr int RTV_EARLY[3] = {5, 3, 1};
 // most rows per block of the plain row passes, per size class (W <= 512, 1024, 2048, 4096, 8192, 16384)
 constexpr int ROW_RB[ADMM_ROW_CLASSES] = {16, 8, 4, 4, 2, 1};
-// Rows longer than 2048 (CPT >= 8): the plain row passes read the stage table
-// from global memory through the caches, so that four padded rows fit the LDS
-// (two rows would write 32-byte pieces of the transposed spectrum, which the
-// caches do not merge at this size: measured at 2.4x the spectrum's bytes), and
-// take up to 32 operands per thread in a stage.
-template <int CPT> constexpr bool row_twg() { return CPT * NT > 2048; }
-template <int CPT> constexpr int row_maxe_c() { return row_twg<CPT>() ? 32 : MAXE_ROW; }
+// Rows longer than 2048: the plain row passes run NTL threads per block up to
+// rows of 8192 (the padded rows fill the LDS of a compute unit, so one block
+// per unit, and 16 waves hide more latency than 8; one row of 16384 keeps 512
+// threads, whose 32 entries each would not fit the 128 registers of a
+// 1024-thread block) and read the stage table from global memory
+// through the caches, so that four padded rows fit the LDS (two rows would
+// write 32-byte pieces of the transposed spectrum, which the caches do not
+// merge at this size: measured at 2.4x the spectrum's bytes).
+constexpr int NTL = 1024;
+template <int CPT, int NTR = NT> constexpr bool row_twg() { return CPT * NTR > 2048; }
+template <int CPT, int NTR = NT> constexpr int row_maxe_c() { return row_twg<CPT, NTR>() && NTR < 1024 ? 32 : MAXE_ROW; }
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -66,8 +70,9 @@ __device__ __forceinline__ void wave_sums_to_lds(const double* v, double* wsum) 
     }
 }
 
-// Sum ADMM_NSUM per-thread values over the block and write them to out[0..NSUM).
-// scratch: >= (NT/64) * ADMM_NSUM doubles of LDS.
+// Sum ADMM_NSUM per-thread values over the block (NTH threads) and write them
+// to out[0..NSUM). scratch: >= (NTH/64) * ADMM_NSUM doubles of LDS.
+template <int NTH = NT>
 __device__ __forceinline__ void block_sums_write(const double* v, double* scratch, double* out) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     __syncthreads();
@@ -79,7 +84,7 @@ __device__ __forceinline__ void block_sums_write(const double* v, double* scratc
     __syncthreads();
     if (tid < ADMM_NSUM) {
         double s = 0.0;
-        for (int w = 0; w < NT / 64; ++w) s += scratch[w * ADMM_NSUM + tid];
+        for (int w = 0; w < NTH / 64; ++w) s += scratch[w * ADMM_NSUM + tid];
         out[tid] = s;
     }
 }
@@ -464,7 +469,7 @@ __device__ __forceinline__ void store_hermitian(float2* X, int pitch, int W, int
     }
 }
 
-template <bool PAD, int NLD, int NTW = 1>
+template <bool PAD, int NLD, int NTW = 1, int NTH = NT>
 __device__ __forceinline__ void load_rows_hermitian(float2* X, int pitch, const float4* __restrict__ S, int H, int W,
                                                     int P, int rbeg, int nrows, int tid, float2* twl = nullptr,
                                                     const float2* __restrict__ tw = nullptr, int ntw = 0) {
@@ -473,21 +478,21 @@ __device__ __forceinline__ void load_rows_hermitian(float2* X, int pitch, const 
     float4 f[NLD];
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
-        const int i = min(tid + u * NT, tot - 1);
+        const int i = min(tid + u * NTH, tot - 1);
         const int k2 = (int)udiv16((unsigned)i, (unsigned)nrows, mr);
         const int r = wrapi(rbeg + i - k2 * nrows, H);
         f[u] = gld(S, (unsigned)(k2 * H + r));
     }
-    if (twl) load_twiddles<NTW>(twl, tw, ntw, tid, NT);
+    if (twl) load_twiddles<NTW>(twl, tw, ntw, tid, NTH);
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
-        const int i = tid + u * NT;
+        const int i = tid + u * NTH;
         if (i < tot) {
             const int k2 = (int)udiv16((unsigned)i, (unsigned)nrows, mr);
             store_hermitian<PAD>(X, pitch, W, P, k2, i - k2 * nrows, f[u]);
         }
     }
-    for (int i = tid + NLD * NT; i < tot; i += NT) {
+    for (int i = tid + NLD * NTH; i < tot; i += NTH) {
         const int k2 = (int)udiv16((unsigned)i, (unsigned)nrows, mr);
         const int rr = i - k2 * nrows;
         store_hermitian<PAD>(X, pitch, W, P, k2, rr, gld(S, (unsigned)(k2 * H + wrapi(rbeg + rr, H))));
@@ -496,12 +501,12 @@ __device__ __forceinline__ void load_rows_hermitian(float2* X, int pitch, const 
 
 // Split the row DFTs C of (a + i b) in X rows [0, nrows) into the half spectra of
 // a and b and store them transposed at rows [r0, r0 + nrows).
-template <bool PAD>
+template <bool PAD, int NTH = NT>
 __device__ __forceinline__ void store_rows_split(const float2* X, int pitch, float4* __restrict__ S, int H, int W,
                                                  int P, int r0, int nrows, int tid) {
     const int tot = P * nrows;
     const unsigned mr = div_magic((unsigned)nrows);
-    for (int i = tid; i < tot; i += NT) {
+    for (int i = tid; i < tot; i += NTH) {
         const int k2 = (int)udiv16((unsigned)i, (unsigned)nrows, mr);
         const int rr = i - k2 * nrows;
         const float2* row = X + rr * pitch;
@@ -709,10 +714,11 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
 }
 
 // ------------------------------------------------------------ plane -> spectrum rows
-// Forward row DFT of (a + i b) for rows [r0, r0 + nr) of two planes. CPT columns
-// per thread (W <= CPT NT), at most RB rows, rows padded (pidx) at row_pitch(W).
-template <int CPT, int RB>
-__global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+// Forward row DFT of (a + i b) for rows [r0, r0 + nr) of two planes. NTR
+// threads, CPT columns per thread (W <= CPT NTR), at most RB rows, rows padded
+// (pidx) at row_pitch(W).
+template <int CPT, int RB, int NTR = NT>
+__global__ __launch_bounds__(NTR) void k_row_fwd(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                 int nitems, int par, int src, const InfoDev* __restrict__ info,
                                                 const float2* __restrict__ tw) {
     extern __shared__ float2 X[];
@@ -729,7 +735,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
     const float* a = p.tmpA + (size_t)r0 * W;
     const float* b = p.tmpB + (size_t)r0 * W;
     const float mu1 = p.mu1;
-    constexpr bool TWG = row_twg<CPT>();
+    constexpr bool TWG = row_twg<CPT, NTR>();
     // the stage table, then bursts of RCH rows of both planes per thread
     // (unconditional loads, rows and columns clamped; the second plane is read
     // but not used for src 1), so that each burst costs one memory latency
@@ -738,7 +744,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
     float2 tv[CPT];
     if constexpr (!TWG) {
 #pragma unroll
-        for (int u = 0; u < CPT; ++u) tv[u] = gld(tws, (unsigned)min(tid + u * NT, W - 1));
+        for (int u = 0; u < CPT; ++u) tv[u] = gld(tws, (unsigned)min(tid + u * NTR, W - 1));
     }
     for (int rb = 0; rb < nr; rb += RCH) {
         float va[RCH][CPT], vb[RCH][CPT];
@@ -747,7 +753,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
             const int rr = min(rb + k, nr - 1);
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const unsigned g = (unsigned)(rr * W + min(tid + j * NT, W - 1));
+                const unsigned g = (unsigned)(rr * W + min(tid + j * NTR, W - 1));
                 va[k][j] = gld(a, g);
                 vb[k][j] = gld(b, g);
             }
@@ -755,22 +761,22 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
         if (!TWG && rb == 0) {
 #pragma unroll
             for (int u = 0; u < CPT; ++u)
-                if (tid + u * NT < W) twl[tid + u * NT] = tv[u];
+                if (tid + u * NTR < W) twl[tid + u * NTR] = tv[u];
         }
 #pragma unroll
         for (int k = 0; k < RCH; ++k) {
             const int rr = rb + k;
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const int c = tid + j * NT;
+                const int c = tid + j * NTR;
                 if (rr < nr && c < W)
                     X[rr * pitch + pidx(c)] = src == 0 ? make_float2(mu1 * va[k][j], vb[k][j]) : make_float2(va[k][j], 0.0f);
             }
         }
     }
     __syncthreads();
-    rows_fft<NT * CPT, NT, RB, row_maxe_c<CPT>(), false, TWG>(X, pitch, p.fr, TWG ? tws : twl, nr, tid);
-    store_rows_split<true>(X, pitch, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
+    rows_fft<NTR * CPT, NTR, RB, row_maxe_c<CPT, NTR>(), false, TWG>(X, pitch, p.fr, TWG ? tws : twl, nr, tid);
+    store_rows_split<true, NTR>(X, pitch, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid);
 }
 
 // ------------------------------------------------------------ spectrum rows -> planes
@@ -782,8 +788,8 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const ProbDesc* __restrict__ pd,
 //   mode 2, 3 (method CG): the two parts to (cgo1, cgao1), (cgo2, cgao2), and the
 //          boundary-system direction and its sums (below).
 // Rows padded as in k_row_fwd.
-template <int CPT, int RB>
-__global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+template <int CPT, int RB, int NTR = NT>
+__global__ __launch_bounds__(NTR) void k_row_inv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                 int nitems, int par, int mode, int flags,
                                                 const InfoDev* __restrict__ info, const float2* __restrict__ tw,
                                                 double* __restrict__ partials) {
@@ -796,22 +802,22 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
     const int nr = min(p.B, H - r0);
     const int tid = threadIdx.x;
     const int pitch = row_pitch(W);
-    constexpr bool TWG = row_twg<CPT>();
+    constexpr bool TWG = row_twg<CPT, NTR>();
     const float2* const tws = tw + p.fr.tw_off + W;
     float2* const twl = TWG ? nullptr : X + (size_t)p.B * pitch;
     const float2* const stab = TWG ? tws : twl;
-    // spectrum rows r0 .. r0 + nr - 1 (P <= NT CPT / 2 + 1 entries each), then the stage table
-    constexpr int NLD = ((NT * CPT / 2 + 1) * RB + NT - 1) / NT;
-    load_rows_hermitian<true, NLD, CPT>(X, pitch, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid, twl, tws, W);
+    // spectrum rows r0 .. r0 + nr - 1 (P <= NTR CPT / 2 + 1 entries each), then the stage table
+    constexpr int NLD = ((NTR * CPT / 2 + 1) * RB + NTR - 1) / NTR;
+    load_rows_hermitian<true, NLD, CPT, NTR>(X, pitch, par ? p.spec1 : p.spec0, H, W, P, r0, nr, tid, twl, tws, W);
     __syncthreads();
-    rows_fft<NT * CPT, NT, RB, row_maxe_c<CPT>(), true, TWG>(X, pitch, p.fr, stab, nr, tid);
+    rows_fft<NTR * CPT, NTR, RB, row_maxe_c<CPT, NTR>(), true, TWG>(X, pitch, p.fr, stab, nr, tid);
     const unsigned off = (unsigned)(r0 * W);
     if (mode == 0) {
         float* const TB = p.tmpB;   // read once: the stores below would make the compiler reload it
         for (int rr = 0; rr < nr; ++rr) {
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const int c = tid + j * NT;
+                const int c = tid + j * NTR;
                 if (c < W) gst(TB, off + (unsigned)(rr * W + c), X[rr * pitch + pidx(c)].x);
             }
         }
@@ -838,7 +844,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
         for (int rr = 0; rr < nr; ++rr) {
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const int c = tid + j * NT;
+                const int c = tid + j * NTR;
                 if (c >= W) continue;
                 const float2 xv = X[rr * pitch + pidx(c)];
                 const unsigned g = off + (unsigned)(rr * W + c);
@@ -860,8 +866,8 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
         }
         if (first) {
             __syncthreads();
-            rows_fft<NT * CPT, NT, RB, row_maxe_c<CPT>(), false, TWG>(X, pitch, p.fr, stab, nr, tid);
-            store_rows_split<true>(X, pitch, p.spec0, H, W, P, r0, nr, tid);
+            rows_fft<NTR * CPT, NTR, RB, row_maxe_c<CPT, NTR>(), false, TWG>(X, pitch, p.fr, stab, nr, tid);
+            store_rows_split<true, NTR>(X, pitch, p.spec0, H, W, P, r0, nr, tid);
         }
         __syncthreads();   // X becomes the reduction scratch
         double* const red = reinterpret_cast<double*>(X);
@@ -870,7 +876,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
         __syncthreads();
         if (tid == 0) {
             double sum = 0.0;
-            for (int w = 0; w < NT / 64; ++w) sum += red[w];
+            for (int w = 0; w < NTR / 64; ++w) sum += red[w];
             partials[(size_t)(p.part_base + it.blk) * 2 + (first ? 0 : 1)] = sum;
         }
         return;
@@ -904,7 +910,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
             const int rr = min(rb + k, nr - 1);
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const unsigned g = off + (unsigned)(rr * W + min(tid + j * NT, W - 1));
+                const unsigned g = off + (unsigned)(rr * W + min(tid + j * NTR, W - 1));
                 d1b[k][j] = gld(D1, g);
                 mb[k][j] = gld(MK, g);
                 yb[k][j] = gld(YV, g);
@@ -915,7 +921,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
             const int rr = rb + k;
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const int c = tid + j * NT;
+                const int c = tid + j * NTR;
                 if (rr >= nr || c >= W) continue;
                 const unsigned g = off + (unsigned)(rr * W + c);
                 const float2 xv = X[rr * pitch + pidx(c)];
@@ -947,7 +953,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const ProbDesc* __restrict__ pd,
             }
         }
     }
-    if (chk) block_sums_write(acc, reinterpret_cast<double*>(X), partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM);
+    if (chk) block_sums_write<NTR>(acc, reinterpret_cast<double*>(X), partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM);
 }
 
 // ------------------------------------------------------------ TV state import
@@ -1226,7 +1232,8 @@ hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags) {
 int row_tv_max_rows(int w) { return w <= NT ? 8 : (w <= 2 * NT ? 6 : 2); }
 
 // The plain row passes (FA rows, blur, state import) per size class of the row
-// length: CPT columns per thread, at most ROW_RB[c] rows per block.
+// length: CPT columns per thread, at most ROW_RB[c] rows per block; NT threads
+// per block, NTL for rows of 2049..8192.
 hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
     const InfoDev* info = gated ? L.info : nullptr;
     for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
@@ -1243,11 +1250,11 @@ hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
             hipLaunchKernelGGL((k_row_fwd<4, ROW_RB[2]>), dim3(n), dim3(NT), L.lds_rrow_c[2], L.stream, L.desc, it, n,
                                par, src, info, L.tw);
         else if (c == 3)
-            hipLaunchKernelGGL((k_row_fwd<8, ROW_RB[3]>), dim3(n), dim3(NT), L.lds_rrow_c[3], L.stream, L.desc, it, n,
-                               par, src, info, L.tw);
+            hipLaunchKernelGGL((k_row_fwd<4, ROW_RB[3], NTL>), dim3(n), dim3(NTL), L.lds_rrow_c[3], L.stream, L.desc, it,
+                               n, par, src, info, L.tw);
         else if (c == 4)
-            hipLaunchKernelGGL((k_row_fwd<16, ROW_RB[4]>), dim3(n), dim3(NT), L.lds_rrow_c[4], L.stream, L.desc, it, n,
-                               par, src, info, L.tw);
+            hipLaunchKernelGGL((k_row_fwd<8, ROW_RB[4], NTL>), dim3(n), dim3(NTL), L.lds_rrow_c[4], L.stream, L.desc, it,
+                               n, par, src, info, L.tw);
         else
             hipLaunchKernelGGL((k_row_fwd<32, ROW_RB[5]>), dim3(n), dim3(NT), L.lds_rrow_c[5], L.stream, L.desc, it, n,
                                par, src, info, L.tw);
@@ -1274,11 +1281,11 @@ hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool
             hipLaunchKernelGGL((k_row_inv<4, ROW_RB[2]>), dim3(n), dim3(NT), L.lds_rrow_c[2], L.stream, L.desc, it, n,
                                par, mode, flags, info, L.tw, part);
         else if (c == 3)
-            hipLaunchKernelGGL((k_row_inv<8, ROW_RB[3]>), dim3(n), dim3(NT), L.lds_rrow_c[3], L.stream, L.desc, it, n,
-                               par, mode, flags, info, L.tw, part);
+            hipLaunchKernelGGL((k_row_inv<4, ROW_RB[3], NTL>), dim3(n), dim3(NTL), L.lds_rrow_c[3], L.stream, L.desc, it,
+                               n, par, mode, flags, info, L.tw, part);
         else if (c == 4)
-            hipLaunchKernelGGL((k_row_inv<16, ROW_RB[4]>), dim3(n), dim3(NT), L.lds_rrow_c[4], L.stream, L.desc, it, n,
-                               par, mode, flags, info, L.tw, part);
+            hipLaunchKernelGGL((k_row_inv<8, ROW_RB[4], NTL>), dim3(n), dim3(NTL), L.lds_rrow_c[4], L.stream, L.desc, it,
+                               n, par, mode, flags, info, L.tw, part);
         else
             hipLaunchKernelGGL((k_row_inv<32, ROW_RB[5]>), dim3(n), dim3(NT), L.lds_rrow_c[5], L.stream, L.desc, it, n,
                                par, mode, flags, info, L.tw, part);
@@ -1350,10 +1357,10 @@ hipError_t allow_dynamic_lds(int bytes) {
         reinterpret_cast<const void*>(&k_row_fwd<1, ROW_RB[0]>),
         reinterpret_cast<const void*>(&k_row_fwd<2, ROW_RB[1]>),
         reinterpret_cast<const void*>(&k_row_fwd<4, ROW_RB[2]>),
-        reinterpret_cast<const void*>(&k_row_fwd<8, ROW_RB[3]>),
-        reinterpret_cast<const void*>(&k_row_inv<8, ROW_RB[3]>),
-        reinterpret_cast<const void*>(&k_row_fwd<16, ROW_RB[4]>),
-        reinterpret_cast<const void*>(&k_row_inv<16, ROW_RB[4]>),
+        reinterpret_cast<const void*>(&k_row_fwd<4, ROW_RB[3], NTL>),
+        reinterpret_cast<const void*>(&k_row_inv<4, ROW_RB[3], NTL>),
+        reinterpret_cast<const void*>(&k_row_fwd<8, ROW_RB[4], NTL>),
+        reinterpret_cast<const void*>(&k_row_inv<8, ROW_RB[4], NTL>),
         reinterpret_cast<const void*>(&k_row_fwd<32, ROW_RB[5]>),
         reinterpret_cast<const void*>(&k_row_inv<32, ROW_RB[5]>),
         reinterpret_cast<const void*>(&k_col_big<512>),
@@ -1372,7 +1379,8 @@ size_t lds_col_bytes(int H, int TC) { return col_lds(H, TC); }
 size_t lds_rowtv_bytes(int W, int B) { return rowtv_lds(W, B); }
 size_t lds_row_bytes(int W, int B) { return row_lds(W, B); }
 int col_max_tiles() { return NTC / 64; }
-int row_maxe(int w) { return w > 2048 ? row_maxe_c<8>() : MAXE_ROW; }   // the same for CPT 16, 32
+int row_maxe(int w) { return w > 8192 ? row_maxe_c<32>() : (w > 2048 ? row_maxe_c<4, NTL>() : MAXE_ROW); }
+int row_threads(int w) { return w > 2048 && w <= 8192 ? NTL : NT; }
 int block_threads() { return NT; }
 
 }  // namespace admm

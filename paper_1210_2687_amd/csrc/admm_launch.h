@@ -94,6 +94,7 @@ int col_split_factor(int h);                // radix of the HBM pass of a split 
 int col_big_threads(int h);                 // threads per block of the block-level column pass
 constexpr int COL_BIG_MAXE = 16;            // its operands per thread in a stage
 int row_maxe(int w);                        // operands per thread in a stage of the row passes for width w
+int row_threads(int w);                     // threads per block of the plain row passes for width w
 int block_threads();
 
 }  // namespace admm
