@@ -321,7 +321,8 @@ def test_planted_mistake_is_caught_by_minimiser_pin(mutation, monkeypatch):
             new.d1 = st.d1 + (Az - new.u1)       # wrong sign of the dual update
             return new, z, aux
         monkeypatch.setattr(oadmm, "tv_md_step", bad_step)
-    out = oadmm.tv_md_run(y, m, h, lam, 0.2, 0.1, iters=3000)
+    with np.errstate(invalid="ignore", over="ignore"):   # the wrong dual sign diverges
+        out = oadmm.tv_md_run(y, m, h, lam, 0.2, 0.1, iters=3000)
     F_bad = O.tv_objective(out["z"], y, m, h, lam) if np.all(np.isfinite(out["z"])) else np.inf
     assert not (F_bad - F_eps <= 1e-9 * F_eps + lam * H * W * 1e-10)
 
