@@ -82,6 +82,19 @@ bool fits(int ntrans, const FftPlanDev& f, int maxe, int nt = block_threads()) {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// The narrower-block launch of fused TV row class c (0..2) that takes problem
+// d, or ADMM_RTV_SUBS for 512-thread blocks: the first whose threads cover the
+// row at 2^c columns each and whose row transforms fit them at the class's
+// most rows per block (so that the choice, and the rounding of the transforms,
+// does not depend on the tile shape).
+int rtv_sub_of(const ProbDesc& d, int c) {
+    for (int t = 0; t < ADMM_RTV_SUBS; ++t) {
+        const int nt = row_tv_sub_threads(c, t);
+        if (nt > 0 && d.W <= (1 << c) * nt && fits(row_tv_max_rows(d.W) + 2, d.fr, row_maxe(d.W), nt)) return t;
+    }
+    return ADMM_RTV_SUBS;
+}
+
 // tw_off: the length's slot in the table arrays (2 N entries: the natural
 // twiddles exp(-2 pi i k / N), then the stage table)
 void fill_plan(FftPlanDev& f, int N, int tw_off, int variant) {
@@ -451,16 +464,25 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         }
         col_cc[c] = (int)col.size() - col_cb[c];
     }
-    // (classes 3 and 4, rows longer than 2048, take the three-pass TV schedule: no fused pass)
+    // (classes 3 to 5, rows longer than 2048, take the three-pass TV schedule: no fused pass)
+    // Within a fused class the problems of its narrower-block launches come first.
+    int rtv_sub[3][ADMM_RTV_SUBS] = {};
+    size_t lds_rtv_sub[3][ADMM_RTV_SUBS] = {};
     for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
         rtv_cb[c] = (int)rowtv.size();
-        for (int i : order) {
-            ProbDesc& d = P->hd[i];
-            if (d.reg == REG_TV && size_class(d.W) == c) {
+        for (int t = 0; t <= ADMM_RTV_SUBS; ++t) {
+            for (int i : order) {
+                ProbDesc& d = P->hd[i];
+                if (d.reg != REG_TV || size_class(d.W) != c || (c < 3 ? rtv_sub_of(d, c) : 0) != t) continue;
                 P->row_beg[i] = (int)rowtv.size();
                 for (int b = 0; b < d.nrowblk; ++b) rowtv.push_back({i, b * d.B, b, 0});
                 P->row_end[i] = (int)rowtv.size();
-                if (c < 3) lds_rtv_c[c] = std::max(lds_rtv_c[c], lds_rowtv_bytes(d.W, d.B));
+                if (c < 3 && t < ADMM_RTV_SUBS) {
+                    rtv_sub[c][t] += d.nrowblk;
+                    lds_rtv_sub[c][t] = std::max(lds_rtv_sub[c][t], lds_rowtv_bytes(d.W, d.B));
+                } else if (c < 3) {
+                    lds_rtv_c[c] = std::max(lds_rtv_c[c], lds_rowtv_bytes(d.W, d.B));
+                }
             }
         }
         rtv_cc[c] = (int)rowtv.size() - rtv_cb[c];
@@ -680,6 +702,11 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         base_ctx.rtv_beg[c] = rtv_cb[c];
         base_ctx.rtv_cnt[c] = rtv_cc[c];
         base_ctx.lds_rtv_c[c] = lds_rtv_c[c];
+        if (c < 3)
+            for (int t = 0; t < ADMM_RTV_SUBS; ++t) {
+                base_ctx.rtv_sub[c][t] = rtv_sub[c][t];
+                base_ctx.lds_rtv_sub[c][t] = lds_rtv_sub[c][t];
+            }
     }
     for (int c = 0; c < ADMM_FRAME_CLASSES; ++c) {
         base_ctx.frm_beg[c] = frm_cb[c];
@@ -1165,9 +1192,15 @@ LaunchCtx single(const admm_plan* P, int i) {
         c.rtv_beg[k] = c.rrow_beg[k] = 0;
         c.rtv_cnt[k] = c.rrow_cnt[k] = 0;
     }
+    for (int k = 0; k < 3; ++k)
+        for (int t = 0; t < ADMM_RTV_SUBS; ++t) c.rtv_sub[k][t] = 0;
     c.col_cnt[col_class(d)] = c.ncol;
     c.rrow_cnt[size_class(d.W)] = c.nrow;
-    if (d.reg == REG_TV) c.rtv_cnt[size_class(d.W)] = c.nrow;
+    if (d.reg == REG_TV) {
+        const int sc = size_class(d.W);
+        c.rtv_cnt[sc] = c.nrow;
+        if (sc < 3 && rtv_sub_of(d, sc) < ADMM_RTV_SUBS) c.rtv_sub[sc][rtv_sub_of(d, sc)] = c.nrow;   // as in the batch
+    }
     return c;
 }
 

@@ -37,6 +37,10 @@ constexpr int ROW_BURST = 8;       // plane elements per thread fetched together
 // transforms, per size class (as many as keep the kernel at 128 VGPRs or fewer,
 // two blocks per compute unit)
 constexpr int RTV_EARLY[3] = {5, 3, 1};
+// Narrower blocks of the TV row pass, per fused size class: rows of at most
+// CPT x RTV_SUB_NT[c][t] take blocks of that many threads (the first such t),
+// so that fewer lanes idle past the row's end; the others 512 (0: unused).
+constexpr int RTV_SUB_NT[3][ADMM_RTV_SUBS] = {{256, 384}, {384, 0}, {0, 0}};
 // most rows per block of the plain row passes, per size class (W <= 512, 1024, 2048, 4096, 8192, 16384)
 constexpr int ROW_RB[ADMM_ROW_CLASSES] = {16, 8, 4, 4, 2, 1};
 // Rows longer than 2048: the plain row passes run NTL threads per block up to
@@ -520,12 +524,13 @@ __device__ __forceinline__ void store_rows_split(const float2* X, int pitch, flo
 }
 
 // ------------------------------------------------------------ fused TV row pass
-// CPT: columns per thread (W <= CPT * NT); RB: most rows per block. All global
+// CPT: columns per thread (W <= CPT * NTR); RB: most rows per block; NTR: threads
+// (512, or fewer for rows that leave most of a 512-thread block idle). All global
 // inputs of the epilogue are loaded in one burst after the inverse transform
 // (register arrays indexed by the unrolled row loop), so the row steps, which
 // exchange delta^h through LDS, wait on memory once rather than once per row.
-template <int MAXE, int CPT, int RB, int EARLY, bool CHK>
-__global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
+template <int MAXE, int CPT, int RB, int EARLY, bool CHK, int NTR = NT>
+__global__ __launch_bounds__(NTR) void k_row_tv(const ProbDesc* __restrict__ pd, const WorkItem* __restrict__ items,
                                                int nitems, int par, int flags, const InfoDev* __restrict__ info,
                                                const float2* __restrict__ tw, double* __restrict__ partials) {
     extern __shared__ float2 X[];
@@ -564,9 +569,9 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     float* dh_out = par ? p.dreg0 : p.dreg1;
     float* dv_out = dh_out + n;
 
-    // spectrum rows r0 - 1 .. r0 + nr (P <= NT CPT / 2 + 1 entries each), then the stage table
-    constexpr int NLD = ((NT * CPT / 2 + 1) * (RB + 2) + NT - 1) / NT;
-    load_rows_hermitian<true, NLD, CPT>(X, pitch, Sin, H, W, P, r0 - 1, nrh, tid, twl, tw + p.fr.tw_off + W, W);
+    // spectrum rows r0 - 1 .. r0 + nr (P <= NTR CPT / 2 + 1 entries each), then the stage table
+    constexpr int NLD = ((NTR * CPT / 2 + 1) * (RB + 2) + NTR - 1) / NTR;
+    load_rows_hermitian<true, NLD, CPT, NTR>(X, pitch, Sin, H, W, P, r0 - 1, nrh, tid, twl, tw + p.fr.tw_off + W, W);
 
     // Epilogue inputs: duals of rows r0-1 .. r0+nr-1, data of rows r0 .. r0+nr-1,
     // fetched unconditionally (rows past nr and columns past W are clamped to
@@ -581,7 +586,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
         const int r = wrapi(r0 - 1 + min(rr, nr), H);
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
-            const unsigned g = (unsigned)(r * W + min(tid + j * NT, W - 1));
+            const unsigned g = (unsigned)(r * W + min(tid + j * NTR, W - 1));
             pdh[j][rr] = gld(dh_in, g);
             pdv[j][rr] = gld(dv_in, g);
             if (rr > 0) {
@@ -599,7 +604,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
 #pragma unroll
     for (int rr = 0; rr < EARLY; ++rr) fetch_row(rr);
     __syncthreads();
-    rows_fft<NT * CPT, NT, RB + 2, MAXE, true>(X, pitch, p.fr, twl, nrh, tid);
+    rows_fft<NTR * CPT, NTR, RB + 2, MAXE, true>(X, pitch, p.fr, twl, nrh, tid);
     // X[rr][c] = z + i A z for row r0 - 1 + rr
 
     const float tau = p.tau, mu2 = p.mu2, c1 = p.inv1pmu1;
@@ -624,8 +629,8 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
         // then used outside any branch and stay in the burst
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
-            const bool live = tid + j * NT < W;
-            const int c = live ? tid + j * NT : W - 1;
+            const bool live = tid + j * NTR < W;
+            const int c = live ? tid + j * NTR : W - 1;
             {
                 const float2 xc = Xr[pidx(c)];
                 const float zc = xc.x;
@@ -697,7 +702,7 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
             float2* Xw = X + rr * pitch;
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const int c = min(tid + j * NT, W - 1);
+                const int c = min(tid + j * NTR, W - 1);
                 const float s = mu2 * ((dlr[c == 0 ? W - 1 : c - 1] - dlr[c]) + (dvp[j] - dvc[j]));
                 Xw[pidx(c)] = make_float2(mu1 * zet[j], s);
             }
@@ -707,10 +712,10 @@ __global__ __launch_bounds__(NT) void k_row_tv(const ProbDesc* __restrict__ pd, 
     }
     __syncthreads();
     if (flags & F_FORWARD) {
-        rows_fft<NT * CPT, NT, RB, MAXE, false>(X + pitch, pitch, p.fr, twl, nr, tid);
-        store_rows_split<true>(X + pitch, pitch, Sout, H, W, P, r0, nr, tid);
+        rows_fft<NTR * CPT, NTR, RB, MAXE, false>(X + pitch, pitch, p.fr, twl, nr, tid);
+        store_rows_split<true, NTR>(X + pitch, pitch, Sout, H, W, P, r0, nr, tid);
     }
-    if (chk) block_sums_write(acc, reinterpret_cast<double*>(X), partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM);
+    if (chk) block_sums_write<NTR>(acc, reinterpret_cast<double*>(X), partials + (size_t)(p.part_base + it.blk) * ADMM_NSUM);
 }
 
 // ------------------------------------------------------------ plane -> spectrum rows
@@ -1201,16 +1206,35 @@ hipError_t launch_col(const LaunchCtx& L, int par, int mode) {
 }
 
 namespace {
-template <int CPT, int RB, int EARLY>
+template <int CPT, int RB, int EARLY, int NTR>
+void launch_row_tv_part(const LaunchCtx& L, const WorkItem* it, int n, size_t lds, int par, int flags) {
+    if (n <= 0) return;
+    if (flags & F_CHECK)
+        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, CPT, RB, EARLY, true, NTR>), dim3(n), dim3(NTR), lds, L.stream, L.desc,
+                           it, n, par, flags, L.info, L.tw, L.partials);
+    else
+        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, CPT, RB, EARLY, false, NTR>), dim3(n), dim3(NTR), lds, L.stream, L.desc,
+                           it, n, par, flags, L.info, L.tw, L.partials);
+}
+
+// The class's items start with those of its narrower blocks (rtv_sub[c][t]
+// items for RTV_SUB_NT[c][t] threads, in order); the rest take 512 threads.
+template <int CPT, int RB, int EARLY, int NT0, int NT1>
 void launch_row_tv_class(const LaunchCtx& L, int c, int par, int flags) {
     const WorkItem* it = L.row_items + L.rtv_beg[c];
     const int n = L.rtv_cnt[c];
-    if (flags & F_CHECK)
-        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, CPT, RB, EARLY, true>), dim3(n), dim3(NT), L.lds_rtv_c[c], L.stream,
-                           L.desc, it, n, par, flags, L.info, L.tw, L.partials);
-    else
-        hipLaunchKernelGGL((k_row_tv<MAXE_ROW, CPT, RB, EARLY, false>), dim3(n), dim3(NT), L.lds_rtv_c[c], L.stream,
-                           L.desc, it, n, par, flags, L.info, L.tw, L.partials);
+    int off = 0;
+    if constexpr (NT0 > 0) {
+        const int m = std::min(L.rtv_sub[c][0], n - off);
+        launch_row_tv_part<CPT, RB, EARLY, NT0>(L, it + off, m, L.lds_rtv_sub[c][0], par, flags);
+        off += m;
+    }
+    if constexpr (NT1 > 0) {
+        const int m = std::min(L.rtv_sub[c][1], n - off);
+        launch_row_tv_part<CPT, RB, EARLY, NT1>(L, it + off, m, L.lds_rtv_sub[c][1], par, flags);
+        off += m;
+    }
+    launch_row_tv_part<CPT, RB, EARLY, NT>(L, it + off, n - off, L.lds_rtv_c[c], par, flags);
 }
 }  // namespace
 
@@ -1218,11 +1242,11 @@ hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags) {
     for (int c = 0; c < 3; ++c) {   // rows longer than 2048 take the three-pass schedule (no fused class)
         if (!L.rtv_cnt[c]) continue;
         if (c == 0)
-            launch_row_tv_class<1, 8, RTV_EARLY[0]>(L, c, par, flags);
+            launch_row_tv_class<1, 8, RTV_EARLY[0], RTV_SUB_NT[0][0], RTV_SUB_NT[0][1]>(L, c, par, flags);
         else if (c == 1)
-            launch_row_tv_class<2, 6, RTV_EARLY[1]>(L, c, par, flags);
+            launch_row_tv_class<2, 6, RTV_EARLY[1], RTV_SUB_NT[1][0], RTV_SUB_NT[1][1]>(L, c, par, flags);
         else
-            launch_row_tv_class<4, 2, RTV_EARLY[2]>(L, c, par, flags);
+            launch_row_tv_class<4, 2, RTV_EARLY[2], RTV_SUB_NT[2][0], RTV_SUB_NT[2][1]>(L, c, par, flags);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1230,6 +1254,7 @@ hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags) {
 }
 
 int row_tv_max_rows(int w) { return w <= NT ? 8 : (w <= 2 * NT ? 6 : 2); }
+int row_tv_sub_threads(int c, int t) { return c >= 0 && c < 3 && t >= 0 && t < ADMM_RTV_SUBS ? RTV_SUB_NT[c][t] : 0; }
 
 // The plain row passes (FA rows, blur, state import) per size class of the row
 // length: CPT columns per thread, at most ROW_RB[c] rows per block; NT threads
@@ -1354,6 +1379,12 @@ hipError_t allow_dynamic_lds(int bytes) {
         reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0], true>),
         reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1], true>),
         reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 4, 2, RTV_EARLY[2], true>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0], false, RTV_SUB_NT[0][0]>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0], true, RTV_SUB_NT[0][0]>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0], false, RTV_SUB_NT[0][1]>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 1, 8, RTV_EARLY[0], true, RTV_SUB_NT[0][1]>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1], false, RTV_SUB_NT[1][0]>),
+        reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1], true, RTV_SUB_NT[1][0]>),
         reinterpret_cast<const void*>(&k_row_fwd<1, ROW_RB[0]>),
         reinterpret_cast<const void*>(&k_row_fwd<2, ROW_RB[1]>),
         reinterpret_cast<const void*>(&k_row_fwd<4, ROW_RB[2]>),

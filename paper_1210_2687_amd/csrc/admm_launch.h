@@ -18,6 +18,7 @@ constexpr int ADMM_COL_CLASSES = 9;
 // with such rows takes the three-pass schedule: inverse rows with the data
 // step, the TV step, forward rows)
 constexpr int ADMM_ROW_CLASSES = 6;
+constexpr int ADMM_RTV_SUBS = 2;   // narrower-block launches per fused TV row class
 
 // Everything a launch needs; item lists are device arrays, counts are the grid sizes.
 struct LaunchCtx {
@@ -41,6 +42,10 @@ struct LaunchCtx {
     size_t lds_col_c[ADMM_COL_CLASSES] = {};
     int rtv_beg[ADMM_ROW_CLASSES] = {}, rtv_cnt[ADMM_ROW_CLASSES] = {};
     size_t lds_rtv_c[ADMM_ROW_CLASSES] = {};
+    // fused TV row classes 0..2: their first rtv_sub[c][0], then rtv_sub[c][1]
+    // items run in blocks of row_tv_sub_threads(c, t) threads (LDS lds_rtv_sub)
+    int rtv_sub[3][ADMM_RTV_SUBS] = {};
+    size_t lds_rtv_sub[3][ADMM_RTV_SUBS] = {};
     // size classes of the plain row passes (FA rows, blur, state import) over row_items
     int rrow_beg[ADMM_ROW_CLASSES] = {}, rrow_cnt[ADMM_ROW_CLASSES] = {};
     size_t lds_rrow_c[ADMM_ROW_CLASSES] = {};
@@ -87,6 +92,7 @@ size_t lds_frame_bytes(int J);
 int frame_class(int H, int W, int J, bool fs);   // 8 fs + 2 (J - 1) + (image smaller than a window)
 int col_max_tiles();                       // columns per column-pass block (one per wave)
 int row_tv_max_rows(int w);                  // rows per block of the TV row pass for width w
+int row_tv_sub_threads(int c, int t);        // threads of narrower-block launch t of fused TV class c (0: none)
 int row_max_rows(int w);                     // rows per block of the plain row passes for width w
 int size_class(int n);                      // 0: n <= 512, 1: <= 1024, 2: <= 2048, 3: <= 4096, 4: <= 8192, 5: larger
 int col_class(const ProbDesc& d);           // 2 size_class(H) + (general column schedule); 6, 7, 8 above 2048

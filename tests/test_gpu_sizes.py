@@ -10,7 +10,8 @@ names the kernel instantiations it runs:
   fixed; otherwise general), the block-level pass for columns of
   2049..4096 and 4097..8192, and split columns above 8192 (a radix-p pass
   through HBM around block-level sub-transforms);
-* TV row pass: one per size class of the row length (rows per block 8, 6, 2);
+* TV row pass: one per size class of the row length (rows per block 8, 6, 2),
+  in blocks of 256 or 384 threads for rows that leave most of 512 idle;
   rows longer than 2048 (classes <= 4096, <= 8192, <= 16384) take the
   three-pass schedule (plain inverse rows with the data step, TV step,
   forward rows);
@@ -87,6 +88,15 @@ def test_tv_fixed_lengths_of_the_middle_class():
     # of length 768 (run-time schedule in the middle class's instantiation)
     announce("TV 1024 x 768, 15 x 15 motion, k = 2, 6")
     _single(full_problem(205, 1024, 768, 15, "motion"), [2, 6])
+
+
+def test_tv_row_widths_of_the_narrow_blocks():
+    # fused TV rows in blocks of as many threads as the row needs: 250 and 256
+    # (256 threads; 256 on the compile-time schedule), 378 and 384 (384 threads),
+    # 448 and 512 (512), 640 and 768 (two columns per thread, 384 threads), 1000 (512)
+    shapes = [(120, 250), (96, 256), (84, 378), (80, 384), (72, 448), (64, 512), (72, 640), (64, 768), (56, 1000)]
+    announce("TV batch of row widths 250..1000, k = 2, 7")
+    _batch([full_problem(210 + i, H, W, 7) for i, (H, W) in enumerate(shapes)], [2, 7])
 
 
 def test_fa_config3_full_size():
