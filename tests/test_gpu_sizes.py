@@ -93,8 +93,10 @@ def test_tv_fixed_lengths_of_the_middle_class():
 def test_tv_row_widths_of_the_narrow_blocks():
     # fused TV rows in blocks of as many threads as the row needs: 250 and 256
     # (256 threads; 256 on the compile-time schedule), 378 and 384 (384 threads),
-    # 448 and 512 (512), 640 and 768 (two columns per thread, 384 threads), 1000 (512)
-    shapes = [(120, 250), (96, 256), (84, 378), (80, 384), (72, 448), (64, 512), (72, 640), (64, 768), (56, 1000)]
+    # 448 and 512 (512), 640 and 720 (two columns per thread, 384 threads), 768
+    # (512: its radix-3 stage needs more than 384 threads at 8 rows) and 1000 (512)
+    shapes = [(120, 250), (96, 256), (84, 378), (80, 384), (72, 448), (64, 512), (72, 640), (60, 720), (64, 768),
+              (56, 1000)]
     announce("TV batch of row widths 250..1000, k = 2, 7")
     _batch([full_problem(210 + i, H, W, 7) for i, (H, W) in enumerate(shapes)], [2, 7])
 
