@@ -36,7 +36,9 @@ The same JSON line also carries, under "configs", the other workloads:
 with a roofline per workload: algorithmic bytes per iteration (this
 schedule's two-launch TV iteration, the FA iteration's four launches) over
 the measured time per iteration, and for the headline the dominant kernel's
-launch duration as well. ``--quick`` runs the headline alone.
+launch duration as well. ``--quick`` runs the headline alone. The CPU
+baseline (the FP64 oracle) also times 5 iterations of the c3 problem and 5
+of four c4 problems when those workloads run.
 """
 
 import argparse
@@ -471,9 +473,11 @@ def run_c5(train_probs, eval_probs, steps, target_batch=500, target_iters=3000):
 
 
 # ------------------------------------------------------------------ CPU baseline (the oracle)
-def cpu_baseline(iters, sample, c1=None):
+def cpu_baseline(iters, sample, c1=None, c3=None, c4=None):
     """The FP64 oracle on a bounded sample of the headline workload (and, if
-    given, the whole 128^2 workload: its headline is the oracle's wall time)."""
+    given, the whole 128^2 workload: its headline is the oracle's wall time; 5
+    iterations of the FA-MD 1024^2 problem; 5 iterations of 4 problems of the
+    ragged batch, extrapolated to the batch)."""
     import oracle as O
     try:
         import threadpoolctl
@@ -495,6 +499,26 @@ def cpu_baseline(iters, sample, c1=None):
         O.tv_md_run(c1.y, c1.mask, c1.kernel, c1.lam, c1.mu1, c1.mu2, iters=200)
         out["config1_oracle_s"] = round(time.perf_counter() - t0, 3)
         out["config1"] = "TV-MD 128x128, 9x9 uniform, 200 iterations, the whole run"
+    if c3 is not None:
+        t0 = time.perf_counter()
+        O.fa_md_run(c3.y, c3.mask, c3.kernel, c3.lam, c3.mu1, c3.mu2, c3.levels, iters=5)
+        dt = time.perf_counter() - t0
+        out["config3"] = {"value": round(c3.y.size * 5 / dt / 1e6, 3), "unit": "Mpx*iter/s",
+                          "s_per_iter": round(dt / 5, 3),
+                          "sample": f"FA-MD {c3.shape[0]}x{c3.shape[1]}, J = {c3.levels}, 5 iterations"}
+    if c4:
+        sub = c4[:4]
+        t0 = time.perf_counter()
+        for p in sub:
+            O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=5)
+        dt = time.perf_counter() - t0
+        rate = sum(p.y.size for p in sub) * 5 / dt
+        out["config4"] = {"value": round(rate / 1e6, 3), "unit": "Mpx*iter/s",
+                          "extrapolated_s_per_iter": round(sum(p.y.size for p in c4) / rate, 2),
+                          "sample": "TV-MD, the first 4 of the 256 ragged problems ("
+                                    + ", ".join(f"{p.shape[0]}x{p.shape[1]}" for p in sub)
+                                    + "), 5 iterations each; the batch's time per iteration extrapolated by its "
+                                      "pixel count"}
     return out
 
 
@@ -626,7 +650,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_iters, [probs[0], probs[4 % len(probs)]], None if args.quick else data["c1"])
+        cpu = cpu_baseline(args.cpu_iters, [probs[0], probs[4 % len(probs)]], None if args.quick else data["c1"],
+                           data.get("c3"), data.get("c4"))
 
     config = {"workload": f"TV-MD batch of {args.batch} x {args.size}x{args.size}, {args.iters} iterations",
               "batch": args.batch, "H": args.size, "W": args.size, "iters": args.iters,
