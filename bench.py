@@ -233,6 +233,26 @@ def dominant_roofline(plan, probs, kt, reps=50):
             "alg_bytes_per_launch": int(alg[dom]), "timing": f"{reps} back-to-back launches between one HIP event pair"}
 
 
+COL_CLASS_NAMES = ["columns <= 512, radix-8 first and last stage", "columns <= 512, general schedule",
+                   "columns 513..1024, radix-8 ends", "columns 513..1024, general", "columns 1025..2048, radix-8 ends",
+                   "columns 1025..2048, general", "columns 2049..4096", "columns 4097..8192", "columns above 8192"]
+ROW_CLASS_NAMES = ["TV rows <= 512", "TV rows 513..1024", "TV rows 1025..2048"]
+
+
+def class_breakdown(plan, reps=20):
+    """Microseconds per launch of each size class of the column and fused TV row
+    passes that the plan has (`reps` back-to-back launches between one HIP event pair)."""
+    from paper_1210_2687_amd import admm as A
+    out = {}
+    for kind, names in (("col", COL_CLASS_NAMES), ("row_tv", ROW_CLASS_NAMES)):
+        for c, nm in enumerate(names):
+            try:
+                out[f"{kind}:{c} ({nm})"] = round(plan.time_pass(f"{kind}:{c}", reps) * 1e3, 2)
+            except A.AdmmError:
+                pass   # no problem of the batch in this class
+    return out
+
+
 def run_throughput(name, probs, iters, steps, warmup, tune, desc, method=0):
     log(f"{name}: {desc}")
     plan, ys, xs, r = timed_batch(probs, iters, steps, warmup, tune, method=method)
@@ -240,6 +260,8 @@ def run_throughput(name, probs, iters, steps, warmup, tune, desc, method=0):
     out = {"workload": desc, "value": round(r["value"], 1), "unit": "Mpx*iter/s", "ms_per_step": round(r["ms_per_step"], 3),
            "steps": steps, "problems": len(probs), "pixels": r["pixels"], "iters": iters, "tiles": r["tiles"],
            "plan_s": r["plan_s"], "us_per_iter": round(r["us_per_iter"], 3), "kernel_us_event_per_launch": kt}
+    if name == "c4":   # the ragged batch: its size classes apart
+        out["class_us_per_launch"] = class_breakdown(plan)
     if method == 0:   # the rooflines price the MD schedule's launches
         out["roofline_iteration"] = iteration_roofline(probs, r["us_per_iter"])
         out["roofline_dominant"] = dominant_roofline(plan, probs, kt)

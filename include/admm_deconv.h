@@ -220,7 +220,11 @@ int32_t admm_plan_kernel_times(const admm_plan* plan, admm_kernel_time* out, int
 
 /* Average duration of one launch of a pass kernel ("col", "row_tv", "frame",
  * "row_inv" or "row_fwd"; a pass split into size classes counts as one
- * launch) over `reps` back-to-back launches on the plan's stream, bracketed by
+ * launch; "col:c" and "row_tv:c" time size class c alone: column classes
+ * 0..8 as 2 x (0: length <= 512, 1: <= 1024, 2: <= 2048) + (general
+ * schedule), 6: <= 4096, 7: <= 8192, 8: longer; fused TV row classes 0..2 by
+ * row length <= 512, <= 1024, <= 2048, each with its narrower-block launches)
+ * over `reps` back-to-back launches on the plan's stream, bracketed by
  * one pair of HIP events, after one untimed launch. For measurement only: it
  * runs plain iterations' launches on whatever the plan's buffers hold (call
  * it after a solve or batch, which sets the data pointers) and leaves that

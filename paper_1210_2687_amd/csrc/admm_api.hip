@@ -1596,9 +1596,28 @@ extern "C" admm_status admm_plan_schedules(const admm_plan* P, int32_t index, in
 
 extern "C" admm_status admm_plan_time_pass(admm_plan* P, const char* kernel, int32_t reps, double* avg_ms) {
     if (!P || !kernel || !avg_ms || reps < 1) return fail(ADMM_E_INVALID, "bad argument");
-    const std::string k = kernel;
+    std::string k = kernel;
+    int cls = -1;   // "col:c", "row_tv:c": size class c alone
+    const size_t colon = k.find(':');
+    if (colon != std::string::npos) {
+        const std::string num = k.substr(colon + 1);
+        k = k.substr(0, colon);
+        const int ncls = k == "col" ? ADMM_COL_CLASSES : 3;
+        if ((k != "col" && k != "row_tv") || num.empty() || num.size() > 1 || num[0] < '0' || num[0] - '0' >= ncls)
+            return fail(ADMM_E_INVALID, "unknown pass kernel %s", kernel);
+        cls = num[0] - '0';
+    }
     const bool fa = k == "frame" || k == "row_inv" || k == "row_fwd";
     if (k != "col" && k != "row_tv" && !fa) return fail(ADMM_E_INVALID, "unknown pass kernel %s", kernel);
+    LaunchCtx ccol = P->all, crow = P->tv;   // with cls >= 0: that class's launches only
+    if (cls >= 0) {
+        for (int c = 0; c < ADMM_COL_CLASSES; ++c)
+            if (c != cls) ccol.col_cnt[c] = 0;
+        for (int c = 0; c < ADMM_ROW_CLASSES; ++c)
+            if (c != cls) crow.rtv_cnt[c] = 0;
+        if ((k == "col" && !ccol.col_cnt[cls]) || (k == "row_tv" && !crow.rtv_cnt[cls]))
+            return fail(ADMM_E_INVALID, "the plan has no %s launches", kernel);
+    }
     // "row_tv": the fused TV row pass and the TV step of long TV rows; "row_inv",
     // "row_fwd": the plain row passes of the frame problems and of long TV rows
     if ((k == "row_tv" && !P->nrowtv) || (k == "frame" && !P->nfa) ||
@@ -1611,12 +1630,12 @@ extern "C" admm_status admm_plan_time_pass(admm_plan* P, const char* kernel, int
     }
     HIP_TRY(hipMemcpyAsync(P->d_info, P->h_info, sizeof(InfoDev) * P->count, hipMemcpyHostToDevice, P->stream));
     auto launch = [&]() -> hipError_t {
-        if (k == "col") return launch_col(P->all, 0, COL_SOLVE);
+        if (k == "col") return launch_col(ccol, 0, COL_SOLVE);
         if (k == "frame") return launch_frame(P->fa, 0, 0, 0, true);
         hipError_t e = hipSuccess;
         if (k == "row_tv") {
-            e = launch_row_tv(P->tv, 0, F_FORWARD);
-            if (e == hipSuccess && P->nrowtvs) e = launch_tv_step(P->tvs, 0, 0);
+            e = launch_row_tv(crow, 0, F_FORWARD);
+            if (e == hipSuccess && P->nrowtvs && cls < 0) e = launch_tv_step(P->tvs, 0, 0);
             return e;
         }
         const bool inv = k == "row_inv";

@@ -81,6 +81,13 @@ def test_pass_timing_entry_point():
             assert 0.0 < ms < 100.0, k
         with pytest.raises(A.AdmmError):
             plan.time_pass("nonsense", reps=5)
+        # one size class alone: columns of 64 (radix-8 ends) and 96 (general), TV rows <= 512
+        for k in ("col:0", "col:1", "row_tv:0"):
+            ms = plan.time_pass(k, reps=5)
+            assert 0.0 < ms < 100.0, k
+        for k in ("col:4", "row_tv:2", "col:9", "row_tv:3", "col:", "col:x", "frame:0"):
+            with pytest.raises(A.AdmmError):
+                plan.time_pass(k, reps=5)
         # a solve after the timing launches starts over from its own initial state
         ref = _run(plan, probs)
     with A.Plan(probs) as plan2:
