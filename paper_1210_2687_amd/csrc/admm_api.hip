@@ -95,6 +95,15 @@ int rtv_sub_of(const ProbDesc& d, int c) {
     return ADMM_RTV_SUBS;
 }
 
+// Plain row passes (frame problems, the CG and blur passes of TV problems) run
+// rows of at most row_sub_threads() columns in blocks of that many threads
+// when every stage of the row's schedule fits them at the class's most rows
+// per block (again independent of the tile shape).
+bool plain_narrow(const ProbDesc& d) {
+    const int nt = row_sub_threads();
+    return size_class(d.W) == 0 && d.W <= nt && fits(row_max_rows(d.W), d.fr, row_maxe(d.W), nt);
+}
+
 // tw_off: the length's slot in the table arrays (2 N entries: the natural
 // twiddles exp(-2 pi i k / N), then the stage table)
 void fill_plan(FftPlanDev& f, int N, int tw_off, int variant) {
@@ -468,12 +477,21 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     // Within a fused class the problems of its narrower-block launches come first.
     int rtv_sub[3][ADMM_RTV_SUBS] = {};
     size_t lds_rtv_sub[3][ADMM_RTV_SUBS] = {};
+    int tv_sub0 = 0, fa_sub0 = 0;   // leading class-0 items of the plain passes' narrower blocks
+    size_t lds_tv_sub0 = 0, lds_fa_sub0 = 0;
     for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
         rtv_cb[c] = (int)rowtv.size();
-        for (int t = 0; t <= ADMM_RTV_SUBS; ++t) {
+        for (int t = 0; t <= ADMM_RTV_SUBS; ++t)
+            for (int pass = 0; pass < 2; ++pass)   // the plain passes' narrower blocks first (a subset of t = 0)
             for (int i : order) {
                 ProbDesc& d = P->hd[i];
                 if (d.reg != REG_TV || size_class(d.W) != c || (c < 3 ? rtv_sub_of(d, c) : 0) != t) continue;
+                const bool late = c == 0 && t == 0 && !plain_narrow(d);
+                if (late != (pass == 1)) continue;
+                if (c == 0 && t == 0 && !late) {
+                    tv_sub0 += d.nrowblk;
+                    lds_tv_sub0 = std::max(lds_tv_sub0, lds_row_bytes(d.W, d.B));
+                }
                 P->row_beg[i] = (int)rowtv.size();
                 for (int b = 0; b < d.nrowblk; ++b) rowtv.push_back({i, b * d.B, b, 0});
                 P->row_end[i] = (int)rowtv.size();
@@ -484,7 +502,6 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
                     lds_rtv_c[c] = std::max(lds_rtv_c[c], lds_rowtv_bytes(d.W, d.B));
                 }
             }
-        }
         rtv_cc[c] = (int)rowtv.size() - rtv_cb[c];
     }
     int part = 0;
@@ -519,10 +536,16 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
     size_t lds_rfa_c[ADMM_ROW_CLASSES] = {}, lds_rtvp_c[ADMM_ROW_CLASSES] = {};
     for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
         rfa_cb[c] = (int)rowfa.size();
+        for (int pass = 0; pass < 2; ++pass)   // the narrower blocks' problems first
         for (int i : order) {
             const ProbDesc& d = P->hd[i];
             if (size_class(d.W) != c) continue;
+            if ((c == 0 && !plain_narrow(d)) != (pass == 1)) continue;
             if (d.reg == REG_FRAME) {
+                if (c == 0 && pass == 0) {
+                    fa_sub0 += d.nrowblk;
+                    lds_fa_sub0 = std::max(lds_fa_sub0, lds_row_bytes(d.W, d.B));
+                }
                 P->row_beg[i] = (int)rowfa.size();
                 for (int b = 0; b < d.nrowblk; ++b) rowfa.push_back({i, b * d.B, b, 0});
                 P->row_end[i] = (int)rowfa.size();
@@ -730,6 +753,10 @@ static admm_status build_plan(admm_plan* P, const admm_problem* probs, int32_t c
         P->fa.rrow_cnt[c] = rfa_cc[c];
         P->fa.lds_rrow_c[c] = lds_rfa_c[c];
     }
+    P->tv.rrow_sub0 = tv_sub0;
+    P->tv.lds_rrow_sub0 = lds_tv_sub0;
+    P->fa.rrow_sub0 = fa_sub0;
+    P->fa.lds_rrow_sub0 = lds_fa_sub0;
     P->fa.frm_items = P->d_items + col.size() + rowtv.size() + rowfa.size();
     P->fa.nfrm = P->nfrm;
     // the TV problems with rows longer than 2048 alone (their row items are the
@@ -1196,6 +1223,7 @@ LaunchCtx single(const admm_plan* P, int i) {
         for (int t = 0; t < ADMM_RTV_SUBS; ++t) c.rtv_sub[k][t] = 0;
     c.col_cnt[col_class(d)] = c.ncol;
     c.rrow_cnt[size_class(d.W)] = c.nrow;
+    c.rrow_sub0 = plain_narrow(d) ? c.nrow : 0;   // as in the batch
     if (d.reg == REG_TV) {
         const int sc = size_class(d.W);
         c.rtv_cnt[sc] = c.nrow;

@@ -41,6 +41,9 @@ constexpr int RTV_EARLY[3] = {5, 3, 1};
 // CPT x RTV_SUB_NT[c][t] take blocks of that many threads (the first such t),
 // so that fewer lanes idle past the row's end; the others 512 (0: unused).
 constexpr int RTV_SUB_NT[3][ADMM_RTV_SUBS] = {{256, 384}, {384, 0}, {0, 0}};
+// The plain row passes likewise run rows of at most RROW_SUB_NT columns (size
+// class 0) in blocks of that many threads.
+constexpr int RROW_SUB_NT = 256;
 // most rows per block of the plain row passes, per size class (W <= 512, 1024, 2048, 4096, 8192, 16384)
 constexpr int ROW_RB[ADMM_ROW_CLASSES] = {16, 8, 4, 4, 2, 1};
 // Rows longer than 2048: the plain row passes run NTL threads per block up to
@@ -1255,16 +1258,28 @@ hipError_t launch_row_tv(const LaunchCtx& L, int par, int flags) {
 
 int row_tv_max_rows(int w) { return w <= NT ? 8 : (w <= 2 * NT ? 6 : 2); }
 int row_tv_sub_threads(int c, int t) { return c >= 0 && c < 3 && t >= 0 && t < ADMM_RTV_SUBS ? RTV_SUB_NT[c][t] : 0; }
+int row_sub_threads() { return RROW_SUB_NT; }
 
 // The plain row passes (FA rows, blur, state import) per size class of the row
 // length: CPT columns per thread, at most ROW_RB[c] rows per block; NT threads
-// per block, NTL for rows of 2049..8192.
+// per block, NTL for rows of 2049..8192, RROW_SUB_NT for the first rrow_sub0
+// items of class 0.
 hipError_t launch_row_fwd(const LaunchCtx& L, int par, int src, bool gated) {
     const InfoDev* info = gated ? L.info : nullptr;
     for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
-        const int n = L.rrow_cnt[c];
+        int n = L.rrow_cnt[c];
         if (!n) continue;
         const WorkItem* it = L.row_items + L.rrow_beg[c];
+        if (c == 0 && L.rrow_sub0 > 0) {
+            const int m = std::min(L.rrow_sub0, n);
+            hipLaunchKernelGGL((k_row_fwd<1, ROW_RB[0], RROW_SUB_NT>), dim3(m), dim3(RROW_SUB_NT), L.lds_rrow_sub0,
+                               L.stream, L.desc, it, m, par, src, info, L.tw);
+            it += m;
+            n -= m;
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            if (!n) continue;
+        }
         if (c == 0)
             hipLaunchKernelGGL((k_row_fwd<1, ROW_RB[0]>), dim3(n), dim3(NT), L.lds_rrow_c[0], L.stream, L.desc, it, n,
                                par, src, info, L.tw);
@@ -1293,9 +1308,19 @@ hipError_t launch_row_inv(const LaunchCtx& L, int par, int mode, int flags, bool
     const InfoDev* info = gated ? L.info : nullptr;
     double* const part = mode >= 2 ? L.cgpart : L.partials;   // modes 2, 3: the CG sums
     for (int c = 0; c < ADMM_ROW_CLASSES; ++c) {
-        const int n = L.rrow_cnt[c];
+        int n = L.rrow_cnt[c];
         if (!n) continue;
         const WorkItem* it = L.row_items + L.rrow_beg[c];
+        if (c == 0 && L.rrow_sub0 > 0) {
+            const int m = std::min(L.rrow_sub0, n);
+            hipLaunchKernelGGL((k_row_inv<1, ROW_RB[0], RROW_SUB_NT>), dim3(m), dim3(RROW_SUB_NT), L.lds_rrow_sub0,
+                               L.stream, L.desc, it, m, par, mode, flags, info, L.tw, part);
+            it += m;
+            n -= m;
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            if (!n) continue;
+        }
         if (c == 0)
             hipLaunchKernelGGL((k_row_inv<1, ROW_RB[0]>), dim3(n), dim3(NT), L.lds_rrow_c[0], L.stream, L.desc, it, n,
                                par, mode, flags, info, L.tw, part);
@@ -1386,6 +1411,8 @@ hipError_t allow_dynamic_lds(int bytes) {
         reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1], false, RTV_SUB_NT[1][0]>),
         reinterpret_cast<const void*>(&k_row_tv<MAXE_ROW, 2, 6, RTV_EARLY[1], true, RTV_SUB_NT[1][0]>),
         reinterpret_cast<const void*>(&k_row_fwd<1, ROW_RB[0]>),
+        reinterpret_cast<const void*>(&k_row_fwd<1, ROW_RB[0], RROW_SUB_NT>),
+        reinterpret_cast<const void*>(&k_row_inv<1, ROW_RB[0], RROW_SUB_NT>),
         reinterpret_cast<const void*>(&k_row_fwd<2, ROW_RB[1]>),
         reinterpret_cast<const void*>(&k_row_fwd<4, ROW_RB[2]>),
         reinterpret_cast<const void*>(&k_row_fwd<4, ROW_RB[3], NTL>),

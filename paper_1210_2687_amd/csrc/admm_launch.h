@@ -49,6 +49,9 @@ struct LaunchCtx {
     // size classes of the plain row passes (FA rows, blur, state import) over row_items
     int rrow_beg[ADMM_ROW_CLASSES] = {}, rrow_cnt[ADMM_ROW_CLASSES] = {};
     size_t lds_rrow_c[ADMM_ROW_CLASSES] = {};
+    // the first rrow_sub0 items of class 0 run in blocks of row_sub_threads() threads
+    int rrow_sub0 = 0;
+    size_t lds_rrow_sub0 = 0;
     // frame classes (levels 1..4, image smaller than a window or not): items of
     // class c are [frm_beg[c], frm_beg[c] + frm_cnt[c]) of frm_items
     int frm_beg[ADMM_FRAME_CLASSES] = {}, frm_cnt[ADMM_FRAME_CLASSES] = {};
@@ -93,6 +96,7 @@ int frame_class(int H, int W, int J, bool fs);   // 8 fs + 2 (J - 1) + (image sm
 int col_max_tiles();                       // columns per column-pass block (one per wave)
 int row_tv_max_rows(int w);                  // rows per block of the TV row pass for width w
 int row_tv_sub_threads(int c, int t);        // threads of narrower-block launch t of fused TV class c (0: none)
+int row_sub_threads();                       // threads of the plain row passes' narrower blocks (rows <= that)
 int row_max_rows(int w);                     // rows per block of the plain row passes for width w
 int size_class(int n);                      // 0: n <= 512, 1: <= 1024, 2: <= 2048, 3: <= 4096, 4: <= 8192, 5: larger
 int col_class(const ProbDesc& d);           // 2 size_class(H) + (general column schedule); 6, 7, 8 above 2048

@@ -15,7 +15,8 @@ names the kernel instantiations it runs:
   rows longer than 2048 (classes <= 4096, <= 8192, <= 16384) take the
   three-pass schedule (plain inverse rows with the data step, TV step,
   forward rows);
-* FA row passes and frame step: per size class of the row length and J.
+* FA row passes and frame step: per size class of the row length and J
+  (rows of at most 256 in 256-thread blocks).
 
 Bar (TV-MD Alg. 3 with the data step of eq. (49); FA-MD Sec. IV-C): relative
 L2 error of z_k <= 1e-4 and every element within 1e-4 of max |z_k|.
@@ -112,6 +113,15 @@ def test_fa_general_lengths_of_the_largest_row_class():
     # (general, largest class of the plain row passes)
     announce("FA 600 x 1250 J = 2, k = 2, 4")
     _single(full_problem(206, 600, 1250, 7, reg="frame", levels=2), [2, 4], graph=False)
+
+
+def test_fa_row_widths_of_the_narrow_plain_blocks():
+    # the plain row passes in 256-thread blocks: frame rows of 224 (run-time
+    # schedule) and 256 (compile-time schedule); 250 keeps 512 threads (its
+    # radix-5 stages need more than 256 threads at 16 rows), 320 is wider
+    shapes = [(96, 224), (80, 256), (72, 250), (64, 320)]
+    announce("FA batch of row widths 224..320, J = 2, k = 2, 6")
+    _batch([full_problem(230 + i, H, W, 5, reg="frame", levels=2) for i, (H, W) in enumerate(shapes)], [2, 6])
 
 
 def test_tv_config2_member_at_its_iteration_count():
