@@ -190,6 +190,10 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
     static_assert(CSched<NF>::rad(0) == 8 && CSched<NF>::rad(NST - 1) == 8 && CSt<NF, 0>::NB == NB8,
                   "fixed column length must start and end with radix 8");
     const bool fixed = H == NF && p.fc.variant == 0;
+    // and half that length (256 in the 512 instantiation: columns of 256^2 problems)
+    constexpr int NH = NF / 2;
+    constexpr bool HALF = NF == 512;
+    const bool fixedh = HALF && H == NH && p.fc.variant == 0;
 
     if (fused) {
         // forward: stage 0 (radix 8, no twiddles) from registers
@@ -210,6 +214,13 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
                 c_stages<NF, 1, NST - 1, false>(buf, stw, lane);
                 c_load<NF, NST - 1>(buf, v, lane);
                 c_bfly<NF, NST - 1, false>(stw, v, lane);
+            } else if (HALF && fixedh) {
+                if constexpr (HALF) {
+                    constexpr int NSH = CSched<NH>::nst();
+                    c_stages<NH, 1, NSH - 1, false>(buf, stw, lane);
+                    c_load<NH, NSH - 1>(buf, v, lane);
+                    c_bfly<NH, NSH - 1, false>(stw, v, lane);
+                }
             } else {
                 wave_stages<EPL, false>(buf, stw, p.fc, 1, nst - 1, lane);
                 // last stage (radix 8, Ns = H / 8): output r of butterfly j is entry j + r H / 8
@@ -253,6 +264,13 @@ __global__ __launch_bounds__(NTC) void k_col(const ProbDesc* __restrict__ pd, co
                 c_stages<NF, 1, NST - 1, true>(buf, stw, lane);
                 c_load<NF, NST - 1>(buf, v, lane);
                 c_bfly<NF, NST - 1, true>(stw, v, lane);
+            } else if (HALF && fixedh) {
+                if constexpr (HALF) {
+                    constexpr int NSH = CSched<NH>::nst();
+                    c_stages<NH, 1, NSH - 1, true>(buf, stw, lane);
+                    c_load<NH, NSH - 1>(buf, v, lane);
+                    c_bfly<NH, NSH - 1, true>(stw, v, lane);
+                }
             } else {
                 wave_stages<EPL, true>(buf, stw, p.fc, 1, nst - 1, lane);
                 const ADMM_LDS float2* tl = stw + p.fc.tso[nst - 1];

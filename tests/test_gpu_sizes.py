@@ -7,7 +7,8 @@ names the kernel instantiations it runs:
 
 * column pass: one instantiation per size class of the column length
   (<= 512, <= 1024, <= 2048) and schedule (first and last stage radix 8:
-  fixed; otherwise general), the block-level pass for columns of
+  fixed; otherwise general; lengths 256, 512, 1024 and 2048 on compile-time
+  schedules), the block-level pass for columns of
   2049..4096 and 4097..8192, and split columns above 8192 (a radix-p pass
   through HBM around block-level sub-transforms);
 * TV row pass: one per size class of the row length (rows per block 8, 6, 2),
@@ -113,6 +114,13 @@ def test_fa_general_lengths_of_the_largest_row_class():
     # (general, largest class of the plain row passes)
     announce("FA 600 x 1250 J = 2, k = 2, 4")
     _single(full_problem(206, 600, 1250, 7, reg="frame", levels=2), [2, 4], graph=False)
+
+
+def test_columns_of_256_on_the_compile_time_schedule():
+    # columns of 256 (radix 8, 4, 8) take a compile-time schedule inside the
+    # 512 instantiation of the column pass: TV and frame problems in one batch
+    announce("TV 256 x 200 + FA 256 x 96 (J = 2), k = 2, 6")
+    _batch([full_problem(240, 256, 200, 9), full_problem(241, 256, 96, 5, reg="frame", levels=2)], [2, 6])
 
 
 def test_fa_row_widths_of_the_narrow_plain_blocks():
