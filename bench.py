@@ -525,7 +525,7 @@ def cpu_baseline(iters, sample, c1=None, c3=None, c4=None):
         t0 = time.perf_counter()
         O.fa_md_run(c3.y, c3.mask, c3.kernel, c3.lam, c3.mu1, c3.mu2, c3.levels, iters=5)
         dt = time.perf_counter() - t0
-        out["config3"] = {"value": round(c3.y.size * 5 / dt / 1e6, 3), "unit": "Mpx*iter/s",
+        out["fa1024"] = {"value": round(c3.y.size * 5 / dt / 1e6, 3), "unit": "Mpx*iter/s",
                           "s_per_iter": round(dt / 5, 3),
                           "sample": f"FA-MD {c3.shape[0]}x{c3.shape[1]}, J = {c3.levels}, 5 iterations"}
     if c4:
@@ -535,7 +535,7 @@ def cpu_baseline(iters, sample, c1=None, c3=None, c4=None):
             O.tv_md_run(p.y, p.mask, p.kernel, p.lam, p.mu1, p.mu2, iters=5)
         dt = time.perf_counter() - t0
         rate = sum(p.y.size for p in sub) * 5 / dt
-        out["config4"] = {"value": round(rate / 1e6, 3), "unit": "Mpx*iter/s",
+        out["ragged256"] = {"value": round(rate / 1e6, 3), "unit": "Mpx*iter/s",
                           "extrapolated_s_per_iter": round(sum(p.y.size for p in c4) / rate, 2),
                           "sample": "TV-MD, the first 4 of the 256 ragged problems ("
                                     + ", ".join(f"{p.shape[0]}x{p.shape[1]}" for p in sub)
